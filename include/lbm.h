@@ -1,0 +1,180 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) library for lattice-BGK with the
+ * entropic equilibrium.
+ *
+ * Method: S. A. Hosseini and I. V. Karlin, "Entropic equilibrium for the lattice
+ * Boltzmann method: Hydrodynamics and numerical properties", arXiv:2303.08163.
+ * One time step of a domain is the LBGK evolution equation of Sec. "Basic
+ * concepts",
+ *     f_i(r + c_i, t + 1) = f_i(r, t) + 2 beta (f_i^eq(rho, u) - f_i(r, t)),
+ * on a periodic D2Q9 or D3Q27 first-neighbour lattice (1-D weights
+ * {1/6, 2/3, 1/6} and their tensor products), in lattice units
+ * (dr = dt = 1, varsigma^2 = 1/3), with
+ *   - f^eq the entropic equilibrium, eq. (Entropic_isothermal_EDF);
+ *   - beta from eq. (relaxation_frequency) with nu = (tau - 1/2) / 3, i.e.
+ *     2 beta = 1 / tau; or, with the bulk-viscosity correction of Sec.
+ *     "Correction of leading-order bulk viscosity error", beta from
+ *     eq. (redefined_relaxation rate) with the entropic A of eq.
+ *     (entropic_bulk) evaluated at the node's own pre-collision velocity.  The
+ *     paper derives A on a 1-D lattice; a multi-dimensional node uses
+ *     A = min over axes of A(u_alpha).
+ *
+ * Conventions shared by every entry point:
+ *   - Fields are node-major planes with x fastest: node n = x + nx (y + ny z).
+ *     A density field is N = nx ny nz doubles; a velocity field is D planes of
+ *     N doubles (u_x plane, then u_y, then u_z for D3Q27).
+ *   - "device pointer" means memory allocated on the GPU the library runs on
+ *     (hipMalloc or a torch CUDA tensor); "host pointer" means CPU memory.
+ *   - Every call returns an lbm_status (0 = LBM_OK, negative = error) unless
+ *     stated otherwise; no exception crosses the ABI.  Arguments are validated
+ *     before any GPU work is enqueued; on error nothing is written to outputs.
+ *   - A handle is not thread-safe.  Distinct handles are independent.  Work is
+ *     enqueued on the handle's HIP stream; calls that return data to the host
+ *     synchronise that stream.
+ *   - The equilibrium is defined only for rho > 0 and |u_alpha| < 1 (Sec.
+ *     "Discrete entropic equilibrium construction"); the library does not
+ *     clamp.  A node that reaches a state outside that domain sets the
+ *     handle's domain flag, reported as LBM_EDOMAIN.
+ */
+#ifndef LBM_ENTROPIC_H
+#define LBM_ENTROPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum lbm_status {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,  /* invalid argument or configuration */
+    LBM_EDOMAIN = -2, /* some node left rho > 0, |u_alpha| < 1 (results still written) */
+    LBM_EDEVICE = -3, /* a HIP runtime call failed */
+    LBM_ENOMEM = -4,  /* a request does not fit the memory budget */
+    LBM_EBUSY = -5    /* no free slot */
+};
+
+/* Lattices: the value is Q. */
+enum { LBM_D2Q9 = 9, LBM_D3Q27 = 27 };
+
+/* Population storage.
+ *   LBM_FP64:     populations stored and computed in IEEE double.
+ *   LBM_FP32_DEV: populations stored in IEEE single as deviations
+ *                 f_i - w_i rho0 from the rest equilibrium at density rho0;
+ *                 every step widens them to double, computes the moments, the
+ *                 equilibrium and the relaxation in double, and rounds the
+ *                 result to nearest-even single on store. */
+enum { LBM_FP64 = 0, LBM_FP32_DEV = 1 };
+
+/* Equilibrium: the entropic one (eq. Entropic_isothermal_EDF). */
+enum { LBM_EQ_ENTROPIC = 0 };
+
+/* Problem statement of one periodic domain (plain data, caller-owned). */
+typedef struct lbm_config {
+    int32_t lattice;         /* LBM_D2Q9 or LBM_D3Q27 */
+    int32_t dtype;           /* LBM_FP64 or LBM_FP32_DEV */
+    int64_t nx, ny, nz;      /* grid extent; nz must be 1 for D2Q9; each >= 1 */
+    double tau;              /* relaxation time, tau > 1/2 and finite; 2 beta = 1/tau */
+    int32_t bulk_correction; /* 0 = off, 1 = eq. (redefined_relaxation rate) */
+    int32_t equilibrium;     /* LBM_EQ_ENTROPIC */
+    double rho0;             /* reference density of LBM_FP32_DEV storage (> 0); ignored for FP64 */
+} lbm_config;
+
+/* Launch tuning (optional).  Zero fields take the library default.  Results do
+ * not depend on the tuning: every node's arithmetic is the same. */
+typedef struct lbm_tuning {
+    int32_t block_x;   /* threads along x per workgroup (multiple of 64 or a power of two <= 64) */
+    int32_t block_y;   /* rows along y per workgroup; block_x * block_y a multiple of 64, <= 256 */
+    int32_t plane_pad; /* extra elements between population planes (>= 0, padding against
+                          HBM channel aliasing; < 0 selects the default) */
+    int32_t reserved;  /* must be 0 */
+} lbm_tuning;
+
+/* Whole-domain diagnostics, all from the current populations. */
+typedef struct lbm_diag {
+    double mass;           /* sum_r rho */
+    double momentum[3];    /* sum_r rho u_alpha (unused components 0) */
+    double kinetic_energy; /* sum_r rho |u|^2 / 2 */
+    double max_abs_u;      /* max over nodes and axes of |u_alpha| */
+    double min_rho;        /* min over nodes of rho */
+    int64_t steps;         /* steps taken since lbm_create */
+    int32_t domain_error;  /* 1 if any node left the domain since lbm_create */
+    int32_t reserved;
+} lbm_diag;
+
+typedef struct lbm_handle lbm_handle;
+
+/* Bytes of device workspace a domain needs: two population buffers
+ * (Q planes each, padded), the domain flag and the reduction scratch.
+ * Returns 0 for an invalid configuration.  Host-only; no GPU call. */
+size_t lbm_workspace_bytes(const lbm_config *cfg);
+
+/* Same with explicit tuning (tuning may be NULL = defaults). */
+size_t lbm_workspace_bytes_tuned(const lbm_config *cfg, const lbm_tuning *tuning);
+
+/* Create a domain and initialise f = f^eq(rho, u) (the state the paper's
+ * experiments start from).
+ *   cfg        host pointer, copied.
+ *   workspace  device pointer to ws_bytes >= lbm_workspace_bytes(cfg) bytes,
+ *              256-byte aligned, owned by the caller and borrowed by the handle
+ *              until lbm_destroy (the library never frees it).
+ *   rho, u     device pointers to the initial density (N doubles) and velocity
+ *              (D * N doubles); read before the call returns.
+ *   stream     hipStream_t to enqueue on (NULL = the null stream).
+ *   out        receives the handle; untouched on error.
+ * Synchronises the stream.  Errors: LBM_EINVAL (NULL pointer, tau <= 1/2 or
+ * not finite, an extent < 1, nz != 1 for D2Q9, more than 2^31 - 1 elements
+ * per population plane, nz or ny blocks beyond the launch limits, bad
+ * lattice/dtype/equilibrium, rho0 <= 0 for FP32_DEV, workspace too small or
+ * misaligned); LBM_EDOMAIN (an initial node has rho <= 0 or |u_alpha| >= 1;
+ * no handle is created); LBM_EDEVICE. */
+int lbm_create(const lbm_config *cfg, void *workspace, size_t ws_bytes, const double *rho,
+               const double *u, void *stream, lbm_handle **out);
+
+/* lbm_create with explicit tuning (tuning may be NULL = defaults). */
+int lbm_create_tuned(const lbm_config *cfg, const lbm_tuning *tuning, void *workspace,
+                     size_t ws_bytes, const double *rho, const double *u, void *stream,
+                     lbm_handle **out);
+
+/* Enqueue nsteps time steps (one fused stream-and-collide kernel launch each)
+ * on the handle's stream and return without synchronising.  nsteps = 0 is a
+ * no-op.  Errors: LBM_EINVAL (h NULL, nsteps < 0); LBM_EDEVICE (launch
+ * failure). */
+int lbm_step(lbm_handle *h, int64_t nsteps);
+
+/* Moments of the current state: rho (N doubles) and u (D * N doubles) into
+ * device pointers, and diagnostics into a host struct.  Any of rho, u, diag may
+ * be NULL.  Synchronises the stream.  Returns LBM_EDOMAIN when any node left
+ * the domain since lbm_create (the outputs are still written), LBM_EINVAL for
+ * h NULL, LBM_EDEVICE on a HIP failure. */
+int lbm_moments(lbm_handle *h, double *rho, double *u, lbm_diag *diag);
+
+/* Copy the current populations out as doubles in the library's canonical
+ * order, population-major: out[i * N + n] for population i, node n, where
+ * i = (c_x + 1) + 3 (c_y + 1) + 9 (c_z + 1) and the stored state is the
+ * post-collision f*(r, t) (its moments equal those of the pre-collision state).
+ * FP32_DEV storage is widened and rho0 w_i added back.  out is a device
+ * pointer to Q * N doubles.  Synchronises the stream. */
+int lbm_get_populations(lbm_handle *h, double *out);
+
+/* Release the handle (host state only; the caller's workspace is untouched).
+ * Synchronises the stream first.  lbm_destroy(NULL) returns LBM_OK. */
+int lbm_destroy(lbm_handle *h);
+
+/* Static, human-readable name of a status code. */
+const char *lbm_status_string(int status);
+
+/* Message of the last error raised on the calling thread (static storage,
+ * empty if none). */
+const char *lbm_last_error(void);
+
+/* Library version string (static). */
+const char *lbm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_ENTROPIC_H */

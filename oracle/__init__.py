@@ -72,6 +72,8 @@ def _load():
                                       ctypes.c_double, ctypes.c_int, ctypes.c_int, dp, dp,
                                       ctypes.c_long, ctypes.c_long, lp, lp, lp, dp, dp]
     lib.oracle_run_sample.restype = ctypes.c_long
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_threads.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -90,6 +92,11 @@ def _grid3(shape):
     if D == 3:
         return 3, shape[2], shape[1], shape[0]
     raise ValueError("grid must be 1-, 2- or 3-dimensional")
+
+
+def set_threads(n: int = 0) -> int:
+    """Set the oracle's OpenMP thread count (n <= 0 keeps it); returns the count in effect."""
+    return int(_load().oracle_set_threads(int(n)))
 
 
 def lattice(D: int):
@@ -140,7 +147,7 @@ def run(rho0, u0, tau: float, steps: int, corr="off", kind: str = "entropic",
     u = np.zeros_like(u0)
     f = np.zeros((3 ** D,) + rho0.shape) if return_f else None
     if threads is not None:
-        os.environ["OMP_NUM_THREADS"] = str(threads)
+        set_threads(threads)
     bad = _load().oracle_run(D, nx, ny, nz, float(tau), EQ_KINDS[kind], CORR_MODES[corr],
                              _dptr(rho0), _dptr(u0), int(steps), _dptr(rho), _dptr(u),
                              _dptr(f) if return_f else None)

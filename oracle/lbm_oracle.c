@@ -51,6 +51,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORACLE_EQ_ENTROPIC 0
 #define ORACLE_EQ_POLY2 1
@@ -402,4 +405,17 @@ long oracle_run_sample(int D, long nx, long ny, long nz, double tau, int kind, i
     free(f);
     free(g);
     return 0;
+}
+
+/* Thread count of the node loops (OpenMP); returns the count in effect. */
+int oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }

@@ -1,0 +1,259 @@
+// kernels.hpp -- gfx950 kernels of one periodic domain: initialisation, the
+// fused pull-stream-and-collide step, moments with deterministic reductions,
+// and population export.
+//
+// Data layout in HBM (structure of arrays): population i of node
+// n = x + nx (y + ny z) lives at buf[i * stride + n]; stride >= N is a
+// multiple of 64 elements plus an optional pad, so every plane starts
+// 256-byte aligned.  Two such buffers alternate (read one, write the other).
+//
+// Streaming (Sec. "Basic concepts", left side of the LBGK equation) is done by
+// pulling: the buffer holds post-collision values f*(r, t), and the step at r
+// reads f*_i(r - c_i, t) = f_i(r, t + 1), collides, and writes f*_i(r, t + 1)
+// back at r.  Every value is read once and written once per step: the
+// algorithmic HBM traffic is 2 Q sizeof(storage) bytes per node update.
+// Workgroups cover (block_x * block_y) nodes of one z plane with x fastest, so
+// a wavefront reads 27 (or 9) rows of 64 consecutive elements shifted by at
+// most one element and writes 27 (or 9) aligned rows; the one-element shifts
+// fall on cache lines that the neighbouring wave of the same workgroup reads.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "node.hpp"
+
+namespace lbm {
+
+template <bool DEV>
+using store_t = typename std::conditional<DEV, float, double>::type;
+
+struct StepArgs {
+    const void *src;
+    void *dst;
+    int nx, ny, nz;
+    int64_t stride;
+    Relax relax;
+    int *flag;
+};
+
+// One LBGK step over the whole domain (grid: x blocks, y blocks, z planes).
+template <int DIM, bool DEV, bool CORR>
+__global__ __launch_bounds__(256) void k_stream_collide(StepArgs a) {
+    using T = store_t<DEV>;
+    constexpr int Q = Lattice<DIM>::Q;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= a.nx || y >= a.ny)
+        return;
+    const T *__restrict__ src = static_cast<const T *>(a.src);
+    T *__restrict__ dst = static_cast<T *>(a.dst);
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+
+    // source coordinate r - c for c = -1, 0, +1 on the periodic grid
+    const int xs[3] = {x + 1 == nx ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};
+    const int ys[3] = {y + 1 == ny ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
+    int zs[3] = {z, z, z};
+    if (DIM == 3) {
+        zs[0] = z + 1 == nz ? 0 : z + 1;
+        zs[2] = z == 0 ? nz - 1 : z - 1;
+    }
+
+    double f[Q];
+#pragma unroll
+    for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
+#pragma unroll
+        for (int cy = 0; cy < 3; ++cy) {
+            const uint32_t row = (uint32_t)((DIM == 3 ? zs[cz] : z) * ny + ys[cy]) * (uint32_t)nx;
+#pragma unroll
+            for (int cx = 0; cx < 3; ++cx) {
+                const int i = cx + 3 * cy + 9 * cz;
+                f[i] = (double)src[(int64_t)i * a.stride + (row + (uint32_t)xs[cx])];
+            }
+        }
+
+    const bool bad = collide<DIM, DEV, CORR>(f, a.relax);
+    if (bad)
+        __hip_atomic_fetch_or(a.flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
+    const uint32_t self = (uint32_t)(z * ny + y) * (uint32_t)nx + (uint32_t)x;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        dst[(int64_t)i * a.stride + self] = (T)f[i];
+}
+
+// Zero `count` 32-bit words (a kernel rather than a memset, so that the call
+// sequence stays valid inside captured HIP graphs).
+__global__ void k_clear_words(int *p, int count) {
+    for (int k = threadIdx.x; k < count; k += blockDim.x)
+        p[k] = 0;
+}
+
+struct InitArgs {
+    void *dst;
+    const double *rho;
+    const double *u;  // D planes of N
+    int64_t n, stride;
+    double rho0;
+    int *flag;
+};
+
+// f = f^eq(rho, u) at every node.
+template <int DIM, bool DEV>
+__global__ __launch_bounds__(256) void k_init(InitArgs a) {
+    using T = store_t<DEV>;
+    constexpr int Q = Lattice<DIM>::Q;
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= a.n)
+        return;
+    double u[3] = {a.u[n], a.u[a.n + n], DIM == 3 ? a.u[2 * a.n + n] : 0.0};
+    double f[Q];
+    const bool bad = equilibrium_stored<DIM, DEV>(a.rho[n], u, a.rho0, f);
+    if (bad)
+        __hip_atomic_fetch_or(a.flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    T *dst = static_cast<T *>(a.dst);
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        dst[i * a.stride + n] = (T)f[i];
+}
+
+// Diagnostics partials per workgroup: mass, momentum x/y/z, kinetic energy,
+// max |u_a|, min rho.
+constexpr int kDiagFields = 7;
+constexpr int kReduceThreads = 256;
+
+struct MomentArgs {
+    const void *src;
+    double *rho;  // may be null
+    double *u;    // may be null
+    int64_t n, stride;
+    double rho0;
+    double *partials;  // gridDim.x * kDiagFields
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Reduce kDiagFields values across a 256-thread workgroup in a fixed order
+// (wavefront butterflies, then the 4 wave results in index order).
+__device__ __forceinline__ void block_reduce_diag(double (&acc)[kDiagFields], double *out) {
+    __shared__ double lds[kReduceThreads / 64][kDiagFields];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+        acc[k] = wave_sum(acc[k]);
+    acc[5] = wave_max(acc[5]);
+    acc[6] = wave_min(acc[6]);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < kDiagFields; ++k)
+            lds[wave][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r[kDiagFields];
+#pragma unroll
+        for (int k = 0; k < kDiagFields; ++k)
+            r[k] = lds[0][k];
+        for (int w = 1; w < kReduceThreads / 64; ++w) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k)
+                r[k] += lds[w][k];
+            r[5] = fmax(r[5], lds[w][5]);
+            r[6] = fmin(r[6], lds[w][6]);
+        }
+#pragma unroll
+        for (int k = 0; k < kDiagFields; ++k)
+            out[k] = r[k];
+    }
+}
+
+template <int DIM, bool DEV>
+__global__ __launch_bounds__(kReduceThreads) void k_moments(MomentArgs a) {
+    using T = store_t<DEV>;
+    constexpr int Q = Lattice<DIM>::Q;
+    const T *src = static_cast<const T *>(a.src);
+    double acc[kDiagFields] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, INFINITY};
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < a.n;
+         n += (int64_t)gridDim.x * blockDim.x) {
+        double f[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            f[i] = (double)src[i * a.stride + n];
+        double rho, j[3];
+        node_moments<DIM>(f, DEV ? a.rho0 : 0.0, rho, j);
+        const double inv = 1.0 / rho;
+        const double u[3] = {j[0] * inv, j[1] * inv, j[2] * inv};
+        if (a.rho)
+            a.rho[n] = rho;
+        if (a.u) {
+#pragma unroll
+            for (int d = 0; d < DIM; ++d)
+                a.u[d * a.n + n] = u[d];
+        }
+        acc[0] += rho;
+        acc[1] += j[0];
+        acc[2] += j[1];
+        acc[3] += j[2];
+        acc[4] += 0.5 * ((j[0] * u[0] + j[1] * u[1]) + j[2] * u[2]);
+        acc[5] = fmax(acc[5], fmax(fabs(u[0]), fmax(fabs(u[1]), fabs(u[2]))));
+        acc[6] = fmin(acc[6], rho);
+    }
+    block_reduce_diag(acc, a.partials + (int64_t)blockIdx.x * kDiagFields);
+}
+
+// Second pass: one workgroup folds the per-workgroup partials in a fixed order.
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_partials(const double *partials, int count,
+                                                                    double *out) {
+    double acc[kDiagFields] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, INFINITY};
+    for (int b = threadIdx.x; b < count; b += blockDim.x) {
+        const double *p = partials + (int64_t)b * kDiagFields;
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+            acc[k] += p[k];
+        acc[5] = fmax(acc[5], p[5]);
+        acc[6] = fmin(acc[6], p[6]);
+    }
+    block_reduce_diag(acc, out);
+}
+
+struct ExportArgs {
+    const void *src;
+    double *out;
+    int64_t n, stride;
+    double rho0;
+};
+
+template <int DIM, bool DEV>
+__global__ __launch_bounds__(256) void k_export(ExportArgs a) {
+    using T = store_t<DEV>;
+    const T *src = static_cast<const T *>(a.src);
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= a.n)
+        return;
+#pragma unroll
+    for (int i = 0; i < Lattice<DIM>::Q; ++i) {
+        double v = (double)src[i * a.stride + n];
+        if (DEV)
+            v = fma(Lattice<DIM>::weight(i), a.rho0, v);
+        a.out[i * a.n + n] = v;
+    }
+}
+
+}  // namespace lbm

@@ -1,0 +1,383 @@
+// lbm_api.hip -- host side of the C ABI declared in include/lbm.h: argument
+// validation, workspace layout, kernel selection and launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "kernels.hpp"
+#include "lbm.h"
+#include "lbm_internal.hpp"
+
+namespace lbm {
+
+thread_local char g_last_error[256] = "";
+
+void set_error(const char *msg) { std::snprintf(g_last_error, sizeof(g_last_error), "%s", msg); }
+
+int hip_fail(hipError_t e, const char *what) {
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s", what, hipGetErrorString(e));
+    return LBM_EDEVICE;
+}
+
+static int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
+    if (!cfg) {
+        set_error("config is NULL");
+        return LBM_EINVAL;
+    }
+    Layout L{};
+    if (cfg->lattice == LBM_D2Q9) {
+        L.dim = 2;
+        L.q = 9;
+    } else if (cfg->lattice == LBM_D3Q27) {
+        L.dim = 3;
+        L.q = 27;
+    } else {
+        set_error("lattice must be LBM_D2Q9 or LBM_D3Q27");
+        return LBM_EINVAL;
+    }
+    if (cfg->dtype == LBM_FP64)
+        L.elem = 8;
+    else if (cfg->dtype == LBM_FP32_DEV)
+        L.elem = 4;
+    else {
+        set_error("dtype must be LBM_FP64 or LBM_FP32_DEV");
+        return LBM_EINVAL;
+    }
+    if (cfg->equilibrium != LBM_EQ_ENTROPIC) {
+        set_error("equilibrium must be LBM_EQ_ENTROPIC");
+        return LBM_EINVAL;
+    }
+    if (!(cfg->tau > 0.5) || !std::isfinite(cfg->tau)) {
+        set_error("tau must be finite and > 1/2");
+        return LBM_EINVAL;
+    }
+    if (cfg->bulk_correction != 0 && cfg->bulk_correction != 1) {
+        set_error("bulk_correction must be 0 or 1");
+        return LBM_EINVAL;
+    }
+    if (cfg->dtype == LBM_FP32_DEV && (!(cfg->rho0 > 0.0) || !std::isfinite(cfg->rho0))) {
+        set_error("rho0 must be finite and > 0 for FP32_DEV storage");
+        return LBM_EINVAL;
+    }
+    if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1) {
+        set_error("grid extents must be >= 1");
+        return LBM_EINVAL;
+    }
+    if (L.dim == 2 && cfg->nz != 1) {
+        set_error("nz must be 1 for D2Q9");
+        return LBM_EINVAL;
+    }
+    if (cfg->nx > INT32_MAX || cfg->ny > INT32_MAX || cfg->nz > 65535) {
+        set_error("grid extent beyond launch limits (nz <= 65535)");
+        return LBM_EINVAL;
+    }
+    L.n = cfg->nx * cfg->ny * cfg->nz;
+    if (L.n > (int64_t)INT32_MAX - 4096) {
+        set_error("more than 2^31 - 4096 nodes per population plane");
+        return LBM_EINVAL;
+    }
+    // tuning
+    int bx = 0, by = 0, pad = -1;
+    if (tun) {
+        if (tun->reserved != 0) {
+            set_error("lbm_tuning.reserved must be 0");
+            return LBM_EINVAL;
+        }
+        bx = tun->block_x;
+        by = tun->block_y;
+        pad = tun->plane_pad;
+    }
+    if (bx == 0) {
+        bx = 64;
+        while (bx > 1 && bx / 2 >= cfg->nx)
+            bx /= 2;
+    }
+    if (by == 0)
+        by = 256 / bx;
+    if (bx < 1 || by < 1 || bx * by > 256 || (bx * by) % 64 != 0 ||
+        (bx % 64 != 0 && (bx > 64 || (bx & (bx - 1)) != 0))) {
+        set_error("block_x * block_y must be a multiple of 64 and <= 256; block_x a multiple "
+                  "of 64 or a power of two <= 64");
+        return LBM_EINVAL;
+    }
+    if ((cfg->ny + by - 1) / by > 65535) {
+        set_error("ny / block_y exceeds the launch limit of 65535 workgroups");
+        return LBM_EINVAL;
+    }
+    L.block_x = bx;
+    L.block_y = by;
+    if (pad < 0)
+        pad = 0;
+    if (pad > (1 << 20)) {
+        set_error("plane_pad too large");
+        return LBM_EINVAL;
+    }
+    L.stride = round_up(L.n, 64) + round_up(pad, 64);
+    if ((int64_t)L.q * L.stride > ((int64_t)1 << 40)) {
+        set_error("domain too large");
+        return LBM_EINVAL;
+    }
+    L.buf_bytes = (size_t)L.q * (size_t)L.stride * L.elem;
+    L.red_blocks = (int)std::min<int64_t>(1024, (L.n + kReduceThreads - 1) / kReduceThreads);
+    // workspace: buffer A | buffer B | flag block (256 B) | diag out (256 B) | partials
+    L.off_buf[0] = 0;
+    L.off_buf[1] = round_up(L.buf_bytes, 256);
+    L.off_flag = L.off_buf[1] + round_up(L.buf_bytes, 256);
+    L.off_diag = L.off_flag + 256;
+    L.off_partials = L.off_diag + 256;
+    L.ws_bytes = L.off_partials + round_up((size_t)L.red_blocks * kDiagFields * sizeof(double), 256);
+    if (out)
+        *out = L;
+    return LBM_OK;
+}
+
+// Kernel tables indexed by [dev][corr].
+using StepFn = void (*)(StepArgs);
+template <int DIM>
+static StepFn step_kernel(bool dev, bool corr) {
+    if (dev)
+        return corr ? k_stream_collide<DIM, true, true> : k_stream_collide<DIM, true, false>;
+    return corr ? k_stream_collide<DIM, false, true> : k_stream_collide<DIM, false, false>;
+}
+
+int launch_step(const Layout &L, const StepArgs &args, bool dev, bool corr, hipStream_t s, int nz) {
+    dim3 block(L.block_x, L.block_y, 1);
+    dim3 grid((unsigned)((args.nx + L.block_x - 1) / L.block_x),
+              (unsigned)((args.ny + L.block_y - 1) / L.block_y), (unsigned)nz);
+    StepFn fn = L.dim == 2 ? step_kernel<2>(dev, corr) : step_kernel<3>(dev, corr);
+    hipLaunchKernelGGL(fn, grid, block, 0, s, args);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return hip_fail(e, "stream-collide launch");
+    return LBM_OK;
+}
+
+}  // namespace lbm
+
+using namespace lbm;
+
+struct lbm_handle {
+    lbm_config cfg;
+    Layout L;
+    char *ws;
+    void *buf[2];
+    int cur;
+    int *flag;
+    double *diag_dev;
+    double *partials;
+    hipStream_t stream;
+    int64_t steps;
+    Relax relax;
+};
+
+extern "C" {
+
+size_t lbm_workspace_bytes_tuned(const lbm_config *cfg, const lbm_tuning *tuning) {
+    Layout L;
+    if (validate_config(cfg, tuning, &L) != LBM_OK)
+        return 0;
+    return L.ws_bytes;
+}
+
+size_t lbm_workspace_bytes(const lbm_config *cfg) { return lbm_workspace_bytes_tuned(cfg, nullptr); }
+
+int lbm_create_tuned(const lbm_config *cfg, const lbm_tuning *tuning, void *workspace, size_t ws_bytes,
+                     const double *rho, const double *u, void *stream, lbm_handle **out) {
+    Layout L;
+    int rc = validate_config(cfg, tuning, &L);
+    if (rc != LBM_OK)
+        return rc;
+    if (!workspace || !rho || !u || !out) {
+        set_error("NULL workspace, rho, u or out");
+        return LBM_EINVAL;
+    }
+    if (ws_bytes < L.ws_bytes) {
+        set_error("workspace smaller than lbm_workspace_bytes()");
+        return LBM_EINVAL;
+    }
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) {
+        set_error("workspace must be 256-byte aligned");
+        return LBM_EINVAL;
+    }
+    lbm_handle *h = new (std::nothrow) lbm_handle();
+    if (!h) {
+        set_error("host allocation failed");
+        return LBM_EINVAL;
+    }
+    h->cfg = *cfg;
+    h->L = L;
+    h->ws = static_cast<char *>(workspace);
+    h->buf[0] = h->ws + L.off_buf[0];
+    h->buf[1] = h->ws + L.off_buf[1];
+    h->cur = 0;
+    h->flag = reinterpret_cast<int *>(h->ws + L.off_flag);
+    h->diag_dev = reinterpret_cast<double *>(h->ws + L.off_diag);
+    h->partials = reinterpret_cast<double *>(h->ws + L.off_partials);
+    h->stream = static_cast<hipStream_t>(stream);
+    h->steps = 0;
+    h->relax.omega = 1.0 / cfg->tau;
+    h->relax.two_tau_m1 = 2.0 * cfg->tau - 1.0;
+    h->relax.rho0 = cfg->dtype == LBM_FP32_DEV ? cfg->rho0 : 0.0;
+
+    hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(64), 0, h->stream, h->flag, 64);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "clearing the domain flag");
+    }
+    InitArgs ia{h->buf[0], rho, u, L.n, L.stride, h->relax.rho0, h->flag};
+    const bool dev = cfg->dtype == LBM_FP32_DEV;
+    dim3 grid((unsigned)((L.n + 255) / 256)), block(256);
+    void (*init_fn)(InitArgs) = L.dim == 2 ? (dev ? k_init<2, true> : k_init<2, false>)
+                                           : (dev ? k_init<3, true> : k_init<3, false>);
+    hipLaunchKernelGGL(init_fn, grid, block, 0, h->stream, ia);
+    e = hipGetLastError();
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "init launch");
+    }
+    int flag = 0;
+    e = hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "init synchronise");
+    }
+    if (flag) {
+        delete h;
+        set_error("initial state has a node with rho <= 0 or |u_alpha| >= 1");
+        return LBM_EDOMAIN;
+    }
+    *out = h;
+    return LBM_OK;
+}
+
+int lbm_create(const lbm_config *cfg, void *workspace, size_t ws_bytes, const double *rho, const double *u,
+               void *stream, lbm_handle **out) {
+    return lbm_create_tuned(cfg, nullptr, workspace, ws_bytes, rho, u, stream, out);
+}
+
+int lbm_step(lbm_handle *h, int64_t nsteps) {
+    if (!h || nsteps < 0) {
+        set_error("NULL handle or negative step count");
+        return LBM_EINVAL;
+    }
+    const bool dev = h->cfg.dtype == LBM_FP32_DEV;
+    const bool corr = h->cfg.bulk_correction != 0;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        StepArgs a{h->buf[h->cur], h->buf[h->cur ^ 1], (int)h->cfg.nx, (int)h->cfg.ny, (int)h->cfg.nz,
+                   h->L.stride, h->relax, h->flag};
+        int rc = launch_step(h->L, a, dev, corr, h->stream, (int)h->cfg.nz);
+        if (rc != LBM_OK)
+            return rc;
+        h->cur ^= 1;
+        h->steps++;
+    }
+    return LBM_OK;
+}
+
+int lbm_moments(lbm_handle *h, double *rho, double *u, lbm_diag *diag) {
+    if (!h) {
+        set_error("NULL handle");
+        return LBM_EINVAL;
+    }
+    const Layout &L = h->L;
+    const bool dev = h->cfg.dtype == LBM_FP32_DEV;
+    MomentArgs ma{h->buf[h->cur], rho, u, L.n, L.stride, h->relax.rho0, h->partials};
+    dim3 grid((unsigned)L.red_blocks), block(kReduceThreads);
+    void (*mom_fn)(MomentArgs) = L.dim == 2 ? (dev ? k_moments<2, true> : k_moments<2, false>)
+                                            : (dev ? k_moments<3, true> : k_moments<3, false>);
+    hipLaunchKernelGGL(mom_fn, grid, block, 0, h->stream, ma);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kReduceThreads), 0, h->stream,
+                       (const double *)h->partials, L.red_blocks, h->diag_dev);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return hip_fail(e, "moments launch");
+    double d[kDiagFields];
+    int flag = 0;
+    e = hipMemcpyAsync(d, h->diag_dev, sizeof(d), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "moments synchronise");
+    if (diag) {
+        diag->mass = d[0];
+        diag->momentum[0] = d[1];
+        diag->momentum[1] = d[2];
+        diag->momentum[2] = d[3];
+        diag->kinetic_energy = d[4];
+        diag->max_abs_u = d[5];
+        diag->min_rho = d[6];
+        diag->steps = h->steps;
+        diag->domain_error = flag ? 1 : 0;
+        diag->reserved = 0;
+    }
+    if (flag) {
+        set_error("a node left rho > 0, |u_alpha| < 1");
+        return LBM_EDOMAIN;
+    }
+    return LBM_OK;
+}
+
+int lbm_get_populations(lbm_handle *h, double *out) {
+    if (!h || !out) {
+        set_error("NULL handle or output");
+        return LBM_EINVAL;
+    }
+    const Layout &L = h->L;
+    const bool dev = h->cfg.dtype == LBM_FP32_DEV;
+    ExportArgs ea{h->buf[h->cur], out, L.n, L.stride, h->relax.rho0};
+    dim3 grid((unsigned)((L.n + 255) / 256)), block(256);
+    void (*exp_fn)(ExportArgs) = L.dim == 2 ? (dev ? k_export<2, true> : k_export<2, false>)
+                                            : (dev ? k_export<3, true> : k_export<3, false>);
+    hipLaunchKernelGGL(exp_fn, grid, block, 0, h->stream, ea);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "population export");
+    return LBM_OK;
+}
+
+int lbm_destroy(lbm_handle *h) {
+    if (!h)
+        return LBM_OK;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    delete h;
+    if (e != hipSuccess)
+        return hip_fail(e, "destroy synchronise");
+    return LBM_OK;
+}
+
+const char *lbm_status_string(int status) {
+    switch (status) {
+    case LBM_OK:
+        return "LBM_OK";
+    case LBM_EINVAL:
+        return "LBM_EINVAL: invalid argument";
+    case LBM_EDOMAIN:
+        return "LBM_EDOMAIN: a node left rho > 0, |u_alpha| < 1";
+    case LBM_EDEVICE:
+        return "LBM_EDEVICE: HIP runtime error";
+    case LBM_ENOMEM:
+        return "LBM_ENOMEM: does not fit the memory budget";
+    case LBM_EBUSY:
+        return "LBM_EBUSY: no free slot";
+    default:
+        return "unknown status";
+    }
+}
+
+const char *lbm_last_error(void) { return g_last_error; }
+
+const char *lbm_version(void) { return "lbm-entropic 0.1 (gfx950)"; }
+
+}  // extern "C"

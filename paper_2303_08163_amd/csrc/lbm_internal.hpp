@@ -1,0 +1,31 @@
+// lbm_internal.hpp -- host-side layout of a domain's workspace and shared
+// helpers of the C-ABI implementation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "kernels.hpp"
+#include "lbm.h"
+
+namespace lbm {
+
+// Workspace layout of one domain (all offsets in bytes, 256-byte aligned).
+struct Layout {
+    int dim, q;
+    size_t elem;       // bytes per stored population
+    int64_t n;         // nodes
+    int64_t stride;    // elements between population planes
+    int block_x, block_y;
+    int red_blocks;    // workgroups of the moments reduction
+    size_t buf_bytes;  // one population buffer
+    size_t off_buf[2], off_flag, off_diag, off_partials, ws_bytes;
+};
+
+void set_error(const char *msg);
+int hip_fail(hipError_t e, const char *what);
+int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out);
+int launch_step(const Layout &L, const StepArgs &args, bool dev, bool corr, hipStream_t s, int nz);
+
+}  // namespace lbm

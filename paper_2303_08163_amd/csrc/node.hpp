@@ -1,0 +1,185 @@
+// node.hpp -- per-node arithmetic of one LBGK step with the entropic
+// equilibrium, shared by every kernel of the library so that a node's result
+// is bitwise the same whichever kernel (single domain, batched, pool) runs it.
+//
+// Method (arXiv:2303.08163):
+//   Sec. "Basic concepts": f_i <- f_i + 2 beta (f_i^eq - f_i), with
+//     rho = sum_i f_i and rho u = sum_i c_i f_i; 2 beta = 1 / tau.
+//   Sec. "Discrete entropic equilibrium construction", eq.
+//     (Entropic_isothermal_EDF).  With S_a = sqrt(1 + 3 u_a^2) the multipliers
+//     Z_a = (2 u_a + S_a) / (1 - u_a) and X^{-1} = rho prod_a (2 - S_a) give
+//     f_i^eq = rho prod_a g_{c_ia}(u_a), where
+//       g_0 = 2 (2 - S) / 3,  g_{+1} = (2 S - 1 + 3 u) / 6,  g_{-1} = (2 S - 1 - 3 u) / 6
+//     because, with S^2 = 1 + 3 u^2, (2 - S)(2 u + S) = (1 - u)(2 S - 1 + 3 u) and
+//     (2 - S)(1 - u) = (2 u + S)(2 S - 1 - 3 u) hold identically.  This needs
+//     one square root per axis and no power, exponential or division.
+//   Sec. "Correction of leading-order bulk viscosity error", eq.
+//     (redefined_relaxation rate) with A from eq. (entropic_bulk):
+//     2 beta = 2 A / (A + 2 tau - 1).  A node uses A = min_a A(u_a); A is even
+//     and decreasing in |u| on [0, 1), so that is A at u_max = max_a |u_a|, i.e.
+//     at S_max = max_a S_a.  Written without cancellation
+//     (v^2 = 3 u_max^2, v^2 + 2 - 2 S = (S - 1)^2 = v^4 / (S + 1)^2):
+//       A = [2 S^2 (S+1)^2 (1 - 3 v^2 / 2) + v^4 (3 (S+1)^2 + 1)] / [2 S^2 (S+1)^2],
+//     so 2 beta = 2 P / (P + (2 tau - 1) Qd) with A = P / Qd: one division.
+//
+// Storage: DEV = false holds f_i in double.  DEV = true holds deviations
+// f_i - w_i rho0 in float; the moments use sum w_i = 1 and sum w_i c_i = 0 so
+// that rho = rho0 + sum_i (f_i - w_i rho0) and rho u = sum_i c_i (f_i - w_i rho0).
+// All arithmetic is double.  The library is compiled with FMA contraction off;
+// the fused multiply-adds below are written out.
+//
+// Population index: i = (c_x + 1) + 3 (c_y + 1) + 9 (c_z + 1).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace lbm {
+
+// 1-D weights of c = -1, 0, +1 (Sec. "Basic concepts").
+__host__ __device__ constexpr double w1(int k) { return k == 1 ? 2.0 / 3.0 : 1.0 / 6.0; }
+
+template <int DIM>
+struct Lattice {
+    static constexpr int Q = DIM == 2 ? 9 : 27;
+    static constexpr int NZ = DIM == 2 ? 1 : 3;  // number of c_z values
+    __host__ __device__ static constexpr double weight(int i) {
+        return w1(i % 3) * w1((i / 3) % 3) * (DIM == 2 ? 1.0 : w1(i / 9));
+    }
+};
+
+// Moments of the stored values of one node.  rho_shift = rho0 for deviation
+// storage, 0 otherwise.  j is the momentum rho u.
+template <int DIM>
+__device__ __forceinline__ void node_moments(const double (&f)[Lattice<DIM>::Q], double rho_shift,
+                                             double &rho, double (&j)[3]) {
+    // Row sums over c_x for every (c_y, c_z), then combine.
+    double row[3][3], rowx[3][3];
+#pragma unroll
+    for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
+#pragma unroll
+        for (int cy = 0; cy < 3; ++cy) {
+            const int b = 3 * cy + 9 * cz;
+            row[cz][cy] = (f[b + 0] + f[b + 1]) + f[b + 2];
+            rowx[cz][cy] = f[b + 2] - f[b + 0];
+        }
+    double s = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz) {
+        const double plane = (row[cz][0] + row[cz][1]) + row[cz][2];
+        s += plane;
+        jx += (rowx[cz][0] + rowx[cz][1]) + rowx[cz][2];
+        jy += row[cz][2] - row[cz][0];
+        if (DIM == 3)
+            jz += (cz == 2 ? plane : (cz == 0 ? -plane : 0.0));
+    }
+    rho = rho_shift + s;
+    j[0] = jx;
+    j[1] = jy;
+    j[2] = jz;
+}
+
+// Per-axis equilibrium factors g_{-1}, g_0, g_{+1} and S = sqrt(1 + 3 u^2).
+__device__ __forceinline__ void axis_factors(double u, double (&g)[3], double &S) {
+    S = sqrt(fma(3.0 * u, u, 1.0));
+    const double twoS_m1 = fma(2.0, S, -1.0);
+    const double three_u = 3.0 * u;
+    g[0] = (twoS_m1 - three_u) * (1.0 / 6.0);
+    g[1] = (2.0 - S) * (2.0 / 3.0);
+    g[2] = (twoS_m1 + three_u) * (1.0 / 6.0);
+}
+
+// 2 beta with the bulk-viscosity correction at the node's largest |u_a|.
+__device__ __forceinline__ double corrected_omega(double umax, double Smax, double two_tau_m1) {
+    const double v2 = 3.0 * umax * umax;
+    const double sp1 = Smax + 1.0;
+    const double q = 2.0 * (Smax * Smax) * (sp1 * sp1);
+    const double p = fma(q, fma(-1.5, v2, 1.0), (v2 * v2) * fma(3.0, sp1 * sp1, 1.0));
+    return (2.0 * p) / fma(two_tau_m1, q, p);
+}
+
+// Relaxation parameters of a domain.
+struct Relax {
+    double omega;       // 1 / tau (no correction)
+    double two_tau_m1;  // 2 tau - 1 (correction)
+    double rho0;        // deviation reference (DEV storage)
+};
+
+// One collision of one node: on entry f holds the stored (pre-collision)
+// values, on exit the stored post-collision values.  Returns true when the
+// node is outside the equilibrium's domain (rho <= 0, |u_a| >= 1 or NaN).
+template <int DIM, bool DEV, bool CORR>
+__device__ __forceinline__ bool collide(double (&f)[Lattice<DIM>::Q], const Relax &r) {
+    constexpr int Q = Lattice<DIM>::Q;
+    double rho, j[3];
+    node_moments<DIM>(f, DEV ? r.rho0 : 0.0, rho, j);
+    const double inv = 1.0 / rho;
+    double u[3] = {j[0] * inv, j[1] * inv, DIM == 3 ? j[2] * inv : 0.0};
+    bool bad = !(rho > 0.0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+        bad |= !(fabs(u[a]) < 1.0);
+
+    double g[3][3], S[3];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+        axis_factors(u[a], g[a], S[a]);
+
+    double omega = r.omega;
+    if (CORR) {
+        double umax = fabs(u[0]), Smax = S[0];
+#pragma unroll
+        for (int a = 1; a < DIM; ++a) {
+            umax = fmax(umax, fabs(u[a]));
+            Smax = fmax(Smax, S[a]);
+        }
+        omega = corrected_omega(umax, Smax, r.two_tau_m1);
+    }
+
+#pragma unroll
+    for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
+#pragma unroll
+        for (int cy = 0; cy < 3; ++cy) {
+            const double t = DIM == 3 ? (rho * g[1][cy]) * g[2][cz] : rho * g[1][cy];
+#pragma unroll
+            for (int cx = 0; cx < 3; ++cx) {
+                const int i = cx + 3 * cy + 9 * cz;
+                double feq = t * g[0][cx];
+                if (DEV)
+                    feq = fma(-Lattice<DIM>::weight(i), r.rho0, feq);
+                f[i] = fma(omega, feq - f[i], f[i]);
+            }
+        }
+    (void)Q;
+    return bad;
+}
+
+// Stored equilibrium of (rho, u) for initialisation; returns the domain flag.
+template <int DIM, bool DEV>
+__device__ __forceinline__ bool equilibrium_stored(double rho, const double (&u)[3], double rho0,
+                                                   double (&f)[Lattice<DIM>::Q]) {
+    bool bad = !(rho > 0.0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+        bad |= !(fabs(u[a]) < 1.0);
+    double g[3][3], S[3];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+        axis_factors(u[a], g[a], S[a]);
+#pragma unroll
+    for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
+#pragma unroll
+        for (int cy = 0; cy < 3; ++cy) {
+            const double t = DIM == 3 ? (rho * g[1][cy]) * g[2][cz] : rho * g[1][cy];
+#pragma unroll
+            for (int cx = 0; cx < 3; ++cx) {
+                const int i = cx + 3 * cy + 9 * cz;
+                double feq = t * g[0][cx];
+                if (DEV)
+                    feq = fma(-Lattice<DIM>::weight(i), rho0, feq);
+                f[i] = feq;
+            }
+        }
+    return bad;
+}
+
+}  // namespace lbm

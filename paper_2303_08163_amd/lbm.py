@@ -1,0 +1,268 @@
+"""Python binding of the C ABI in ``include/lbm.h`` (argument marshalling only).
+
+Every function here has the name of the C entry point it wraps and does nothing
+but convert arguments, call the native library and turn a negative status into
+an exception.  All arithmetic of the method runs in the library's HIP kernels;
+there is no Python or CPU fallback: if the built library is missing, loading
+fails with an error.
+
+``Domain`` is a convenience owner of one domain's device memory: it allocates
+the workspace and the initial fields as torch CUDA tensors (torch is used for
+device memory and streams only) and calls the functions above.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm_entropic.so")
+
+# status codes (enum lbm_status)
+LBM_OK, LBM_EINVAL, LBM_EDOMAIN, LBM_EDEVICE, LBM_ENOMEM, LBM_EBUSY = 0, -1, -2, -3, -4, -5
+LBM_D2Q9, LBM_D3Q27 = 9, 27
+LBM_FP64, LBM_FP32_DEV = 0, 1
+LBM_EQ_ENTROPIC = 0
+
+DTYPES = {"fp64": LBM_FP64, "fp32_dev": LBM_FP32_DEV}
+
+
+class lbm_config(ctypes.Structure):
+    _fields_ = [("lattice", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
+                ("tau", ctypes.c_double), ("bulk_correction", ctypes.c_int32),
+                ("equilibrium", ctypes.c_int32), ("rho0", ctypes.c_double)]
+
+
+class lbm_tuning(ctypes.Structure):
+    _fields_ = [("block_x", ctypes.c_int32), ("block_y", ctypes.c_int32),
+                ("plane_pad", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class lbm_diag(ctypes.Structure):
+    _fields_ = [("mass", ctypes.c_double), ("momentum", ctypes.c_double * 3),
+                ("kinetic_energy", ctypes.c_double), ("max_abs_u", ctypes.c_double),
+                ("min_rho", ctypes.c_double), ("steps", ctypes.c_int64),
+                ("domain_error", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {"mass": self.mass, "momentum": list(self.momentum),
+                "kinetic_energy": self.kinetic_energy, "max_abs_u": self.max_abs_u,
+                "min_rho": self.min_rho, "steps": int(self.steps),
+                "domain_error": bool(self.domain_error)}
+
+
+class LBMError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str = ""):
+        self.status = status
+        super().__init__(f"{where}: {lbm_status_string(status)}" + (f" ({message})" if message else ""))
+
+
+class LBMDomainError(LBMError):
+    """A node left rho > 0, |u_alpha| < 1 (outputs were still written)."""
+
+
+_lib = None
+
+# Exported symbols the header declares (checked by the CPU test suite).
+EXPORTS = ("lbm_workspace_bytes", "lbm_workspace_bytes_tuned", "lbm_create", "lbm_create_tuned",
+           "lbm_step", "lbm_moments", "lbm_get_populations", "lbm_destroy", "lbm_status_string",
+           "lbm_last_error", "lbm_version")
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the native library (raises OSError/ImportError when it is not built).
+
+    torch is imported first so that the library binds to the HIP runtime torch
+    already loaded (same soname): one runtime per process, so torch's device
+    pointers and streams are valid handles for the library."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"native library {path} is not built; run __graft_entry__.build()")
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(path)
+    vp, sz, i64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64
+    cfgp, tunp = ctypes.POINTER(lbm_config), ctypes.POINTER(lbm_tuning)
+    sig = {
+        "lbm_workspace_bytes": (sz, [cfgp]),
+        "lbm_workspace_bytes_tuned": (sz, [cfgp, tunp]),
+        "lbm_create": (ctypes.c_int, [cfgp, vp, sz, vp, vp, vp, ctypes.POINTER(vp)]),
+        "lbm_create_tuned": (ctypes.c_int, [cfgp, tunp, vp, sz, vp, vp, vp, ctypes.POINTER(vp)]),
+        "lbm_step": (ctypes.c_int, [vp, i64]),
+        "lbm_moments": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(lbm_diag)]),
+        "lbm_get_populations": (ctypes.c_int, [vp, vp]),
+        "lbm_destroy": (ctypes.c_int, [vp]),
+        "lbm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "lbm_last_error": (ctypes.c_char_p, []),
+        "lbm_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str) -> int:
+    if status == LBM_OK:
+        return status
+    msg = load_library().lbm_last_error().decode()
+    if status == LBM_EDOMAIN:
+        raise LBMDomainError(status, where, msg)
+    raise LBMError(status, where, msg)
+
+
+def make_config(lattice: int, shape, tau: float, dtype="fp32_dev", bulk_correction=False,
+                rho0: float = 1.0) -> lbm_config:
+    """shape = (nx, ny) for D2Q9 or (nx, ny, nz) for D3Q27 (x first)."""
+    nx, ny = int(shape[0]), int(shape[1])
+    nz = int(shape[2]) if len(shape) > 2 else 1
+    return lbm_config(int(lattice), DTYPES.get(dtype, dtype), nx, ny, nz, float(tau),
+                      int(bool(bulk_correction)), LBM_EQ_ENTROPIC, float(rho0))
+
+
+def make_tuning(block_x=0, block_y=0, plane_pad=-1) -> lbm_tuning:
+    return lbm_tuning(int(block_x), int(block_y), int(plane_pad), 0)
+
+
+def lbm_workspace_bytes(cfg: lbm_config, tuning: lbm_tuning | None = None) -> int:
+    lib = load_library()
+    if tuning is None:
+        return int(lib.lbm_workspace_bytes(ctypes.byref(cfg)))
+    return int(lib.lbm_workspace_bytes_tuned(ctypes.byref(cfg), ctypes.byref(tuning)))
+
+
+def lbm_create(cfg: lbm_config, workspace: int, ws_bytes: int, rho: int, u: int, stream: int = 0,
+               tuning: lbm_tuning | None = None) -> ctypes.c_void_p:
+    """Pointers are integers (device addresses / hipStream_t); returns the handle."""
+    lib = load_library()
+    h = ctypes.c_void_p()
+    if tuning is None:
+        st = lib.lbm_create(ctypes.byref(cfg), workspace, ws_bytes, rho, u, stream, ctypes.byref(h))
+    else:
+        st = lib.lbm_create_tuned(ctypes.byref(cfg), ctypes.byref(tuning), workspace, ws_bytes, rho, u,
+                                  stream, ctypes.byref(h))
+    _check(st, "lbm_create")
+    return h
+
+
+def lbm_step(h, nsteps: int) -> None:
+    _check(load_library().lbm_step(h, int(nsteps)), "lbm_step")
+
+
+def lbm_moments(h, rho: int | None, u: int | None, raise_on_domain: bool = True) -> lbm_diag:
+    d = lbm_diag()
+    st = load_library().lbm_moments(h, rho, u, ctypes.byref(d))
+    if st == LBM_EDOMAIN and not raise_on_domain:
+        return d
+    _check(st, "lbm_moments")
+    return d
+
+
+def lbm_get_populations(h, out: int) -> None:
+    _check(load_library().lbm_get_populations(h, out), "lbm_get_populations")
+
+
+def lbm_destroy(h) -> None:
+    _check(load_library().lbm_destroy(h), "lbm_destroy")
+
+
+def lbm_status_string(status: int) -> str:
+    return load_library().lbm_status_string(int(status)).decode()
+
+
+def lbm_version() -> str:
+    return load_library().lbm_version().decode()
+
+
+class Domain:
+    """One periodic domain on the GPU.
+
+    rho: numpy array of the grid's shape ((ny, nx) or (nz, ny, nx), x fastest);
+    u: (D, *rho.shape).  The fields are copied to the device as float64.
+    stream: a torch.cuda.Stream (default: torch's current stream).
+    """
+
+    def __init__(self, rho, u, tau: float, dtype="fp32_dev", bulk_correction=False, rho0: float = 1.0,
+                 stream=None, tuning: lbm_tuning | None = None, device="cuda:0"):
+        import torch
+        load_library()
+        rho = np.asarray(rho, dtype=np.float64)
+        u = np.asarray(u, dtype=np.float64)
+        D = rho.ndim
+        if D not in (2, 3) or u.shape != (D,) + rho.shape:
+            raise ValueError("rho must be 2-D or 3-D and u of shape (D, *rho.shape)")
+        self.shape = rho.shape
+        self.D = D
+        self.lattice = LBM_D2Q9 if D == 2 else LBM_D3Q27
+        self.Q = 9 if D == 2 else 27
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.cfg = make_config(self.lattice, rho.shape[::-1], tau, dtype, bulk_correction, rho0)
+        self.tuning = tuning
+        nbytes = lbm_workspace_bytes(self.cfg, tuning)
+        if nbytes == 0:
+            raise LBMError(LBM_EINVAL, "lbm_workspace_bytes", load_library().lbm_last_error().decode())
+        self.ws_bytes = nbytes
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        with torch.cuda.stream(self.stream):
+            rho_d = torch.from_numpy(np.ascontiguousarray(rho)).to(self.device)
+            u_d = torch.from_numpy(np.ascontiguousarray(u)).to(self.device)
+        self.stream.synchronize()
+        self.handle = lbm_create(self.cfg, self._ws_ptr, nbytes, rho_d.data_ptr(), u_d.data_ptr(),
+                                 self.stream.cuda_stream, tuning)
+        del rho_d, u_d
+
+    @property
+    def n(self) -> int:
+        return int(np.prod(self.shape))
+
+    def step(self, nsteps: int) -> None:
+        lbm_step(self.handle, nsteps)
+
+    def moments(self, fields: bool = True, raise_on_domain: bool = True):
+        """(rho, u, diag) with rho, u as numpy float64 arrays (None if fields=False)."""
+        import torch
+        if not fields:
+            return None, None, lbm_moments(self.handle, None, None, raise_on_domain).as_dict()
+        rho_d = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        u_d = torch.empty((self.D,) + self.shape, dtype=torch.float64, device=self.device)
+        d = lbm_moments(self.handle, rho_d.data_ptr(), u_d.data_ptr(), raise_on_domain)
+        return rho_d.cpu().numpy(), u_d.cpu().numpy(), d.as_dict()
+
+    def moments_device(self, rho_d, u_d, raise_on_domain: bool = True) -> dict:
+        return lbm_moments(self.handle, rho_d.data_ptr(), u_d.data_ptr(), raise_on_domain).as_dict()
+
+    def populations(self):
+        import torch
+        out = torch.empty((self.Q,) + self.shape, dtype=torch.float64, device=self.device)
+        lbm_get_populations(self.handle, out.data_ptr())
+        return out.cpu().numpy()
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None:
+            lbm_destroy(self.handle)
+            self.handle = None
+            self._ws = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

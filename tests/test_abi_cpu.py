@@ -1,0 +1,120 @@
+"""CPU checks of the C-ABI library: it loads, exports every function the
+header declares, and its host-only logic (configuration validation, workspace
+sizing, status strings, argument checks that precede any GPU call) behaves as
+documented.  No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    from paper_2303_08163_amd import lbm as m
+    if not os.path.exists(m.LIB_PATH):
+        from paper_2303_08163_amd import build
+        build.build()
+    m.load_library()
+    return m
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_every_declared_symbol_is_exported(lbm):
+    lib = lbm.load_library()
+    names = declared_functions()
+    assert "lbm_step" in names and "lbm_create" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(lbm.EXPORTS) <= set(names)
+
+
+def test_status_strings(lbm):
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lbm.lbm_status_string(code).startswith("LBM_")
+    assert lbm.lbm_status_string(7) == "unknown status"
+    assert "gfx950" in lbm.lbm_version()
+
+
+def _cfg(lbm, **kw):
+    base = dict(lattice=9, shape=(64, 32), tau=0.6, dtype="fp64", bulk_correction=False, rho0=1.0)
+    base.update(kw)
+    return lbm.make_config(base["lattice"], base["shape"], base["tau"], base["dtype"], base["bulk_correction"],
+                           base["rho0"])
+
+
+def test_workspace_bytes_layout(lbm):
+    # D2Q9 FP64 64x32: two buffers of 9 * 2048 doubles, flag, diag, partials
+    n = 64 * 32
+    buf = 9 * n * 8
+    red = min(1024, (n + 255) // 256)
+    expect = 2 * buf + 256 + 256 + ((red * 7 * 8 + 255) // 256) * 256
+    assert lbm.lbm_workspace_bytes(_cfg(lbm)) == expect
+    # FP32 deviation storage halves the buffers
+    assert lbm.lbm_workspace_bytes(_cfg(lbm, dtype="fp32_dev")) == expect - buf
+    # D3Q27 256^3 FP32: 2 x 27 x 256^3 x 4 bytes plus scratch
+    b3 = lbm.lbm_workspace_bytes(_cfg(lbm, lattice=27, shape=(256, 256, 256), dtype="fp32_dev"))
+    assert 2 * 27 * 256 ** 3 * 4 < b3 < 2 * 27 * 256 ** 3 * 4 + 2 ** 20
+    # padding adds whole 64-element blocks per plane
+    t = lbm.make_tuning(0, 0, 100)
+    assert lbm.lbm_workspace_bytes(_cfg(lbm), t) == expect + 2 * 9 * 128 * 8
+
+
+@pytest.mark.parametrize("bad", [
+    dict(tau=0.5), dict(tau=0.3), dict(tau=float("nan")), dict(tau=float("inf")),
+    dict(lattice=19), dict(dtype=7), dict(shape=(0, 5)), dict(shape=(5, 0)),
+    dict(shape=(4, 4, 2)), dict(lattice=27, shape=(4, 4, 0)), dict(dtype="fp32_dev", rho0=0.0),
+    dict(dtype="fp32_dev", rho0=-1.0), dict(shape=(70000, 70000)), dict(lattice=27, shape=(2, 2, 70000)),
+])
+def test_invalid_configs_are_rejected(lbm, bad):
+    assert lbm.lbm_workspace_bytes(_cfg(lbm, **bad)) == 0
+
+
+@pytest.mark.parametrize("tun", [(48, 4, 0), (64, 8, 0), (3, 64, 0), (64, 5, 0), (64, 4, 1 << 21)])
+def test_invalid_tuning_rejected(lbm, tun):
+    assert lbm.lbm_workspace_bytes(_cfg(lbm), lbm.make_tuning(*tun)) == 0
+
+
+def test_create_argument_checks_precede_gpu_work(lbm):
+    lib = lbm.load_library()
+    cfg = _cfg(lbm)
+    h = ctypes.c_void_p()
+    # NULL workspace / fields / out: rejected on the host
+    assert lib.lbm_create(ctypes.byref(cfg), None, 1 << 30, 8, 8, None, ctypes.byref(h)) == lbm.LBM_EINVAL
+    assert lib.lbm_create(ctypes.byref(cfg), 256, 1 << 30, None, 8, None, ctypes.byref(h)) == lbm.LBM_EINVAL
+    assert lib.lbm_create(ctypes.byref(cfg), 256, 1 << 30, 8, 8, None, None) == lbm.LBM_EINVAL
+    # workspace too small or misaligned
+    assert lib.lbm_create(ctypes.byref(cfg), 256, 16, 8, 8, None, ctypes.byref(h)) == lbm.LBM_EINVAL
+    assert lib.lbm_create(ctypes.byref(cfg), 260, 1 << 30, 8, 8, None, ctypes.byref(h)) == lbm.LBM_EINVAL
+    assert h.value is None
+    # NULL handle
+    assert lib.lbm_step(None, 1) == lbm.LBM_EINVAL
+    assert lib.lbm_moments(None, None, None, None) == lbm.LBM_EINVAL
+    assert lib.lbm_get_populations(None, None) == lbm.LBM_EINVAL
+    assert lib.lbm_destroy(None) == lbm.LBM_OK
+    assert b"NULL" in lib.lbm_last_error()
+
+
+def test_product_package_never_touches_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2303_08163_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle\b", text, flags=re.M), fn
+                assert "lbm_oracle" not in text and "liblbm_oracle" not in text, fn
+    for fn in os.listdir(os.path.join(ROOT, "oracle")):
+        if fn.endswith((".py", ".c", ".h")):
+            text = open(os.path.join(ROOT, "oracle", fn)).read()
+            assert "paper_2303_08163_amd" not in text and "lbm.h" not in text, fn

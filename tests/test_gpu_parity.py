@@ -1,0 +1,264 @@
+"""GPU parity: the HIP library against the FP64 CPU oracle, element by element
+on the same seeded inputs.
+
+Error measure (normwise, stated per result): max_r |gpu - oracle| / max_r |oracle|,
+for rho, and jointly over the velocity vector field (max over components and
+nodes).  Tolerances: 1e-12 for FP64 storage, 1e-5 for FP32 deviation storage.
+The GPU stores post-collision populations and the oracle pre-collision ones;
+rho and u are collision invariants, so the moments compare directly.
+
+Full-size grids (4096^2 D2Q9, 256^3 D3Q27) are checked in the launch
+configuration the benchmark times: at sampled nodes against the oracle's
+light-cone runner after a few steps, and after the full step count through
+properties (FP32 deviation storage against FP64 storage, conservation).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2303_08163_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32_dev": 1e-5}
+
+
+def _lbm():
+    from paper_2303_08163_amd import lbm
+    return lbm
+
+
+def rel_err(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / np.max(np.abs(b)))
+
+
+def run_gpu(rho0, u0, tau, steps, dtype, corr, tuning=None, populations=False):
+    lbm = _lbm()
+    with lbm.Domain(rho0, u0, tau, dtype=dtype, bulk_correction=corr, tuning=tuning) as d:
+        d.step(steps)
+        rho, u, diag = d.moments(raise_on_domain=False)
+        f = d.populations() if populations else None
+    return rho, u, diag, f
+
+
+def report(name, er, eu):
+    print(f"[parity] {name}: rel err rho {er:.3e}  u {eu:.3e}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def c1_oracle():
+    rho0, u0 = workloads.taylor_green_2d(64, u0=0.05)
+    return rho0, u0, {c: oracle.run(rho0, u0, 0.51, 1000, corr=c) for c in ("off", "min")}
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32_dev"])
+@pytest.mark.parametrize("corr", [False, True])
+def test_c1_taylor_green_64_1000_steps(c1_oracle, dtype, corr):
+    rho0, u0, ref = c1_oracle
+    r_ref, u_ref, bad = ref["min" if corr else "off"]
+    assert bad == 0
+    rho, u, diag, _ = run_gpu(rho0, u0, 0.51, 1000, dtype, corr)
+    er, eu = rel_err(rho, r_ref), rel_err(u, u_ref)
+    report(f"D2Q9 64^2 TG tau=0.51 1000 steps {dtype} corr={corr}", er, eu)
+    assert not diag["domain_error"]
+    assert er < TOL[dtype] and eu < TOL[dtype]
+
+
+GRIDS = [(9, (1, 1)), (9, (2, 3)), (9, (17, 31)), (9, (65, 3)), (9, (130, 7)),
+         (27, (1, 1, 1)), (27, (5, 7, 3)), (27, (17, 9, 4)), (27, (67, 5, 3)), (27, (2, 1, 66))]
+
+
+@pytest.mark.parametrize("lattice,shape", GRIDS)
+@pytest.mark.parametrize("dtype", ["fp64", "fp32_dev"])
+@pytest.mark.parametrize("corr", [False, True])
+def test_ragged_grids_random_fields(lattice, shape, dtype, corr):
+    grid = shape[::-1]  # numpy order (.., y, x)
+    for seed, umax, steps in ((11, 0.5, 7), (12, 0.9, 1)):
+        rho0, u0 = workloads.random_field(grid, seed=seed + len(shape), umax=umax)
+        r_ref, u_ref, bad = oracle.run(rho0, u0, 0.53, steps, corr="min" if corr else "off")
+        rho, u, diag, _ = run_gpu(rho0, u0, 0.53, steps, dtype, corr)
+        assert diag["domain_error"] == (bad > 0)
+        er, eu = rel_err(rho, r_ref), rel_err(u, u_ref)
+        assert er < TOL[dtype] and eu < TOL[dtype], (shape, seed, er, eu)
+
+
+@pytest.fixture(scope="module")
+def c3_64_oracle():
+    rho0, u0 = workloads.taylor_green_3d(64, u0=0.05)
+    oracle.set_threads(16)
+    return rho0, u0, oracle.run(rho0, u0, 0.5005, 500)
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32_dev"])
+def test_c3_taylor_green_64cubed_500_steps(c3_64_oracle, dtype):
+    rho0, u0, (r_ref, u_ref, bad) = c3_64_oracle
+    assert bad == 0
+    rho, u, diag, _ = run_gpu(rho0, u0, 0.5005, 500, dtype, False)
+    er, eu = rel_err(rho, r_ref), rel_err(u, u_ref)
+    report(f"D3Q27 64^3 TG tau=0.5005 500 steps {dtype}", er, eu)
+    assert er < TOL[dtype] and eu < TOL[dtype]
+
+
+def _sample_points(shape_xyz, count, seed):
+    rng = np.random.default_rng(seed)
+    pts = np.stack([rng.integers(0, n, count) for n in shape_xyz], axis=1)
+    # always include the corners, where the periodic wrap is taken
+    corner = np.array([[0] * len(shape_xyz), [n - 1 for n in shape_xyz]])
+    return np.concatenate([corner, pts])
+
+
+def _check_samples(rho, u, pts, rs, us, tol, name):
+    idx = tuple(pts[:, a] for a in range(pts.shape[1]))[::-1]
+    g_r = rho[idx]
+    g_u = np.stack([u[a][idx] for a in range(u.shape[0])])
+    er, eu = rel_err(g_r, rs), rel_err(g_u, us)
+    report(name + " (sampled)", er, eu)
+    assert er < tol and eu < tol
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32_dev"])
+@pytest.mark.parametrize("corr", [False, True])
+def test_c2_double_shear_layer_4096_sampled(dtype, corr):
+    n, steps, tau = 4096, 60, 0.5001
+    rho0, u0 = workloads.double_shear_layer(n)
+    rho, u, diag, _ = run_gpu(rho0, u0, tau, steps, dtype, corr)
+    pts = _sample_points((n, n), 10, seed=21)
+    # put samples inside both shear layers too
+    pts = np.concatenate([pts, [[17, n // 4], [n // 2, 3 * n // 4 + 5], [n - 3, n // 4 - 40]]])
+    oracle.set_threads(16)
+    rs, us = oracle.run_sample(rho0, u0, tau, steps, pts, corr="min" if corr else "off")
+    _check_samples(rho, u, pts, rs, us, TOL[dtype], f"D2Q9 4096^2 shear layer {steps} steps {dtype} corr={corr}")
+    assert not diag["domain_error"]
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32_dev"])
+@pytest.mark.parametrize("corr", [False, True])
+def test_c3_taylor_green_256_sampled(dtype, corr):
+    n, steps, tau = 256, 8, 0.5005
+    rho0, u0 = workloads.taylor_green_3d(n, u0=0.05)
+    rho, u, diag, _ = run_gpu(rho0, u0, tau, steps, dtype, corr)
+    pts = _sample_points((n, n, n), 10, seed=22)
+    rs, us = oracle.run_sample(rho0, u0, tau, steps, pts, corr="min" if corr else "off")
+    _check_samples(rho, u, pts, rs, us, TOL[dtype], f"D3Q27 256^3 TG {steps} steps {dtype} corr={corr}")
+
+
+@pytest.mark.parametrize("corr", [False, True])
+def test_c3_256_full_steps_fp32_vs_fp64(corr):
+    """C3 at full size and step count: FP32 deviation storage vs FP64 storage
+    (both on the GPU, the FP64 path being oracle-matched at 64^3 and sampled at
+    256^3), and exact mass conservation of the FP64 run."""
+    n, steps, tau = 256, 500, 0.5005
+    rho0, u0 = workloads.taylor_green_3d(n, u0=0.05)
+    r64, u64, d64, _ = run_gpu(rho0, u0, tau, steps, "fp64", corr)
+    r32, u32, d32, _ = run_gpu(rho0, u0, tau, steps, "fp32_dev", corr)
+    er, eu = rel_err(r32, r64), rel_err(u32, u64)
+    report(f"D3Q27 256^3 TG 500 steps fp32_dev vs fp64 corr={corr}", er, eu)
+    assert er < 1e-5 and eu < 1e-5
+    assert abs(d64["mass"] / rho0.sum() - 1) < 1e-12
+    for a in range(3):
+        assert abs(d64["momentum"][a] - float(np.sum(rho0 * u0[a]))) < 1e-12 * rho0.size
+
+
+@pytest.mark.parametrize("corr", [False, True])
+def test_c2_4096_full_steps_fp32_vs_fp64(corr):
+    n, steps, tau = 4096, 1000, 0.5001
+    rho0, u0 = workloads.double_shear_layer(n)
+    r64, u64, d64, _ = run_gpu(rho0, u0, tau, steps, "fp64", corr)
+    r32, u32, _, _ = run_gpu(rho0, u0, tau, steps, "fp32_dev", corr)
+    er, eu = rel_err(r32, r64), rel_err(u32, u64)
+    eux, euy = rel_err(u32[0], u64[0]), rel_err(u32[1], u64[1])
+    report(f"D2Q9 4096^2 shear layer 1000 steps fp32_dev vs fp64 corr={corr} (u_x {eux:.2e}, u_y {euy:.2e})", er, eu)
+    assert er < 1e-5 and eu < 1e-5
+    assert abs(d64["mass"] / rho0.sum() - 1) < 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32_dev"])
+def test_translation_equivariance_bitwise(dtype):
+    rho0, u0 = workloads.random_field((9, 12, 20), seed=31, umax=0.3)
+    sh = (2, 5, 7)
+    _, _, _, f1 = run_gpu(rho0, u0, 0.52, 9, dtype, True, populations=True)
+    _, _, _, f2 = run_gpu(np.roll(rho0, sh, axis=(0, 1, 2)), np.roll(u0, sh, axis=(1, 2, 3)), 0.52, 9,
+                          dtype, True, populations=True)
+    assert np.array_equal(np.roll(f1, sh, axis=(1, 2, 3)), f2)
+
+
+@pytest.mark.parametrize("lattice", [9, 27])
+def test_tuning_invariance_bitwise(lattice):
+    lbm = _lbm()
+    grid = (70, 66) if lattice == 9 else (6, 33, 70)
+    rho0, u0 = workloads.random_field(grid, seed=41, umax=0.3)
+    base = None
+    for bx, by, pad in ((0, 0, -1), (64, 4, 0), (128, 2, 64), (256, 1, 4096), (32, 8, 128), (64, 1, 0)):
+        rho, u, _, f = run_gpu(rho0, u0, 0.55, 5, "fp32_dev", True, tuning=lbm.make_tuning(bx, by, pad),
+                               populations=True)
+        if base is None:
+            base = (rho, u, f)
+        else:
+            assert np.array_equal(base[0], rho) and np.array_equal(base[1], u) and np.array_equal(base[2], f)
+
+
+@pytest.mark.parametrize("lattice", [9, 27])
+def test_populations_match_oracle(lattice):
+    """Post-collision populations after n steps equal the oracle's pre-collision
+    populations after n + 1 steps, moved back by one link: f*_i(r, n) = f_i(r + c_i, n + 1)."""
+    grid = (11, 13) if lattice == 9 else (5, 6, 7)
+    D = len(grid)
+    rho0, u0 = workloads.random_field(grid, seed=51, umax=0.4)
+    _, _, _, f_gpu = run_gpu(rho0, u0, 0.6, 4, "fp64", True, populations=True)
+    _, _, _, f_or = oracle.run(rho0, u0, 0.6, 5, corr="min", return_f=True)
+    c, _ = oracle.lattice(D)
+    for k, ck in enumerate(c):
+        i = int(ck[0] + 1) + 3 * int(ck[1] + 1) + (9 * int(ck[2] + 1) if D == 3 else 0)
+        back = np.roll(f_or[k], shift=tuple(-int(v) for v in ck), axis=tuple(range(D))[::-1])
+        assert np.max(np.abs(f_gpu[i] - back)) < 1e-13
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32_dev"])
+def test_diagnostics_match_oracle(dtype):
+    rho0, u0 = workloads.taylor_green_3d(24, u0=0.1)
+    r_ref, u_ref, _ = oracle.run(rho0, u0, 0.52, 30, corr="min")
+    ref = oracle.diagnostics(r_ref, u_ref)
+    _, _, diag, _ = run_gpu(rho0, u0, 0.52, 30, dtype, True)
+    tol = TOL[dtype]
+    assert diag["mass"] == pytest.approx(ref["mass"], rel=tol)
+    for a in range(3):
+        assert abs(diag["momentum"][a] - ref["momentum"][a]) < tol * ref["mass"] * 0.1
+    assert diag["kinetic_energy"] == pytest.approx(ref["kinetic_energy"], rel=10 * tol)
+    assert diag["max_abs_u"] == pytest.approx(ref["max_abs_u"], rel=tol)
+    assert diag["min_rho"] == pytest.approx(ref["min_rho"], rel=tol)
+    assert diag["steps"] == 30
+
+
+def test_domain_errors():
+    lbm = _lbm()
+    rho0, u0 = workloads.random_field((8, 8), seed=61, umax=0.3)
+    u0[0, 3, 4] = 1.0
+    with pytest.raises(lbm.LBMDomainError):
+        lbm.Domain(rho0, u0, 0.6)
+    # a rough field near |u| = 1 leaves the domain: flag iff the oracle counts exits
+    for seed in range(3):
+        rho0, u0 = workloads.random_field((16, 16), seed=70 + seed, umax=0.99, rho_lo=0.3, rho_hi=2.0)
+        _, _, bad = oracle.run(rho0, u0, 0.5001, 6)
+        with lbm.Domain(rho0, u0, 0.5001, dtype="fp64") as d:
+            d.step(6)
+            if bad:
+                with pytest.raises(lbm.LBMDomainError):
+                    d.moments()
+            else:
+                d.moments()
+
+
+def test_invalid_arguments_raise():
+    lbm = _lbm()
+    rho0, u0 = workloads.random_field((8, 8), seed=62, umax=0.3)
+    with pytest.raises(lbm.LBMError):
+        lbm.Domain(rho0, u0, 0.5)
+    with pytest.raises(lbm.LBMError):
+        lbm.Domain(rho0, u0, 0.6, dtype="fp32_dev", rho0=0.0)
+    with lbm.Domain(rho0, u0, 0.6) as d:
+        with pytest.raises(lbm.LBMError):
+            d.step(-1)
+        d.step(0)
+        assert d.moments(fields=False)[2]["steps"] == 0
