@@ -59,14 +59,21 @@ enum lbm_status {
 /* Lattices: the value is Q. */
 enum { LBM_D2Q9 = 9, LBM_D3Q27 = 27 };
 
-/* Population storage.
- *   LBM_FP64:     populations stored and computed in IEEE double.
- *   LBM_FP32_DEV: populations stored in IEEE single as deviations
- *                 f_i - w_i rho0 from the rest equilibrium at density rho0;
- *                 every step widens them to double, computes the moments, the
- *                 equilibrium and the relaxation in double, and rounds the
- *                 result to nearest-even single on store. */
-enum { LBM_FP64 = 0, LBM_FP32_DEV = 1 };
+/* Population storage and arithmetic.
+ *   LBM_FP64:           populations stored and computed in IEEE double.
+ *   LBM_FP32_DEV:       populations stored in IEEE single as deviations
+ *                       f_i - w_i rho0 from the rest equilibrium at density rho0;
+ *                       every step widens them to double, computes moments,
+ *                       equilibrium and relaxation in double, and rounds the
+ *                       result to nearest-even single on store.
+ *   LBM_FP32_DEV_MIXED: the same storage; moment sums, square roots and the
+ *                       per-axis equilibrium factors in double, the
+ *                       per-population equilibrium and relaxation in single on
+ *                       deviation-sized quantities (precision ablation).
+ *   LBM_FP32_DEV_F32:   the same storage with every operation in single
+ *                       (precision ablation).
+ * The two ablation modes are not held to the FP32 error budget. */
+enum { LBM_FP64 = 0, LBM_FP32_DEV = 1, LBM_FP32_DEV_MIXED = 2, LBM_FP32_DEV_F32 = 3 };
 
 /* Equilibrium: the entropic one (eq. Entropic_isothermal_EDF). */
 enum { LBM_EQ_ENTROPIC = 0 };
@@ -74,23 +81,31 @@ enum { LBM_EQ_ENTROPIC = 0 };
 /* Problem statement of one periodic domain (plain data, caller-owned). */
 typedef struct lbm_config {
     int32_t lattice;         /* LBM_D2Q9 or LBM_D3Q27 */
-    int32_t dtype;           /* LBM_FP64 or LBM_FP32_DEV */
+    int32_t dtype;           /* LBM_FP64, LBM_FP32_DEV, LBM_FP32_DEV_MIXED or LBM_FP32_DEV_F32 */
     int64_t nx, ny, nz;      /* grid extent; nz must be 1 for D2Q9; each >= 1 */
     double tau;              /* relaxation time, tau > 1/2 and finite; 2 beta = 1/tau */
     int32_t bulk_correction; /* 0 = off, 1 = eq. (redefined_relaxation rate) */
     int32_t equilibrium;     /* LBM_EQ_ENTROPIC */
-    double rho0;             /* reference density of LBM_FP32_DEV storage (> 0); ignored for FP64 */
+    double rho0;             /* reference density of the FP32 deviation storage (> 0); ignored for FP64 */
 } lbm_config;
 
 /* Launch tuning (optional).  Zero fields take the library default.  Results do
  * not depend on the tuning: every node's arithmetic is the same. */
 typedef struct lbm_tuning {
-    int32_t block_x;   /* threads along x per workgroup (multiple of 64 or a power of two <= 64) */
-    int32_t block_y;   /* rows along y per workgroup; block_x * block_y a multiple of 64, <= 256 */
-    int32_t plane_pad; /* extra elements between population planes (>= 0, padding against
-                          HBM channel aliasing; < 0 selects the default) */
-    int32_t reserved;  /* must be 0 */
+    int32_t block_x;          /* threads along x per workgroup: a multiple of 64, or (one node
+                                 per thread only) a power of two below 64 */
+    int32_t block_y;          /* rows along y per workgroup; block_x * block_y a multiple of 64,
+                                 <= 256 */
+    int32_t plane_pad;        /* extra elements between population planes (>= 0, padding against
+                                 HBM channel aliasing; < 0 selects the default) */
+    int32_t nodes_per_thread; /* consecutive x nodes per thread: 1, 2 or 4 (4 for FP32 storage
+                                 only); > 1 needs nx % (block_x * nodes_per_thread) == 0 */
+    int32_t flags;            /* LBM_TUNE_* bits for the vector kernels; < 0 selects the default */
+    int32_t reserved;         /* must be 0 */
 } lbm_tuning;
+
+/* lbm_tuning.flags bits. */
+enum { LBM_TUNE_NT_STORE = 1, LBM_TUNE_NT_LOAD = 2 };
 
 /* Whole-domain diagnostics, all from the current populations. */
 typedef struct lbm_diag {
@@ -125,10 +140,9 @@ size_t lbm_workspace_bytes_tuned(const lbm_config *cfg, const lbm_tuning *tuning
  *   stream     hipStream_t to enqueue on (NULL = the null stream).
  *   out        receives the handle; untouched on error.
  * Synchronises the stream.  Errors: LBM_EINVAL (NULL pointer, tau <= 1/2 or
- * not finite, an extent < 1, nz != 1 for D2Q9, more than 2^31 - 1 elements
- * per population plane, nz or ny blocks beyond the launch limits, bad
- * lattice/dtype/equilibrium, rho0 <= 0 for FP32_DEV, workspace too small or
- * misaligned); LBM_EDOMAIN (an initial node has rho <= 0 or |u_alpha| >= 1;
+ * not finite, an extent < 1, nz != 1 for D2Q9, more than 2^31 - 4096 nodes,
+ * bad lattice/dtype/equilibrium/tuning, rho0 <= 0 for FP32_DEV, workspace too
+ * small or misaligned); LBM_EDOMAIN (an initial node has rho <= 0 or |u_alpha| >= 1;
  * no handle is created); LBM_EDEVICE. */
 int lbm_create(const lbm_config *cfg, void *workspace, size_t ws_bytes, const double *rho,
                const double *u, void *stream, lbm_handle **out);

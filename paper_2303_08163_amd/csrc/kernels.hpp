@@ -12,10 +12,12 @@
 // reads f*_i(r - c_i, t) = f_i(r, t + 1), collides, and writes f*_i(r, t + 1)
 // back at r.  Every value is read once and written once per step: the
 // algorithmic HBM traffic is 2 Q sizeof(storage) bytes per node update.
-// Workgroups cover (block_x * block_y) nodes of one z plane with x fastest, so
-// a wavefront reads 27 (or 9) rows of 64 consecutive elements shifted by at
-// most one element and writes 27 (or 9) aligned rows; the one-element shifts
-// fall on cache lines that the neighbouring wave of the same workgroup reads.
+// Workgroups cover (block_x * block_y) nodes of one z plane with x fastest
+// (by default a whole row of up to 256 nodes), so a wavefront reads 27 (or 9)
+// rows of 64 consecutive elements shifted by at most one element and writes
+// 27 (or 9) aligned rows; the one-element shifts fall on cache lines that the
+// neighbouring wave of the same workgroup reads, and the tiles of a row are
+// kept on one XCD (xcd_tile), so the shifts cost no extra HBM traffic.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,32 +27,35 @@
 
 namespace lbm {
 
-template <bool DEV>
-using store_t = typename std::conditional<DEV, float, double>::type;
-
 struct StepArgs {
     const void *src;
     void *dst;
     int nx, ny, nz;
+    int tiles_x, tiles_y;  // workgroup tiles per row / per plane
     int64_t stride;
     Relax relax;
     int *flag;
 };
 
-// One LBGK step over the whole domain (grid: x blocks, y blocks, z planes).
-template <int DIM, bool DEV, bool CORR>
-__global__ __launch_bounds__(256) void k_stream_collide(StepArgs a) {
-    using T = store_t<DEV>;
-    constexpr int Q = Lattice<DIM>::Q;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= a.nx || y >= a.ny)
-        return;
-    const T *__restrict__ src = static_cast<const T *>(a.src);
-    T *__restrict__ dst = static_cast<T *>(a.dst);
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup w runs on
+// XCD w mod 8).  Give each XCD one contiguous range of tiles, walked in order,
+// so that tiles adjacent in x (which share the cache lines at their boundary
+// through the one-element shifted loads) run on the same XCD and its L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int w, int count) {
+    const int per = count / kXcds, rem = count % kXcds;
+    const int xcd = w % kXcds, k = w / kXcds;
+    return xcd * per + (xcd < rem ? xcd : rem) + k;
+}
 
+// One node's pull-stream, collision and store.  src/dst are population
+// buffers of one domain; (x, y, z) must lie inside the grid.
+template <int DIM, int DT, bool CORR>
+__device__ __forceinline__ void step_node(const store_t<DT> *__restrict__ src, store_t<DT> *__restrict__ dst,
+                                          int nx, int ny, int nz, int64_t stride, const Relax &relax,
+                                          int *flag, int x, int y, int z) {
+    using T = store_t<DT>;
+    constexpr int Q = Lattice<DIM>::Q;
     // source coordinate r - c for c = -1, 0, +1 on the periodic grid
     const int xs[3] = {x + 1 == nx ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};
     const int ys[3] = {y + 1 == ny ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
@@ -59,28 +64,177 @@ __global__ __launch_bounds__(256) void k_stream_collide(StepArgs a) {
         zs[0] = z + 1 == nz ? 0 : z + 1;
         zs[2] = z == 0 ? nz - 1 : z - 1;
     }
-
-    double f[Q];
+    T f[Q];
 #pragma unroll
     for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
 #pragma unroll
         for (int cy = 0; cy < 3; ++cy) {
-            const uint32_t row = (uint32_t)((DIM == 3 ? zs[cz] : z) * ny + ys[cy]) * (uint32_t)nx;
+            const uint32_t row = (uint32_t)(zs[cz] * ny + ys[cy]) * (uint32_t)nx;
 #pragma unroll
             for (int cx = 0; cx < 3; ++cx) {
                 const int i = cx + 3 * cy + 9 * cz;
-                f[i] = (double)src[(int64_t)i * a.stride + (row + (uint32_t)xs[cx])];
+                const T *__restrict__ plane = src + (int64_t)i * stride;  // wave-uniform base
+                f[i] = plane[row + (uint32_t)xs[cx]];
             }
         }
 
-    const bool bad = collide<DIM, DEV, CORR>(f, a.relax);
+    const bool bad = collide_dt<DIM, DT, CORR>(f, relax);
     if (bad)
-        __hip_atomic_fetch_or(a.flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_or(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
     const uint32_t self = (uint32_t)(z * ny + y) * (uint32_t)nx + (uint32_t)x;
 #pragma unroll
-    for (int i = 0; i < Q; ++i)
-        dst[(int64_t)i * a.stride + self] = (T)f[i];
+    for (int i = 0; i < Q; ++i) {
+        T *__restrict__ plane = dst + (int64_t)i * stride;
+        plane[self] = f[i];
+    }
+}
+
+// One LBGK step over the whole domain.  1-D grid of tiles_x * tiles_y * nz
+// workgroups of blockDim.x * blockDim.y threads, one node per thread.
+template <int DIM, int DT, bool CORR>
+__global__ __launch_bounds__(256) void k_stream_collide(StepArgs a) {
+    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int tx = t % a.tiles_x;
+    const int ty = (t / a.tiles_x) % a.tiles_y;
+    const int z = t / (a.tiles_x * a.tiles_y);
+    const int x = tx * (int)blockDim.x + (int)threadIdx.x;
+    const int y = ty * (int)blockDim.y + (int)threadIdx.y;
+    if (x >= a.nx || y >= a.ny)
+        return;
+    step_node<DIM, DT, CORR>(static_cast<const store_t<DT> *>(a.src), static_cast<store_t<DT> *>(a.dst),
+                              a.nx, a.ny, a.nz, a.stride, a.relax, a.flag, x, y, z);
+}
+
+// ---------------------------------------------------------------------------
+// Vectorised step: each thread owns NPT consecutive nodes of a row and moves
+// every population plane with one aligned NPT-wide load and store (16 bytes
+// for float x 4 or double x 2).  The x-shifted planes need one element beyond
+// the thread's run on one side; it comes from the neighbouring lane of the
+// same wavefront by a lane rotation, and at the two ends of the wavefront's
+// run from a single-lane load (or, when one wavefront spans the whole row,
+// from the rotation itself, which then is the periodic wrap).  Needs
+// nx % (64 * NPT) == 0 and blockDim.x a multiple of 64 dividing nx / NPT.
+template <typename T, int NPT>
+struct VecT;
+template <>
+struct VecT<float, 4> {
+    typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct VecT<float, 2> {
+    typedef float type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct VecT<double, 2> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+
+// Kernel flags (results never depend on them).
+constexpr int kNtStore = 1;  // non-temporal stores
+constexpr int kNtLoad = 2;   // non-temporal loads
+
+template <typename V, int FLAGS>
+__device__ __forceinline__ V load_vec(const V *p) {
+    if (FLAGS & kNtLoad)
+        return __builtin_nontemporal_load(p);
+    return *p;
+}
+template <typename V, int FLAGS>
+__device__ __forceinline__ void store_vec(V v, V *p) {
+    if (FLAGS & kNtStore)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
+template <int DIM, int DT, bool CORR, int NPT, bool ROWWAVE, int FLAGS>
+__global__ __launch_bounds__(256) void k_stream_collide_vec(StepArgs a) {
+    using T = store_t<DT>;
+    using V = typename VecT<T, NPT>::type;
+    constexpr int Q = Lattice<DIM>::Q;
+    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int tx = t % a.tiles_x;
+    const int ty = (t / a.tiles_x) % a.tiles_y;
+    const int z = t / (a.tiles_x * a.tiles_y);
+    const int y = ty * (int)blockDim.y + (int)threadIdx.y;
+    if (y >= a.ny)  // uniform per row of threads
+        return;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int lane = (int)threadIdx.x & 63;
+    const int x0 = (tx * (int)blockDim.x + (int)threadIdx.x) * NPT;  // first node of this thread
+    const T *__restrict__ src = static_cast<const T *>(a.src);
+    T *__restrict__ dst = static_cast<T *>(a.dst);
+
+    const int ys[3] = {y + 1 == ny ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
+    int zs[3] = {z, z, z};
+    if (DIM == 3) {
+        zs[0] = z + 1 == nz ? 0 : z + 1;
+        zs[2] = z == 0 ? nz - 1 : z - 1;
+    }
+    // neighbours of the run at the wavefront's ends (periodic in x)
+    const int x_left = x0 == 0 ? nx - 1 : x0 - 1;
+    const int x_right = x0 + NPT == nx ? 0 : x0 + NPT;
+
+    T g[Q][NPT];  // g[i][k]: value population i pulls into node x0 + k
+#pragma unroll
+    for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
+#pragma unroll
+        for (int cy = 0; cy < 3; ++cy) {
+            const uint32_t row = (uint32_t)(zs[cz] * ny + ys[cy]) * (uint32_t)nx;
+#pragma unroll
+            for (int cx = 0; cx < 3; ++cx) {
+                const int i = cx + 3 * cy + 9 * cz;
+                const T *__restrict__ plane = src + (int64_t)i * a.stride;
+                const V v = load_vec<V, FLAGS>(reinterpret_cast<const V *>(plane + row + (uint32_t)x0));
+                if (cx == 1) {  // c_x = 0: aligned
+#pragma unroll
+                    for (int k = 0; k < NPT; ++k)
+                        g[i][k] = v[k];
+                } else if (cx == 2) {  // c_x = +1 pulls from x - 1
+                    T left = __shfl(v[NPT - 1], (lane + 63) & 63, 64);
+                    if (!ROWWAVE && lane == 0)
+                        left = plane[row + (uint32_t)x_left];
+                    g[i][0] = left;
+#pragma unroll
+                    for (int k = 1; k < NPT; ++k)
+                        g[i][k] = v[k - 1];
+                } else {  // c_x = -1 pulls from x + 1
+                    T right = __shfl(v[0], (lane + 1) & 63, 64);
+                    if (!ROWWAVE && lane == 63)
+                        right = plane[row + (uint32_t)x_right];
+#pragma unroll
+                    for (int k = 0; k < NPT - 1; ++k)
+                        g[i][k] = v[k + 1];
+                    g[i][NPT - 1] = right;
+                }
+            }
+        }
+
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        T f[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            f[i] = g[i][k];
+        bad |= collide_dt<DIM, DT, CORR>(f, a.relax);
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            g[i][k] = f[i];
+    }
+    if (bad)
+        __hip_atomic_fetch_or(a.flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
+    const uint32_t self = (uint32_t)(z * ny + y) * (uint32_t)nx + (uint32_t)x0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        V v;
+#pragma unroll
+        for (int k = 0; k < NPT; ++k)
+            v[k] = g[i][k];
+        store_vec<V, FLAGS>(v, reinterpret_cast<V *>(dst + (int64_t)i * a.stride + self));
+    }
 }
 
 // Zero `count` 32-bit words (a kernel rather than a memset, so that the call

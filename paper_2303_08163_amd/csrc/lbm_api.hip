@@ -42,10 +42,10 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
     }
     if (cfg->dtype == LBM_FP64)
         L.elem = 8;
-    else if (cfg->dtype == LBM_FP32_DEV)
+    else if (cfg->dtype == LBM_FP32_DEV || cfg->dtype == LBM_FP32_DEV_MIXED || cfg->dtype == LBM_FP32_DEV_F32)
         L.elem = 4;
     else {
-        set_error("dtype must be LBM_FP64 or LBM_FP32_DEV");
+        set_error("dtype must be LBM_FP64, LBM_FP32_DEV, LBM_FP32_DEV_MIXED or LBM_FP32_DEV_F32");
         return LBM_EINVAL;
     }
     if (cfg->equilibrium != LBM_EQ_ENTROPIC) {
@@ -60,7 +60,7 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
         set_error("bulk_correction must be 0 or 1");
         return LBM_EINVAL;
     }
-    if (cfg->dtype == LBM_FP32_DEV && (!(cfg->rho0 > 0.0) || !std::isfinite(cfg->rho0))) {
+    if (L.elem == 4 && (!(cfg->rho0 > 0.0) || !std::isfinite(cfg->rho0))) {
         set_error("rho0 must be finite and > 0 for FP32_DEV storage");
         return LBM_EINVAL;
     }
@@ -72,8 +72,8 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
         set_error("nz must be 1 for D2Q9");
         return LBM_EINVAL;
     }
-    if (cfg->nx > INT32_MAX || cfg->ny > INT32_MAX || cfg->nz > 65535) {
-        set_error("grid extent beyond launch limits (nz <= 65535)");
+    if (cfg->nx > INT32_MAX || cfg->ny > INT32_MAX || cfg->nz > INT32_MAX) {
+        set_error("grid extent beyond 2^31 - 1");
         return LBM_EINVAL;
     }
     L.n = cfg->nx * cfg->ny * cfg->nz;
@@ -82,7 +82,7 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
         return LBM_EINVAL;
     }
     // tuning
-    int bx = 0, by = 0, pad = -1;
+    int bx = 0, by = 0, pad = -1, npt = 0, flags = -1;
     if (tun) {
         if (tun->reserved != 0) {
             set_error("lbm_tuning.reserved must be 0");
@@ -91,11 +91,41 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
         bx = tun->block_x;
         by = tun->block_y;
         pad = tun->plane_pad;
+        npt = tun->nodes_per_thread;
+        flags = tun->flags;
+    }
+    const bool fp32 = L.elem == 4;
+    if (npt == 0) {
+        // default: 16-byte vectors (4 floats or 2 doubles per thread) when rows tile evenly
+        const int v = fp32 ? 4 : 2;
+        npt = (cfg->nx % (64 * v) == 0) ? v : 1;
+    }
+    if (npt != 1 && npt != 2 && npt != 4) {
+        set_error("nodes_per_thread must be 1, 2 or 4");
+        return LBM_EINVAL;
+    }
+    if (npt == 4 && !fp32) {
+        set_error("nodes_per_thread = 4 needs FP32 storage");
+        return LBM_EINVAL;
+    }
+    if (flags < 0)
+        flags = npt > 1 ? LBM_TUNE_NT_STORE : 0;
+    if (flags > (LBM_TUNE_NT_STORE | LBM_TUNE_NT_LOAD) || (npt == 1 && flags != 0) ||
+        flags == LBM_TUNE_NT_LOAD) {
+        set_error("flags: NT_STORE, NT_STORE | NT_LOAD or 0, and only with nodes_per_thread > 1");
+        return LBM_EINVAL;
     }
     if (bx == 0) {
-        bx = 64;
-        while (bx > 1 && bx / 2 >= cfg->nx)
-            bx /= 2;
+        if (npt > 1) {
+            bx = 64;
+        } else if (cfg->nx >= 64) {
+            // a whole row per workgroup when it fits, else 256-wide tiles
+            bx = (int)std::min<int64_t>(256, round_up(cfg->nx, 64));
+        } else {
+            bx = 64;
+            while (bx > 1 && bx / 2 >= cfg->nx)
+                bx /= 2;
+        }
     }
     if (by == 0)
         by = 256 / bx;
@@ -105,12 +135,24 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
                   "of 64 or a power of two <= 64");
         return LBM_EINVAL;
     }
-    if ((cfg->ny + by - 1) / by > 65535) {
-        set_error("ny / block_y exceeds the launch limit of 65535 workgroups");
+    if (npt > 1 && (bx % 64 != 0 || cfg->nx % ((int64_t)bx * npt) != 0)) {
+        set_error("nodes_per_thread > 1 needs block_x a multiple of 64 and nx % (block_x * "
+                  "nodes_per_thread) == 0");
         return LBM_EINVAL;
+    }
+    {
+        const int64_t tiles = ((cfg->nx + (int64_t)bx * npt - 1) / ((int64_t)bx * npt)) *
+                              ((cfg->ny + by - 1) / by) * cfg->nz;
+        if (tiles > (int64_t)INT32_MAX) {
+            set_error("more than 2^31 - 1 workgroup tiles");
+            return LBM_EINVAL;
+        }
     }
     L.block_x = bx;
     L.block_y = by;
+    L.npt = npt;
+    L.flags = flags;
+    L.rowwave = npt > 1 && cfg->nx == (int64_t)64 * npt;
     if (pad < 0)
         pad = 0;
     if (pad > (1 << 20)) {
@@ -136,20 +178,51 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
     return LBM_OK;
 }
 
-// Kernel tables indexed by [dev][corr].
+// Kernel selection.
 using StepFn = void (*)(StepArgs);
+template <int DIM, int DT, bool CORR, int NPT, bool RW>
+static StepFn vec_kernel(int flags) {
+    switch (flags) {
+    case LBM_TUNE_NT_STORE:
+        return k_stream_collide_vec<DIM, DT, CORR, NPT, RW, kNtStore>;
+    case LBM_TUNE_NT_STORE | LBM_TUNE_NT_LOAD:
+        return k_stream_collide_vec<DIM, DT, CORR, NPT, RW, kNtStore | kNtLoad>;
+    default:
+        return k_stream_collide_vec<DIM, DT, CORR, NPT, RW, 0>;
+    }
+}
+template <int DIM, int DT, bool CORR>
+static StepFn step_kernel_for(const Layout &L) {
+    if (L.npt == 1)
+        return k_stream_collide<DIM, DT, CORR>;
+    if constexpr (DT != kF64) {
+        if (L.npt == 4)
+            return L.rowwave ? vec_kernel<DIM, DT, CORR, 4, true>(L.flags) : vec_kernel<DIM, DT, CORR, 4, false>(L.flags);
+    }
+    return L.rowwave ? vec_kernel<DIM, DT, CORR, 2, true>(L.flags) : vec_kernel<DIM, DT, CORR, 2, false>(L.flags);
+}
+template <int DIM, int DT>
+static StepFn step_kernel_dt(const Layout &L, bool corr) {
+    return corr ? step_kernel_for<DIM, DT, true>(L) : step_kernel_for<DIM, DT, false>(L);
+}
 template <int DIM>
-static StepFn step_kernel(bool dev, bool corr) {
-    if (dev)
-        return corr ? k_stream_collide<DIM, true, true> : k_stream_collide<DIM, true, false>;
-    return corr ? k_stream_collide<DIM, false, true> : k_stream_collide<DIM, false, false>;
+static StepFn step_kernel(const Layout &L, int dtype, bool corr) {
+    switch (dtype) {
+    case kDevMixed:
+        return step_kernel_dt<DIM, kDevMixed>(L, corr);
+    case kDevF64:
+        return step_kernel_dt<DIM, kDevF64>(L, corr);
+    case kDevF32:
+        return step_kernel_dt<DIM, kDevF32>(L, corr);
+    default:
+        return step_kernel_dt<DIM, kF64>(L, corr);
+    }
 }
 
-int launch_step(const Layout &L, const StepArgs &args, bool dev, bool corr, hipStream_t s, int nz) {
+int launch_step(const Layout &L, const StepArgs &args, int dtype, bool corr, hipStream_t s, int nz) {
     dim3 block(L.block_x, L.block_y, 1);
-    dim3 grid((unsigned)((args.nx + L.block_x - 1) / L.block_x),
-              (unsigned)((args.ny + L.block_y - 1) / L.block_y), (unsigned)nz);
-    StepFn fn = L.dim == 2 ? step_kernel<2>(dev, corr) : step_kernel<3>(dev, corr);
+    dim3 grid((unsigned)(args.tiles_x * args.tiles_y * nz));
+    StepFn fn = L.dim == 2 ? step_kernel<2>(L, dtype, corr) : step_kernel<3>(L, dtype, corr);
     hipLaunchKernelGGL(fn, grid, block, 0, s, args);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
@@ -222,7 +295,7 @@ int lbm_create_tuned(const lbm_config *cfg, const lbm_tuning *tuning, void *work
     h->steps = 0;
     h->relax.omega = 1.0 / cfg->tau;
     h->relax.two_tau_m1 = 2.0 * cfg->tau - 1.0;
-    h->relax.rho0 = cfg->dtype == LBM_FP32_DEV ? cfg->rho0 : 0.0;
+    h->relax.rho0 = cfg->dtype != LBM_FP64 ? cfg->rho0 : 0.0;
 
     hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(64), 0, h->stream, h->flag, 64);
     hipError_t e = hipGetLastError();
@@ -231,7 +304,7 @@ int lbm_create_tuned(const lbm_config *cfg, const lbm_tuning *tuning, void *work
         return hip_fail(e, "clearing the domain flag");
     }
     InitArgs ia{h->buf[0], rho, u, L.n, L.stride, h->relax.rho0, h->flag};
-    const bool dev = cfg->dtype == LBM_FP32_DEV;
+    const bool dev = cfg->dtype != LBM_FP64;
     dim3 grid((unsigned)((L.n + 255) / 256)), block(256);
     void (*init_fn)(InitArgs) = L.dim == 2 ? (dev ? k_init<2, true> : k_init<2, false>)
                                            : (dev ? k_init<3, true> : k_init<3, false>);
@@ -268,12 +341,19 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
         set_error("NULL handle or negative step count");
         return LBM_EINVAL;
     }
-    const bool dev = h->cfg.dtype == LBM_FP32_DEV;
     const bool corr = h->cfg.bulk_correction != 0;
     for (int64_t s = 0; s < nsteps; ++s) {
-        StepArgs a{h->buf[h->cur], h->buf[h->cur ^ 1], (int)h->cfg.nx, (int)h->cfg.ny, (int)h->cfg.nz,
-                   h->L.stride, h->relax, h->flag};
-        int rc = launch_step(h->L, a, dev, corr, h->stream, (int)h->cfg.nz);
+        StepArgs a{h->buf[h->cur],
+                   h->buf[h->cur ^ 1],
+                   (int)h->cfg.nx,
+                   (int)h->cfg.ny,
+                   (int)h->cfg.nz,
+                   (int)((h->cfg.nx + (int64_t)h->L.block_x * h->L.npt - 1) / ((int64_t)h->L.block_x * h->L.npt)),
+                   (int)((h->cfg.ny + h->L.block_y - 1) / h->L.block_y),
+                   h->L.stride,
+                   h->relax,
+                   h->flag};
+        int rc = launch_step(h->L, a, h->cfg.dtype, corr, h->stream, (int)h->cfg.nz);
         if (rc != LBM_OK)
             return rc;
         h->cur ^= 1;
@@ -288,7 +368,7 @@ int lbm_moments(lbm_handle *h, double *rho, double *u, lbm_diag *diag) {
         return LBM_EINVAL;
     }
     const Layout &L = h->L;
-    const bool dev = h->cfg.dtype == LBM_FP32_DEV;
+    const bool dev = h->cfg.dtype != LBM_FP64;
     MomentArgs ma{h->buf[h->cur], rho, u, L.n, L.stride, h->relax.rho0, h->partials};
     dim3 grid((unsigned)L.red_blocks), block(kReduceThreads);
     void (*mom_fn)(MomentArgs) = L.dim == 2 ? (dev ? k_moments<2, true> : k_moments<2, false>)
@@ -333,7 +413,7 @@ int lbm_get_populations(lbm_handle *h, double *out) {
         return LBM_EINVAL;
     }
     const Layout &L = h->L;
-    const bool dev = h->cfg.dtype == LBM_FP32_DEV;
+    const bool dev = h->cfg.dtype != LBM_FP64;
     ExportArgs ea{h->buf[h->cur], out, L.n, L.stride, h->relax.rho0};
     dim3 grid((unsigned)((L.n + 255) / 256)), block(256);
     void (*exp_fn)(ExportArgs) = L.dim == 2 ? (dev ? k_export<2, true> : k_export<2, false>)

@@ -18,6 +18,9 @@ struct Layout {
     int64_t n;         // nodes
     int64_t stride;    // elements between population planes
     int block_x, block_y;
+    int npt;           // nodes per thread along x
+    int flags;         // LBM_TUNE_* bits
+    bool rowwave;      // one wavefront spans a whole row (vector kernels)
     int red_blocks;    // workgroups of the moments reduction
     size_t buf_bytes;  // one population buffer
     size_t off_buf[2], off_flag, off_diag, off_partials, ws_bytes;
@@ -26,6 +29,6 @@ struct Layout {
 void set_error(const char *msg);
 int hip_fail(hipError_t e, const char *what);
 int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out);
-int launch_step(const Layout &L, const StepArgs &args, bool dev, bool corr, hipStream_t s, int nz);
+int launch_step(const Layout &L, const StepArgs &args, int dtype, bool corr, hipStream_t s, int nz);
 
 }  // namespace lbm

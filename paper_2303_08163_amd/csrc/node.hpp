@@ -35,6 +35,17 @@
 
 namespace lbm {
 
+// Storage and arithmetic of a domain (the values of lbm_config.dtype):
+//   kF64:        double storage, double arithmetic;
+//   kDevF64:     float deviations f_i - w_i rho0, all arithmetic in double;
+//   kDevMixed:   float deviations; moments, square roots and the per-axis
+//                factor deviations in double, per-population products and
+//                relaxation in float on deviations (precision ablation);
+//   kDevF32:     float deviations, all arithmetic in float (precision ablation).
+constexpr int kF64 = 0, kDevF64 = 1, kDevMixed = 2, kDevF32 = 3;
+template <int DT>
+using store_t = typename std::conditional<DT == kF64, double, float>::type;
+
 // 1-D weights of c = -1, 0, +1 (Sec. "Basic concepts").
 __host__ __device__ constexpr double w1(int k) { return k == 1 ? 2.0 / 3.0 : 1.0 / 6.0; }
 
@@ -104,12 +115,18 @@ struct Relax {
     double rho0;        // deviation reference (DEV storage)
 };
 
-// One collision of one node: on entry f holds the stored (pre-collision)
-// values, on exit the stored post-collision values.  Returns true when the
-// node is outside the equilibrium's domain (rho <= 0, |u_a| >= 1 or NaN).
-template <int DIM, bool DEV, bool CORR>
-__device__ __forceinline__ bool collide(double (&f)[Lattice<DIM>::Q], const Relax &r) {
-    constexpr int Q = Lattice<DIM>::Q;
+// One collision of one node: on entry v holds the stored (pre-collision)
+// values, on exit the stored post-collision values (rounded to nearest from
+// double when the storage is float).  Returns true when the node is outside
+// the equilibrium's domain (rho <= 0, |u_a| >= 1 or NaN).  T is the storage
+// type; every kernel calls this one function, so a node's result does not
+// depend on which kernel or launch shape computed it.
+template <int DIM, bool DEV, bool CORR, typename T>
+__device__ __forceinline__ bool collide(T (&v)[Lattice<DIM>::Q], const Relax &r) {
+    double f[Lattice<DIM>::Q];
+#pragma unroll
+    for (int i = 0; i < Lattice<DIM>::Q; ++i)
+        f[i] = (double)v[i];
     double rho, j[3];
     node_moments<DIM>(f, DEV ? r.rho0 : 0.0, rho, j);
     const double inv = 1.0 / rho;
@@ -146,11 +163,105 @@ __device__ __forceinline__ bool collide(double (&f)[Lattice<DIM>::Q], const Rela
                 double feq = t * g[0][cx];
                 if (DEV)
                     feq = fma(-Lattice<DIM>::weight(i), r.rho0, feq);
-                f[i] = fma(omega, feq - f[i], f[i]);
+                T vi = v[i];
+                if (sizeof(T) == 4)
+                    // Widen again rather than keep the first pass's doubles alive:
+                    // an empty asm hides vi's origin (no instruction is emitted and
+                    // the value is unchanged), halving the registers held here.
+                    asm volatile("" : "+v"(vi));
+                const double fi = (double)vi;
+                v[i] = (T)fma(omega, feq - fi, fi);
             }
         }
-    (void)Q;
     return bad;
+}
+
+// Collision on deviation storage with float per-population arithmetic.
+// With S = sqrt(1 + 3 u^2) and q = S - 1 = 3 u^2 / (1 + S), each 1-D factor is
+// g(c) = w1(c) (1 + d(c)) with d(0) = -q and d(+-1) = 2 q +- 3 u, so
+//   f_i^eq - w_i rho0 = w_i [(rho - rho0) + rho P_i],  P_i = prod_a (1 + d_a) - 1,
+// and P_i is formed as nested d + e + d e terms: every float operation acts on
+// deviation-sized numbers, never on w_i rho0 itself.  F64MOM selects double
+// (else float) for the moment sums, the square roots and d.
+template <int DIM, bool CORR, bool F64MOM>
+__device__ __forceinline__ bool collide_dev_f32(float (&v)[Lattice<DIM>::Q], const Relax &r) {
+    using R = typename std::conditional<F64MOM, double, float>::type;
+    constexpr int Q = Lattice<DIM>::Q;
+    R f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        f[i] = (R)v[i];
+    // moment sums of the deviations (row sums over c_x, then planes)
+    R row[3][3], rowx[3][3];
+#pragma unroll
+    for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
+#pragma unroll
+        for (int cy = 0; cy < 3; ++cy) {
+            const int b = 3 * cy + 9 * cz;
+            row[cz][cy] = (f[b + 0] + f[b + 1]) + f[b + 2];
+            rowx[cz][cy] = f[b + 2] - f[b + 0];
+        }
+    R drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz) {
+        const R plane = (row[cz][0] + row[cz][1]) + row[cz][2];
+        drho += plane;
+        jx += (rowx[cz][0] + rowx[cz][1]) + rowx[cz][2];
+        jy += row[cz][2] - row[cz][0];
+        if (DIM == 3)
+            jz += (cz == 2 ? plane : (cz == 0 ? -plane : R(0)));
+    }
+    const R rho = (R)r.rho0 + drho;
+    const R inv = R(1) / rho;
+    const R u[3] = {jx * inv, jy * inv, DIM == 3 ? jz * inv : R(0)};
+    bool bad = !(rho > R(0));
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+        bad |= !(fabs(u[a]) < R(1));
+
+    float d[3][3];
+    R Smax = 0, umax = 0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const R three_u = R(3) * u[a];
+        const R S = sqrt(fma(three_u, u[a], R(1)));
+        const R q = (three_u * u[a]) / (R(1) + S);
+        d[a][0] = (float)fma(R(2), q, -three_u);
+        d[a][1] = (float)(-q);
+        d[a][2] = (float)fma(R(2), q, three_u);
+        Smax = a == 0 ? S : fmax(Smax, S);
+        umax = a == 0 ? fabs(u[a]) : fmax(umax, fabs(u[a]));
+    }
+    float omega = (float)r.omega;
+    if (CORR)
+        omega = (float)corrected_omega((double)umax, (double)Smax, r.two_tau_m1);
+
+    const float rf = (float)rho, drf = (float)drho;
+#pragma unroll
+    for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
+#pragma unroll
+        for (int cy = 0; cy < 3; ++cy) {
+            const float e = DIM == 3 ? fmaf(d[1][cy], d[2][cz], d[1][cy] + d[2][cz]) : d[1][cy];
+#pragma unroll
+            for (int cx = 0; cx < 3; ++cx) {
+                const int i = cx + 3 * cy + 9 * cz;
+                const float P = fmaf(d[0][cx], e, d[0][cx] + e);
+                const float feq = (float)Lattice<DIM>::weight(i) * fmaf(rf, P, drf);
+                v[i] = fmaf(omega, feq - v[i], v[i]);
+            }
+        }
+    return bad;
+}
+
+// Collision of a node for storage/arithmetic code DT.
+template <int DIM, int DT, bool CORR>
+__device__ __forceinline__ bool collide_dt(store_t<DT> (&v)[Lattice<DIM>::Q], const Relax &r) {
+    if constexpr (DT == kDevMixed)
+        return collide_dev_f32<DIM, CORR, true>(v, r);
+    else if constexpr (DT == kDevF32)
+        return collide_dev_f32<DIM, CORR, false>(v, r);
+    else
+        return collide<DIM, DT != kF64, CORR>(v, r);
 }
 
 // Stored equilibrium of (rho, u) for initialisation; returns the domain flag.

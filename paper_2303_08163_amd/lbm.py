@@ -23,10 +23,11 @@ LIB_PATH = os.path.join(_HERE, "liblbm_entropic.so")
 # status codes (enum lbm_status)
 LBM_OK, LBM_EINVAL, LBM_EDOMAIN, LBM_EDEVICE, LBM_ENOMEM, LBM_EBUSY = 0, -1, -2, -3, -4, -5
 LBM_D2Q9, LBM_D3Q27 = 9, 27
-LBM_FP64, LBM_FP32_DEV = 0, 1
+LBM_FP64, LBM_FP32_DEV, LBM_FP32_DEV_MIXED, LBM_FP32_DEV_F32 = 0, 1, 2, 3
 LBM_EQ_ENTROPIC = 0
 
-DTYPES = {"fp64": LBM_FP64, "fp32_dev": LBM_FP32_DEV}
+DTYPES = {"fp64": LBM_FP64, "fp32_dev": LBM_FP32_DEV, "fp32_dev_mixed": LBM_FP32_DEV_MIXED,
+          "fp32_dev_f32": LBM_FP32_DEV_F32}
 
 
 class lbm_config(ctypes.Structure):
@@ -38,7 +39,8 @@ class lbm_config(ctypes.Structure):
 
 class lbm_tuning(ctypes.Structure):
     _fields_ = [("block_x", ctypes.c_int32), ("block_y", ctypes.c_int32),
-                ("plane_pad", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("plane_pad", ctypes.c_int32), ("nodes_per_thread", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class lbm_diag(ctypes.Structure):
@@ -129,8 +131,11 @@ def make_config(lattice: int, shape, tau: float, dtype="fp32_dev", bulk_correcti
                       int(bool(bulk_correction)), LBM_EQ_ENTROPIC, float(rho0))
 
 
-def make_tuning(block_x=0, block_y=0, plane_pad=-1) -> lbm_tuning:
-    return lbm_tuning(int(block_x), int(block_y), int(plane_pad), 0)
+LBM_TUNE_NT_STORE, LBM_TUNE_NT_LOAD = 1, 2
+
+
+def make_tuning(block_x=0, block_y=0, plane_pad=-1, nodes_per_thread=0, flags=-1) -> lbm_tuning:
+    return lbm_tuning(int(block_x), int(block_y), int(plane_pad), int(nodes_per_thread), int(flags), 0)
 
 
 def lbm_workspace_bytes(cfg: lbm_config, tuning: lbm_tuning | None = None) -> int:

@@ -75,7 +75,7 @@ def test_workspace_bytes_layout(lbm):
     dict(tau=0.5), dict(tau=0.3), dict(tau=float("nan")), dict(tau=float("inf")),
     dict(lattice=19), dict(dtype=7), dict(shape=(0, 5)), dict(shape=(5, 0)),
     dict(shape=(4, 4, 2)), dict(lattice=27, shape=(4, 4, 0)), dict(dtype="fp32_dev", rho0=0.0),
-    dict(dtype="fp32_dev", rho0=-1.0), dict(shape=(70000, 70000)), dict(lattice=27, shape=(2, 2, 70000)),
+    dict(dtype="fp32_dev", rho0=-1.0), dict(shape=(70000, 70000)), dict(lattice=27, shape=(2, 2, 2 ** 30)), dict(shape=(2 ** 31, 1)),
 ])
 def test_invalid_configs_are_rejected(lbm, bad):
     assert lbm.lbm_workspace_bytes(_cfg(lbm, **bad)) == 0

@@ -23,6 +23,8 @@ from paper_2303_08163_amd import workloads
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": 1e-12, "fp32_dev": 1e-5}
+DTYPES = ["fp64", "fp32_dev"]
+ABLATION = ["fp32_dev_mixed", "fp32_dev_f32"]  # reported, not held to the FP32 budget
 
 
 def _lbm():
@@ -53,7 +55,7 @@ def c1_oracle():
     return rho0, u0, {c: oracle.run(rho0, u0, 0.51, 1000, corr=c) for c in ("off", "min")}
 
 
-@pytest.mark.parametrize("dtype", ["fp64", "fp32_dev"])
+@pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("corr", [False, True])
 def test_c1_taylor_green_64_1000_steps(c1_oracle, dtype, corr):
     rho0, u0, ref = c1_oracle
@@ -66,12 +68,24 @@ def test_c1_taylor_green_64_1000_steps(c1_oracle, dtype, corr):
     assert er < TOL[dtype] and eu < TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", ABLATION)
+def test_c1_precision_ablation_report(c1_oracle, dtype):
+    """Single-precision arithmetic on the FP32 storage (ablation): errors are
+    stated, and bounded loosely, but not held to the 1e-5 budget."""
+    rho0, u0, ref = c1_oracle
+    r_ref, u_ref, _ = ref["off"]
+    rho, u, _, _ = run_gpu(rho0, u0, 0.51, 1000, dtype, False)
+    er, eu = rel_err(rho, r_ref), rel_err(u, u_ref)
+    report(f"D2Q9 64^2 TG tau=0.51 1000 steps {dtype} (ablation)", er, eu)
+    assert er < 1e-3 and eu < 1e-2
+
+
 GRIDS = [(9, (1, 1)), (9, (2, 3)), (9, (17, 31)), (9, (65, 3)), (9, (130, 7)),
          (27, (1, 1, 1)), (27, (5, 7, 3)), (27, (17, 9, 4)), (27, (67, 5, 3)), (27, (2, 1, 66))]
 
 
 @pytest.mark.parametrize("lattice,shape", GRIDS)
-@pytest.mark.parametrize("dtype", ["fp64", "fp32_dev"])
+@pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("corr", [False, True])
 def test_ragged_grids_random_fields(lattice, shape, dtype, corr):
     grid = shape[::-1]  # numpy order (.., y, x)
@@ -91,7 +105,7 @@ def c3_64_oracle():
     return rho0, u0, oracle.run(rho0, u0, 0.5005, 500)
 
 
-@pytest.mark.parametrize("dtype", ["fp64", "fp32_dev"])
+@pytest.mark.parametrize("dtype", DTYPES)
 def test_c3_taylor_green_64cubed_500_steps(c3_64_oracle, dtype):
     rho0, u0, (r_ref, u_ref, bad) = c3_64_oracle
     assert bad == 0
@@ -118,7 +132,7 @@ def _check_samples(rho, u, pts, rs, us, tol, name):
     assert er < tol and eu < tol
 
 
-@pytest.mark.parametrize("dtype", ["fp64", "fp32_dev"])
+@pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("corr", [False, True])
 def test_c2_double_shear_layer_4096_sampled(dtype, corr):
     n, steps, tau = 4096, 60, 0.5001
@@ -133,7 +147,7 @@ def test_c2_double_shear_layer_4096_sampled(dtype, corr):
     assert not diag["domain_error"]
 
 
-@pytest.mark.parametrize("dtype", ["fp64", "fp32_dev"])
+@pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("corr", [False, True])
 def test_c3_taylor_green_256_sampled(dtype, corr):
     n, steps, tau = 256, 8, 0.5005
@@ -148,14 +162,17 @@ def test_c3_taylor_green_256_sampled(dtype, corr):
 def test_c3_256_full_steps_fp32_vs_fp64(corr):
     """C3 at full size and step count: FP32 deviation storage vs FP64 storage
     (both on the GPU, the FP64 path being oracle-matched at 64^3 and sampled at
-    256^3), and exact mass conservation of the FP64 run."""
+    256^3), and exact mass conservation of the FP64 run.  The all-single
+    arithmetic variant is reported (precision ablation), not held to 1e-5."""
     n, steps, tau = 256, 500, 0.5005
     rho0, u0 = workloads.taylor_green_3d(n, u0=0.05)
     r64, u64, d64, _ = run_gpu(rho0, u0, tau, steps, "fp64", corr)
-    r32, u32, d32, _ = run_gpu(rho0, u0, tau, steps, "fp32_dev", corr)
-    er, eu = rel_err(r32, r64), rel_err(u32, u64)
-    report(f"D3Q27 256^3 TG 500 steps fp32_dev vs fp64 corr={corr}", er, eu)
-    assert er < 1e-5 and eu < 1e-5
+    for dt in ["fp32_dev"] + ABLATION:
+        r32, u32, d32, _ = run_gpu(rho0, u0, tau, steps, dt, corr)
+        er, eu = rel_err(r32, r64), rel_err(u32, u64)
+        report(f"D3Q27 256^3 TG 500 steps {dt} vs fp64 corr={corr}", er, eu)
+        if dt == "fp32_dev":
+            assert er < 1e-5 and eu < 1e-5
     assert abs(d64["mass"] / rho0.sum() - 1) < 1e-12
     for a in range(3):
         assert abs(d64["momentum"][a] - float(np.sum(rho0 * u0[a]))) < 1e-12 * rho0.size
@@ -166,15 +183,17 @@ def test_c2_4096_full_steps_fp32_vs_fp64(corr):
     n, steps, tau = 4096, 1000, 0.5001
     rho0, u0 = workloads.double_shear_layer(n)
     r64, u64, d64, _ = run_gpu(rho0, u0, tau, steps, "fp64", corr)
-    r32, u32, _, _ = run_gpu(rho0, u0, tau, steps, "fp32_dev", corr)
-    er, eu = rel_err(r32, r64), rel_err(u32, u64)
-    eux, euy = rel_err(u32[0], u64[0]), rel_err(u32[1], u64[1])
-    report(f"D2Q9 4096^2 shear layer 1000 steps fp32_dev vs fp64 corr={corr} (u_x {eux:.2e}, u_y {euy:.2e})", er, eu)
-    assert er < 1e-5 and eu < 1e-5
+    for dt in ["fp32_dev"] + ABLATION:
+        r32, u32, _, _ = run_gpu(rho0, u0, tau, steps, dt, corr)
+        er, eu = rel_err(r32, r64), rel_err(u32, u64)
+        eux, euy = rel_err(u32[0], u64[0]), rel_err(u32[1], u64[1])
+        report(f"D2Q9 4096^2 shear layer 1000 steps {dt} vs fp64 corr={corr} (u_x {eux:.2e}, u_y {euy:.2e})", er, eu)
+        if dt == "fp32_dev":
+            assert er < 1e-5 and eu < 1e-5
     assert abs(d64["mass"] / rho0.sum() - 1) < 1e-12
 
 
-@pytest.mark.parametrize("dtype", ["fp64", "fp32_dev"])
+@pytest.mark.parametrize("dtype", DTYPES + ABLATION)
 def test_translation_equivariance_bitwise(dtype):
     rho0, u0 = workloads.random_field((9, 12, 20), seed=31, umax=0.3)
     sh = (2, 5, 7)
@@ -184,19 +203,41 @@ def test_translation_equivariance_bitwise(dtype):
     assert np.array_equal(np.roll(f1, sh, axis=(1, 2, 3)), f2)
 
 
-@pytest.mark.parametrize("lattice", [9, 27])
-def test_tuning_invariance_bitwise(lattice):
+SCALAR_TUNINGS = [(0, 0, -1, 1, 0), (64, 4, 0, 1, 0), (128, 2, 64, 1, 0), (256, 1, 4096, 1, 0),
+                  (32, 8, 128, 1, 0), (64, 1, 0, 1, 0)]
+VECTOR_TUNINGS = [(64, 4, 0, 2, 0), (64, 1, 64, 2, 1), (128, 2, 0, 2, 3), (64, 4, 0, 4, 0), (64, 2, 0, 4, 1),
+                  (64, 4, 256, 4, 3), (128, 1, 0, 4, 1), (0, 0, -1, 0, -1)]
+
+
+@pytest.mark.parametrize("lattice,grid", [(9, (5, 256)), (9, (4, 512)), (9, (3, 1024)),
+                                          (27, (2, 3, 256)), (27, (3, 2, 512)), (27, (2, 2, 128))])
+@pytest.mark.parametrize("dtype", DTYPES + ABLATION)
+def test_tuning_invariance_bitwise(lattice, grid, dtype):
+    """Every launch shape and kernel variant (one node per thread, 2 or 4 nodes
+    per thread with lane rotation, non-temporal hints) gives bitwise the same
+    populations, and matches the oracle."""
     lbm = _lbm()
-    grid = (70, 66) if lattice == 9 else (6, 33, 70)
     rho0, u0 = workloads.random_field(grid, seed=41, umax=0.3)
     base = None
-    for bx, by, pad in ((0, 0, -1), (64, 4, 0), (128, 2, 64), (256, 1, 4096), (32, 8, 128), (64, 1, 0)):
-        rho, u, _, f = run_gpu(rho0, u0, 0.55, 5, "fp32_dev", True, tuning=lbm.make_tuning(bx, by, pad),
-                               populations=True)
+    nx = grid[-1]
+    ran = 0
+    for bx, by, pad, npt, flags in SCALAR_TUNINGS + VECTOR_TUNINGS:
+        if npt == 4 and dtype == "fp64":
+            continue
+        if npt > 1 and nx % (bx * npt) != 0:
+            continue
+        rho, u, _, f = run_gpu(rho0, u0, 0.55, 5, dtype, True,
+                               tuning=lbm.make_tuning(bx, by, pad, npt, flags), populations=True)
+        ran += 1
         if base is None:
             base = (rho, u, f)
+            r_ref, u_ref, _ = oracle.run(rho0, u0, 0.55, 5, corr="min")
+            tol = TOL.get(dtype, 1e-4)
+            assert rel_err(rho, r_ref) < tol and rel_err(u, u_ref) < tol
         else:
-            assert np.array_equal(base[0], rho) and np.array_equal(base[1], u) and np.array_equal(base[2], f)
+            assert np.array_equal(base[0], rho) and np.array_equal(base[1], u) and np.array_equal(base[2], f), \
+                (bx, by, pad, npt, flags)
+    assert ran >= 7
 
 
 @pytest.mark.parametrize("lattice", [9, 27])
@@ -215,7 +256,7 @@ def test_populations_match_oracle(lattice):
         assert np.max(np.abs(f_gpu[i] - back)) < 1e-13
 
 
-@pytest.mark.parametrize("dtype", ["fp64", "fp32_dev"])
+@pytest.mark.parametrize("dtype", DTYPES)
 def test_diagnostics_match_oracle(dtype):
     rho0, u0 = workloads.taylor_green_3d(24, u0=0.1)
     r_ref, u_ref, _ = oracle.run(rho0, u0, 0.52, 30, corr="min")
