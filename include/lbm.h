@@ -96,16 +96,26 @@ typedef struct lbm_tuning {
                                  per thread only) a power of two below 64 */
     int32_t block_y;          /* rows along y per workgroup; block_x * block_y a multiple of 64,
                                  <= 256 */
-    int32_t plane_pad;        /* extra elements between population planes (>= 0, padding against
-                                 HBM channel aliasing; < 0 selects the default) */
+    int32_t plane_pad;        /* LBM_LAYOUT_PLANES only: extra elements between population
+                                 planes (>= 0; < 0 selects the default, 0) */
     int32_t nodes_per_thread; /* consecutive x nodes per thread: 1, 2 or 4 (4 for FP32 storage
                                  only); > 1 needs nx % (block_x * nodes_per_thread) == 0 */
     int32_t flags;            /* LBM_TUNE_* bits for the vector kernels; < 0 selects the default */
+    int32_t layout;           /* LBM_LAYOUT_*; 0 = default (row-interleaved) */
     int32_t reserved;         /* must be 0 */
 } lbm_tuning;
 
 /* lbm_tuning.flags bits. */
 enum { LBM_TUNE_NT_STORE = 1, LBM_TUNE_NT_LOAD = 2 };
+
+/* Population layouts in device memory (the library's private format; results
+ * do not depend on it).  Rows run along x; row = z ny + y.
+ *   LBM_LAYOUT_ROWS:   each row holds its Q population runs back to back,
+ *                      each run padded to a multiple of 64 elements
+ *                      ([z][y][i][x]).
+ *   LBM_LAYOUT_PLANES: one plane of N nodes per population ([i][z][y][x]),
+ *                      planes padded to 64 elements plus plane_pad. */
+enum { LBM_LAYOUT_DEFAULT = 0, LBM_LAYOUT_ROWS = 1, LBM_LAYOUT_PLANES = 2 };
 
 /* Whole-domain diagnostics, all from the current populations. */
 typedef struct lbm_diag {

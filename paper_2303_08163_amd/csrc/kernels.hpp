@@ -2,22 +2,24 @@
 // fused pull-stream-and-collide step, moments with deterministic reductions,
 // and population export.
 //
-// Data layout in HBM (structure of arrays): population i of node
-// n = x + nx (y + ny z) lives at buf[i * stride + n]; stride >= N is a
-// multiple of 64 elements plus an optional pad, so every plane starts
-// 256-byte aligned.  Two such buffers alternate (read one, write the other).
+// Data layout in HBM.  Nodes are grouped in rows along x: row = z ny + y.
+// Population i of node (x, row) lives at buf[i * ps + row * rs + x], where
+//   - row-interleaved layout (default): ps = pitch, rs = Q * pitch, i.e. each
+//     row stores its Q population runs back to back ([z][y][i][x]); pitch is
+//     nx rounded up to 64 elements (nx itself below 64);
+//   - plane layout: ps = plane stride (>= N, a multiple of 64 plus optional
+//     padding), rs = nx ([i][z][y][x], one plane per population).
+// With the row-interleaved layout a row update reads 9 (D3Q27) or 3 (D2Q9)
+// contiguous runs of 3 populations from the source rows (y - c_y, z - c_z) and
+// writes one contiguous run of Q populations, so far fewer DRAM pages are open
+// at once than with Q separate planes.  Two buffers alternate (read one,
+// write the other).
 //
 // Streaming (Sec. "Basic concepts", left side of the LBGK equation) is done by
 // pulling: the buffer holds post-collision values f*(r, t), and the step at r
 // reads f*_i(r - c_i, t) = f_i(r, t + 1), collides, and writes f*_i(r, t + 1)
 // back at r.  Every value is read once and written once per step: the
 // algorithmic HBM traffic is 2 Q sizeof(storage) bytes per node update.
-// Workgroups cover (block_x * block_y) nodes of one z plane with x fastest
-// (by default a whole row of up to 256 nodes), so a wavefront reads 27 (or 9)
-// rows of 64 consecutive elements shifted by at most one element and writes
-// 27 (or 9) aligned rows; the one-element shifts fall on cache lines that the
-// neighbouring wave of the same workgroup reads, and the tiles of a row are
-// kept on one XCD (xcd_tile), so the shifts cost no extra HBM traffic.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -32,7 +34,7 @@ struct StepArgs {
     void *dst;
     int nx, ny, nz;
     int tiles_x, tiles_y;  // workgroup tiles per row / per plane
-    int64_t stride;
+    int64_t ps, rs;        // population and row strides (elements)
     Relax relax;
     int *flag;
 };
@@ -48,46 +50,53 @@ __device__ __forceinline__ int xcd_tile(int w, int count) {
     return xcd * per + (xcd < rem ? xcd : rem) + k;
 }
 
-// One node's pull-stream, collision and store.  src/dst are population
-// buffers of one domain; (x, y, z) must lie inside the grid.
-template <int DIM, int DT, bool CORR>
-__device__ __forceinline__ void step_node(const store_t<DT> *__restrict__ src, store_t<DT> *__restrict__ dst,
-                                          int nx, int ny, int nz, int64_t stride, const Relax &relax,
-                                          int *flag, int x, int y, int z) {
-    using T = store_t<DT>;
-    constexpr int Q = Lattice<DIM>::Q;
-    // source coordinate r - c for c = -1, 0, +1 on the periodic grid
-    const int xs[3] = {x + 1 == nx ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};
+// Source rows r - c for c_y, c_z = -1, 0, +1 on the periodic grid, as element
+// offsets of population 0.
+template <int DIM>
+__device__ __forceinline__ void source_rows(int y, int z, int ny, int nz, int64_t rs, int64_t (&rowoff)[3][3]) {
     const int ys[3] = {y + 1 == ny ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
     int zs[3] = {z, z, z};
     if (DIM == 3) {
         zs[0] = z + 1 == nz ? 0 : z + 1;
         zs[2] = z == 0 ? nz - 1 : z - 1;
     }
+#pragma unroll
+    for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
+#pragma unroll
+        for (int cy = 0; cy < 3; ++cy)
+            rowoff[cz][cy] = (int64_t)(zs[cz] * ny + ys[cy]) * rs;
+}
+
+// One node's pull-stream, collision and store.  src/dst are population
+// buffers of one domain; (x, y, z) must lie inside the grid.
+template <int DIM, int DT, bool CORR>
+__device__ __forceinline__ void step_node(const store_t<DT> *__restrict__ src, store_t<DT> *__restrict__ dst,
+                                          int nx, int ny, int nz, int64_t ps, int64_t rs, const Relax &relax,
+                                          int *flag, int x, int y, int z) {
+    using T = store_t<DT>;
+    constexpr int Q = Lattice<DIM>::Q;
+    const int xs[3] = {x + 1 == nx ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};  // x - c_x
+    int64_t rowoff[3][3];
+    source_rows<DIM>(y, z, ny, nz, rs, rowoff);
     T f[Q];
 #pragma unroll
     for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
 #pragma unroll
-        for (int cy = 0; cy < 3; ++cy) {
-            const uint32_t row = (uint32_t)(zs[cz] * ny + ys[cy]) * (uint32_t)nx;
+        for (int cy = 0; cy < 3; ++cy)
 #pragma unroll
             for (int cx = 0; cx < 3; ++cx) {
                 const int i = cx + 3 * cy + 9 * cz;
-                const T *__restrict__ plane = src + (int64_t)i * stride;  // wave-uniform base
-                f[i] = plane[row + (uint32_t)xs[cx]];
+                f[i] = src[rowoff[cz][cy] + i * ps + xs[cx]];
             }
-        }
 
     const bool bad = collide_dt<DIM, DT, CORR>(f, relax);
     if (bad)
         __hip_atomic_fetch_or(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
-    const uint32_t self = (uint32_t)(z * ny + y) * (uint32_t)nx + (uint32_t)x;
+    const int64_t self = (int64_t)(z * ny + y) * rs + x;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        T *__restrict__ plane = dst + (int64_t)i * stride;
-        plane[self] = f[i];
-    }
+    for (int i = 0; i < Q; ++i)
+        dst[self + i * ps] = f[i];
 }
 
 // One LBGK step over the whole domain.  1-D grid of tiles_x * tiles_y * nz
@@ -102,19 +111,20 @@ __global__ __launch_bounds__(256) void k_stream_collide(StepArgs a) {
     const int y = ty * (int)blockDim.y + (int)threadIdx.y;
     if (x >= a.nx || y >= a.ny)
         return;
-    step_node<DIM, DT, CORR>(static_cast<const store_t<DT> *>(a.src), static_cast<store_t<DT> *>(a.dst),
-                              a.nx, a.ny, a.nz, a.stride, a.relax, a.flag, x, y, z);
+    step_node<DIM, DT, CORR>(static_cast<const store_t<DT> *>(a.src), static_cast<store_t<DT> *>(a.dst), a.nx,
+                             a.ny, a.nz, a.ps, a.rs, a.relax, a.flag, x, y, z);
 }
 
 // ---------------------------------------------------------------------------
 // Vectorised step: each thread owns NPT consecutive nodes of a row and moves
-// every population plane with one aligned NPT-wide load and store (16 bytes
-// for float x 4 or double x 2).  The x-shifted planes need one element beyond
-// the thread's run on one side; it comes from the neighbouring lane of the
-// same wavefront by a lane rotation, and at the two ends of the wavefront's
-// run from a single-lane load (or, when one wavefront spans the whole row,
-// from the rotation itself, which then is the periodic wrap).  Needs
-// nx % (64 * NPT) == 0 and blockDim.x a multiple of 64 dividing nx / NPT.
+// every population run with one aligned NPT-wide load and store (16 bytes for
+// float x 4 or double x 2).  The x-shifted populations need one element
+// beyond the thread's run on one side; it comes from the neighbouring lane of
+// the same wavefront by a lane rotation, and at the two ends of the
+// wavefront's run from a single-lane load (or, when one wavefront spans the
+// whole row, from the rotation itself, which then is the periodic wrap).
+// Needs nx % (blockDim.x * NPT) == 0, blockDim.x a multiple of 64, and
+// 16-byte aligned runs (ps and rs multiples of NPT).
 template <typename T, int NPT>
 struct VecT;
 template <>
@@ -158,20 +168,17 @@ __global__ __launch_bounds__(256) void k_stream_collide_vec(StepArgs a) {
     const int ty = (t / a.tiles_x) % a.tiles_y;
     const int z = t / (a.tiles_x * a.tiles_y);
     const int y = ty * (int)blockDim.y + (int)threadIdx.y;
-    if (y >= a.ny)  // uniform per row of threads
+    if (y >= a.ny)  // uniform per wavefront
         return;
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int nx = a.nx;
+    const int64_t ps = a.ps;
     const int lane = (int)threadIdx.x & 63;
     const int x0 = (tx * (int)blockDim.x + (int)threadIdx.x) * NPT;  // first node of this thread
     const T *__restrict__ src = static_cast<const T *>(a.src);
     T *__restrict__ dst = static_cast<T *>(a.dst);
 
-    const int ys[3] = {y + 1 == ny ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
-    int zs[3] = {z, z, z};
-    if (DIM == 3) {
-        zs[0] = z + 1 == nz ? 0 : z + 1;
-        zs[2] = z == 0 ? nz - 1 : z - 1;
-    }
+    int64_t rowoff[3][3];
+    source_rows<DIM>(y, z, a.ny, a.nz, a.rs, rowoff);
     // neighbours of the run at the wavefront's ends (periodic in x)
     const int x_left = x0 == 0 ? nx - 1 : x0 - 1;
     const int x_right = x0 + NPT == nx ? 0 : x0 + NPT;
@@ -180,13 +187,12 @@ __global__ __launch_bounds__(256) void k_stream_collide_vec(StepArgs a) {
 #pragma unroll
     for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
 #pragma unroll
-        for (int cy = 0; cy < 3; ++cy) {
-            const uint32_t row = (uint32_t)(zs[cz] * ny + ys[cy]) * (uint32_t)nx;
+        for (int cy = 0; cy < 3; ++cy)
 #pragma unroll
             for (int cx = 0; cx < 3; ++cx) {
                 const int i = cx + 3 * cy + 9 * cz;
-                const T *__restrict__ plane = src + (int64_t)i * a.stride;
-                const V v = load_vec<V, FLAGS>(reinterpret_cast<const V *>(plane + row + (uint32_t)x0));
+                const T *__restrict__ run = src + rowoff[cz][cy] + i * ps;
+                const V v = load_vec<V, FLAGS>(reinterpret_cast<const V *>(run + x0));
                 if (cx == 1) {  // c_x = 0: aligned
 #pragma unroll
                     for (int k = 0; k < NPT; ++k)
@@ -194,7 +200,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_vec(StepArgs a) {
                 } else if (cx == 2) {  // c_x = +1 pulls from x - 1
                     T left = __shfl(v[NPT - 1], (lane + 63) & 63, 64);
                     if (!ROWWAVE && lane == 0)
-                        left = plane[row + (uint32_t)x_left];
+                        left = run[x_left];
                     g[i][0] = left;
 #pragma unroll
                     for (int k = 1; k < NPT; ++k)
@@ -202,14 +208,13 @@ __global__ __launch_bounds__(256) void k_stream_collide_vec(StepArgs a) {
                 } else {  // c_x = -1 pulls from x + 1
                     T right = __shfl(v[0], (lane + 1) & 63, 64);
                     if (!ROWWAVE && lane == 63)
-                        right = plane[row + (uint32_t)x_right];
+                        right = run[x_right];
 #pragma unroll
                     for (int k = 0; k < NPT - 1; ++k)
                         g[i][k] = v[k + 1];
                     g[i][NPT - 1] = right;
                 }
             }
-        }
 
     bool bad = false;
 #pragma unroll
@@ -226,14 +231,14 @@ __global__ __launch_bounds__(256) void k_stream_collide_vec(StepArgs a) {
     if (bad)
         __hip_atomic_fetch_or(a.flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
-    const uint32_t self = (uint32_t)(z * ny + y) * (uint32_t)nx + (uint32_t)x0;
+    const int64_t self = (int64_t)(z * a.ny + y) * a.rs + x0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         V v;
 #pragma unroll
         for (int k = 0; k < NPT; ++k)
             v[k] = g[i][k];
-        store_vec<V, FLAGS>(v, reinterpret_cast<V *>(dst + (int64_t)i * a.stride + self));
+        store_vec<V, FLAGS>(v, reinterpret_cast<V *>(dst + self + i * ps));
     }
 }
 
@@ -244,11 +249,19 @@ __global__ void k_clear_words(int *p, int count) {
         p[k] = 0;
 }
 
+// Element offset of population 0 of node n (x fastest) in a buffer.
+__device__ __forceinline__ int64_t node_offset(int64_t n, int nx, int64_t rs) {
+    const int64_t row = n / nx;
+    return row * rs + (n - row * nx);
+}
+
 struct InitArgs {
     void *dst;
     const double *rho;
     const double *u;  // D planes of N
-    int64_t n, stride;
+    int64_t n;
+    int nx;
+    int64_t ps, rs;
     double rho0;
     int *flag;
 };
@@ -266,10 +279,10 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a) {
     const bool bad = equilibrium_stored<DIM, DEV>(a.rho[n], u, a.rho0, f);
     if (bad)
         __hip_atomic_fetch_or(a.flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    T *dst = static_cast<T *>(a.dst);
+    T *dst = static_cast<T *>(a.dst) + node_offset(n, a.nx, a.rs);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-        dst[i * a.stride + n] = (T)f[i];
+        dst[i * a.ps] = (T)f[i];
 }
 
 // Diagnostics partials per workgroup: mass, momentum x/y/z, kinetic energy,
@@ -281,7 +294,9 @@ struct MomentArgs {
     const void *src;
     double *rho;  // may be null
     double *u;    // may be null
-    int64_t n, stride;
+    int64_t n;
+    int nx;
+    int64_t ps, rs;
     double rho0;
     double *partials;  // gridDim.x * kDiagFields
 };
@@ -346,10 +361,11 @@ __global__ __launch_bounds__(kReduceThreads) void k_moments(MomentArgs a) {
     double acc[kDiagFields] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, INFINITY};
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < a.n;
          n += (int64_t)gridDim.x * blockDim.x) {
+        const T *p = src + node_offset(n, a.nx, a.rs);
         double f[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i)
-            f[i] = (double)src[i * a.stride + n];
+            f[i] = (double)p[i * a.ps];
         double rho, j[3];
         node_moments<DIM>(f, DEV ? a.rho0 : 0.0, rho, j);
         const double inv = 1.0 / rho;
@@ -390,20 +406,22 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_partials(const double
 struct ExportArgs {
     const void *src;
     double *out;
-    int64_t n, stride;
+    int64_t n;
+    int nx;
+    int64_t ps, rs;
     double rho0;
 };
 
 template <int DIM, bool DEV>
 __global__ __launch_bounds__(256) void k_export(ExportArgs a) {
     using T = store_t<DEV>;
-    const T *src = static_cast<const T *>(a.src);
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= a.n)
         return;
+    const T *p = static_cast<const T *>(a.src) + node_offset(n, a.nx, a.rs);
 #pragma unroll
     for (int i = 0; i < Lattice<DIM>::Q; ++i) {
-        double v = (double)src[i * a.stride + n];
+        double v = (double)p[i * a.ps];
         if (DEV)
             v = fma(Lattice<DIM>::weight(i), a.rho0, v);
         a.out[i * a.n + n] = v;

@@ -82,7 +82,7 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
         return LBM_EINVAL;
     }
     // tuning
-    int bx = 0, by = 0, pad = -1, npt = 0, flags = -1;
+    int bx = 0, by = 0, pad = -1, npt = 0, flags = -1, layout = 0;
     if (tun) {
         if (tun->reserved != 0) {
             set_error("lbm_tuning.reserved must be 0");
@@ -93,6 +93,13 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
         pad = tun->plane_pad;
         npt = tun->nodes_per_thread;
         flags = tun->flags;
+        layout = tun->layout;
+    }
+    if (layout == LBM_LAYOUT_DEFAULT)
+        layout = LBM_LAYOUT_ROWS;
+    if (layout != LBM_LAYOUT_ROWS && layout != LBM_LAYOUT_PLANES) {
+        set_error("layout must be LBM_LAYOUT_ROWS or LBM_LAYOUT_PLANES");
+        return LBM_EINVAL;
     }
     const bool fp32 = L.elem == 4;
     if (npt == 0) {
@@ -108,8 +115,8 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
         set_error("nodes_per_thread = 4 needs FP32 storage");
         return LBM_EINVAL;
     }
-    if (flags < 0)
-        flags = npt > 1 ? LBM_TUNE_NT_STORE : 0;
+    if (flags < 0)  // measured best: non-temporal loads and stores for float runs, stores for double
+        flags = npt > 1 ? (fp32 ? LBM_TUNE_NT_STORE | LBM_TUNE_NT_LOAD : LBM_TUNE_NT_STORE) : 0;
     if (flags > (LBM_TUNE_NT_STORE | LBM_TUNE_NT_LOAD) || (npt == 1 && flags != 0) ||
         flags == LBM_TUNE_NT_LOAD) {
         set_error("flags: NT_STORE, NT_STORE | NT_LOAD or 0, and only with nodes_per_thread > 1");
@@ -159,12 +166,21 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
         set_error("plane_pad too large");
         return LBM_EINVAL;
     }
-    L.stride = round_up(L.n, 64) + round_up(pad, 64);
-    if ((int64_t)L.q * L.stride > ((int64_t)1 << 40)) {
+    L.layout = layout;
+    if (layout == LBM_LAYOUT_PLANES) {
+        L.ps = round_up(L.n, 64) + round_up(pad, 64);
+        L.rs = cfg->nx;
+    } else {
+        const int64_t pitch = cfg->nx < 64 ? cfg->nx : round_up(cfg->nx, 64);
+        L.ps = pitch;
+        L.rs = (int64_t)L.q * pitch;
+    }
+    const int64_t elems = layout == LBM_LAYOUT_PLANES ? (int64_t)L.q * L.ps : L.rs * (L.n / cfg->nx);
+    if (elems > ((int64_t)1 << 40)) {
         set_error("domain too large");
         return LBM_EINVAL;
     }
-    L.buf_bytes = (size_t)L.q * (size_t)L.stride * L.elem;
+    L.buf_bytes = (size_t)elems * L.elem;
     L.red_blocks = (int)std::min<int64_t>(1024, (L.n + kReduceThreads - 1) / kReduceThreads);
     // workspace: buffer A | buffer B | flag block (256 B) | diag out (256 B) | partials
     L.off_buf[0] = 0;
@@ -303,7 +319,7 @@ int lbm_create_tuned(const lbm_config *cfg, const lbm_tuning *tuning, void *work
         delete h;
         return hip_fail(e, "clearing the domain flag");
     }
-    InitArgs ia{h->buf[0], rho, u, L.n, L.stride, h->relax.rho0, h->flag};
+    InitArgs ia{h->buf[0], rho, u, L.n, (int)cfg->nx, L.ps, L.rs, h->relax.rho0, h->flag};
     const bool dev = cfg->dtype != LBM_FP64;
     dim3 grid((unsigned)((L.n + 255) / 256)), block(256);
     void (*init_fn)(InitArgs) = L.dim == 2 ? (dev ? k_init<2, true> : k_init<2, false>)
@@ -350,7 +366,8 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
                    (int)h->cfg.nz,
                    (int)((h->cfg.nx + (int64_t)h->L.block_x * h->L.npt - 1) / ((int64_t)h->L.block_x * h->L.npt)),
                    (int)((h->cfg.ny + h->L.block_y - 1) / h->L.block_y),
-                   h->L.stride,
+                   h->L.ps,
+                   h->L.rs,
                    h->relax,
                    h->flag};
         int rc = launch_step(h->L, a, h->cfg.dtype, corr, h->stream, (int)h->cfg.nz);
@@ -369,7 +386,7 @@ int lbm_moments(lbm_handle *h, double *rho, double *u, lbm_diag *diag) {
     }
     const Layout &L = h->L;
     const bool dev = h->cfg.dtype != LBM_FP64;
-    MomentArgs ma{h->buf[h->cur], rho, u, L.n, L.stride, h->relax.rho0, h->partials};
+    MomentArgs ma{h->buf[h->cur], rho, u, L.n, (int)h->cfg.nx, L.ps, L.rs, h->relax.rho0, h->partials};
     dim3 grid((unsigned)L.red_blocks), block(kReduceThreads);
     void (*mom_fn)(MomentArgs) = L.dim == 2 ? (dev ? k_moments<2, true> : k_moments<2, false>)
                                             : (dev ? k_moments<3, true> : k_moments<3, false>);
@@ -414,7 +431,7 @@ int lbm_get_populations(lbm_handle *h, double *out) {
     }
     const Layout &L = h->L;
     const bool dev = h->cfg.dtype != LBM_FP64;
-    ExportArgs ea{h->buf[h->cur], out, L.n, L.stride, h->relax.rho0};
+    ExportArgs ea{h->buf[h->cur], out, L.n, (int)h->cfg.nx, L.ps, L.rs, h->relax.rho0};
     dim3 grid((unsigned)((L.n + 255) / 256)), block(256);
     void (*exp_fn)(ExportArgs) = L.dim == 2 ? (dev ? k_export<2, true> : k_export<2, false>)
                                             : (dev ? k_export<3, true> : k_export<3, false>);

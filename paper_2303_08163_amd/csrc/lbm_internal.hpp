@@ -16,7 +16,8 @@ struct Layout {
     int dim, q;
     size_t elem;       // bytes per stored population
     int64_t n;         // nodes
-    int64_t stride;    // elements between population planes
+    int layout;        // LBM_LAYOUT_ROWS or LBM_LAYOUT_PLANES
+    int64_t ps, rs;    // population and row strides (elements)
     int block_x, block_y;
     int npt;           // nodes per thread along x
     int flags;         // LBM_TUNE_* bits

@@ -66,9 +66,14 @@ def test_workspace_bytes_layout(lbm):
     # D3Q27 256^3 FP32: 2 x 27 x 256^3 x 4 bytes plus scratch
     b3 = lbm.lbm_workspace_bytes(_cfg(lbm, lattice=27, shape=(256, 256, 256), dtype="fp32_dev"))
     assert 2 * 27 * 256 ** 3 * 4 < b3 < 2 * 27 * 256 ** 3 * 4 + 2 ** 20
-    # padding adds whole 64-element blocks per plane
-    t = lbm.make_tuning(0, 0, 100)
+    # plane layout: padding adds whole 64-element blocks per plane
+    t = lbm.make_tuning(0, 0, 100, layout=lbm.LBM_LAYOUT_PLANES)
     assert lbm.lbm_workspace_bytes(_cfg(lbm), t) == expect + 2 * 9 * 128 * 8
+    # row-interleaved layout (default): each population run padded to 64 elements
+    e70 = lbm.lbm_workspace_bytes(_cfg(lbm, shape=(70, 32)))
+    assert e70 == 2 * 9 * 128 * 32 * 8 + 256 + 256 + ((9 * 7 * 8 + 255) // 256) * 256
+    # below 64 the run is not padded
+    assert lbm.lbm_workspace_bytes(_cfg(lbm, shape=(5, 3))) == 2 * 1280 + 256 + 256 + 256  # 1080 B buffers, 256-aligned
 
 
 @pytest.mark.parametrize("bad", [
@@ -81,9 +86,19 @@ def test_invalid_configs_are_rejected(lbm, bad):
     assert lbm.lbm_workspace_bytes(_cfg(lbm, **bad)) == 0
 
 
-@pytest.mark.parametrize("tun", [(48, 4, 0), (64, 8, 0), (3, 64, 0), (64, 5, 0), (64, 4, 1 << 21)])
+@pytest.mark.parametrize("tun", [(48, 4, 0), (64, 8, 0), (3, 64, 0), (64, 5, 0), (64, 4, 1 << 21, 1, 0, 2),
+                                 (64, 4, 0, 3), (64, 4, 0, 4), (64, 4, 0, 2, 2), (64, 4, 0, 2, 4), (64, 4, 0, 1, 1),
+                                 (32, 8, 0, 2, 1), (0, 0, -1, 0, -1, 3)])
 def test_invalid_tuning_rejected(lbm, tun):
+    # cfg: D2Q9 FP64 64 x 32 (4 nodes per thread needs FP32; 64 * 2 does not divide 64)
     assert lbm.lbm_workspace_bytes(_cfg(lbm), lbm.make_tuning(*tun)) == 0
+
+
+def test_valid_tunings_accepted(lbm):
+    cfg = _cfg(lbm, shape=(256, 8), dtype="fp32_dev")
+    for tun in [(0, 0, -1, 0, -1, 0), (64, 4, 0, 4, 3, 1), (64, 1, 0, 2, 1, 2), (128, 2, 64, 2, 0, 2),
+                (256, 1, 0, 1, 0, 1), (32, 8, 0, 1, 0, 0)]:
+        assert lbm.lbm_workspace_bytes(cfg, lbm.make_tuning(*tun)) > 0, tun
 
 
 def test_create_argument_checks_precede_gpu_work(lbm):

@@ -203,14 +203,15 @@ def test_translation_equivariance_bitwise(dtype):
     assert np.array_equal(np.roll(f1, sh, axis=(1, 2, 3)), f2)
 
 
-SCALAR_TUNINGS = [(0, 0, -1, 1, 0), (64, 4, 0, 1, 0), (128, 2, 64, 1, 0), (256, 1, 4096, 1, 0),
-                  (32, 8, 128, 1, 0), (64, 1, 0, 1, 0)]
-VECTOR_TUNINGS = [(64, 4, 0, 2, 0), (64, 1, 64, 2, 1), (128, 2, 0, 2, 3), (64, 4, 0, 4, 0), (64, 2, 0, 4, 1),
-                  (64, 4, 256, 4, 3), (128, 1, 0, 4, 1), (0, 0, -1, 0, -1)]
+# (block_x, block_y, plane_pad, nodes_per_thread, flags, layout): layout 1 = rows, 2 = planes
+SCALAR_TUNINGS = [(0, 0, -1, 1, 0, 1), (64, 4, 0, 1, 0, 2), (128, 2, 64, 1, 0, 2), (256, 1, 4096, 1, 0, 2),
+                  (32, 8, 128, 1, 0, 1), (64, 1, 0, 1, 0, 1)]
+VECTOR_TUNINGS = [(64, 4, 0, 2, 0, 1), (64, 1, 64, 2, 1, 2), (128, 2, 0, 2, 3, 1), (64, 4, 0, 4, 0, 2),
+                  (64, 2, 0, 4, 1, 1), (64, 4, 256, 4, 3, 2), (128, 1, 0, 4, 1, 1), (0, 0, -1, 0, -1, 0)]
 
 
-@pytest.mark.parametrize("lattice,grid", [(9, (5, 256)), (9, (4, 512)), (9, (3, 1024)),
-                                          (27, (2, 3, 256)), (27, (3, 2, 512)), (27, (2, 2, 128))])
+@pytest.mark.parametrize("lattice,grid", [(9, (5, 256)), (9, (4, 512)), (9, (3, 1024)), (9, (7, 70)),
+                                          (27, (2, 3, 256)), (27, (3, 2, 512)), (27, (2, 2, 128)), (27, (3, 4, 33))])
 @pytest.mark.parametrize("dtype", DTYPES + ABLATION)
 def test_tuning_invariance_bitwise(lattice, grid, dtype):
     """Every launch shape and kernel variant (one node per thread, 2 or 4 nodes
@@ -221,13 +222,13 @@ def test_tuning_invariance_bitwise(lattice, grid, dtype):
     base = None
     nx = grid[-1]
     ran = 0
-    for bx, by, pad, npt, flags in SCALAR_TUNINGS + VECTOR_TUNINGS:
+    for bx, by, pad, npt, flags, layout in SCALAR_TUNINGS + VECTOR_TUNINGS:
         if npt == 4 and dtype == "fp64":
             continue
         if npt > 1 and nx % (bx * npt) != 0:
             continue
         rho, u, _, f = run_gpu(rho0, u0, 0.55, 5, dtype, True,
-                               tuning=lbm.make_tuning(bx, by, pad, npt, flags), populations=True)
+                               tuning=lbm.make_tuning(bx, by, pad, npt, flags, layout), populations=True)
         ran += 1
         if base is None:
             base = (rho, u, f)
@@ -236,7 +237,7 @@ def test_tuning_invariance_bitwise(lattice, grid, dtype):
             assert rel_err(rho, r_ref) < tol and rel_err(u, u_ref) < tol
         else:
             assert np.array_equal(base[0], rho) and np.array_equal(base[1], u) and np.array_equal(base[2], f), \
-                (bx, by, pad, npt, flags)
+                (bx, by, pad, npt, flags, layout)
     assert ran >= 7
 
 
