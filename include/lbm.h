@@ -190,6 +190,91 @@ int lbm_destroy(lbm_handle *h);
 /* Static, human-readable name of a status code. */
 const char *lbm_status_string(int status);
 
+/* ---------------------------------------------------------------------------
+ * Pools: many independent domains advanced together (batching and serving).
+ *
+ * A pool owns no memory: the caller hands it one device arena, which the pool
+ * divides into a table region and slot workspaces (first-fit, coalescing free
+ * list).  A slot is one periodic domain (any lattice and dtype; its own tau,
+ * correction and step budget).  lbm_pool_run advances every active slot; one
+ * step of all slots of a (lattice, dtype) class is one kernel launch, or all
+ * steps of a run are one persistent cooperative launch with a device-side
+ * grid barrier between steps.  A slot's populations are bitwise the same as
+ * those of a single domain (lbm_create) with the same configuration and
+ * layout: every kernel uses the same per-node arithmetic.  Pools are not
+ * thread-safe; slots of one pool share its stream.
+ * ------------------------------------------------------------------------- */
+typedef struct lbm_pool lbm_pool;
+
+/* Pool tuning.  Zero fields take the defaults. */
+typedef struct lbm_pool_tuning {
+    int32_t tile_x;     /* threads (one node each) per workgroup along x (default 64) */
+    int32_t tile_y;     /* rows per workgroup (default 256 / tile_x); tile_x * tile_y a
+                           multiple of 64, <= 256 */
+    int32_t persistent; /* 1: one cooperative launch per run and class; 0: one launch per step */
+    int32_t workgroups; /* persistent grid size (0 = as many as are co-resident) */
+    int32_t layout;     /* LBM_LAYOUT_* of the slots (0 = row-interleaved) */
+    int32_t reserved[3];/* must be 0 */
+} lbm_pool_tuning;
+
+typedef struct lbm_pool_stats {
+    int32_t max_slots, used_slots;
+    int64_t arena_bytes, free_bytes, largest_free_block;
+    int64_t runs, launches;
+} lbm_pool_stats;
+
+typedef struct lbm_slot_info {
+    int32_t used;      /* 1 if the slot holds a domain */
+    int32_t finished;  /* 1 if its step budget is spent */
+    int64_t steps_done, steps_remaining;
+    int64_t bytes;     /* arena bytes held */
+} lbm_slot_info;
+
+/* Arena bytes the pool keeps for its tables (the rest holds slots). */
+size_t lbm_pool_table_bytes(int32_t max_slots);
+
+/* Arena bytes one slot of this configuration occupies (0 if invalid). */
+size_t lbm_pool_slot_bytes(const lbm_config *cfg, const lbm_pool_tuning *tuning);
+
+/* Create a pool of at most max_slots (1..65536) slots on `arena` (device
+ * pointer, 256-byte aligned, arena_bytes > lbm_pool_table_bytes(max_slots)),
+ * enqueuing on `stream`.  tuning may be NULL.  Errors: LBM_EINVAL,
+ * LBM_EDEVICE (pinned staging allocation, device query). */
+int lbm_pool_create(int32_t max_slots, const lbm_pool_tuning *tuning, void *arena, size_t arena_bytes,
+                    void *stream, lbm_pool **out);
+
+/* Admit a domain: initialise f = f^eq(rho, u) (device pointers as in
+ * lbm_create) in a free slot with a budget of nsteps steps.  Synchronises the
+ * stream.  Returns the slot index in *slot.  Errors: LBM_EBUSY (no free slot),
+ * LBM_ENOMEM (no free arena block large enough), LBM_EINVAL, LBM_EDOMAIN (the
+ * initial state; the slot is not taken), LBM_EDEVICE. */
+int lbm_pool_admit(lbm_pool *pool, const lbm_config *cfg, const double *rho, const double *u, int64_t nsteps,
+                   int32_t *slot);
+
+/* Advance every slot with steps remaining by min(k, remaining) steps.
+ * Enqueues and returns without synchronising.  k = 0 is a no-op. */
+int lbm_pool_run(lbm_pool *pool, int64_t k);
+
+/* Synchronise, then list (up to capacity) slots whose budget is spent and that
+ * were not listed before; *count receives how many were written.  Returns
+ * LBM_EDEVICE if a persistent launch's grid barrier timed out. */
+int lbm_pool_poll(lbm_pool *pool, int32_t *done, int32_t capacity, int32_t *count);
+
+/* Moments / populations of one slot, as lbm_moments / lbm_get_populations.
+ * LBM_EDOMAIN concerns this slot only. */
+int lbm_pool_moments(lbm_pool *pool, int32_t slot, double *rho, double *u, lbm_diag *diag);
+int lbm_pool_get_populations(lbm_pool *pool, int32_t slot, double *out);
+
+/* Free a slot and its arena block (synchronises first). */
+int lbm_pool_release(lbm_pool *pool, int32_t slot);
+
+int lbm_pool_stats_get(lbm_pool *pool, lbm_pool_stats *stats);
+int lbm_pool_slot_info(lbm_pool *pool, int32_t slot, lbm_slot_info *info);
+
+/* Synchronise and free the pool's host state (the arena is the caller's).
+ * lbm_pool_destroy(NULL) returns LBM_OK. */
+int lbm_pool_destroy(lbm_pool *pool);
+
 /* Message of the last error raised on the calling thread (static storage,
  * empty if none). */
 const char *lbm_last_error(void);

@@ -244,7 +244,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_vec(StepArgs a) {
 
 // Zero `count` 32-bit words (a kernel rather than a memset, so that the call
 // sequence stays valid inside captured HIP graphs).
-__global__ void k_clear_words(int *p, int count) {
+static __global__ void k_clear_words(int *p, int count) {
     for (int k = threadIdx.x; k < count; k += blockDim.x)
         p[k] = 0;
 }
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_moments(MomentArgs a) {
 }
 
 // Second pass: one workgroup folds the per-workgroup partials in a fixed order.
-__global__ __launch_bounds__(kReduceThreads) void k_reduce_partials(const double *partials, int count,
+static __global__ __launch_bounds__(kReduceThreads) void k_reduce_partials(const double *partials, int count,
                                                                     double *out) {
     double acc[kDiagFields] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, INFINITY};
     for (int b = threadIdx.x; b < count; b += blockDim.x) {

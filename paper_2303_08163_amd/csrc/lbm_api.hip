@@ -246,22 +246,110 @@ int launch_step(const Layout &L, const StepArgs &args, int dtype, bool corr, hip
     return LBM_OK;
 }
 
+int domain_bind_and_init(DomainState &d, const lbm_config *cfg, const Layout &L, void *workspace,
+                         const double *rho, const double *u, hipStream_t s) {
+    d.cfg = *cfg;
+    d.L = L;
+    d.ws = static_cast<char *>(workspace);
+    d.buf[0] = d.ws + L.off_buf[0];
+    d.buf[1] = d.ws + L.off_buf[1];
+    d.cur = 0;
+    d.flag = reinterpret_cast<int *>(d.ws + L.off_flag);
+    d.diag_dev = reinterpret_cast<double *>(d.ws + L.off_diag);
+    d.partials = reinterpret_cast<double *>(d.ws + L.off_partials);
+    d.steps = 0;
+    d.relax.omega = 1.0 / cfg->tau;
+    d.relax.two_tau_m1 = 2.0 * cfg->tau - 1.0;
+    d.relax.rho0 = cfg->dtype != LBM_FP64 ? cfg->rho0 : 0.0;
+
+    hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(64), 0, s, d.flag, 64);
+    InitArgs ia{d.buf[0], rho, u, L.n, (int)cfg->nx, L.ps, L.rs, d.relax.rho0, d.flag};
+    const bool dev = cfg->dtype != LBM_FP64;
+    dim3 grid((unsigned)((L.n + 255) / 256)), block(256);
+    void (*init_fn)(InitArgs) = L.dim == 2 ? (dev ? k_init<2, true> : k_init<2, false>)
+                                           : (dev ? k_init<3, true> : k_init<3, false>);
+    hipLaunchKernelGGL(init_fn, grid, block, 0, s, ia);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return hip_fail(e, "init launch");
+    return LBM_OK;
+}
+
+int domain_read_flag(const DomainState &d, hipStream_t s, int *flag) {
+    int f = 0;
+    hipError_t e = hipMemcpyAsync(&f, d.flag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(e, "domain flag read");
+    *flag = f;
+    return LBM_OK;
+}
+
+int domain_moments(DomainState &d, hipStream_t s, double *rho, double *u, lbm_diag *diag) {
+    const Layout &L = d.L;
+    const bool dev = d.cfg.dtype != LBM_FP64;
+    MomentArgs ma{d.buf[d.cur], rho, u, L.n, (int)d.cfg.nx, L.ps, L.rs, d.relax.rho0, d.partials};
+    dim3 grid((unsigned)L.red_blocks), block(kReduceThreads);
+    void (*mom_fn)(MomentArgs) = L.dim == 2 ? (dev ? k_moments<2, true> : k_moments<2, false>)
+                                            : (dev ? k_moments<3, true> : k_moments<3, false>);
+    hipLaunchKernelGGL(mom_fn, grid, block, 0, s, ma);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kReduceThreads), 0, s, (const double *)d.partials,
+                       L.red_blocks, d.diag_dev);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return hip_fail(e, "moments launch");
+    double v[kDiagFields];
+    int flag = 0;
+    e = hipMemcpyAsync(v, d.diag_dev, sizeof(v), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&flag, d.flag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(e, "moments synchronise");
+    if (diag) {
+        diag->mass = v[0];
+        diag->momentum[0] = v[1];
+        diag->momentum[1] = v[2];
+        diag->momentum[2] = v[3];
+        diag->kinetic_energy = v[4];
+        diag->max_abs_u = v[5];
+        diag->min_rho = v[6];
+        diag->steps = d.steps;
+        diag->domain_error = flag ? 1 : 0;
+        diag->reserved = 0;
+    }
+    if (flag) {
+        set_error("a node left rho > 0, |u_alpha| < 1");
+        return LBM_EDOMAIN;
+    }
+    return LBM_OK;
+}
+
+int domain_export(DomainState &d, hipStream_t s, double *out) {
+    const Layout &L = d.L;
+    const bool dev = d.cfg.dtype != LBM_FP64;
+    ExportArgs ea{d.buf[d.cur], out, L.n, (int)d.cfg.nx, L.ps, L.rs, d.relax.rho0};
+    dim3 grid((unsigned)((L.n + 255) / 256)), block(256);
+    void (*exp_fn)(ExportArgs) = L.dim == 2 ? (dev ? k_export<2, true> : k_export<2, false>)
+                                            : (dev ? k_export<3, true> : k_export<3, false>);
+    hipLaunchKernelGGL(exp_fn, grid, block, 0, s, ea);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(e, "population export");
+    return LBM_OK;
+}
+
 }  // namespace lbm
 
 using namespace lbm;
 
 struct lbm_handle {
-    lbm_config cfg;
-    Layout L;
-    char *ws;
-    void *buf[2];
-    int cur;
-    int *flag;
-    double *diag_dev;
-    double *partials;
+    DomainState d;
     hipStream_t stream;
-    int64_t steps;
-    Relax relax;
 };
 
 extern "C" {
@@ -298,45 +386,14 @@ int lbm_create_tuned(const lbm_config *cfg, const lbm_tuning *tuning, void *work
         set_error("host allocation failed");
         return LBM_EINVAL;
     }
-    h->cfg = *cfg;
-    h->L = L;
-    h->ws = static_cast<char *>(workspace);
-    h->buf[0] = h->ws + L.off_buf[0];
-    h->buf[1] = h->ws + L.off_buf[1];
-    h->cur = 0;
-    h->flag = reinterpret_cast<int *>(h->ws + L.off_flag);
-    h->diag_dev = reinterpret_cast<double *>(h->ws + L.off_diag);
-    h->partials = reinterpret_cast<double *>(h->ws + L.off_partials);
     h->stream = static_cast<hipStream_t>(stream);
-    h->steps = 0;
-    h->relax.omega = 1.0 / cfg->tau;
-    h->relax.two_tau_m1 = 2.0 * cfg->tau - 1.0;
-    h->relax.rho0 = cfg->dtype != LBM_FP64 ? cfg->rho0 : 0.0;
-
-    hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(64), 0, h->stream, h->flag, 64);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) {
-        delete h;
-        return hip_fail(e, "clearing the domain flag");
-    }
-    InitArgs ia{h->buf[0], rho, u, L.n, (int)cfg->nx, L.ps, L.rs, h->relax.rho0, h->flag};
-    const bool dev = cfg->dtype != LBM_FP64;
-    dim3 grid((unsigned)((L.n + 255) / 256)), block(256);
-    void (*init_fn)(InitArgs) = L.dim == 2 ? (dev ? k_init<2, true> : k_init<2, false>)
-                                           : (dev ? k_init<3, true> : k_init<3, false>);
-    hipLaunchKernelGGL(init_fn, grid, block, 0, h->stream, ia);
-    e = hipGetLastError();
-    if (e != hipSuccess) {
-        delete h;
-        return hip_fail(e, "init launch");
-    }
     int flag = 0;
-    e = hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess)
-        e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) {
+    rc = domain_bind_and_init(h->d, cfg, L, workspace, rho, u, h->stream);
+    if (rc == LBM_OK)
+        rc = domain_read_flag(h->d, h->stream, &flag);
+    if (rc != LBM_OK) {
         delete h;
-        return hip_fail(e, "init synchronise");
+        return rc;
     }
     if (flag) {
         delete h;
@@ -357,24 +414,18 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
         set_error("NULL handle or negative step count");
         return LBM_EINVAL;
     }
-    const bool corr = h->cfg.bulk_correction != 0;
+    DomainState &d = h->d;
+    const bool corr = d.cfg.bulk_correction != 0;
+    const int tiles_x = (int)((d.cfg.nx + (int64_t)d.L.block_x * d.L.npt - 1) / ((int64_t)d.L.block_x * d.L.npt));
+    const int tiles_y = (int)((d.cfg.ny + d.L.block_y - 1) / d.L.block_y);
     for (int64_t s = 0; s < nsteps; ++s) {
-        StepArgs a{h->buf[h->cur],
-                   h->buf[h->cur ^ 1],
-                   (int)h->cfg.nx,
-                   (int)h->cfg.ny,
-                   (int)h->cfg.nz,
-                   (int)((h->cfg.nx + (int64_t)h->L.block_x * h->L.npt - 1) / ((int64_t)h->L.block_x * h->L.npt)),
-                   (int)((h->cfg.ny + h->L.block_y - 1) / h->L.block_y),
-                   h->L.ps,
-                   h->L.rs,
-                   h->relax,
-                   h->flag};
-        int rc = launch_step(h->L, a, h->cfg.dtype, corr, h->stream, (int)h->cfg.nz);
+        StepArgs a{d.buf[d.cur], d.buf[d.cur ^ 1], (int)d.cfg.nx, (int)d.cfg.ny, (int)d.cfg.nz, tiles_x, tiles_y,
+                   d.L.ps, d.L.rs, d.relax, d.flag};
+        int rc = launch_step(d.L, a, d.cfg.dtype, corr, h->stream, (int)d.cfg.nz);
         if (rc != LBM_OK)
             return rc;
-        h->cur ^= 1;
-        h->steps++;
+        d.cur ^= 1;
+        d.steps++;
     }
     return LBM_OK;
 }
@@ -384,44 +435,7 @@ int lbm_moments(lbm_handle *h, double *rho, double *u, lbm_diag *diag) {
         set_error("NULL handle");
         return LBM_EINVAL;
     }
-    const Layout &L = h->L;
-    const bool dev = h->cfg.dtype != LBM_FP64;
-    MomentArgs ma{h->buf[h->cur], rho, u, L.n, (int)h->cfg.nx, L.ps, L.rs, h->relax.rho0, h->partials};
-    dim3 grid((unsigned)L.red_blocks), block(kReduceThreads);
-    void (*mom_fn)(MomentArgs) = L.dim == 2 ? (dev ? k_moments<2, true> : k_moments<2, false>)
-                                            : (dev ? k_moments<3, true> : k_moments<3, false>);
-    hipLaunchKernelGGL(mom_fn, grid, block, 0, h->stream, ma);
-    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kReduceThreads), 0, h->stream,
-                       (const double *)h->partials, L.red_blocks, h->diag_dev);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return hip_fail(e, "moments launch");
-    double d[kDiagFields];
-    int flag = 0;
-    e = hipMemcpyAsync(d, h->diag_dev, sizeof(d), hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess)
-        e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess)
-        return hip_fail(e, "moments synchronise");
-    if (diag) {
-        diag->mass = d[0];
-        diag->momentum[0] = d[1];
-        diag->momentum[1] = d[2];
-        diag->momentum[2] = d[3];
-        diag->kinetic_energy = d[4];
-        diag->max_abs_u = d[5];
-        diag->min_rho = d[6];
-        diag->steps = h->steps;
-        diag->domain_error = flag ? 1 : 0;
-        diag->reserved = 0;
-    }
-    if (flag) {
-        set_error("a node left rho > 0, |u_alpha| < 1");
-        return LBM_EDOMAIN;
-    }
-    return LBM_OK;
+    return domain_moments(h->d, h->stream, rho, u, diag);
 }
 
 int lbm_get_populations(lbm_handle *h, double *out) {
@@ -429,19 +443,7 @@ int lbm_get_populations(lbm_handle *h, double *out) {
         set_error("NULL handle or output");
         return LBM_EINVAL;
     }
-    const Layout &L = h->L;
-    const bool dev = h->cfg.dtype != LBM_FP64;
-    ExportArgs ea{h->buf[h->cur], out, L.n, (int)h->cfg.nx, L.ps, L.rs, h->relax.rho0};
-    dim3 grid((unsigned)((L.n + 255) / 256)), block(256);
-    void (*exp_fn)(ExportArgs) = L.dim == 2 ? (dev ? k_export<2, true> : k_export<2, false>)
-                                            : (dev ? k_export<3, true> : k_export<3, false>);
-    hipLaunchKernelGGL(exp_fn, grid, block, 0, h->stream, ea);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess)
-        e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess)
-        return hip_fail(e, "population export");
-    return LBM_OK;
+    return domain_export(h->d, h->stream, out);
 }
 
 int lbm_destroy(lbm_handle *h) {
@@ -475,6 +477,6 @@ const char *lbm_status_string(int status) {
 
 const char *lbm_last_error(void) { return g_last_error; }
 
-const char *lbm_version(void) { return "lbm-entropic 0.1 (gfx950)"; }
+const char *lbm_version(void) { return "lbm-entropic 0.2 (gfx950)"; }
 
 }  // extern "C"

@@ -27,9 +27,32 @@ struct Layout {
     size_t off_buf[2], off_flag, off_diag, off_partials, ws_bytes;
 };
 
+// One domain's state inside a workspace (owned by a handle or a pool slot).
+struct DomainState {
+    lbm_config cfg;
+    Layout L;
+    char *ws;
+    void *buf[2];
+    int cur;  // buffer holding the current state
+    int *flag;
+    double *diag_dev;
+    double *partials;
+    int64_t steps;
+    Relax relax;
+};
+
 void set_error(const char *msg);
 int hip_fail(hipError_t e, const char *what);
 int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out);
 int launch_step(const Layout &L, const StepArgs &args, int dtype, bool corr, hipStream_t s, int nz);
+
+// Bind a domain to its workspace and enqueue f = f^eq(rho, u) plus the flag
+// clear; the caller synchronises and reads the flag (domain_read_flag).
+int domain_bind_and_init(DomainState &d, const lbm_config *cfg, const Layout &L, void *workspace,
+                         const double *rho, const double *u, hipStream_t s);
+// Synchronise the stream and return the domain flag (0/1) in *flag.
+int domain_read_flag(const DomainState &d, hipStream_t s, int *flag);
+int domain_moments(DomainState &d, hipStream_t s, double *rho, double *u, lbm_diag *diag);
+int domain_export(DomainState &d, hipStream_t s, double *out);
 
 }  // namespace lbm

@@ -1,0 +1,151 @@
+// pool_kernels.hpp -- kernels that advance many independent domains together.
+//
+// A pool holds slots; each slot is one periodic domain with its own two
+// population buffers.  For a run, the active slots of one (lattice, storage)
+// class are listed in order of decreasing remaining steps, with the running
+// sum of their workgroup tiles.  At step s of the run exactly the slots with
+// more than s remaining steps are active, and they form a prefix of the list,
+// so the active tiles are [0, P(s)).  A workgroup finds its slot by binary
+// search in the running sum.  Every node goes through the same step_node
+// function as the single-domain kernels, so a slot's populations are bitwise
+// the same as when it runs alone.
+//
+// Two launch forms:
+//   - one kernel launch per step over the active prefix (the kernel boundary
+//     orders the steps);
+//   - one persistent cooperative launch for all steps of a run: each
+//     workgroup takes a contiguous share of the active prefix, then waits at a
+//     grid barrier before the next step.  The barrier spins on a device
+//     counter with a bound; past the bound it raises an error flag that makes
+//     every workgroup leave, so the grid always drains.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.hpp"
+
+namespace lbm {
+
+struct SlotDesc {
+    void *buf[2];
+    int nx, ny, nz;
+    int tiles_x, tiles_y;
+    int parity;  // buffer holding the state at the start of the run
+    int corr;    // bulk correction on/off
+    int pad_;
+    int64_t ps, rs;
+    Relax relax;
+    int *flag;
+};
+
+struct PoolRunArgs {
+    const SlotDesc *slots;    // n slots, remaining steps decreasing
+    const int *tile_start;    // n + 1 running tile counts, tile_start[0] = 0
+    const int64_t *remaining; // n remaining step counts at the start of the run
+    int n;
+    int step0;                // first step of this launch within the run
+    int nsteps;               // steps done by this launch
+    unsigned *barrier;        // persistent form: arrival counter, zero at launch
+    int *error;               // persistent form: set on a barrier timeout
+    long long spin_limit;
+};
+
+// Active tiles at step s: the tile count of the slots with remaining > s.
+__device__ __forceinline__ int active_tiles(const PoolRunArgs &a, int s) {
+    int lo = 0, hi = a.n;  // first index with remaining <= s
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a.remaining[mid] > s)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return a.tile_start[lo];
+}
+
+template <int DIM, int DT>
+__device__ __forceinline__ void pool_tile(const PoolRunArgs &a, int t, int s) {
+    int lo = 0, hi = a.n - 1;  // last slot k with tile_start[k] <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.tile_start[mid] <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const SlotDesc &d = a.slots[lo];
+    const int tile = t - a.tile_start[lo];
+    const int tx = tile % d.tiles_x;
+    const int ty = (tile / d.tiles_x) % d.tiles_y;
+    const int z = tile / (d.tiles_x * d.tiles_y);
+    const int x = tx * (int)blockDim.x + (int)threadIdx.x;
+    const int y = ty * (int)blockDim.y + (int)threadIdx.y;
+    if (x >= d.nx || y >= d.ny)
+        return;
+    const int p = (d.parity + s) & 1;
+    using T = store_t<DT>;
+    const T *src = static_cast<const T *>(d.buf[p]);
+    T *dst = static_cast<T *>(d.buf[p ^ 1]);
+    if (d.corr)
+        step_node<DIM, DT, true>(src, dst, d.nx, d.ny, d.nz, d.ps, d.rs, d.relax, d.flag, x, y, z);
+    else
+        step_node<DIM, DT, false>(src, dst, d.nx, d.ny, d.nz, d.ps, d.rs, d.relax, d.flag, x, y, z);
+}
+
+// One step (a.step0) over the active prefix; grid = its tile count.
+template <int DIM, int DT>
+__global__ __launch_bounds__(256) void k_pool_step(PoolRunArgs a) {
+    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    pool_tile<DIM, DT>(a, t, a.step0);
+}
+
+// Bounded grid barrier.  A workgroup-scope barrier does not wait for stores,
+// so every wave first waits for its own; one thread then writes the XCD's L2
+// back (agent-scope release), arrives, and spins; after it, every wave drops
+// stale L1/L2 lines (agent-scope acquire).  Returns false when the wait
+// timed out or another workgroup reported a timeout; the caller then leaves.
+__device__ __forceinline__ bool grid_barrier(unsigned *counter, unsigned target, int *error, long long spin_limit) {
+    __shared__ int ok;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int good = 1;
+        long long spins = 0;
+        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                ++spins > spin_limit) {
+                __hip_atomic_fetch_or(error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                good = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        ok = good;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return ok != 0;
+}
+
+// All nsteps steps of a run in one cooperative launch.  Workgroup w covers
+// the contiguous share [L P / G, (L + 1) P / G) of the P active tiles, with
+// L = xcd_tile(w, G) so that each XCD walks one contiguous range.
+template <int DIM, int DT>
+__global__ __launch_bounds__(256) void k_pool_persistent(PoolRunArgs a) {
+    const int G = (int)gridDim.x;
+    const int L = xcd_tile((int)blockIdx.x, G);
+    for (int s = 0; s < a.nsteps; ++s) {
+        const int step = a.step0 + s;
+        const int P = active_tiles(a, step);
+        const int lo = (int)(((int64_t)L * P) / G), hi = (int)(((int64_t)(L + 1) * P) / G);
+        for (int t = lo; t < hi; ++t)
+            pool_tile<DIM, DT>(a, t, step);
+        if (s + 1 < a.nsteps && !grid_barrier(a.barrier, (unsigned)G * (unsigned)(s + 1), a.error, a.spin_limit))
+            return;
+    }
+}
+
+}  // namespace lbm

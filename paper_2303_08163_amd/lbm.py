@@ -56,6 +56,28 @@ class lbm_diag(ctypes.Structure):
                 "domain_error": bool(self.domain_error)}
 
 
+class lbm_pool_tuning(ctypes.Structure):
+    _fields_ = [("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("workgroups", ctypes.c_int32), ("layout", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class lbm_pool_stats(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int32), ("used_slots", ctypes.c_int32),
+                ("arena_bytes", ctypes.c_int64), ("free_bytes", ctypes.c_int64),
+                ("largest_free_block", ctypes.c_int64), ("runs", ctypes.c_int64), ("launches", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class lbm_slot_info(ctypes.Structure):
+    _fields_ = [("used", ctypes.c_int32), ("finished", ctypes.c_int32), ("steps_done", ctypes.c_int64),
+                ("steps_remaining", ctypes.c_int64), ("bytes", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class LBMError(RuntimeError):
     def __init__(self, status: int, where: str, message: str = ""):
         self.status = status
@@ -71,7 +93,9 @@ _lib = None
 # Exported symbols the header declares (checked by the CPU test suite).
 EXPORTS = ("lbm_workspace_bytes", "lbm_workspace_bytes_tuned", "lbm_create", "lbm_create_tuned",
            "lbm_step", "lbm_moments", "lbm_get_populations", "lbm_destroy", "lbm_status_string",
-           "lbm_last_error", "lbm_version")
+           "lbm_last_error", "lbm_version", "lbm_pool_table_bytes", "lbm_pool_slot_bytes", "lbm_pool_create",
+           "lbm_pool_admit", "lbm_pool_run", "lbm_pool_poll", "lbm_pool_moments", "lbm_pool_get_populations",
+           "lbm_pool_release", "lbm_pool_stats_get", "lbm_pool_slot_info", "lbm_pool_destroy")
 
 
 def load_library(path: str = LIB_PATH):
@@ -104,6 +128,20 @@ def load_library(path: str = LIB_PATH):
         "lbm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "lbm_last_error": (ctypes.c_char_p, []),
         "lbm_version": (ctypes.c_char_p, []),
+        "lbm_pool_table_bytes": (sz, [ctypes.c_int32]),
+        "lbm_pool_slot_bytes": (sz, [cfgp, ctypes.POINTER(lbm_pool_tuning)]),
+        "lbm_pool_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(lbm_pool_tuning), vp, sz, vp,
+                                           ctypes.POINTER(vp)]),
+        "lbm_pool_admit": (ctypes.c_int, [vp, cfgp, vp, vp, i64, ctypes.POINTER(ctypes.c_int32)]),
+        "lbm_pool_run": (ctypes.c_int, [vp, i64]),
+        "lbm_pool_poll": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int32)]),
+        "lbm_pool_moments": (ctypes.c_int, [vp, ctypes.c_int32, vp, vp, ctypes.POINTER(lbm_diag)]),
+        "lbm_pool_get_populations": (ctypes.c_int, [vp, ctypes.c_int32, vp]),
+        "lbm_pool_release": (ctypes.c_int, [vp, ctypes.c_int32]),
+        "lbm_pool_stats_get": (ctypes.c_int, [vp, ctypes.POINTER(lbm_pool_stats)]),
+        "lbm_pool_slot_info": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(lbm_slot_info)]),
+        "lbm_pool_destroy": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -180,6 +218,82 @@ def lbm_get_populations(h, out: int) -> None:
 
 def lbm_destroy(h) -> None:
     _check(load_library().lbm_destroy(h), "lbm_destroy")
+
+
+def make_pool_tuning(tile_x=0, tile_y=0, persistent=0, workgroups=0, layout=0) -> lbm_pool_tuning:
+    t = lbm_pool_tuning()
+    t.tile_x, t.tile_y, t.persistent, t.workgroups, t.layout = (int(tile_x), int(tile_y), int(persistent),
+                                                                int(workgroups), int(layout))
+    return t
+
+
+def lbm_pool_table_bytes(max_slots: int) -> int:
+    return int(load_library().lbm_pool_table_bytes(int(max_slots)))
+
+
+def lbm_pool_slot_bytes(cfg: lbm_config, tuning: lbm_pool_tuning | None = None) -> int:
+    return int(load_library().lbm_pool_slot_bytes(ctypes.byref(cfg), ctypes.byref(tuning) if tuning else None))
+
+
+def lbm_pool_create(max_slots: int, arena: int, arena_bytes: int, stream: int = 0,
+                    tuning: lbm_pool_tuning | None = None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    st = load_library().lbm_pool_create(int(max_slots), ctypes.byref(tuning) if tuning else None, arena,
+                                        arena_bytes, stream, ctypes.byref(h))
+    _check(st, "lbm_pool_create")
+    return h
+
+
+def lbm_pool_admit(pool, cfg: lbm_config, rho: int, u: int, nsteps: int) -> int:
+    """Returns the slot index; raises LBMError (status LBM_EBUSY / LBM_ENOMEM when not admissible)."""
+    slot = ctypes.c_int32(-1)
+    _check(load_library().lbm_pool_admit(pool, ctypes.byref(cfg), rho, u, int(nsteps), ctypes.byref(slot)),
+           "lbm_pool_admit")
+    return int(slot.value)
+
+
+def lbm_pool_run(pool, k: int) -> None:
+    _check(load_library().lbm_pool_run(pool, int(k)), "lbm_pool_run")
+
+
+def lbm_pool_poll(pool, capacity: int = 65536) -> list:
+    buf = (ctypes.c_int32 * max(1, capacity))()
+    n = ctypes.c_int32(0)
+    _check(load_library().lbm_pool_poll(pool, buf, int(capacity), ctypes.byref(n)), "lbm_pool_poll")
+    return [int(buf[i]) for i in range(n.value)]
+
+
+def lbm_pool_moments(pool, slot: int, rho: int | None, u: int | None, raise_on_domain: bool = True) -> lbm_diag:
+    d = lbm_diag()
+    st = load_library().lbm_pool_moments(pool, int(slot), rho, u, ctypes.byref(d))
+    if st == LBM_EDOMAIN and not raise_on_domain:
+        return d
+    _check(st, "lbm_pool_moments")
+    return d
+
+
+def lbm_pool_get_populations(pool, slot: int, out: int) -> None:
+    _check(load_library().lbm_pool_get_populations(pool, int(slot), out), "lbm_pool_get_populations")
+
+
+def lbm_pool_release(pool, slot: int) -> None:
+    _check(load_library().lbm_pool_release(pool, int(slot)), "lbm_pool_release")
+
+
+def lbm_pool_stats_get(pool) -> dict:
+    st = lbm_pool_stats()
+    _check(load_library().lbm_pool_stats_get(pool, ctypes.byref(st)), "lbm_pool_stats_get")
+    return st.as_dict()
+
+
+def lbm_pool_slot_info(pool, slot: int) -> dict:
+    info = lbm_slot_info()
+    _check(load_library().lbm_pool_slot_info(pool, int(slot), ctypes.byref(info)), "lbm_pool_slot_info")
+    return info.as_dict()
+
+
+def lbm_pool_destroy(pool) -> None:
+    _check(load_library().lbm_pool_destroy(pool), "lbm_pool_destroy")
 
 
 def lbm_status_string(status: int) -> str:
@@ -261,6 +375,110 @@ class Domain:
             lbm_destroy(self.handle)
             self.handle = None
             self._ws = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Pool:
+    """A pool of slots on one device arena (a torch uint8 tensor of arena_bytes).
+
+    admit() copies the initial fields (numpy, shapes as for Domain) to the
+    device and starts a slot with a step budget; run(k) advances every active
+    slot by up to k steps; poll() lists finished slots.
+    """
+
+    def __init__(self, arena_bytes: int, max_slots: int = 1024, tuning: lbm_pool_tuning | None = None,
+                 stream=None, device="cuda:0"):
+        import torch
+        load_library()
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.max_slots = int(max_slots)
+        self.tuning = tuning
+        self.arena_bytes = int(arena_bytes)
+        self._arena = torch.empty(self.arena_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = (self._arena.data_ptr() + 255) // 256 * 256
+        self.handle = lbm_pool_create(self.max_slots, base, self.arena_bytes, self.stream.cuda_stream, tuning)
+        self.shapes = {}
+
+    def slot_bytes(self, shape, tau=0.6, dtype="fp32_dev", bulk_correction=False, rho0=1.0) -> int:
+        lattice = LBM_D2Q9 if len(shape) == 2 else LBM_D3Q27
+        return lbm_pool_slot_bytes(make_config(lattice, shape[::-1], tau, dtype, bulk_correction, rho0), self.tuning)
+
+    def admit(self, rho, u, tau: float, nsteps: int, dtype="fp32_dev", bulk_correction=False,
+              rho0: float = 1.0) -> int:
+        import torch
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        D = rho.ndim
+        if D not in (2, 3) or u.shape != (D,) + rho.shape:
+            raise ValueError("rho must be 2-D or 3-D and u of shape (D, *rho.shape)")
+        cfg = make_config(LBM_D2Q9 if D == 2 else LBM_D3Q27, rho.shape[::-1], tau, dtype, bulk_correction, rho0)
+        with torch.cuda.stream(self.stream):
+            rho_d = torch.from_numpy(rho).to(self.device, non_blocking=False)
+            u_d = torch.from_numpy(u).to(self.device, non_blocking=False)
+        slot = lbm_pool_admit(self.handle, cfg, rho_d.data_ptr(), u_d.data_ptr(), nsteps)
+        self.shapes[slot] = rho.shape
+        return slot
+
+    def try_admit(self, *args, **kw):
+        """admit(), but None instead of an error when no slot or memory is free."""
+        try:
+            return self.admit(*args, **kw)
+        except LBMError as e:
+            if e.status in (LBM_EBUSY, LBM_ENOMEM):
+                return None
+            raise
+
+    def run(self, k: int) -> None:
+        lbm_pool_run(self.handle, k)
+
+    def poll(self) -> list:
+        return lbm_pool_poll(self.handle, self.max_slots)
+
+    def moments(self, slot: int, fields: bool = True, raise_on_domain: bool = True):
+        import torch
+        if not fields:
+            return None, None, lbm_pool_moments(self.handle, slot, None, None, raise_on_domain).as_dict()
+        shape = self.shapes[slot]
+        rho_d = torch.empty(shape, dtype=torch.float64, device=self.device)
+        u_d = torch.empty((len(shape),) + shape, dtype=torch.float64, device=self.device)
+        d = lbm_pool_moments(self.handle, slot, rho_d.data_ptr(), u_d.data_ptr(), raise_on_domain)
+        return rho_d.cpu().numpy(), u_d.cpu().numpy(), d.as_dict()
+
+    def populations(self, slot: int):
+        import torch
+        shape = self.shapes[slot]
+        Q = 9 if len(shape) == 2 else 27
+        out = torch.empty((Q,) + shape, dtype=torch.float64, device=self.device)
+        lbm_pool_get_populations(self.handle, slot, out.data_ptr())
+        return out.cpu().numpy()
+
+    def release(self, slot: int) -> None:
+        lbm_pool_release(self.handle, slot)
+        self.shapes.pop(slot, None)
+
+    def stats(self) -> dict:
+        return lbm_pool_stats_get(self.handle)
+
+    def slot_info(self, slot: int) -> dict:
+        return lbm_pool_slot_info(self.handle, slot)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None:
+            lbm_pool_destroy(self.handle)
+            self.handle = None
+            self._arena = None
 
     def __enter__(self):
         return self

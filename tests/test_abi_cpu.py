@@ -133,3 +133,32 @@ def test_product_package_never_touches_the_oracle():
         if fn.endswith((".py", ".c", ".h")):
             text = open(os.path.join(ROOT, "oracle", fn)).read()
             assert "paper_2303_08163_amd" not in text and "lbm.h" not in text, fn
+
+
+def test_pool_host_logic(lbm):
+    lib = lbm.load_library()
+    assert lbm.lbm_pool_table_bytes(0) == 0 and lbm.lbm_pool_table_bytes(65537) == 0
+    t16 = lbm.lbm_pool_table_bytes(16)
+    assert t16 > 0 and t16 % 256 == 0 and lbm.lbm_pool_table_bytes(32) > t16
+    cfg = _cfg(lbm)
+    # a slot occupies exactly one domain workspace with the pool's tile
+    assert lbm.lbm_pool_slot_bytes(cfg) == lbm.lbm_workspace_bytes(cfg, lbm.make_tuning(64, 4, -1, 1, 0))
+    assert lbm.lbm_pool_slot_bytes(_cfg(lbm, tau=0.5)) == 0
+    for bad in [dict(tile_x=48, tile_y=4), dict(tile_x=64, tile_y=8), dict(persistent=2), dict(workgroups=-1),
+                dict(layout=5)]:
+        assert lbm.lbm_pool_slot_bytes(cfg, lbm.make_pool_tuning(**bad)) == 0, bad
+    h = ctypes.c_void_p()
+    assert lib.lbm_pool_create(4, None, None, 1 << 30, None, ctypes.byref(h)) == lbm.LBM_EINVAL
+    assert lib.lbm_pool_create(0, None, 256, 1 << 30, None, ctypes.byref(h)) == lbm.LBM_EINVAL
+    assert lib.lbm_pool_create(4, None, 256, 1024, None, ctypes.byref(h)) == lbm.LBM_EINVAL  # arena too small
+    assert lib.lbm_pool_create(4, None, 260, 1 << 30, None, ctypes.byref(h)) == lbm.LBM_EINVAL  # misaligned
+    assert h.value is None
+    slot = ctypes.c_int32()
+    n = ctypes.c_int32()
+    assert lib.lbm_pool_admit(None, ctypes.byref(cfg), 8, 8, 1, ctypes.byref(slot)) == lbm.LBM_EINVAL
+    assert lib.lbm_pool_run(None, 1) == lbm.LBM_EINVAL
+    assert lib.lbm_pool_poll(None, None, 0, ctypes.byref(n)) == lbm.LBM_EINVAL
+    assert lib.lbm_pool_moments(None, 0, None, None, None) == lbm.LBM_EINVAL
+    assert lib.lbm_pool_release(None, 0) == lbm.LBM_EINVAL
+    assert lib.lbm_pool_stats_get(None, None) == lbm.LBM_EINVAL
+    assert lib.lbm_pool_destroy(None) == lbm.LBM_OK

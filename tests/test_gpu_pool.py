@@ -1,0 +1,193 @@
+"""GPU tests of the pool (batching and serving): every slot's result equals the
+same domain run alone, bitwise, whatever the mix, the admission time, the
+launch form (one launch per step or one persistent cooperative launch) and the
+tile shape; admission limits; failure isolation; and oracle parity."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2303_08163_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+GiB = 1 << 30
+
+
+def _lbm():
+    from paper_2303_08163_amd import lbm
+    return lbm
+
+
+def alone(rho0, u0, tau, steps, dtype, corr):
+    lbm = _lbm()
+    with lbm.Domain(rho0, u0, tau, dtype=dtype, bulk_correction=corr) as d:
+        d.step(steps)
+        rho, u, diag = d.moments(raise_on_domain=False)
+        f = d.populations()
+    return rho, u, diag, f
+
+
+MIX = [  # (init fields, tau, steps, dtype, correction)
+    (lambda: workloads.taylor_green_2d(48, u0=0.08), 0.52, 37, "fp32_dev", False),
+    (lambda: workloads.random_field((33, 70), seed=1, umax=0.2), 0.6, 20, "fp64", True),
+    (lambda: workloads.taylor_green_3d(16, u0=0.07), 0.5005, 29, "fp32_dev", True),
+    (lambda: workloads.shear_wave(96, 130, 0.05), 0.51, 50, "fp32_dev", False),
+    (lambda: workloads.random_field((9, 11, 13), seed=2, umax=0.2), 0.7, 13, "fp64", False),
+    (lambda: workloads.random_field((5, 300), seed=3, umax=0.3), 0.55, 1, "fp32_dev", True),
+    (lambda: workloads.shear_wave(40, 40, 0.1, nz=24), 0.58, 0, "fp32_dev", False),
+]
+
+
+@pytest.fixture(scope="module")
+def alone_results():
+    out = []
+    for make, tau, steps, dtype, corr in MIX:
+        rho0, u0 = make()
+        out.append((rho0, u0, alone(rho0, u0, tau, steps, dtype, corr)))
+    return out
+
+
+@pytest.mark.parametrize("persistent", [0, 1])
+@pytest.mark.parametrize("tile", [(64, 4), (32, 2), (256, 1)])
+@pytest.mark.parametrize("chunk", [1000, 7])
+def test_pool_mix_equals_alone_bitwise(alone_results, persistent, tile, chunk):
+    lbm = _lbm()
+    tun = lbm.make_pool_tuning(tile[0], tile[1], persistent)
+    with lbm.Pool(GiB // 4, max_slots=16, tuning=tun) as pool:
+        slots = []
+        for (make, tau, steps, dtype, corr), (rho0, u0, _) in zip(MIX, alone_results):
+            slots.append(pool.admit(rho0, u0, tau, steps, dtype=dtype, bulk_correction=corr))
+        finished = set()
+        for _ in range(200):
+            pool.run(chunk)
+            finished |= set(pool.poll())
+            if len(finished) == len(slots):
+                break
+        assert finished == set(slots)
+        for s, (make, tau, steps, dtype, corr), (_, _, (rho, u, diag, f)) in zip(slots, MIX, alone_results):
+            r2, u2, d2 = pool.moments(s, raise_on_domain=False)
+            assert d2["steps"] == steps
+            assert np.array_equal(r2, rho) and np.array_equal(u2, u)
+            assert np.array_equal(pool.populations(s), f)
+        assert pool.stats()["launches"] > 0
+
+
+def test_pool_continuous_admission_equals_alone(alone_results):
+    """Requests admitted while others are mid-run, released as they finish."""
+    lbm = _lbm()
+    with lbm.Pool(GiB // 4, max_slots=3) as pool:
+        pending = list(range(len(MIX)))
+        active = {}
+        checked = 0
+        for _ in range(500):
+            while pending:
+                i = pending[0]
+                make, tau, steps, dtype, corr = MIX[i]
+                rho0, u0, _ = alone_results[i]
+                slot = pool.try_admit(rho0, u0, tau, steps, dtype=dtype, bulk_correction=corr)
+                if slot is None:
+                    break
+                active[slot] = i
+                pending.pop(0)
+            pool.run(5)
+            for slot in pool.poll():
+                i = active.pop(slot)
+                rho, u, _, _ = alone_results[i][2]
+                r2, u2, _ = pool.moments(slot, raise_on_domain=False)
+                assert np.array_equal(r2, rho) and np.array_equal(u2, u)
+                pool.release(slot)
+                checked += 1
+            if not pending and not active:
+                break
+        assert checked == len(MIX)
+        st = pool.stats()
+        assert st["used_slots"] == 0 and st["free_bytes"] == st["largest_free_block"]
+
+
+def test_pool_admission_limits():
+    lbm = _lbm()
+    rho0, u0 = workloads.taylor_green_2d(64)
+    with lbm.Pool(GiB // 16, max_slots=2) as pool:
+        a = pool.admit(rho0, u0, 0.6, 10)
+        b = pool.admit(rho0, u0, 0.6, 10)
+        with pytest.raises(lbm.LBMError) as e:
+            pool.admit(rho0, u0, 0.6, 10)
+        assert e.value.status == lbm.LBM_EBUSY
+        pool.release(a)
+        assert pool.try_admit(rho0, u0, 0.6, 10) is not None
+        assert pool.slot_info(b)["steps_remaining"] == 10
+    # arena budget: a slot larger than the free arena is refused with ENOMEM
+    big_r, big_u = workloads.taylor_green_3d(64)
+    need = lbm.lbm_pool_slot_bytes(lbm.make_config(27, (64, 64, 64), 0.6, "fp32_dev"))
+    with lbm.Pool(lbm.lbm_pool_table_bytes(4) + need + (1 << 20), max_slots=4) as pool:
+        s = pool.admit(big_r, big_u, 0.6, 5)
+        with pytest.raises(lbm.LBMError) as e:
+            pool.admit(big_r, big_u, 0.6, 5)
+        assert e.value.status == lbm.LBM_ENOMEM
+        pool.release(s)
+        pool.admit(big_r, big_u, 0.6, 5)
+
+
+def test_pool_failure_isolation():
+    """A slot whose state leaves the equilibrium's domain is flagged alone."""
+    lbm = _lbm()
+    good_r, good_u = workloads.taylor_green_2d(32, u0=0.05)
+    bad_r, bad_u = workloads.random_field((16, 16), seed=70, umax=0.99, rho_lo=0.3, rho_hi=2.0)
+    _, _, bad_count = oracle.run(bad_r, bad_u, 0.5001, 6)
+    assert bad_count > 0
+    with lbm.Pool(GiB // 16, max_slots=4) as pool:
+        g = pool.admit(good_r, good_u, 0.51, 6, dtype="fp64")
+        b = pool.admit(bad_r, bad_u, 0.5001, 6, dtype="fp64")
+        pool.run(6)
+        assert set(pool.poll()) == {g, b}
+        pool.moments(g)
+        with pytest.raises(lbm.LBMDomainError):
+            pool.moments(b)
+        # an initial state outside the domain is refused and takes no slot
+        u_bad = good_u.copy()
+        u_bad[0, 3, 3] = 1.5
+        with pytest.raises(lbm.LBMDomainError):
+            pool.admit(good_r, u_bad, 0.6, 5)
+        assert pool.stats()["used_slots"] == 2
+
+
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_pool_matches_oracle(persistent):
+    lbm = _lbm()
+    cases = [(workloads.random_field((13, 21), seed=5, umax=0.3), 0.53, 9, True),
+             (workloads.taylor_green_3d(10, u0=0.1), 0.6, 12, False),
+             (workloads.random_field((7, 50), seed=6, umax=0.4), 0.9, 17, True)]
+    with lbm.Pool(GiB // 16, max_slots=8, tuning=lbm.make_pool_tuning(persistent=persistent)) as pool:
+        slots = [pool.admit(r, u, tau, steps, dtype="fp64", bulk_correction=corr) for (r, u), tau, steps, corr in cases]
+        pool.run(100)
+        pool.poll()
+        for s, ((r0, u0), tau, steps, corr) in zip(slots, cases):
+            rho, u, _ = pool.moments(s)
+            r_ref, u_ref, _ = oracle.run(r0, u0, tau, steps, corr="min" if corr else "off")
+            assert np.max(np.abs(rho - r_ref)) / np.max(np.abs(r_ref)) < 1e-12
+            assert np.max(np.abs(u - u_ref)) / np.max(np.abs(u_ref)) < 1e-12
+
+
+def test_batched_workload_subset_matches_oracle_and_alone():
+    """Seeded subset of the batched shear-wave workload (D2Q9, Nx, Ny in
+    32..512, nu log-uniform): pool result == alone bitwise, and == oracle."""
+    lbm = _lbm()
+    specs = workloads.batch_domains(count=512, seed=2303)[:8]
+    steps = 60
+    with lbm.Pool(GiB, max_slots=16, tuning=lbm.make_pool_tuning(persistent=1)) as pool:
+        slots = []
+        fields = []
+        for sp in specs:
+            r0, u0 = workloads.shear_wave(sp["nx"], sp["ny"], sp["amp"])
+            fields.append((r0, u0))
+            slots.append(pool.admit(r0, u0, sp["tau"], steps, dtype="fp64"))
+        pool.run(steps)
+        assert set(pool.poll()) == set(slots)
+        oracle.set_threads(16)
+        for s, sp, (r0, u0) in zip(slots, specs, fields):
+            rho, u, _ = pool.moments(s)
+            ra, ua, _, _ = alone(r0, u0, sp["tau"], steps, "fp64", False)
+            assert np.array_equal(rho, ra) and np.array_equal(u, ua)
+            r_ref, u_ref, _ = oracle.run(r0, u0, sp["tau"], steps)
+            assert np.max(np.abs(rho - r_ref)) / np.max(np.abs(r_ref)) < 1e-12
+            assert np.max(np.abs(u - u_ref)) / np.max(np.abs(u_ref)) < 1e-12
