@@ -81,6 +81,88 @@ def cpu_baseline(budget_s: float = 12.0) -> dict:
             "sample": f"D3Q27 64^3 Taylor-Green, FP64, {steps} steps, {dt:.1f} s, {threads} OpenMP threads"}
 
 
+def bench_batched(count: int, steps: int, dtypes=("fp32_dev", "fp64"), baseline: bool = True) -> dict:
+    """Batched workload: `count` independent D2Q9 shear-wave domains (Nx, Ny
+    uniform in 32..512, amplitude U[0.01, 0.2], nu log-uniform 1e-5..1e-1),
+    `steps` steps each, all advanced by one persistent launch (or one launch
+    per step, whichever the autotuner picks), against the plain path: one
+    domain at a time, one kernel launch per step (count * steps launches)."""
+    import torch
+
+    from paper_2303_08163_amd import autotune, lbm, workloads
+    specs = workloads.batch_domains(count=count, seed=2303)
+    nodes = sum(sp["nx"] * sp["ny"] for sp in specs)
+    fields = [workloads.shear_wave(sp["nx"], sp["ny"], sp["amp"]) for sp in specs]
+    out = {"workload": f"{count} D2Q9 periodic shear-wave domains, Nx,Ny ~ U{{32..512}}, {steps} steps each",
+           "nodes": nodes}
+    for dtype in dtypes:
+        doms = [(9, (sp["nx"], sp["ny"]), dtype) for sp in specs]
+        tuning, rep = autotune.tune_pool(doms, steps=10)
+        tun = lbm.make_pool_tuning(**tuning)
+        arena = lbm.lbm_pool_table_bytes(count) + sum(
+            lbm.lbm_pool_slot_bytes(lbm.make_config(9, (sp["nx"], sp["ny"]), sp["tau"], dtype), tun) for sp in specs)
+        with lbm.Pool(arena + (1 << 20), max_slots=count, tuning=tun) as pool:
+            for sp, (r0, u0) in zip(specs, fields):
+                pool.admit(r0, u0, sp["tau"], steps, dtype=dtype)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pool.run(steps)
+            done = pool.poll()
+            dt = time.perf_counter() - t0
+            st = pool.stats()
+        assert len(done) == count
+        rec = {"solves_per_s": round(count / dt, 2), "seconds": round(dt, 4), "mlups": round(nodes * steps / dt / 1e6, 1),
+               "tuning": tuning, "launches": st["launches"], "autotune_cached": rep.get("cached", False)}
+        if baseline and dtype == dtypes[0]:
+            doms_alone = [lbm.Domain(r0, u0, sp["tau"], dtype=dtype) for sp, (r0, u0) in zip(specs, fields)]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for d in doms_alone:
+                d.step(steps)
+            torch.cuda.synchronize()
+            tb = time.perf_counter() - t0
+            for d in doms_alone:
+                d.close()
+            rec["one_domain_per_launch"] = {"solves_per_s": round(count / tb, 2), "seconds": round(tb, 3),
+                                            "launches": count * steps, "mlups": round(nodes * steps / tb / 1e6, 1)}
+            rec["speedup_vs_one_domain_per_launch"] = round(tb / dt, 2)
+        out[dtype] = rec
+    return out
+
+
+def bench_serving(n_requests: int, rate: float, light_requests: int) -> dict:
+    """Serving: Poisson request stream (seed 8163) mixing D2Q9 64^2..1024^2 and
+    D3Q27 32^3..192^3 (log-uniform sides), Taylor-Green or shear-wave starts,
+    u0 ~ U[0.01, 0.15], tau ~ U[0.5001, 0.6], 200..5000 steps, FP32 storage;
+    continuous batching on one pool against a serial one-request-at-a-time
+    server on the same GPU.  The stated rate is far above one GPU's capacity,
+    so latency there is queueing; a second, lighter stream at about half the
+    measured capacity is reported as well."""
+    from paper_2303_08163_amd import serve, workloads
+    res = {}
+    trace = workloads.serving_trace(n_requests=n_requests, rate=rate, seed=8163)
+    be = serve.PoolBackend(96 << 30, max_slots=512)
+    try:
+        pool_out = serve.Server(be).serve(trace)
+    finally:
+        be.close()
+    base_out = serve.serial_serve(trace)
+    ps, bs = serve.summarize(pool_out), serve.summarize(base_out)
+    res["stated_rate"] = {"rate_req_s": rate, "requests": n_requests, "continuous_batching": ps, "serial": bs}
+    cap = ps["solves_per_s"] or 1.0
+    light_rate = max(0.5, 0.5 * cap)
+    trace_l = workloads.serving_trace(n_requests=light_requests, rate=light_rate, seed=8164)
+    be = serve.PoolBackend(96 << 30, max_slots=512)
+    try:
+        pl = serve.summarize(serve.Server(be).serve(trace_l))
+    finally:
+        be.close()
+    bl = serve.summarize(serve.serial_serve(trace_l))
+    res["half_capacity_rate"] = {"rate_req_s": round(light_rate, 2), "requests": light_requests,
+                                 "continuous_batching": pl, "serial": bl}
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,7 +170,15 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256, help="grid side (headline: 256)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sections", default="headline,batched,serving",
+                    help="comma list of headline, batched, serving")
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-light-requests", type=int, default=40)
     args = ap.parse_args()
+    sections = set(args.sections.split(","))
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs each domain on a single GPU "
               "(multi-GPU slab decomposition is a design, not built).", file=sys.stderr)
@@ -176,6 +266,10 @@ def main() -> int:
         "mass_drift": abs(diag["mass"] / (nodes * 1.0) - 1.0),
         "kernel_source_digest": kernel_source_digest(),
     }
+    if "batched" in sections:
+        out["batched"] = bench_batched(args.batch_count, args.batch_steps)
+    if "serving" in sections:
+        out["serving"] = bench_serving(args.serve_requests, args.serve_rate, args.serve_light_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

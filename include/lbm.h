@@ -224,10 +224,12 @@ typedef struct lbm_pool_stats {
 } lbm_pool_stats;
 
 typedef struct lbm_slot_info {
-    int32_t used;      /* 1 if the slot holds a domain */
-    int32_t finished;  /* 1 if its step budget is spent */
+    int32_t used;         /* 1 if the slot holds a domain */
+    int32_t finished;     /* 1 if its step budget is spent (or it was retired) */
     int64_t steps_done, steps_remaining;
-    int64_t bytes;     /* arena bytes held */
+    int64_t bytes;        /* arena bytes held */
+    int32_t domain_error; /* 1 if lbm_pool_poll retired it: its state left the domain */
+    int32_t reserved;
 } lbm_slot_info;
 
 /* Arena bytes the pool keeps for its tables (the rest holds slots). */
@@ -256,7 +258,10 @@ int lbm_pool_admit(lbm_pool *pool, const lbm_config *cfg, const double *rho, con
 int lbm_pool_run(lbm_pool *pool, int64_t k);
 
 /* Synchronise, then list (up to capacity) slots whose budget is spent and that
- * were not listed before; *count receives how many were written.  Returns
+ * were not listed before; *count receives how many were written.  A slot whose
+ * domain flag is set (some node left rho > 0, |u_alpha| < 1) is retired here:
+ * its remaining steps are dropped, it is listed as done, its slot info shows
+ * domain_error = 1 and lbm_pool_moments returns LBM_EDOMAIN for it.  Returns
  * LBM_EDEVICE if a persistent launch's grid barrier timed out. */
 int lbm_pool_poll(lbm_pool *pool, int32_t *done, int32_t capacity, int32_t *count);
 

@@ -50,6 +50,19 @@ __device__ __forceinline__ int xcd_tile(int w, int count) {
     return xcd * per + (xcd < rem ? xcd : rem) + k;
 }
 
+// Record that some node of the calling wavefront left the equilibrium's
+// domain: one store per wavefront (by its first active lane), not one atomic
+// per node, so a domain that has blown up costs no more per step than a
+// healthy one.  Every writer stores the same value, so the race is benign.
+__device__ __forceinline__ void raise_flag(int *flag, bool bad) {
+    const unsigned long long any = __ballot(bad);
+    if (any != 0ull) {
+        const unsigned long long active = __ballot(1);
+        if ((int)__lane_id() == __ffsll((long long)active) - 1)
+            __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 // Source rows r - c for c_y, c_z = -1, 0, +1 on the periodic grid, as element
 // offsets of population 0.
 template <int DIM>
@@ -90,8 +103,7 @@ __device__ __forceinline__ void step_node(const store_t<DT> *__restrict__ src, s
             }
 
     const bool bad = collide_dt<DIM, DT, CORR>(f, relax);
-    if (bad)
-        __hip_atomic_fetch_or(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    raise_flag(flag, bad);
 
     const int64_t self = (int64_t)(z * ny + y) * rs + x;
 #pragma unroll
@@ -228,8 +240,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_vec(StepArgs a) {
         for (int i = 0; i < Q; ++i)
             g[i][k] = f[i];
     }
-    if (bad)
-        __hip_atomic_fetch_or(a.flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    raise_flag(a.flag, bad);
 
     const int64_t self = (int64_t)(z * a.ny + y) * a.rs + x0;
 #pragma unroll
@@ -277,8 +288,7 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a) {
     double u[3] = {a.u[n], a.u[a.n + n], DIM == 3 ? a.u[2 * a.n + n] : 0.0};
     double f[Q];
     const bool bad = equilibrium_stored<DIM, DEV>(a.rho[n], u, a.rho0, f);
-    if (bad)
-        __hip_atomic_fetch_or(a.flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    raise_flag(a.flag, bad);
     T *dst = static_cast<T *>(a.dst) + node_offset(n, a.nx, a.rs);
 #pragma unroll
     for (int i = 0; i < Q; ++i)

@@ -15,7 +15,7 @@
 
 namespace lbm {
 
-constexpr int kClasses = 8;  // (D2Q9, D3Q27) x 4 dtypes
+constexpr int kClasses = 16;  // (D2Q9, D3Q27) x 4 dtypes x (correction off, on)
 constexpr long long kSpinLimit = 1ll << 26;
 
 static size_t round256(size_t v) { return (v + 255) / 256 * 256; }
@@ -73,20 +73,29 @@ static int slot_layout(const lbm_config *cfg, const lbm_pool_tuning &t, Layout *
     return validate_config(cfg, &st, L);
 }
 
-static int class_of(const lbm_config *cfg) { return (cfg->lattice == LBM_D3Q27 ? 4 : 0) + cfg->dtype; }
+// class = 8 * (D3Q27) + 2 * dtype + correction
+static int class_of(const lbm_config *cfg) {
+    return (cfg->lattice == LBM_D3Q27 ? 8 : 0) + 2 * cfg->dtype + (cfg->bulk_correction ? 1 : 0);
+}
 
 using PoolStepFn = void (*)(PoolRunArgs);
+template <int DIM, int DT>
+static PoolStepFn pool_kernel_dt(bool corr, bool persistent) {
+    if (corr)
+        return persistent ? k_pool_persistent<DIM, DT, true> : k_pool_step<DIM, DT, true>;
+    return persistent ? k_pool_persistent<DIM, DT, false> : k_pool_step<DIM, DT, false>;
+}
 template <int DIM>
-static PoolStepFn pool_kernel(int dtype, bool persistent) {
+static PoolStepFn pool_kernel(int dtype, bool corr, bool persistent) {
     switch (dtype) {
     case kDevF64:
-        return persistent ? k_pool_persistent<DIM, kDevF64> : k_pool_step<DIM, kDevF64>;
+        return pool_kernel_dt<DIM, kDevF64>(corr, persistent);
     case kDevMixed:
-        return persistent ? k_pool_persistent<DIM, kDevMixed> : k_pool_step<DIM, kDevMixed>;
+        return pool_kernel_dt<DIM, kDevMixed>(corr, persistent);
     case kDevF32:
-        return persistent ? k_pool_persistent<DIM, kDevF32> : k_pool_step<DIM, kDevF32>;
+        return pool_kernel_dt<DIM, kDevF32>(corr, persistent);
     default:
-        return persistent ? k_pool_persistent<DIM, kF64> : k_pool_step<DIM, kF64>;
+        return pool_kernel_dt<DIM, kF64>(corr, persistent);
     }
 }
 
@@ -96,6 +105,7 @@ struct Slot {
     DomainState d{};
     size_t off = 0, bytes = 0;
     int64_t remaining = 0;
+    bool failed = false;  // retired at poll: its state left the equilibrium's domain
     int tiles_x = 0, tiles_y = 0, tiles = 0;
     int cls = 0;
 };
@@ -116,6 +126,8 @@ struct lbm_pool {
     unsigned *barrier = nullptr;
     int *error = nullptr;
     char *staging = nullptr;  // pinned host copy of one class table
+    char *gather_host = nullptr;  // pinned: flag pointers, then flag values
+    char *gather_dev = nullptr;
     hipEvent_t staging_done = nullptr;
     bool staging_pending = false;
     int cu_count = 0;
@@ -167,10 +179,15 @@ int check_slot(lbm_pool *p, int32_t slot) {
 
 extern "C" {
 
+// Gather area: flag pointers and flag values of up to max_slots slots.
+static size_t gather_bytes(int max_slots) {
+    return round256(sizeof(int *) * (size_t)max_slots) + round256(sizeof(int) * (size_t)max_slots);
+}
+
 size_t lbm_pool_table_bytes(int32_t max_slots) {
     if (max_slots < 1 || max_slots > 65536)
         return 0;
-    return (size_t)kClasses * class_table_bytes(max_slots) + 512;
+    return (size_t)kClasses * class_table_bytes(max_slots) + 512 + gather_bytes(max_slots);
 }
 
 size_t lbm_pool_slot_bytes(const lbm_config *cfg, const lbm_pool_tuning *tuning) {
@@ -214,13 +231,18 @@ int lbm_pool_create(int32_t max_slots, const lbm_pool_tuning *tuning, void *aren
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess)
         e = hipDeviceGetAttribute(&p->cu_count, hipDeviceAttributeMultiprocessorCount, dev);
+    p->gather_dev = p->arena + (size_t)kClasses * p->class_bytes + 512;
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void **>(&p->staging), p->class_bytes, hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void **>(&p->gather_host), gather_bytes(max_slots), hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipEventCreateWithFlags(&p->staging_done, hipEventDisableTiming);
     if (e != hipSuccess) {
         if (p->staging)
             (void)hipHostFree(p->staging);
+        if (p->gather_host)
+            (void)hipHostFree(p->gather_host);
         delete p;
         return hip_fail(e, "pool create");
     }
@@ -228,6 +250,7 @@ int lbm_pool_create(int32_t max_slots, const lbm_pool_tuning *tuning, void *aren
     e = hipGetLastError();
     if (e != hipSuccess) {
         (void)hipHostFree(p->staging);
+        (void)hipHostFree(p->gather_host);
         (void)hipEventDestroy(p->staging_done);
         delete p;
         return hip_fail(e, "pool create");
@@ -348,7 +371,6 @@ int lbm_pool_run(lbm_pool *p, int64_t k) {
             d.tiles_x = s.tiles_x;
             d.tiles_y = s.tiles_y;
             d.parity = s.d.cur;
-            d.corr = s.d.cfg.bulk_correction;
             d.ps = s.d.L.ps;
             d.rs = s.d.L.rs;
             d.relax = s.d.relax;
@@ -373,8 +395,10 @@ int lbm_pool_run(lbm_pool *p, int64_t k) {
         a.barrier = p->barrier;
         a.error = p->error;
         a.spin_limit = kSpinLimit;
-        const int dim = c >= 4 ? 3 : 2, dtype = c % 4;
-        PoolStepFn fn = dim == 3 ? pool_kernel<3>(dtype, p->tun.persistent) : pool_kernel<2>(dtype, p->tun.persistent);
+        const int dim = c >= 8 ? 3 : 2, dtype = (c % 8) / 2;
+        const bool corr = (c & 1) != 0;
+        PoolStepFn fn = dim == 3 ? pool_kernel<3>(dtype, corr, p->tun.persistent)
+                                 : pool_kernel<2>(dtype, corr, p->tun.persistent);
         dim3 block(p->tun.tile_x, p->tun.tile_y);
         if (p->tun.persistent) {
             int per_cu = 0;
@@ -435,11 +459,41 @@ int lbm_pool_poll(lbm_pool *p, int32_t *done, int32_t capacity, int32_t *count) 
     }
     int err = 0;
     hipError_t e = hipMemcpyAsync(&err, p->error, sizeof(int), hipMemcpyDeviceToHost, p->stream);
+    // domain flags of the slots still running: a slot whose state left the
+    // equilibrium's domain is retired (its remaining steps are dropped)
+    std::vector<int> running;
+    for (int i = 0; i < p->max_slots; ++i)
+        if (p->slots[i].used && p->slots[i].remaining > 0)
+            running.push_back(i);
+    const int nr = (int)running.size();
+    int **ptrs = reinterpret_cast<int **>(p->gather_host);
+    int *vals = reinterpret_cast<int *>(p->gather_host + round256(sizeof(int *) * (size_t)p->max_slots));
+    int *dvals = reinterpret_cast<int *>(p->gather_dev + round256(sizeof(int *) * (size_t)p->max_slots));
+    if (e == hipSuccess && nr > 0) {
+        e = hipStreamSynchronize(p->stream);  // the pinned pointer list may still feed an earlier copy
+        for (int j = 0; j < nr && e == hipSuccess; ++j)
+            ptrs[j] = p->slots[running[j]].d.flag;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(p->gather_dev, ptrs, sizeof(int *) * nr, hipMemcpyHostToDevice, p->stream);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_gather_flags, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, p->stream,
+                               (const int *const *)p->gather_dev, nr, dvals);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(vals, dvals, sizeof(int) * nr, hipMemcpyDeviceToHost, p->stream);
+    }
     if (e == hipSuccess)
         e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess)
         return hip_fail(e, "pool poll synchronise");
     p->staging_pending = false;
+    for (int j = 0; j < nr; ++j)
+        if (vals[j]) {
+            Slot &s = p->slots[running[j]];
+            s.failed = true;
+            s.remaining = 0;
+        }
     int32_t c = 0;
     for (int i = 0; i < p->max_slots && c < capacity; ++i) {
         Slot &s = p->slots[i];
@@ -520,6 +574,8 @@ int lbm_pool_slot_info(lbm_pool *p, int32_t slot, lbm_slot_info *info) {
     info->steps_done = s.used ? s.d.steps : 0;
     info->steps_remaining = s.used ? s.remaining : 0;
     info->bytes = s.used ? (int64_t)s.bytes : 0;
+    info->domain_error = (s.used && s.failed) ? 1 : 0;
+    info->reserved = 0;
     return LBM_OK;
 }
 
@@ -528,6 +584,7 @@ int lbm_pool_destroy(lbm_pool *p) {
         return LBM_OK;
     hipError_t e = hipStreamSynchronize(p->stream);
     (void)hipHostFree(p->staging);
+    (void)hipHostFree(p->gather_host);
     (void)hipEventDestroy(p->staging_done);
     delete p;
     if (e != hipSuccess)

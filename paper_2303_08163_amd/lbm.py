@@ -72,7 +72,8 @@ class lbm_pool_stats(ctypes.Structure):
 
 class lbm_slot_info(ctypes.Structure):
     _fields_ = [("used", ctypes.c_int32), ("finished", ctypes.c_int32), ("steps_done", ctypes.c_int64),
-                ("steps_remaining", ctypes.c_int64), ("bytes", ctypes.c_int64)]
+                ("steps_remaining", ctypes.c_int64), ("bytes", ctypes.c_int64), ("domain_error", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -316,12 +317,14 @@ class Domain:
                  stream=None, tuning: lbm_tuning | None = None, device="cuda:0"):
         import torch
         load_library()
-        rho = np.asarray(rho, dtype=np.float64)
-        u = np.asarray(u, dtype=np.float64)
+        on_device = isinstance(rho, torch.Tensor) and rho.is_cuda
+        if not on_device:
+            rho = np.asarray(rho, dtype=np.float64)
+            u = np.asarray(u, dtype=np.float64)
         D = rho.ndim
-        if D not in (2, 3) or u.shape != (D,) + rho.shape:
+        if D not in (2, 3) or tuple(u.shape) != (D,) + tuple(rho.shape):
             raise ValueError("rho must be 2-D or 3-D and u of shape (D, *rho.shape)")
-        self.shape = rho.shape
+        self.shape = tuple(rho.shape)
         self.D = D
         self.lattice = LBM_D2Q9 if D == 2 else LBM_D3Q27
         self.Q = 9 if D == 2 else 27
@@ -336,13 +339,23 @@ class Domain:
         self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self._ws.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
-        with torch.cuda.stream(self.stream):
-            rho_d = torch.from_numpy(np.ascontiguousarray(rho)).to(self.device)
-            u_d = torch.from_numpy(np.ascontiguousarray(u)).to(self.device)
+        if on_device:
+            rho_d = rho.to(self.device, torch.float64).contiguous()
+            u_d = u.to(self.device, torch.float64).contiguous()
+            torch.cuda.current_stream(self.device).synchronize()
+        else:
+            with torch.cuda.stream(self.stream):
+                rho_d = torch.from_numpy(np.ascontiguousarray(rho)).to(self.device)
+                u_d = torch.from_numpy(np.ascontiguousarray(u)).to(self.device)
         self.stream.synchronize()
         self.handle = lbm_create(self.cfg, self._ws_ptr, nbytes, rho_d.data_ptr(), u_d.data_ptr(),
                                  self.stream.cuda_stream, tuning)
         del rho_d, u_d
+
+    @classmethod
+    def from_device(cls, rho, u, tau: float, **kw):
+        """Domain from float64 CUDA tensors already on the device."""
+        return cls(rho, u, tau, **kw)
 
     @property
     def n(self) -> int:

@@ -1,0 +1,224 @@
+"""Continuous-batching server for simulation requests on one GPU.
+
+Requests (lattice, grid, initial field, u0, tau, step count) arrive over time.
+The server keeps the populations of admitted requests resident in HBM as slots
+of one pool, admits queued requests whenever a slot and a large enough block
+of the arena are free (admission by memory footprint), advances every active
+slot in chunks of K steps (one pool run: one kernel launch per step, or one
+persistent launch, covering all active requests of a class), and returns a
+result as soon as a request's steps are done.  Requests arriving while others
+run join the next chunk, so their work overlaps on the device.
+
+Latency is measured from a request's arrival to the moment its result
+(diagnostics read back from the GPU) is available.
+
+The scheduling logic takes a backend object (admit / run / poll / result /
+release / cost estimate), so it can be exercised with a stand-in backend and a
+virtual clock; the production backend is PoolBackend over the native pool.
+"""
+from __future__ import annotations
+
+import math
+import time
+from collections import deque
+
+import numpy as np
+
+
+def init_fields_device(req: dict, device):
+    """Initial (rho, u) of a request as float64 torch tensors on `device`,
+    assembled from 1-D profiles (the same formulas as the workloads module)."""
+    import torch
+    n, u0 = req["n"], req["u0"]
+    k = 2.0 * math.pi / n
+    x = np.arange(n, dtype=np.float64)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+    if req["lattice"] == 9:
+        if req["init"] == "taylor_green":
+            cx, sx, c2x = t(np.cos(k * x)), t(np.sin(k * x)), t(np.cos(2 * k * x))
+            ux = -u0 * cx[None, :] * sx[:, None]
+            uy = u0 * sx[None, :] * cx[:, None]
+            rho = 1.0 * (1.0 - 0.75 * u0 * u0 * (c2x[None, :] + c2x[:, None]))
+            return rho.contiguous(), torch.stack([ux, uy]).contiguous()
+        s = t(u0 * np.sin(2.0 * math.pi * x / n))
+        ux = s[:, None].expand(n, n)
+        return torch.ones((n, n), dtype=torch.float64, device=device), \
+            torch.stack([ux, torch.zeros_like(ux)]).contiguous()
+    if req["init"] == "taylor_green":
+        sx, cx, c2x = t(np.sin(k * x)), t(np.cos(k * x)), t(np.cos(2 * k * x))
+        ux = u0 * sx[None, None, :] * cx[None, :, None] * cx[:, None, None]
+        uy = -u0 * cx[None, None, :] * sx[None, :, None] * cx[:, None, None]
+        rho = 1.0 + (3.0 * u0 * u0 / 16.0) * (c2x[None, None, :] + c2x[None, :, None]) * (c2x[:, None, None] + 2.0)
+        return rho.contiguous(), torch.stack([ux, uy, torch.zeros_like(ux)]).contiguous()
+    s = t(u0 * np.sin(2.0 * math.pi * x / n))
+    ux = s[None, :, None].expand(n, n, n)
+    z = torch.zeros((n, n, n), dtype=torch.float64, device=device)
+    return torch.ones((n, n, n), dtype=torch.float64, device=device), torch.stack([ux, z, z]).contiguous()
+
+
+class PoolBackend:
+    """Backend over the native pool (one arena of `budget_bytes` of HBM)."""
+
+    def __init__(self, budget_bytes: int, max_slots: int = 256, tuning=None, dtype: str = "fp32_dev",
+                 device="cuda:0", bytes_per_s: float = 5.0e12):
+        from . import lbm
+        self.lbm = lbm
+        self.dtype = dtype
+        self.pool = lbm.Pool(budget_bytes, max_slots=max_slots, tuning=tuning, device=device)
+        self.device = self.pool.device
+        self.bytes_per_s = bytes_per_s
+        self.slot_req = {}
+
+    def footprint(self, req) -> int:
+        lbm = self.lbm
+        n = req["n"]
+        shape = (n, n) if req["lattice"] == 9 else (n, n, n)
+        return lbm.lbm_pool_slot_bytes(lbm.make_config(req["lattice"], shape, req["tau"], self.dtype),
+                                       self.pool.tuning)
+
+    def try_admit(self, req, fields=None):
+        lbm = self.lbm
+        rho, u = fields if fields is not None else init_fields_device(req, self.device)
+        cfg = lbm.make_config(req["lattice"], tuple(rho.shape[::-1]), req["tau"], self.dtype)
+        try:
+            slot = lbm.lbm_pool_admit(self.pool.handle, cfg, rho.data_ptr(), u.data_ptr(), req["steps"])
+        except lbm.LBMError as e:
+            if e.status in (lbm.LBM_EBUSY, lbm.LBM_ENOMEM):
+                return None
+            raise
+        self.pool.shapes[slot] = tuple(rho.shape)
+        self.slot_req[slot] = req
+        return slot
+
+    def step_seconds(self, slots) -> float:
+        """Estimated GPU time of one step of the given slots (memory-bound)."""
+        b = 0
+        for s in slots:
+            r = self.slot_req[s]
+            q, nodes = (9, r["n"] ** 2) if r["lattice"] == 9 else (27, r["n"] ** 3)
+            b += 2 * q * 4 * nodes
+        return b / self.bytes_per_s
+
+    def remaining(self, slot) -> int:
+        return int(self.pool.slot_info(slot)["steps_remaining"])
+
+    def run(self, k: int) -> None:
+        self.pool.run(k)
+
+    def poll(self):
+        return self.pool.poll()
+
+    def result(self, slot) -> dict:
+        _, _, d = self.pool.moments(slot, fields=False, raise_on_domain=False)
+        return d
+
+    def release(self, slot) -> None:
+        self.pool.release(slot)
+        self.slot_req.pop(slot, None)
+
+    def close(self):
+        self.pool.close()
+
+
+class Server:
+    """Continuous batching over a backend.
+
+    chunk_s: target GPU time of one run (bounds how long a newly arrived
+    request waits before it joins); lookahead: how many queued requests are
+    tried per admission pass (first-fit within the window, arrival order).
+    """
+
+    def __init__(self, backend, chunk_s: float = 0.02, lookahead: int = 8, max_chunk: int = 2000,
+                 clock=time.perf_counter, sleep=time.sleep):
+        self.b = backend
+        self.chunk_s = chunk_s
+        self.lookahead = lookahead
+        self.max_chunk = max_chunk
+        self.clock = clock
+        self.sleep = sleep
+
+    def serve(self, trace):
+        """Serve a list of requests (dicts with 'arrival' seconds from start).
+        Returns one record per request: id, arrival, admitted, finished,
+        latency (finished - arrival), diagnostics."""
+        b = self.b
+        t0 = self.clock()
+        now = lambda: self.clock() - t0
+        queue = deque()
+        active = {}  # slot -> (request, admitted time)
+        out = []
+        i = 0
+        trace = sorted(trace, key=lambda r: r["arrival"])
+        while i < len(trace) or queue or active:
+            t = now()
+            while i < len(trace) and trace[i]["arrival"] <= t:
+                queue.append(trace[i])
+                i += 1
+            # admission: first fit within the look-ahead window, in arrival order
+            tried = 0
+            for req in list(queue):
+                if tried >= self.lookahead:
+                    break
+                tried += 1
+                slot = b.try_admit(req)
+                if slot is not None:
+                    active[slot] = (req, now())
+                    queue.remove(req)
+            if not active:
+                if i < len(trace):
+                    wait = trace[i]["arrival"] - now()
+                    if wait > 0:
+                        self.sleep(wait)
+                    continue
+                if queue:
+                    raise RuntimeError(f"request {queue[0]['id']} can never be admitted (larger than the pool)")
+                break
+            # one chunk: long enough to amortise launches, short enough for admission,
+            # and ending exactly when the next active request finishes
+            step_s = max(b.step_seconds(list(active)), 1e-7)
+            k = int(max(1, min(self.max_chunk, self.chunk_s / step_s)))
+            k = min(k, min(b.remaining(s) for s in active))
+            b.run(max(1, k))
+            for slot in b.poll():
+                req, adm = active.pop(slot)
+                diag = b.result(slot)
+                fin = now()
+                out.append(dict(id=req["id"], arrival=req["arrival"], admitted=adm, finished=fin,
+                                latency=fin - req["arrival"], diag=diag))
+                b.release(slot)
+        return out
+
+
+def serial_serve(trace, dtype: str = "fp32_dev", device="cuda:0", clock=time.perf_counter, sleep=time.sleep):
+    """The plain baseline: one request at a time, in arrival order, each a
+    single domain stepped with one kernel launch per step."""
+    import torch
+    from . import lbm
+    dev = torch.device(device)
+    t0 = clock()
+    out = []
+    for req in sorted(trace, key=lambda r: r["arrival"]):
+        wait = req["arrival"] - (clock() - t0)
+        if wait > 0:
+            sleep(wait)
+        rho, u = init_fields_device(req, dev)
+        start = clock() - t0
+        d = lbm.Domain.from_device(rho, u, req["tau"], dtype=dtype)
+        d.step(req["steps"])
+        _, _, diag = d.moments(fields=False, raise_on_domain=False)
+        d.close()
+        fin = clock() - t0
+        out.append(dict(id=req["id"], arrival=req["arrival"], admitted=start, finished=fin,
+                        latency=fin - req["arrival"], diag=diag))
+    return out
+
+
+def summarize(records, wall_s: float | None = None) -> dict:
+    lat = np.array([r["latency"] for r in records])
+    fin = max(r["finished"] for r in records) if records else 0.0
+    wall = wall_s if wall_s is not None else fin
+    return {"requests": len(records), "solves_per_s": round(len(records) / wall, 3) if wall > 0 else None,
+            "p50_latency_s": round(float(np.percentile(lat, 50)), 4) if len(lat) else None,
+            "p99_latency_s": round(float(np.percentile(lat, 99)), 4) if len(lat) else None,
+            "mean_latency_s": round(float(lat.mean()), 4) if len(lat) else None,
+            "makespan_s": round(fin, 3)}

@@ -191,3 +191,26 @@ def test_batched_workload_subset_matches_oracle_and_alone():
             r_ref, u_ref, _ = oracle.run(r0, u0, sp["tau"], steps)
             assert np.max(np.abs(rho - r_ref)) / np.max(np.abs(r_ref)) < 1e-12
             assert np.max(np.abs(u - u_ref)) / np.max(np.abs(u_ref)) < 1e-12
+
+
+def test_pool_retires_failed_slots():
+    """A slot whose state leaves the equilibrium's domain is retired at the next
+    poll (remaining steps dropped, reported with its flag); the others go on."""
+    lbm = _lbm()
+    good_r, good_u = workloads.taylor_green_2d(32, u0=0.05)
+    bad_r, bad_u = workloads.random_field((16, 16), seed=70, umax=0.99, rho_lo=0.3, rho_hi=2.0)
+    with lbm.Pool(GiB // 16, max_slots=4) as pool:
+        g = pool.admit(good_r, good_u, 0.51, 100, dtype="fp64")
+        b = pool.admit(bad_r, bad_u, 0.5001, 100000, dtype="fp64")
+        pool.run(20)
+        assert pool.poll() == [b]
+        info = pool.slot_info(b)
+        assert info["domain_error"] == 1 and info["finished"] == 1 and info["steps_remaining"] == 0
+        assert info["steps_done"] == 20
+        assert pool.slot_info(g)["steps_remaining"] == 80 and pool.slot_info(g)["domain_error"] == 0
+        pool.run(1000)
+        assert pool.poll() == [g]
+        _, _, d = pool.moments(g)
+        assert d["steps"] == 100 and not d["domain_error"]
+        with pytest.raises(lbm.LBMDomainError):
+            pool.moments(b)
