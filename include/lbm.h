@@ -75,8 +75,19 @@ enum { LBM_D2Q9 = 9, LBM_D3Q27 = 27 };
  * The two ablation modes are not held to the FP32 error budget. */
 enum { LBM_FP64 = 0, LBM_FP32_DEV = 1, LBM_FP32_DEV_MIXED = 2, LBM_FP32_DEV_F32 = 3 };
 
-/* Equilibrium: the entropic one (eq. Entropic_isothermal_EDF). */
-enum { LBM_EQ_ENTROPIC = 0 };
+/* Equilibrium.
+ *   LBM_EQ_ENTROPIC: eq. (Entropic_isothermal_EDF), the product form of the
+ *                    exact entropic equilibrium (every storage mode).
+ *   LBM_EQ_POLY2:    eq. (Poly2_isothermal_EDF), the second-order polynomial
+ *                    equilibrium (LBM_FP64 and LBM_FP32_DEV only).
+ *   LBM_EQ_PRODUCT:  eq. (Product_isothermal_EDF), the product-form polynomial
+ *                    equilibrium (LBM_FP64 and LBM_FP32_DEV only).
+ * With bulk_correction = 1 the two polynomial kinds use A = 1 - (3/2) u^2 / varsigma^2
+ * (eq. LBGK_bulk) in eq. (redefined_relaxation rate_poly), A taken at the node's
+ * largest |u_alpha|; A is not clamped.  The polynomial kinds run on the
+ * single-domain entry points only (lbm_pool_admit returns LBM_EINVAL) and, with
+ * nodes_per_thread > 1, only with the default vector width and flags. */
+enum { LBM_EQ_ENTROPIC = 0, LBM_EQ_POLY2 = 1, LBM_EQ_PRODUCT = 2 };
 
 /* Problem statement of one periodic domain (plain data, caller-owned). */
 typedef struct lbm_config {
@@ -85,7 +96,7 @@ typedef struct lbm_config {
     int64_t nx, ny, nz;      /* grid extent; nz must be 1 for D2Q9; each >= 1 */
     double tau;              /* relaxation time, tau > 1/2 and finite; 2 beta = 1/tau */
     int32_t bulk_correction; /* 0 = off, 1 = eq. (redefined_relaxation rate) */
-    int32_t equilibrium;     /* LBM_EQ_ENTROPIC */
+    int32_t equilibrium;     /* LBM_EQ_ENTROPIC, LBM_EQ_POLY2 or LBM_EQ_PRODUCT */
     double rho0;             /* reference density of the FP32 deviation storage (> 0); ignored for FP64 */
 } lbm_config;
 

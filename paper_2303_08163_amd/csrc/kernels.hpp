@@ -82,7 +82,7 @@ __device__ __forceinline__ void source_rows(int y, int z, int ny, int nz, int64_
 
 // One node's pull-stream, collision and store.  src/dst are population
 // buffers of one domain; (x, y, z) must lie inside the grid.
-template <int DIM, int DT, bool CORR>
+template <int DIM, int DT, bool CORR, int EQ = kEqEntropic>
 __device__ __forceinline__ void step_node(const store_t<DT> *__restrict__ src, store_t<DT> *__restrict__ dst,
                                           int nx, int ny, int nz, int64_t ps, int64_t rs, const Relax &relax,
                                           int *flag, int x, int y, int z) {
@@ -102,7 +102,7 @@ __device__ __forceinline__ void step_node(const store_t<DT> *__restrict__ src, s
                 f[i] = src[rowoff[cz][cy] + i * ps + xs[cx]];
             }
 
-    const bool bad = collide_dt<DIM, DT, CORR>(f, relax);
+    const bool bad = collide_dt<DIM, DT, CORR, EQ>(f, relax);
     raise_flag(flag, bad);
 
     const int64_t self = (int64_t)(z * ny + y) * rs + x;
@@ -113,7 +113,7 @@ __device__ __forceinline__ void step_node(const store_t<DT> *__restrict__ src, s
 
 // One LBGK step over the whole domain.  1-D grid of tiles_x * tiles_y * nz
 // workgroups of blockDim.x * blockDim.y threads, one node per thread.
-template <int DIM, int DT, bool CORR>
+template <int DIM, int DT, bool CORR, int EQ = kEqEntropic>
 __global__ __launch_bounds__(256) void k_stream_collide(StepArgs a) {
     const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int tx = t % a.tiles_x;
@@ -123,8 +123,8 @@ __global__ __launch_bounds__(256) void k_stream_collide(StepArgs a) {
     const int y = ty * (int)blockDim.y + (int)threadIdx.y;
     if (x >= a.nx || y >= a.ny)
         return;
-    step_node<DIM, DT, CORR>(static_cast<const store_t<DT> *>(a.src), static_cast<store_t<DT> *>(a.dst), a.nx,
-                             a.ny, a.nz, a.ps, a.rs, a.relax, a.flag, x, y, z);
+    step_node<DIM, DT, CORR, EQ>(static_cast<const store_t<DT> *>(a.src), static_cast<store_t<DT> *>(a.dst), a.nx,
+                                 a.ny, a.nz, a.ps, a.rs, a.relax, a.flag, x, y, z);
 }
 
 // ---------------------------------------------------------------------------
@@ -170,7 +170,7 @@ __device__ __forceinline__ void store_vec(V v, V *p) {
         *p = v;
 }
 
-template <int DIM, int DT, bool CORR, int NPT, bool ROWWAVE, int FLAGS>
+template <int DIM, int DT, bool CORR, int NPT, bool ROWWAVE, int FLAGS, int EQ = kEqEntropic>
 __global__ __launch_bounds__(256) void k_stream_collide_vec(StepArgs a) {
     using T = store_t<DT>;
     using V = typename VecT<T, NPT>::type;
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_vec(StepArgs a) {
 #pragma unroll
         for (int i = 0; i < Q; ++i)
             f[i] = g[i][k];
-        bad |= collide_dt<DIM, DT, CORR>(f, a.relax);
+        bad |= collide_dt<DIM, DT, CORR, EQ>(f, a.relax);
 #pragma unroll
         for (int i = 0; i < Q; ++i)
             g[i][k] = f[i];
@@ -278,7 +278,7 @@ struct InitArgs {
 };
 
 // f = f^eq(rho, u) at every node.
-template <int DIM, bool DEV>
+template <int DIM, bool DEV, int EQ = kEqEntropic>
 __global__ __launch_bounds__(256) void k_init(InitArgs a) {
     using T = store_t<DEV>;
     constexpr int Q = Lattice<DIM>::Q;
@@ -287,7 +287,7 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a) {
         return;
     double u[3] = {a.u[n], a.u[a.n + n], DIM == 3 ? a.u[2 * a.n + n] : 0.0};
     double f[Q];
-    const bool bad = equilibrium_stored<DIM, DEV>(a.rho[n], u, a.rho0, f);
+    const bool bad = equilibrium_stored<DIM, DEV, EQ>(a.rho[n], u, a.rho0, f);
     raise_flag(a.flag, bad);
     T *dst = static_cast<T *>(a.dst) + node_offset(n, a.nx, a.rs);
 #pragma unroll

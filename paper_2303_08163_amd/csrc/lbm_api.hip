@@ -48,10 +48,16 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
         set_error("dtype must be LBM_FP64, LBM_FP32_DEV, LBM_FP32_DEV_MIXED or LBM_FP32_DEV_F32");
         return LBM_EINVAL;
     }
-    if (cfg->equilibrium != LBM_EQ_ENTROPIC) {
-        set_error("equilibrium must be LBM_EQ_ENTROPIC");
+    if (cfg->equilibrium != LBM_EQ_ENTROPIC && cfg->equilibrium != LBM_EQ_POLY2 &&
+        cfg->equilibrium != LBM_EQ_PRODUCT) {
+        set_error("equilibrium must be LBM_EQ_ENTROPIC, LBM_EQ_POLY2 or LBM_EQ_PRODUCT");
         return LBM_EINVAL;
     }
+    if (cfg->equilibrium != LBM_EQ_ENTROPIC && cfg->dtype != LBM_FP64 && cfg->dtype != LBM_FP32_DEV) {
+        set_error("the polynomial equilibria run with LBM_FP64 or LBM_FP32_DEV storage only");
+        return LBM_EINVAL;
+    }
+    L.eq = cfg->equilibrium;
     if (!(cfg->tau > 0.5) || !std::isfinite(cfg->tau)) {
         set_error("tau must be finite and > 1/2");
         return LBM_EINVAL;
@@ -115,11 +121,18 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
         set_error("nodes_per_thread = 4 needs FP32 storage");
         return LBM_EINVAL;
     }
-    if (flags < 0)  // measured best: non-temporal loads and stores for float runs, stores for double
-        flags = npt > 1 ? (fp32 ? LBM_TUNE_NT_STORE | LBM_TUNE_NT_LOAD : LBM_TUNE_NT_STORE) : 0;
+    // measured best: non-temporal loads and stores for float runs, stores for double
+    const int default_flags = fp32 ? LBM_TUNE_NT_STORE | LBM_TUNE_NT_LOAD : LBM_TUNE_NT_STORE;
+    if (flags < 0)
+        flags = npt > 1 ? default_flags : 0;
     if (flags > (LBM_TUNE_NT_STORE | LBM_TUNE_NT_LOAD) || (npt == 1 && flags != 0) ||
         flags == LBM_TUNE_NT_LOAD) {
         set_error("flags: NT_STORE, NT_STORE | NT_LOAD or 0, and only with nodes_per_thread > 1");
+        return LBM_EINVAL;
+    }
+    if (L.eq != LBM_EQ_ENTROPIC && npt > 1 && (npt != (fp32 ? 4 : 2) || flags != default_flags)) {
+        set_error("the polynomial equilibria take nodes_per_thread 1, or the default vector width "
+                  "with the default flags");
         return LBM_EINVAL;
     }
     if (bx == 0) {
@@ -208,7 +221,7 @@ static StepFn vec_kernel(int flags) {
     }
 }
 template <int DIM, int DT, bool CORR>
-static StepFn step_kernel_for(const Layout &L) {
+static StepFn step_kernel_entropic(const Layout &L) {
     if (L.npt == 1)
         return k_stream_collide<DIM, DT, CORR>;
     if constexpr (DT != kF64) {
@@ -216,6 +229,27 @@ static StepFn step_kernel_for(const Layout &L) {
             return L.rowwave ? vec_kernel<DIM, DT, CORR, 4, true>(L.flags) : vec_kernel<DIM, DT, CORR, 4, false>(L.flags);
     }
     return L.rowwave ? vec_kernel<DIM, DT, CORR, 2, true>(L.flags) : vec_kernel<DIM, DT, CORR, 2, false>(L.flags);
+}
+// Polynomial equilibria: the scalar kernel, or the default vector width and
+// flags (validate_config refuses other tunings for them).
+template <int DIM, int DT, bool CORR, int EQ>
+static StepFn step_kernel_poly(const Layout &L) {
+    if (L.npt == 1)
+        return k_stream_collide<DIM, DT, CORR, EQ>;
+    constexpr int NPT = DT == kF64 ? 2 : 4;
+    constexpr int FL = DT == kF64 ? kNtStore : kNtStore | kNtLoad;
+    return L.rowwave ? k_stream_collide_vec<DIM, DT, CORR, NPT, true, FL, EQ>
+                     : k_stream_collide_vec<DIM, DT, CORR, NPT, false, FL, EQ>;
+}
+template <int DIM, int DT, bool CORR>
+static StepFn step_kernel_for(const Layout &L) {
+    if constexpr (DT == kF64 || DT == kDevF64) {
+        if (L.eq == LBM_EQ_POLY2)
+            return step_kernel_poly<DIM, DT, CORR, kEqPoly2>(L);
+        if (L.eq == LBM_EQ_PRODUCT)
+            return step_kernel_poly<DIM, DT, CORR, kEqProduct>(L);
+    }
+    return step_kernel_entropic<DIM, DT, CORR>(L);
 }
 template <int DIM, int DT>
 static StepFn step_kernel_dt(const Layout &L, bool corr) {
@@ -233,6 +267,16 @@ static StepFn step_kernel(const Layout &L, int dtype, bool corr) {
     default:
         return step_kernel_dt<DIM, kF64>(L, corr);
     }
+}
+
+using InitFn = void (*)(InitArgs);
+template <int DIM, bool DEV>
+static InitFn init_kernel(int eq) {
+    if (eq == LBM_EQ_POLY2)
+        return k_init<DIM, DEV, kEqPoly2>;
+    if (eq == LBM_EQ_PRODUCT)
+        return k_init<DIM, DEV, kEqProduct>;
+    return k_init<DIM, DEV, kEqEntropic>;
 }
 
 int launch_step(const Layout &L, const StepArgs &args, int dtype, bool corr, hipStream_t s, int nz) {
@@ -266,8 +310,8 @@ int domain_bind_and_init(DomainState &d, const lbm_config *cfg, const Layout &L,
     InitArgs ia{d.buf[0], rho, u, L.n, (int)cfg->nx, L.ps, L.rs, d.relax.rho0, d.flag};
     const bool dev = cfg->dtype != LBM_FP64;
     dim3 grid((unsigned)((L.n + 255) / 256)), block(256);
-    void (*init_fn)(InitArgs) = L.dim == 2 ? (dev ? k_init<2, true> : k_init<2, false>)
-                                           : (dev ? k_init<3, true> : k_init<3, false>);
+    InitFn init_fn = L.dim == 2 ? (dev ? init_kernel<2, true>(L.eq) : init_kernel<2, false>(L.eq))
+                                : (dev ? init_kernel<3, true>(L.eq) : init_kernel<3, false>(L.eq));
     hipLaunchKernelGGL(init_fn, grid, block, 0, s, ia);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)

@@ -17,6 +17,7 @@ struct Layout {
     size_t elem;       // bytes per stored population
     int64_t n;         // nodes
     int layout;        // LBM_LAYOUT_ROWS or LBM_LAYOUT_PLANES
+    int eq;            // LBM_EQ_* (kEq* in the device code)
     int64_t ps, rs;    // population and row strides (elements)
     int block_x, block_y;
     int npt;           // nodes per thread along x

@@ -108,6 +108,30 @@ __device__ __forceinline__ double corrected_omega(double umax, double Smax, doub
     return (2.0 * p) / fma(two_tau_m1, q, p);
 }
 
+// Equilibrium kinds (the values of lbm_config.equilibrium).
+//   kEqEntropic: eq. (Entropic_isothermal_EDF), the product of the 1-D factors above;
+//   kEqPoly2:    eq. (Poly2_isothermal_EDF),
+//                w_i rho (1 + c.u / s2 + (c.u)^2 / (2 s2^2) - u^2 / (2 s2)), s2 = 1/3;
+//   kEqProduct:  eq. (Product_isothermal_EDF), rho prod_a phi_{c_ia}(u_a) with
+//                phi_0 = 1 - s2 - u^2 and phi_{+-1} = (+-u + s2 + u^2) / 2.
+constexpr int kEqEntropic = 0, kEqPoly2 = 1, kEqProduct = 2;
+
+__device__ __forceinline__ void product_factors(double u, double (&g)[3]) {
+    const double u2 = u * u;
+    const double base = 1.0 / 3.0 + u2;
+    g[0] = (base - u) * 0.5;
+    g[1] = (2.0 / 3.0) - u2;
+    g[2] = (base + u) * 0.5;
+}
+
+// 2 beta with the correction for polynomial equilibria, eq. (redefined_relaxation
+// rate_poly): A = 1 - (3/2) u^2 / s2 (eq. LBGK_bulk) at the node's largest |u_a|.
+// A < 0 beyond |u| = s2^(1/2) (2/3)^(1/2) and beta leaves [0, 1]; nothing is clamped.
+__device__ __forceinline__ double corrected_omega_poly(double umax, double two_tau_m1) {
+    const double A = fma(-4.5 * umax, umax, 1.0);
+    return (2.0 * A) / (A + two_tau_m1);
+}
+
 // Relaxation parameters of a domain.
 struct Relax {
     double omega;       // 1 / tau (no correction)
@@ -121,7 +145,7 @@ struct Relax {
 // the equilibrium's domain (rho <= 0, |u_a| >= 1 or NaN).  T is the storage
 // type; every kernel calls this one function, so a node's result does not
 // depend on which kernel or launch shape computed it.
-template <int DIM, bool DEV, bool CORR, typename T>
+template <int DIM, bool DEV, bool CORR, int EQ = kEqEntropic, typename T>
 __device__ __forceinline__ bool collide(T (&v)[Lattice<DIM>::Q], const Relax &r) {
     double f[Lattice<DIM>::Q];
 #pragma unroll
@@ -137,30 +161,56 @@ __device__ __forceinline__ bool collide(T (&v)[Lattice<DIM>::Q], const Relax &r)
         bad |= !(fabs(u[a]) < 1.0);
 
     double g[3][3], S[3];
+    double usq = 0.0;
+    if constexpr (EQ == kEqEntropic) {
 #pragma unroll
-    for (int a = 0; a < DIM; ++a)
-        axis_factors(u[a], g[a], S[a]);
+        for (int a = 0; a < DIM; ++a)
+            axis_factors(u[a], g[a], S[a]);
+    } else if constexpr (EQ == kEqProduct) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+            product_factors(u[a], g[a]);
+    } else {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+            usq = fma(u[a], u[a], usq);
+    }
 
     double omega = r.omega;
     if (CORR) {
-        double umax = fabs(u[0]), Smax = S[0];
+        double umax = fabs(u[0]);
+        if constexpr (EQ == kEqEntropic) {
+            double Smax = S[0];
 #pragma unroll
-        for (int a = 1; a < DIM; ++a) {
-            umax = fmax(umax, fabs(u[a]));
-            Smax = fmax(Smax, S[a]);
+            for (int a = 1; a < DIM; ++a) {
+                umax = fmax(umax, fabs(u[a]));
+                Smax = fmax(Smax, S[a]);
+            }
+            omega = corrected_omega(umax, Smax, r.two_tau_m1);
+        } else {
+#pragma unroll
+            for (int a = 1; a < DIM; ++a)
+                umax = fmax(umax, fabs(u[a]));
+            omega = corrected_omega_poly(umax, r.two_tau_m1);
         }
-        omega = corrected_omega(umax, Smax, r.two_tau_m1);
     }
 
+    const double base_poly = fma(-1.5, usq, 1.0);
 #pragma unroll
     for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
 #pragma unroll
         for (int cy = 0; cy < 3; ++cy) {
-            const double t = DIM == 3 ? (rho * g[1][cy]) * g[2][cz] : rho * g[1][cy];
+            const double t = EQ == kEqPoly2 ? 0.0 : (DIM == 3 ? (rho * g[1][cy]) * g[2][cz] : rho * g[1][cy]);
 #pragma unroll
             for (int cx = 0; cx < 3; ++cx) {
                 const int i = cx + 3 * cy + 9 * cz;
-                double feq = t * g[0][cx];
+                double feq;
+                if constexpr (EQ == kEqPoly2) {
+                    const double cu = (cx - 1) * u[0] + (cy - 1) * u[1] + (DIM == 3 ? (cz - 1) * u[2] : 0.0);
+                    feq = (Lattice<DIM>::weight(i) * rho) * fma(cu, fma(4.5, cu, 3.0), base_poly);
+                } else {
+                    feq = t * g[0][cx];
+                }
                 if (DEV)
                     feq = fma(-Lattice<DIM>::weight(i), r.rho0, feq);
                 T vi = v[i];
@@ -254,18 +304,19 @@ __device__ __forceinline__ bool collide_dev_f32(float (&v)[Lattice<DIM>::Q], con
 }
 
 // Collision of a node for storage/arithmetic code DT.
-template <int DIM, int DT, bool CORR>
+// (The single-precision ablation modes exist for the entropic equilibrium only.)
+template <int DIM, int DT, bool CORR, int EQ = kEqEntropic>
 __device__ __forceinline__ bool collide_dt(store_t<DT> (&v)[Lattice<DIM>::Q], const Relax &r) {
     if constexpr (DT == kDevMixed)
         return collide_dev_f32<DIM, CORR, true>(v, r);
     else if constexpr (DT == kDevF32)
         return collide_dev_f32<DIM, CORR, false>(v, r);
     else
-        return collide<DIM, DT != kF64, CORR>(v, r);
+        return collide<DIM, DT != kF64, CORR, EQ>(v, r);
 }
 
 // Stored equilibrium of (rho, u) for initialisation; returns the domain flag.
-template <int DIM, bool DEV>
+template <int DIM, bool DEV, int EQ = kEqEntropic>
 __device__ __forceinline__ bool equilibrium_stored(double rho, const double (&u)[3], double rho0,
                                                    double (&f)[Lattice<DIM>::Q]) {
     bool bad = !(rho > 0.0);
@@ -273,18 +324,32 @@ __device__ __forceinline__ bool equilibrium_stored(double rho, const double (&u)
     for (int a = 0; a < DIM; ++a)
         bad |= !(fabs(u[a]) < 1.0);
     double g[3][3], S[3];
+    double usq = 0.0;
 #pragma unroll
-    for (int a = 0; a < DIM; ++a)
-        axis_factors(u[a], g[a], S[a]);
+    for (int a = 0; a < DIM; ++a) {
+        if constexpr (EQ == kEqEntropic)
+            axis_factors(u[a], g[a], S[a]);
+        else if constexpr (EQ == kEqProduct)
+            product_factors(u[a], g[a]);
+        else
+            usq = fma(u[a], u[a], usq);
+    }
+    const double base_poly = fma(-1.5, usq, 1.0);
 #pragma unroll
     for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
 #pragma unroll
         for (int cy = 0; cy < 3; ++cy) {
-            const double t = DIM == 3 ? (rho * g[1][cy]) * g[2][cz] : rho * g[1][cy];
+            const double t = EQ == kEqPoly2 ? 0.0 : (DIM == 3 ? (rho * g[1][cy]) * g[2][cz] : rho * g[1][cy]);
 #pragma unroll
             for (int cx = 0; cx < 3; ++cx) {
                 const int i = cx + 3 * cy + 9 * cz;
-                double feq = t * g[0][cx];
+                double feq;
+                if constexpr (EQ == kEqPoly2) {
+                    const double cu = (cx - 1) * u[0] + (cy - 1) * u[1] + (DIM == 3 ? (cz - 1) * u[2] : 0.0);
+                    feq = (Lattice<DIM>::weight(i) * rho) * fma(cu, fma(4.5, cu, 3.0), base_poly);
+                } else {
+                    feq = t * g[0][cx];
+                }
                 if (DEV)
                     feq = fma(-Lattice<DIM>::weight(i), rho0, feq);
                 f[i] = feq;

@@ -63,6 +63,10 @@ static int resolve_tuning(const lbm_pool_tuning *t, lbm_pool_tuning *out) {
 // Layout of a slot: the single-domain layout with the pool's tile and one
 // node per thread (the pool kernels are the one-node-per-thread kind).
 static int slot_layout(const lbm_config *cfg, const lbm_pool_tuning &t, Layout *L) {
+    if (cfg && cfg->equilibrium != LBM_EQ_ENTROPIC) {
+        set_error("pool slots run the entropic equilibrium only");
+        return LBM_EINVAL;
+    }
     lbm_tuning st{};
     st.block_x = t.tile_x;
     st.block_y = t.tile_y;

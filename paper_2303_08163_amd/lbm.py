@@ -24,7 +24,8 @@ LIB_PATH = os.path.join(_HERE, "liblbm_entropic.so")
 LBM_OK, LBM_EINVAL, LBM_EDOMAIN, LBM_EDEVICE, LBM_ENOMEM, LBM_EBUSY = 0, -1, -2, -3, -4, -5
 LBM_D2Q9, LBM_D3Q27 = 9, 27
 LBM_FP64, LBM_FP32_DEV, LBM_FP32_DEV_MIXED, LBM_FP32_DEV_F32 = 0, 1, 2, 3
-LBM_EQ_ENTROPIC = 0
+LBM_EQ_ENTROPIC, LBM_EQ_POLY2, LBM_EQ_PRODUCT = 0, 1, 2
+EQUILIBRIA = {"entropic": LBM_EQ_ENTROPIC, "poly2": LBM_EQ_POLY2, "product": LBM_EQ_PRODUCT}
 
 DTYPES = {"fp64": LBM_FP64, "fp32_dev": LBM_FP32_DEV, "fp32_dev_mixed": LBM_FP32_DEV_MIXED,
           "fp32_dev_f32": LBM_FP32_DEV_F32}
@@ -162,12 +163,13 @@ def _check(status: int, where: str) -> int:
 
 
 def make_config(lattice: int, shape, tau: float, dtype="fp32_dev", bulk_correction=False,
-                rho0: float = 1.0) -> lbm_config:
-    """shape = (nx, ny) for D2Q9 or (nx, ny, nz) for D3Q27 (x first)."""
+                rho0: float = 1.0, equilibrium="entropic") -> lbm_config:
+    """shape = (nx, ny) for D2Q9 or (nx, ny, nz) for D3Q27 (x first);
+    equilibrium: "entropic", "poly2", "product" or an LBM_EQ_* value."""
     nx, ny = int(shape[0]), int(shape[1])
     nz = int(shape[2]) if len(shape) > 2 else 1
     return lbm_config(int(lattice), DTYPES.get(dtype, dtype), nx, ny, nz, float(tau),
-                      int(bool(bulk_correction)), LBM_EQ_ENTROPIC, float(rho0))
+                      int(bool(bulk_correction)), EQUILIBRIA.get(equilibrium, equilibrium), float(rho0))
 
 
 LBM_TUNE_NT_STORE, LBM_TUNE_NT_LOAD = 1, 2
@@ -311,10 +313,11 @@ class Domain:
     rho: numpy array of the grid's shape ((ny, nx) or (nz, ny, nx), x fastest);
     u: (D, *rho.shape).  The fields are copied to the device as float64.
     stream: a torch.cuda.Stream (default: torch's current stream).
+    equilibrium: "entropic" (default), "poly2" or "product" (LBM_EQ_*).
     """
 
     def __init__(self, rho, u, tau: float, dtype="fp32_dev", bulk_correction=False, rho0: float = 1.0,
-                 stream=None, tuning: lbm_tuning | None = None, device="cuda:0"):
+                 stream=None, tuning: lbm_tuning | None = None, device="cuda:0", equilibrium="entropic"):
         import torch
         load_library()
         on_device = isinstance(rho, torch.Tensor) and rho.is_cuda
@@ -330,7 +333,7 @@ class Domain:
         self.Q = 9 if D == 2 else 27
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.cfg = make_config(self.lattice, rho.shape[::-1], tau, dtype, bulk_correction, rho0)
+        self.cfg = make_config(self.lattice, rho.shape[::-1], tau, dtype, bulk_correction, rho0, equilibrium)
         self.tuning = tuning
         nbytes = lbm_workspace_bytes(self.cfg, tuning)
         if nbytes == 0:

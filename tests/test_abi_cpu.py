@@ -48,10 +48,11 @@ def test_status_strings(lbm):
 
 
 def _cfg(lbm, **kw):
-    base = dict(lattice=9, shape=(64, 32), tau=0.6, dtype="fp64", bulk_correction=False, rho0=1.0)
+    base = dict(lattice=9, shape=(64, 32), tau=0.6, dtype="fp64", bulk_correction=False, rho0=1.0,
+                equilibrium="entropic")
     base.update(kw)
     return lbm.make_config(base["lattice"], base["shape"], base["tau"], base["dtype"], base["bulk_correction"],
-                           base["rho0"])
+                           base["rho0"], base["equilibrium"])
 
 
 def test_workspace_bytes_layout(lbm):
@@ -81,6 +82,8 @@ def test_workspace_bytes_layout(lbm):
     dict(lattice=19), dict(dtype=7), dict(shape=(0, 5)), dict(shape=(5, 0)),
     dict(shape=(4, 4, 2)), dict(lattice=27, shape=(4, 4, 0)), dict(dtype="fp32_dev", rho0=0.0),
     dict(dtype="fp32_dev", rho0=-1.0), dict(shape=(70000, 70000)), dict(lattice=27, shape=(2, 2, 2 ** 30)), dict(shape=(2 ** 31, 1)),
+    dict(equilibrium=3), dict(equilibrium=-1), dict(equilibrium="poly2", dtype="fp32_dev_mixed"),
+    dict(equilibrium="product", dtype="fp32_dev_f32"),
 ])
 def test_invalid_configs_are_rejected(lbm, bad):
     assert lbm.lbm_workspace_bytes(_cfg(lbm, **bad)) == 0
@@ -99,6 +102,26 @@ def test_valid_tunings_accepted(lbm):
     for tun in [(0, 0, -1, 0, -1, 0), (64, 4, 0, 4, 3, 1), (64, 1, 0, 2, 1, 2), (128, 2, 64, 2, 0, 2),
                 (256, 1, 0, 1, 0, 1), (32, 8, 0, 1, 0, 0)]:
         assert lbm.lbm_workspace_bytes(cfg, lbm.make_tuning(*tun)) > 0, tun
+
+
+def test_polynomial_equilibria_configs(lbm):
+    """The polynomial kinds take both production storage modes and the scalar
+    or default vector kernel; other vector tunings are refused."""
+    for eq in ("poly2", "product"):
+        for dt in ("fp64", "fp32_dev"):
+            cfg = _cfg(lbm, shape=(256, 8), dtype=dt, equilibrium=eq)
+            ref = lbm.lbm_workspace_bytes(_cfg(lbm, shape=(256, 8), dtype=dt))
+            assert lbm.lbm_workspace_bytes(cfg) == ref > 0
+            assert lbm.lbm_workspace_bytes(cfg, lbm.make_tuning(64, 4, -1, 1, 0)) > 0
+        f32 = _cfg(lbm, shape=(256, 8), dtype="fp32_dev", equilibrium=eq)
+        assert lbm.lbm_workspace_bytes(f32, lbm.make_tuning(64, 4, -1, 4, 3)) > 0
+        assert lbm.lbm_workspace_bytes(f32, lbm.make_tuning(64, 4, -1, 2, -1)) == 0
+        assert lbm.lbm_workspace_bytes(f32, lbm.make_tuning(64, 4, -1, 4, 1)) == 0
+        f64 = _cfg(lbm, shape=(256, 8), dtype="fp64", equilibrium=eq)
+        assert lbm.lbm_workspace_bytes(f64, lbm.make_tuning(64, 4, -1, 2, 0)) == 0
+        # pool slots run the entropic equilibrium only
+        assert lbm.lbm_pool_slot_bytes(f64) == 0
+        assert b"entropic" in lbm.load_library().lbm_last_error()
 
 
 def test_create_argument_checks_precede_gpu_work(lbm):

@@ -1,0 +1,141 @@
+"""GPU parity of the polynomial equilibria: the second-order polynomial
+(eq. Poly2_isothermal_EDF) and the product form (eq. Product_isothermal_EDF),
+each with and without the bulk-viscosity correction of eq. (redefined_relaxation
+rate_poly), against the FP64 CPU oracle's same kind on the same seeded inputs.
+
+Error measure and tolerances as for the entropic equilibrium: normwise
+max |gpu - oracle| / max |oracle| for rho and jointly for u; 1e-12 with FP64
+storage, 1e-5 with FP32 deviation storage."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2303_08163_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32_dev": 1e-5}
+DTYPES = ["fp64", "fp32_dev"]
+KINDS = ["poly2", "product"]
+GiB = 1 << 30
+
+
+def _lbm():
+    from paper_2303_08163_amd import lbm
+    return lbm
+
+
+def rel_err(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / np.max(np.abs(b)))
+
+
+def run_gpu(rho0, u0, tau, steps, dtype, corr, eq, tuning=None, populations=False):
+    lbm = _lbm()
+    with lbm.Domain(rho0, u0, tau, dtype=dtype, bulk_correction=corr, tuning=tuning, equilibrium=eq) as d:
+        d.step(steps)
+        rho, u, diag = d.moments(raise_on_domain=False)
+        f = d.populations() if populations else None
+    return rho, u, diag, f
+
+
+CASES = {  # name: (fields, tau, steps) -- ragged grids spanning several tiles
+    "D2Q9 70x33 random": (lambda: workloads.random_field((33, 70), seed=81, umax=0.15), 0.53, 40),
+    "D2Q9 64^2 TG": (lambda: workloads.taylor_green_2d(64, u0=0.05), 0.51, 1000),
+    "D3Q27 19x13x11 random": (lambda: workloads.random_field((11, 13, 19), seed=82, umax=0.12), 0.55, 20),
+    "D3Q27 24^3 TG": (lambda: workloads.taylor_green_3d(24, u0=0.08), 0.52, 60),
+}
+
+
+@pytest.fixture(scope="module")
+def oracle_results():
+    oracle.set_threads(16)
+    out = {}
+    for name, (make, tau, steps) in CASES.items():
+        rho0, u0 = make()
+        for kind in KINDS:
+            for corr in ("off", "min"):
+                out[name, kind, corr] = (rho0, u0, oracle.run(rho0, u0, tau, steps, corr=corr, kind=kind))
+    return out
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("corr", [False, True])
+def test_polynomial_equilibria_match_oracle(oracle_results, name, kind, dtype, corr):
+    _, tau, steps = CASES[name]
+    rho0, u0, (r_ref, u_ref, bad) = oracle_results[name, kind, "min" if corr else "off"]
+    assert bad == 0
+    rho, u, diag, _ = run_gpu(rho0, u0, tau, steps, dtype, corr, kind)
+    er, eu = rel_err(rho, r_ref), rel_err(u, u_ref)
+    print(f"[parity] {name} {kind} {dtype} corr={corr} tau={tau} {steps} steps: "
+          f"rel err rho {er:.3e}  u {eu:.3e}", flush=True)
+    assert not diag["domain_error"] and diag["steps"] == steps
+    assert er < TOL[dtype] and eu < TOL[dtype]
+
+
+def test_kinds_differ_from_entropic():
+    """The three equilibria give different trajectories (the kind reaches the
+    kernel), and the differences are of the size the oracle predicts."""
+    rho0, u0 = workloads.random_field((33, 70), seed=81, umax=0.15)
+    rho_e, u_e, _, _ = run_gpu(rho0, u0, 0.53, 40, "fp64", True, "entropic")
+    for kind in KINDS:
+        _, u_k, _, _ = run_gpu(rho0, u0, 0.53, 40, "fp64", True, kind)
+        _, u_ref_k, _ = oracle.run(rho0, u0, 0.53, 40, corr="min", kind=kind)
+        _, u_ref_e, _ = oracle.run(rho0, u0, 0.53, 40, corr="min")
+        d_gpu, d_ref = np.max(np.abs(u_k - u_e)), np.max(np.abs(u_ref_k - u_ref_e))
+        assert d_ref > 1e-8
+        assert abs(d_gpu - d_ref) < 1e-12 * np.max(np.abs(u_ref_e)) + 1e-3 * d_ref
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("dtype,nx", [("fp32_dev", 256), ("fp32_dev", 512), ("fp64", 128), ("fp64", 256)])
+@pytest.mark.parametrize("D", [2, 3])
+def test_vector_kernel_equals_scalar_bitwise(kind, dtype, nx, D):
+    """The default vector kernel (whole-row wavefront at nx = 64 x width, and
+    the general form beyond) gives the same bits as one node per thread."""
+    lbm = _lbm()
+    shape = (20, nx) if D == 2 else (3, 5, nx)
+    rho0, u0 = workloads.random_field(shape, seed=83, umax=0.12)
+    scalar = lbm.make_tuning(64, 4, -1, 1, 0)
+    a = run_gpu(rho0, u0, 0.56, 9, dtype, True, kind, tuning=scalar, populations=True)
+    b = run_gpu(rho0, u0, 0.56, 9, dtype, True, kind, populations=True)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[3], b[3])
+    r_ref, u_ref, _ = oracle.run(rho0, u0, 0.56, 9, corr="min", kind=kind)
+    assert rel_err(b[0], r_ref) < TOL[dtype] and rel_err(b[1], u_ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("lattice", [9, 27])
+def test_polynomial_populations_match_oracle(kind, lattice):
+    """Post-collision populations after n steps equal the oracle's populations
+    after n + 1 steps moved back one link, f*_i(r, n) = f_i(r + c_i, n + 1)."""
+    grid = (11, 13) if lattice == 9 else (5, 6, 7)
+    D = len(grid)
+    rho0, u0 = workloads.random_field(grid, seed=84, umax=0.2)
+    _, _, _, f_gpu = run_gpu(rho0, u0, 0.6, 4, "fp64", True, kind, populations=True)
+    _, _, _, f_or = oracle.run(rho0, u0, 0.6, 5, corr="min", kind=kind, return_f=True)
+    c, _ = oracle.lattice(D)
+    for k, ck in enumerate(c):
+        i = int(ck[0] + 1) + 3 * int(ck[1] + 1) + (9 * int(ck[2] + 1) if D == 3 else 0)
+        back = np.roll(f_or[k], shift=tuple(-int(v) for v in ck), axis=tuple(range(D))[::-1])
+        assert np.max(np.abs(f_gpu[i] - back)) < 1e-13
+
+
+def test_pool_refuses_polynomial_equilibria():
+    lbm = _lbm()
+    rho0, u0 = workloads.taylor_green_2d(32)
+    cfg = lbm.make_config(9, (32, 32), 0.6, "fp64", False, 1.0, "poly2")
+    assert lbm.lbm_pool_slot_bytes(cfg) == 0
+    with lbm.Pool(GiB // 16, max_slots=2) as pool:
+        slot = lbm.ctypes.c_int32()
+        lib = lbm.load_library()
+        r = np.ascontiguousarray(rho0)
+        import torch
+        rd = torch.from_numpy(r).cuda()
+        ud = torch.from_numpy(np.ascontiguousarray(u0)).cuda()
+        torch.cuda.synchronize()
+        rc = lib.lbm_pool_admit(pool.handle, lbm.ctypes.byref(cfg), rd.data_ptr(), ud.data_ptr(), 5,
+                                lbm.ctypes.byref(slot))
+        assert rc == lbm.LBM_EINVAL
+        assert pool.stats()["used_slots"] == 0
