@@ -163,6 +163,31 @@ def bench_serving(n_requests: int, rate: float, light_requests: int) -> dict:
     return res
 
 
+def bench_wave(steps: int = 2000) -> dict:
+    """Isothermal pressure-wave sweep: effective viscosity vs U0 for the
+    entropic and product-form equilibria, with and without the bulk correction
+    (D1Q3, nx = 64, tau = 0.65, drho = 1e-3, FP64, energy every 10 steps, fit
+    over t >= 200)."""
+    import torch
+
+    from paper_2303_08163_amd import wave
+
+    U0s = [round(-0.3 + 0.05 * k, 2) for k in range(13)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rows = wave.sweep(U0s, nx=64, tau=0.65, drho=1e-3, steps=steps, every=10, t_min=200)
+    wall = time.perf_counter() - t0
+    table = {}
+    for r in rows:
+        key = f"{r['equilibrium']}_{'corrected' if r['bulk_correction'] else 'plain'}"
+        table.setdefault(key, []).append(round(r["normalised"], 5))
+    return {"workload": "D1Q3 pressure wave rho = 1 + 1e-3 sin(2 pi x / 64) at uniform U0, tau = 0.65, "
+                        f"{steps} steps, nu_eff from the decay of the acoustic energy",
+            "U0": sorted(set(U0s) | {0.0}), "nu_eff_over_nu_eff_at_rest": table,
+            "nu_eff_over_nu_at_rest": round(next(r["ratio"] for r in rows if r["U0"] == 0.0), 5),
+            "runs": len(rows), "wall_s": round(wall, 3)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,8 +195,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256, help="grid side (headline: 256)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sections", default="headline,batched,serving",
-                    help="comma list of headline, batched, serving")
+    ap.add_argument("--sections", default="headline,batched,serving,wave",
+                    help="comma list of headline, batched, serving, wave")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--serve-requests", type=int, default=120)
@@ -270,6 +295,8 @@ def main() -> int:
         out["batched"] = bench_batched(args.batch_count, args.batch_steps)
     if "serving" in sections:
         out["serving"] = bench_serving(args.serve_requests, args.serve_rate, args.serve_light_requests)
+    if "wave" in sections:
+        out["wave"] = bench_wave()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -7,8 +7,8 @@
  * One time step of a domain is the LBGK evolution equation of Sec. "Basic
  * concepts",
  *     f_i(r + c_i, t + 1) = f_i(r, t) + 2 beta (f_i^eq(rho, u) - f_i(r, t)),
- * on a periodic D2Q9 or D3Q27 first-neighbour lattice (1-D weights
- * {1/6, 2/3, 1/6} and their tensor products), in lattice units
+ * on a periodic D1Q3, D2Q9 or D3Q27 first-neighbour lattice (Sec. "Basic
+ * concepts": 1-D weights {1/6, 2/3, 1/6} and their tensor products), in lattice units
  * (dr = dt = 1, varsigma^2 = 1/3), with
  *   - f^eq the entropic equilibrium, eq. (Entropic_isothermal_EDF);
  *   - beta from eq. (relaxation_frequency) with nu = (tau - 1/2) / 3, i.e.
@@ -22,7 +22,7 @@
  * Conventions shared by every entry point:
  *   - Fields are node-major planes with x fastest: node n = x + nx (y + ny z).
  *     A density field is N = nx ny nz doubles; a velocity field is D planes of
- *     N doubles (u_x plane, then u_y, then u_z for D3Q27).
+ *     N doubles (u_x plane, then u_y, then u_z for D3Q27; D = 1, 2, 3).
  *   - "device pointer" means memory allocated on the GPU the library runs on
  *     (hipMalloc or a torch CUDA tensor); "host pointer" means CPU memory.
  *   - Every call returns an lbm_status (0 = LBM_OK, negative = error) unless
@@ -56,8 +56,9 @@ enum lbm_status {
     LBM_EBUSY = -5    /* no free slot */
 };
 
-/* Lattices: the value is Q. */
-enum { LBM_D2Q9 = 9, LBM_D3Q27 = 27 };
+/* Lattices: the value is Q.  D1Q3 domains have ny = nz = 1 and run on the
+ * single-domain entry points only. */
+enum { LBM_D1Q3 = 3, LBM_D2Q9 = 9, LBM_D3Q27 = 27 };
 
 /* Population storage and arithmetic.
  *   LBM_FP64:           populations stored and computed in IEEE double.
@@ -91,7 +92,7 @@ enum { LBM_EQ_ENTROPIC = 0, LBM_EQ_POLY2 = 1, LBM_EQ_PRODUCT = 2 };
 
 /* Problem statement of one periodic domain (plain data, caller-owned). */
 typedef struct lbm_config {
-    int32_t lattice;         /* LBM_D2Q9 or LBM_D3Q27 */
+    int32_t lattice;         /* LBM_D1Q3, LBM_D2Q9 or LBM_D3Q27 */
     int32_t dtype;           /* LBM_FP64, LBM_FP32_DEV, LBM_FP32_DEV_MIXED or LBM_FP32_DEV_F32 */
     int64_t nx, ny, nz;      /* grid extent; nz must be 1 for D2Q9; each >= 1 */
     double tau;              /* relaxation time, tau > 1/2 and finite; 2 beta = 1/tau */
@@ -161,7 +162,7 @@ size_t lbm_workspace_bytes_tuned(const lbm_config *cfg, const lbm_tuning *tuning
  *   stream     hipStream_t to enqueue on (NULL = the null stream).
  *   out        receives the handle; untouched on error.
  * Synchronises the stream.  Errors: LBM_EINVAL (NULL pointer, tau <= 1/2 or
- * not finite, an extent < 1, nz != 1 for D2Q9, more than 2^31 - 4096 nodes,
+ * not finite, an extent < 1, nz != 1 for D2Q9, ny or nz != 1 for D1Q3, more than 2^31 - 4096 nodes,
  * bad lattice/dtype/equilibrium/tuning, rho0 <= 0 for FP32_DEV, workspace too
  * small or misaligned); LBM_EDOMAIN (an initial node has rho <= 0 or |u_alpha| >= 1;
  * no handle is created); LBM_EDEVICE. */
@@ -188,11 +189,29 @@ int lbm_moments(lbm_handle *h, double *rho, double *u, lbm_diag *diag);
 
 /* Copy the current populations out as doubles in the library's canonical
  * order, population-major: out[i * N + n] for population i, node n, where
- * i = (c_x + 1) + 3 (c_y + 1) + 9 (c_z + 1) and the stored state is the
+ * i = (c_x + 1) + 3 (c_y + 1) + 9 (c_z + 1) (D1Q3: i = c_x + 1) and the stored state is the
  * post-collision f*(r, t) (its moments equal those of the pre-collision state).
  * FP32_DEV storage is widened and rho0 w_i added back.  out is a device
  * pointer to Q * N doubles.  Synchronises the stream. */
 int lbm_get_populations(lbm_handle *h, double *out);
+
+/* Quadratic acoustic energy of the current state about a reference state
+ * (rho_ref, U), summed over the nodes:
+ *     E = sum_r [ rho_ref |u - U|^2 / 2 + c_s^2 (rho - rho_ref)^2 / (2 rho_ref) ],
+ * c_s^2 = 1/3 (Sec. "Validation via dissipation of isothermal pressure waves":
+ * the energy whose decay rate gives the effective viscosity; the paper's
+ * printed integrand is linear in rho - rho0 and sums to a constant on a
+ * periodic grid, so the quadratic form of linear acoustics is used).
+ *   U        host pointer to D doubles (NULL = zero velocity).
+ *   rho_ref  > 0 and finite.
+ *   out      device pointer to one double, written when the stream reaches
+ *            the call.
+ * Enqueues two kernels and returns without synchronising, so that an energy
+ * history E(t) can be recorded step by step into a device array and read
+ * once.  The sum is taken in a fixed order (bitwise reproducible).  Errors:
+ * LBM_EINVAL (h or out NULL, rho_ref <= 0 or not finite, U not finite);
+ * LBM_EDEVICE. */
+int lbm_energy(lbm_handle *h, const double *U, double rho_ref, double *out);
 
 /* Release the handle (host state only; the caller's workspace is untouched).
  * Synchronises the stream first.  lbm_destroy(NULL) returns LBM_OK. */

@@ -76,8 +76,8 @@ __device__ __forceinline__ void source_rows(int y, int z, int ny, int nz, int64_
 #pragma unroll
     for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
 #pragma unroll
-        for (int cy = 0; cy < 3; ++cy)
-            rowoff[cz][cy] = (int64_t)(zs[cz] * ny + ys[cy]) * rs;
+        for (int cy = 0; cy < Lattice<DIM>::NY; ++cy)
+            rowoff[cz][cy] = (int64_t)(zs[cz] * ny + (DIM == 1 ? y : ys[cy])) * rs;
 }
 
 // One node's pull-stream, collision and store.  src/dst are population
@@ -95,7 +95,7 @@ __device__ __forceinline__ void step_node(const store_t<DT> *__restrict__ src, s
 #pragma unroll
     for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
 #pragma unroll
-        for (int cy = 0; cy < 3; ++cy)
+        for (int cy = 0; cy < Lattice<DIM>::NY; ++cy)
 #pragma unroll
             for (int cx = 0; cx < 3; ++cx) {
                 const int i = cx + 3 * cy + 9 * cz;
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_vec(StepArgs a) {
 #pragma unroll
     for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
 #pragma unroll
-        for (int cy = 0; cy < 3; ++cy)
+        for (int cy = 0; cy < Lattice<DIM>::NY; ++cy)
 #pragma unroll
             for (int cx = 0; cx < 3; ++cx) {
                 const int i = cx + 3 * cy + 9 * cz;
@@ -285,7 +285,7 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a) {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= a.n)
         return;
-    double u[3] = {a.u[n], a.u[a.n + n], DIM == 3 ? a.u[2 * a.n + n] : 0.0};
+    double u[3] = {a.u[n], DIM >= 2 ? a.u[a.n + n] : 0.0, DIM == 3 ? a.u[2 * a.n + n] : 0.0};
     double f[Q];
     const bool bad = equilibrium_stored<DIM, DEV, EQ>(a.rho[n], u, a.rho0, f);
     raise_flag(a.flag, bad);
@@ -411,6 +411,74 @@ static __global__ __launch_bounds__(kReduceThreads) void k_reduce_partials(const
         acc[6] = fmin(acc[6], p[6]);
     }
     block_reduce_diag(acc, out);
+}
+
+// Quadratic acoustic energy about a reference state (rho_ref, U), summed over
+// the grid: e = rho_ref |u - U|^2 / 2 + c_s^2 (rho - rho_ref)^2 / (2 rho_ref),
+// c_s^2 = 1/3.  Per-workgroup partial sums, then one fixed-order fold.
+struct EnergyArgs {
+    const void *src;
+    int64_t n;
+    int nx;
+    int64_t ps, rs;
+    double rho0;  // deviation reference of the storage (0 for FP64 storage)
+    double rho_ref;
+    double U[3];
+    double *partials;  // gridDim.x values
+};
+
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double lds[kReduceThreads / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    v = wave_sum(v);
+    if (lane == 0)
+        lds[wave] = v;
+    __syncthreads();
+    double r = lds[0];
+    for (int w = 1; w < kReduceThreads / 64; ++w)
+        r += lds[w];
+    return r;
+}
+
+template <int DIM, bool DEV>
+__global__ __launch_bounds__(kReduceThreads) void k_energy(EnergyArgs a) {
+    using T = store_t<DEV>;
+    constexpr int Q = Lattice<DIM>::Q;
+    const T *src = static_cast<const T *>(a.src);
+    const double half_cs2_over_rho = (1.0 / 6.0) / a.rho_ref;
+    double acc = 0.0;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < a.n;
+         n += (int64_t)gridDim.x * blockDim.x) {
+        const T *p = src + node_offset(n, a.nx, a.rs);
+        double f[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            f[i] = (double)p[i * a.ps];
+        double rho, j[3];
+        node_moments<DIM>(f, DEV ? a.rho0 : 0.0, rho, j);
+        const double inv = 1.0 / rho;
+        double du2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            const double du = j[d] * inv - a.U[d];
+            du2 = fma(du, du, du2);
+        }
+        const double dr = rho - a.rho_ref;
+        acc += fma(0.5 * a.rho_ref, du2, (dr * dr) * half_cs2_over_rho);
+    }
+    const double r = block_sum(acc);
+    if (threadIdx.x == 0)
+        a.partials[blockIdx.x] = r;
+}
+
+static __global__ __launch_bounds__(kReduceThreads) void k_sum_partials(const double *partials, int count,
+                                                                        double *out) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < count; b += blockDim.x)
+        acc += partials[b];
+    const double r = block_sum(acc);
+    if (threadIdx.x == 0)
+        *out = r;
 }
 
 struct ExportArgs {

@@ -30,14 +30,17 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
         return LBM_EINVAL;
     }
     Layout L{};
-    if (cfg->lattice == LBM_D2Q9) {
+    if (cfg->lattice == LBM_D1Q3) {
+        L.dim = 1;
+        L.q = 3;
+    } else if (cfg->lattice == LBM_D2Q9) {
         L.dim = 2;
         L.q = 9;
     } else if (cfg->lattice == LBM_D3Q27) {
         L.dim = 3;
         L.q = 27;
     } else {
-        set_error("lattice must be LBM_D2Q9 or LBM_D3Q27");
+        set_error("lattice must be LBM_D1Q3, LBM_D2Q9 or LBM_D3Q27");
         return LBM_EINVAL;
     }
     if (cfg->dtype == LBM_FP64)
@@ -72,6 +75,10 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
     }
     if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1) {
         set_error("grid extents must be >= 1");
+        return LBM_EINVAL;
+    }
+    if (L.dim == 1 && (cfg->ny != 1 || cfg->nz != 1)) {
+        set_error("ny and nz must be 1 for D1Q3");
         return LBM_EINVAL;
     }
     if (L.dim == 2 && cfg->nz != 1) {
@@ -148,7 +155,7 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
         }
     }
     if (by == 0)
-        by = 256 / bx;
+        by = L.dim == 1 && bx % 64 == 0 ? 1 : 256 / bx;  // a D1Q3 grid has one row
     if (bx < 1 || by < 1 || bx * by > 256 || (bx * by) % 64 != 0 ||
         (bx % 64 != 0 && (bx > 64 || (bx & (bx - 1)) != 0))) {
         set_error("block_x * block_y must be a multiple of 64 and <= 256; block_x a multiple "
@@ -282,7 +289,9 @@ static InitFn init_kernel(int eq) {
 int launch_step(const Layout &L, const StepArgs &args, int dtype, bool corr, hipStream_t s, int nz) {
     dim3 block(L.block_x, L.block_y, 1);
     dim3 grid((unsigned)(args.tiles_x * args.tiles_y * nz));
-    StepFn fn = L.dim == 2 ? step_kernel<2>(L, dtype, corr) : step_kernel<3>(L, dtype, corr);
+    StepFn fn = L.dim == 1   ? step_kernel<1>(L, dtype, corr)
+                : L.dim == 2 ? step_kernel<2>(L, dtype, corr)
+                             : step_kernel<3>(L, dtype, corr);
     hipLaunchKernelGGL(fn, grid, block, 0, s, args);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
@@ -310,8 +319,9 @@ int domain_bind_and_init(DomainState &d, const lbm_config *cfg, const Layout &L,
     InitArgs ia{d.buf[0], rho, u, L.n, (int)cfg->nx, L.ps, L.rs, d.relax.rho0, d.flag};
     const bool dev = cfg->dtype != LBM_FP64;
     dim3 grid((unsigned)((L.n + 255) / 256)), block(256);
-    InitFn init_fn = L.dim == 2 ? (dev ? init_kernel<2, true>(L.eq) : init_kernel<2, false>(L.eq))
-                                : (dev ? init_kernel<3, true>(L.eq) : init_kernel<3, false>(L.eq));
+    InitFn init_fn = L.dim == 1   ? (dev ? init_kernel<1, true>(L.eq) : init_kernel<1, false>(L.eq))
+                     : L.dim == 2 ? (dev ? init_kernel<2, true>(L.eq) : init_kernel<2, false>(L.eq))
+                                  : (dev ? init_kernel<3, true>(L.eq) : init_kernel<3, false>(L.eq));
     hipLaunchKernelGGL(init_fn, grid, block, 0, s, ia);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
@@ -335,8 +345,9 @@ int domain_moments(DomainState &d, hipStream_t s, double *rho, double *u, lbm_di
     const bool dev = d.cfg.dtype != LBM_FP64;
     MomentArgs ma{d.buf[d.cur], rho, u, L.n, (int)d.cfg.nx, L.ps, L.rs, d.relax.rho0, d.partials};
     dim3 grid((unsigned)L.red_blocks), block(kReduceThreads);
-    void (*mom_fn)(MomentArgs) = L.dim == 2 ? (dev ? k_moments<2, true> : k_moments<2, false>)
-                                            : (dev ? k_moments<3, true> : k_moments<3, false>);
+    void (*mom_fn)(MomentArgs) = L.dim == 1   ? (dev ? k_moments<1, true> : k_moments<1, false>)
+                                 : L.dim == 2 ? (dev ? k_moments<2, true> : k_moments<2, false>)
+                                              : (dev ? k_moments<3, true> : k_moments<3, false>);
     hipLaunchKernelGGL(mom_fn, grid, block, 0, s, ma);
     hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kReduceThreads), 0, s, (const double *)d.partials,
                        L.red_blocks, d.diag_dev);
@@ -376,14 +387,34 @@ int domain_export(DomainState &d, hipStream_t s, double *out) {
     const bool dev = d.cfg.dtype != LBM_FP64;
     ExportArgs ea{d.buf[d.cur], out, L.n, (int)d.cfg.nx, L.ps, L.rs, d.relax.rho0};
     dim3 grid((unsigned)((L.n + 255) / 256)), block(256);
-    void (*exp_fn)(ExportArgs) = L.dim == 2 ? (dev ? k_export<2, true> : k_export<2, false>)
-                                            : (dev ? k_export<3, true> : k_export<3, false>);
+    void (*exp_fn)(ExportArgs) = L.dim == 1   ? (dev ? k_export<1, true> : k_export<1, false>)
+                                 : L.dim == 2 ? (dev ? k_export<2, true> : k_export<2, false>)
+                                              : (dev ? k_export<3, true> : k_export<3, false>);
     hipLaunchKernelGGL(exp_fn, grid, block, 0, s, ea);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess)
         e = hipStreamSynchronize(s);
     if (e != hipSuccess)
         return hip_fail(e, "population export");
+    return LBM_OK;
+}
+
+int domain_energy(DomainState &d, hipStream_t s, const double *U, double rho_ref, double *out) {
+    const Layout &L = d.L;
+    const bool dev = d.cfg.dtype != LBM_FP64;
+    EnergyArgs ea{d.buf[d.cur], L.n, (int)d.cfg.nx, L.ps, L.rs, d.relax.rho0, rho_ref, {0.0, 0.0, 0.0},
+                  d.partials};
+    for (int a = 0; a < L.dim; ++a)
+        ea.U[a] = U ? U[a] : 0.0;
+    void (*fn)(EnergyArgs) = L.dim == 1   ? (dev ? k_energy<1, true> : k_energy<1, false>)
+                             : L.dim == 2 ? (dev ? k_energy<2, true> : k_energy<2, false>)
+                                          : (dev ? k_energy<3, true> : k_energy<3, false>);
+    hipLaunchKernelGGL(fn, dim3((unsigned)L.red_blocks), dim3(kReduceThreads), 0, s, ea);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kReduceThreads), 0, s, (const double *)d.partials,
+                       L.red_blocks, out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return hip_fail(e, "energy launch");
     return LBM_OK;
 }
 
@@ -482,6 +513,24 @@ int lbm_moments(lbm_handle *h, double *rho, double *u, lbm_diag *diag) {
     return domain_moments(h->d, h->stream, rho, u, diag);
 }
 
+int lbm_energy(lbm_handle *h, const double *U, double rho_ref, double *out) {
+    if (!h || !out) {
+        set_error("NULL handle or output");
+        return LBM_EINVAL;
+    }
+    if (!(rho_ref > 0.0) || !std::isfinite(rho_ref)) {
+        set_error("rho_ref must be finite and > 0");
+        return LBM_EINVAL;
+    }
+    if (U)
+        for (int a = 0; a < h->d.L.dim; ++a)
+            if (!std::isfinite(U[a])) {
+                set_error("U must be finite");
+                return LBM_EINVAL;
+            }
+    return domain_energy(h->d, h->stream, U, rho_ref, out);
+}
+
 int lbm_get_populations(lbm_handle *h, double *out) {
     if (!h || !out) {
         set_error("NULL handle or output");
@@ -521,6 +570,6 @@ const char *lbm_status_string(int status) {
 
 const char *lbm_last_error(void) { return g_last_error; }
 
-const char *lbm_version(void) { return "lbm-entropic 0.2 (gfx950)"; }
+const char *lbm_version(void) { return "lbm-entropic 0.3 (gfx950)"; }
 
 }  // extern "C"

@@ -55,5 +55,7 @@ int domain_bind_and_init(DomainState &d, const lbm_config *cfg, const Layout &L,
 int domain_read_flag(const DomainState &d, hipStream_t s, int *flag);
 int domain_moments(DomainState &d, hipStream_t s, double *rho, double *u, lbm_diag *diag);
 int domain_export(DomainState &d, hipStream_t s, double *out);
+// Enqueue the acoustic energy about (rho_ref, U) into the device double *out.
+int domain_energy(DomainState &d, hipStream_t s, const double *U, double rho_ref, double *out);
 
 }  // namespace lbm

@@ -28,7 +28,7 @@
 // All arithmetic is double.  The library is compiled with FMA contraction off;
 // the fused multiply-adds below are written out.
 //
-// Population index: i = (c_x + 1) + 3 (c_y + 1) + 9 (c_z + 1).
+// Population index: i = (c_x + 1) + 3 (c_y + 1) + 9 (c_z + 1) (D1Q3: i = c_x + 1).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -49,12 +49,16 @@ using store_t = typename std::conditional<DT == kF64, double, float>::type;
 // 1-D weights of c = -1, 0, +1 (Sec. "Basic concepts").
 __host__ __device__ constexpr double w1(int k) { return k == 1 ? 2.0 / 3.0 : 1.0 / 6.0; }
 
+// D1Q3, D2Q9 and D3Q27 as tensor products of the 1-D stencil.  Loops over
+// (cz, cy, cx) with cy < NY, cz < NZ visit i = cx + 3 cy + 9 cz; the lattice
+// velocity along y is cy - 1 when DIM >= 2 (along z likewise when DIM == 3).
 template <int DIM>
 struct Lattice {
-    static constexpr int Q = DIM == 2 ? 9 : 27;
-    static constexpr int NZ = DIM == 2 ? 1 : 3;  // number of c_z values
+    static constexpr int Q = DIM == 1 ? 3 : (DIM == 2 ? 9 : 27);
+    static constexpr int NY = DIM >= 2 ? 3 : 1;  // number of c_y values
+    static constexpr int NZ = DIM == 3 ? 3 : 1;  // number of c_z values
     __host__ __device__ static constexpr double weight(int i) {
-        return w1(i % 3) * w1((i / 3) % 3) * (DIM == 2 ? 1.0 : w1(i / 9));
+        return DIM == 1 ? w1(i) : w1(i % 3) * w1((i / 3) % 3) * (DIM == 2 ? 1.0 : w1(i / 9));
     }
 };
 
@@ -63,30 +67,37 @@ struct Lattice {
 template <int DIM>
 __device__ __forceinline__ void node_moments(const double (&f)[Lattice<DIM>::Q], double rho_shift,
                                              double &rho, double (&j)[3]) {
-    // Row sums over c_x for every (c_y, c_z), then combine.
-    double row[3][3], rowx[3][3];
+    if constexpr (DIM == 1) {
+        rho = rho_shift + ((f[0] + f[1]) + f[2]);
+        j[0] = f[2] - f[0];
+        j[1] = 0.0;
+        j[2] = 0.0;
+    } else {
+        // Row sums over c_x for every (c_y, c_z), then combine.
+        double row[3][3], rowx[3][3];
 #pragma unroll
-    for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
+        for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
 #pragma unroll
-        for (int cy = 0; cy < 3; ++cy) {
-            const int b = 3 * cy + 9 * cz;
-            row[cz][cy] = (f[b + 0] + f[b + 1]) + f[b + 2];
-            rowx[cz][cy] = f[b + 2] - f[b + 0];
+            for (int cy = 0; cy < 3; ++cy) {
+                const int b = 3 * cy + 9 * cz;
+                row[cz][cy] = (f[b + 0] + f[b + 1]) + f[b + 2];
+                rowx[cz][cy] = f[b + 2] - f[b + 0];
+            }
+        double s = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+        for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz) {
+            const double plane = (row[cz][0] + row[cz][1]) + row[cz][2];
+            s += plane;
+            jx += (rowx[cz][0] + rowx[cz][1]) + rowx[cz][2];
+            jy += row[cz][2] - row[cz][0];
+            if (DIM == 3)
+                jz += (cz == 2 ? plane : (cz == 0 ? -plane : 0.0));
         }
-    double s = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-#pragma unroll
-    for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz) {
-        const double plane = (row[cz][0] + row[cz][1]) + row[cz][2];
-        s += plane;
-        jx += (rowx[cz][0] + rowx[cz][1]) + rowx[cz][2];
-        jy += row[cz][2] - row[cz][0];
-        if (DIM == 3)
-            jz += (cz == 2 ? plane : (cz == 0 ? -plane : 0.0));
+        rho = rho_shift + s;
+        j[0] = jx;
+        j[1] = jy;
+        j[2] = jz;
     }
-    rho = rho_shift + s;
-    j[0] = jx;
-    j[1] = jy;
-    j[2] = jz;
 }
 
 // Per-axis equilibrium factors g_{-1}, g_0, g_{+1} and S = sqrt(1 + 3 u^2).
@@ -199,14 +210,17 @@ __device__ __forceinline__ bool collide(T (&v)[Lattice<DIM>::Q], const Relax &r)
 #pragma unroll
     for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
 #pragma unroll
-        for (int cy = 0; cy < 3; ++cy) {
-            const double t = EQ == kEqPoly2 ? 0.0 : (DIM == 3 ? (rho * g[1][cy]) * g[2][cz] : rho * g[1][cy]);
+        for (int cy = 0; cy < Lattice<DIM>::NY; ++cy) {
+            const double t = EQ == kEqPoly2 || DIM == 1
+                                 ? rho
+                                 : (DIM == 3 ? (rho * g[1][cy]) * g[2][cz] : rho * g[1][cy]);
 #pragma unroll
             for (int cx = 0; cx < 3; ++cx) {
                 const int i = cx + 3 * cy + 9 * cz;
                 double feq;
                 if constexpr (EQ == kEqPoly2) {
-                    const double cu = (cx - 1) * u[0] + (cy - 1) * u[1] + (DIM == 3 ? (cz - 1) * u[2] : 0.0);
+                    const double cu = (cx - 1) * u[0] + (DIM >= 2 ? (cy - 1) * u[1] : 0.0) +
+                                      (DIM == 3 ? (cz - 1) * u[2] : 0.0);
                     feq = (Lattice<DIM>::weight(i) * rho) * fma(cu, fma(4.5, cu, 3.0), base_poly);
                 } else {
                     feq = t * g[0][cx];
@@ -242,28 +256,33 @@ __device__ __forceinline__ bool collide_dev_f32(float (&v)[Lattice<DIM>::Q], con
     for (int i = 0; i < Q; ++i)
         f[i] = (R)v[i];
     // moment sums of the deviations (row sums over c_x, then planes)
-    R row[3][3], rowx[3][3];
-#pragma unroll
-    for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
-#pragma unroll
-        for (int cy = 0; cy < 3; ++cy) {
-            const int b = 3 * cy + 9 * cz;
-            row[cz][cy] = (f[b + 0] + f[b + 1]) + f[b + 2];
-            rowx[cz][cy] = f[b + 2] - f[b + 0];
-        }
     R drho = 0, jx = 0, jy = 0, jz = 0;
+    if constexpr (DIM == 1) {
+        drho = (f[0] + f[1]) + f[2];
+        jx = f[2] - f[0];
+    } else {
+        R row[3][3], rowx[3][3];
 #pragma unroll
-    for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz) {
-        const R plane = (row[cz][0] + row[cz][1]) + row[cz][2];
-        drho += plane;
-        jx += (rowx[cz][0] + rowx[cz][1]) + rowx[cz][2];
-        jy += row[cz][2] - row[cz][0];
-        if (DIM == 3)
-            jz += (cz == 2 ? plane : (cz == 0 ? -plane : R(0)));
+        for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
+#pragma unroll
+            for (int cy = 0; cy < 3; ++cy) {
+                const int b = 3 * cy + 9 * cz;
+                row[cz][cy] = (f[b + 0] + f[b + 1]) + f[b + 2];
+                rowx[cz][cy] = f[b + 2] - f[b + 0];
+            }
+#pragma unroll
+        for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz) {
+            const R plane = (row[cz][0] + row[cz][1]) + row[cz][2];
+            drho += plane;
+            jx += (rowx[cz][0] + rowx[cz][1]) + rowx[cz][2];
+            jy += row[cz][2] - row[cz][0];
+            if (DIM == 3)
+                jz += (cz == 2 ? plane : (cz == 0 ? -plane : R(0)));
+        }
     }
     const R rho = (R)r.rho0 + drho;
     const R inv = R(1) / rho;
-    const R u[3] = {jx * inv, jy * inv, DIM == 3 ? jz * inv : R(0)};
+    const R u[3] = {jx * inv, DIM >= 2 ? jy * inv : R(0), DIM == 3 ? jz * inv : R(0)};
     bool bad = !(rho > R(0));
 #pragma unroll
     for (int a = 0; a < DIM; ++a)
@@ -290,8 +309,8 @@ __device__ __forceinline__ bool collide_dev_f32(float (&v)[Lattice<DIM>::Q], con
 #pragma unroll
     for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
 #pragma unroll
-        for (int cy = 0; cy < 3; ++cy) {
-            const float e = DIM == 3 ? fmaf(d[1][cy], d[2][cz], d[1][cy] + d[2][cz]) : d[1][cy];
+        for (int cy = 0; cy < Lattice<DIM>::NY; ++cy) {
+            const float e = DIM == 3 ? fmaf(d[1][cy], d[2][cz], d[1][cy] + d[2][cz]) : (DIM == 2 ? d[1][cy] : 0.0f);
 #pragma unroll
             for (int cx = 0; cx < 3; ++cx) {
                 const int i = cx + 3 * cy + 9 * cz;
@@ -338,14 +357,17 @@ __device__ __forceinline__ bool equilibrium_stored(double rho, const double (&u)
 #pragma unroll
     for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
 #pragma unroll
-        for (int cy = 0; cy < 3; ++cy) {
-            const double t = EQ == kEqPoly2 ? 0.0 : (DIM == 3 ? (rho * g[1][cy]) * g[2][cz] : rho * g[1][cy]);
+        for (int cy = 0; cy < Lattice<DIM>::NY; ++cy) {
+            const double t = EQ == kEqPoly2 || DIM == 1
+                                 ? rho
+                                 : (DIM == 3 ? (rho * g[1][cy]) * g[2][cz] : rho * g[1][cy]);
 #pragma unroll
             for (int cx = 0; cx < 3; ++cx) {
                 const int i = cx + 3 * cy + 9 * cz;
                 double feq;
                 if constexpr (EQ == kEqPoly2) {
-                    const double cu = (cx - 1) * u[0] + (cy - 1) * u[1] + (DIM == 3 ? (cz - 1) * u[2] : 0.0);
+                    const double cu = (cx - 1) * u[0] + (DIM >= 2 ? (cy - 1) * u[1] : 0.0) +
+                                      (DIM == 3 ? (cz - 1) * u[2] : 0.0);
                     feq = (Lattice<DIM>::weight(i) * rho) * fma(cu, fma(4.5, cu, 3.0), base_poly);
                 } else {
                     feq = t * g[0][cx];

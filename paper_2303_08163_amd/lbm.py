@@ -22,7 +22,8 @@ LIB_PATH = os.path.join(_HERE, "liblbm_entropic.so")
 
 # status codes (enum lbm_status)
 LBM_OK, LBM_EINVAL, LBM_EDOMAIN, LBM_EDEVICE, LBM_ENOMEM, LBM_EBUSY = 0, -1, -2, -3, -4, -5
-LBM_D2Q9, LBM_D3Q27 = 9, 27
+LBM_D1Q3, LBM_D2Q9, LBM_D3Q27 = 3, 9, 27
+LATTICE_OF_DIM = {1: LBM_D1Q3, 2: LBM_D2Q9, 3: LBM_D3Q27}
 LBM_FP64, LBM_FP32_DEV, LBM_FP32_DEV_MIXED, LBM_FP32_DEV_F32 = 0, 1, 2, 3
 LBM_EQ_ENTROPIC, LBM_EQ_POLY2, LBM_EQ_PRODUCT = 0, 1, 2
 EQUILIBRIA = {"entropic": LBM_EQ_ENTROPIC, "poly2": LBM_EQ_POLY2, "product": LBM_EQ_PRODUCT}
@@ -94,7 +95,7 @@ _lib = None
 
 # Exported symbols the header declares (checked by the CPU test suite).
 EXPORTS = ("lbm_workspace_bytes", "lbm_workspace_bytes_tuned", "lbm_create", "lbm_create_tuned",
-           "lbm_step", "lbm_moments", "lbm_get_populations", "lbm_destroy", "lbm_status_string",
+           "lbm_step", "lbm_moments", "lbm_get_populations", "lbm_energy", "lbm_destroy", "lbm_status_string",
            "lbm_last_error", "lbm_version", "lbm_pool_table_bytes", "lbm_pool_slot_bytes", "lbm_pool_create",
            "lbm_pool_admit", "lbm_pool_run", "lbm_pool_poll", "lbm_pool_moments", "lbm_pool_get_populations",
            "lbm_pool_release", "lbm_pool_stats_get", "lbm_pool_slot_info", "lbm_pool_destroy")
@@ -126,6 +127,7 @@ def load_library(path: str = LIB_PATH):
         "lbm_step": (ctypes.c_int, [vp, i64]),
         "lbm_moments": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(lbm_diag)]),
         "lbm_get_populations": (ctypes.c_int, [vp, vp]),
+        "lbm_energy": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_double, vp]),
         "lbm_destroy": (ctypes.c_int, [vp]),
         "lbm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "lbm_last_error": (ctypes.c_char_p, []),
@@ -164,9 +166,10 @@ def _check(status: int, where: str) -> int:
 
 def make_config(lattice: int, shape, tau: float, dtype="fp32_dev", bulk_correction=False,
                 rho0: float = 1.0, equilibrium="entropic") -> lbm_config:
-    """shape = (nx, ny) for D2Q9 or (nx, ny, nz) for D3Q27 (x first);
+    """shape = (nx,) for D1Q3, (nx, ny) for D2Q9 or (nx, ny, nz) for D3Q27 (x first);
     equilibrium: "entropic", "poly2", "product" or an LBM_EQ_* value."""
-    nx, ny = int(shape[0]), int(shape[1])
+    nx = int(shape[0])
+    ny = int(shape[1]) if len(shape) > 1 else 1
     nz = int(shape[2]) if len(shape) > 2 else 1
     return lbm_config(int(lattice), DTYPES.get(dtype, dtype), nx, ny, nz, float(tau),
                       int(bool(bulk_correction)), EQUILIBRIA.get(equilibrium, equilibrium), float(rho0))
@@ -217,6 +220,12 @@ def lbm_moments(h, rho: int | None, u: int | None, raise_on_domain: bool = True)
 
 def lbm_get_populations(h, out: int) -> None:
     _check(load_library().lbm_get_populations(h, out), "lbm_get_populations")
+
+
+def lbm_energy(h, U, rho_ref: float, out: int) -> None:
+    """Enqueue E about (rho_ref, U) into the device double at address out."""
+    arr = None if U is None else (ctypes.c_double * 3)(*[float(v) for v in U] + [0.0] * (3 - len(U)))
+    _check(load_library().lbm_energy(h, arr, float(rho_ref), out), "lbm_energy")
 
 
 def lbm_destroy(h) -> None:
@@ -310,7 +319,7 @@ def lbm_version() -> str:
 class Domain:
     """One periodic domain on the GPU.
 
-    rho: numpy array of the grid's shape ((ny, nx) or (nz, ny, nx), x fastest);
+    rho: numpy array of the grid's shape ((nx,), (ny, nx) or (nz, ny, nx), x fastest);
     u: (D, *rho.shape).  The fields are copied to the device as float64.
     stream: a torch.cuda.Stream (default: torch's current stream).
     equilibrium: "entropic" (default), "poly2" or "product" (LBM_EQ_*).
@@ -325,12 +334,12 @@ class Domain:
             rho = np.asarray(rho, dtype=np.float64)
             u = np.asarray(u, dtype=np.float64)
         D = rho.ndim
-        if D not in (2, 3) or tuple(u.shape) != (D,) + tuple(rho.shape):
-            raise ValueError("rho must be 2-D or 3-D and u of shape (D, *rho.shape)")
+        if D not in (1, 2, 3) or tuple(u.shape) != (D,) + tuple(rho.shape):
+            raise ValueError("rho must be 1-D, 2-D or 3-D and u of shape (D, *rho.shape)")
         self.shape = tuple(rho.shape)
         self.D = D
-        self.lattice = LBM_D2Q9 if D == 2 else LBM_D3Q27
-        self.Q = 9 if D == 2 else 27
+        self.lattice = LATTICE_OF_DIM[D]
+        self.Q = 3 ** D
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.cfg = make_config(self.lattice, rho.shape[::-1], tau, dtype, bulk_correction, rho0, equilibrium)
@@ -385,6 +394,19 @@ class Domain:
         out = torch.empty((self.Q,) + self.shape, dtype=torch.float64, device=self.device)
         lbm_get_populations(self.handle, out.data_ptr())
         return out.cpu().numpy()
+
+    def energy(self, U=None, rho_ref: float = 1.0, out=None):
+        """Enqueue the acoustic energy about (rho_ref, U) (no synchronisation).
+
+        out: a float64 CUDA tensor element to write (e.g. history[t]); a new
+        one-element tensor when None.  Returns the tensor written."""
+        import torch
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=self.device)
+        if out.dtype != torch.float64 or not out.is_cuda:
+            raise ValueError("out must be a float64 CUDA tensor")
+        lbm_energy(self.handle, U, rho_ref, out.data_ptr())
+        return out
 
     def close(self) -> None:
         if getattr(self, "handle", None) is not None:

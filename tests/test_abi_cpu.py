@@ -73,6 +73,9 @@ def test_workspace_bytes_layout(lbm):
     # row-interleaved layout (default): each population run padded to 64 elements
     e70 = lbm.lbm_workspace_bytes(_cfg(lbm, shape=(70, 32)))
     assert e70 == 2 * 9 * 128 * 32 * 8 + 256 + 256 + ((9 * 7 * 8 + 255) // 256) * 256
+    # D1Q3: one row of 3 runs; 64 x 3 doubles per buffer, one reduction block
+    assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(64,))) == 2 * 3 * 64 * 8 + 256 + 256 + 256
+    assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(70,))) == 2 * 3 * 128 * 8 + 256 + 256 + 256
     # below 64 the run is not padded
     assert lbm.lbm_workspace_bytes(_cfg(lbm, shape=(5, 3))) == 2 * 1280 + 256 + 256 + 256  # 1080 B buffers, 256-aligned
 
@@ -82,6 +85,7 @@ def test_workspace_bytes_layout(lbm):
     dict(lattice=19), dict(dtype=7), dict(shape=(0, 5)), dict(shape=(5, 0)),
     dict(shape=(4, 4, 2)), dict(lattice=27, shape=(4, 4, 0)), dict(dtype="fp32_dev", rho0=0.0),
     dict(dtype="fp32_dev", rho0=-1.0), dict(shape=(70000, 70000)), dict(lattice=27, shape=(2, 2, 2 ** 30)), dict(shape=(2 ** 31, 1)),
+    dict(lattice=3, shape=(64, 2)), dict(lattice=3, shape=(64, 1, 2)), dict(lattice=3, shape=(0,)),
     dict(equilibrium=3), dict(equilibrium=-1), dict(equilibrium="poly2", dtype="fp32_dev_mixed"),
     dict(equilibrium="product", dtype="fp32_dev_f32"),
 ])
@@ -124,6 +128,18 @@ def test_polynomial_equilibria_configs(lbm):
         assert b"entropic" in lbm.load_library().lbm_last_error()
 
 
+def test_d1q3_configs(lbm):
+    for dt in ("fp64", "fp32_dev", "fp32_dev_mixed", "fp32_dev_f32"):
+        assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(300,), dtype=dt)) > 0
+    for eq in ("entropic", "poly2", "product"):
+        assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(512,), dtype="fp32_dev", equilibrium=eq)) > 0
+    # vector kernels: 4 floats or 2 doubles per thread when nx tiles evenly
+    assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(256,), dtype="fp32_dev"),
+                                   lbm.make_tuning(64, 1, -1, 4, 3)) > 0
+    # pool slots run D2Q9 or D3Q27
+    assert lbm.lbm_pool_slot_bytes(_cfg(lbm, lattice=3, shape=(64,))) == 0
+
+
 def test_create_argument_checks_precede_gpu_work(lbm):
     lib = lbm.load_library()
     cfg = _cfg(lbm)
@@ -140,6 +156,7 @@ def test_create_argument_checks_precede_gpu_work(lbm):
     assert lib.lbm_step(None, 1) == lbm.LBM_EINVAL
     assert lib.lbm_moments(None, None, None, None) == lbm.LBM_EINVAL
     assert lib.lbm_get_populations(None, None) == lbm.LBM_EINVAL
+    assert lib.lbm_energy(None, None, 1.0, 256) == lbm.LBM_EINVAL
     assert lib.lbm_destroy(None) == lbm.LBM_OK
     assert b"NULL" in lib.lbm_last_error()
 

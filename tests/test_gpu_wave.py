@@ -1,0 +1,219 @@
+"""GPU tests of the D1Q3 lattice, the acoustic-energy reduction (lbm_energy)
+and the isothermal pressure-wave workload (Sec. "Validation via dissipation of
+isothermal pressure waves").
+
+D1Q3 runs are compared with the FP64 oracle element by element (normwise,
+1e-12 FP64 / 1e-5 FP32 deviation storage).  The energy is compared with the
+same sum written out in numpy over the oracle's moments: it is a sum of
+squares of deviations from (rho_ref, U), so its relative error is the moments'
+relative error amplified by |u| / |u - U| (about 10^2 for a pressure wave of
+amplitude 1e-3 carried at U0 = 0.2); the FP64 bound is 1e-10 for that reason."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2303_08163_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32_dev": 1e-5}
+DTYPES = ["fp64", "fp32_dev"]
+CS2 = 1.0 / 3.0
+
+
+def _lbm():
+    from paper_2303_08163_amd import lbm
+    return lbm
+
+
+def _wave():
+    from paper_2303_08163_amd import wave
+    return wave
+
+
+def rel_err(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / np.max(np.abs(b)))
+
+
+def run_gpu(rho0, u0, tau, steps, dtype, corr, eq="entropic", tuning=None, populations=False):
+    lbm = _lbm()
+    with lbm.Domain(rho0, u0, tau, dtype=dtype, bulk_correction=corr, tuning=tuning, equilibrium=eq) as d:
+        d.step(steps)
+        rho, u, diag = d.moments(raise_on_domain=False)
+        f = d.populations() if populations else None
+    return rho, u, diag, f
+
+
+def energy_np(rho, u, U, rho_ref=1.0):
+    du2 = sum((u[a] - U[a]) ** 2 for a in range(u.shape[0]))
+    return float(np.sum(0.5 * rho_ref * du2 + CS2 * (rho - rho_ref) ** 2 / (2.0 * rho_ref)))
+
+
+# --- D1Q3 -----------------------------------------------------------------
+
+@pytest.mark.parametrize("eq", ["entropic", "poly2", "product"])
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("corr", [False, True])
+@pytest.mark.parametrize("nx", [300, 256, 512, 37])
+def test_d1q3_matches_oracle(eq, dtype, corr, nx):
+    rho0, u0 = workloads.random_field((nx,), seed=91, umax=0.3)
+    rho, u, diag, _ = run_gpu(rho0, u0, 0.56, 25, dtype, corr, eq)
+    r_ref, u_ref, bad = oracle.run(rho0, u0, 0.56, 25, corr="min" if corr else "off", kind=eq)
+    assert bad == 0 and not diag["domain_error"]
+    er, eu = rel_err(rho, r_ref), rel_err(u, u_ref)
+    print(f"[parity] D1Q3 nx={nx} {eq} {dtype} corr={corr}: rel err rho {er:.3e}  u {eu:.3e}", flush=True)
+    assert er < TOL[dtype] and eu < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32_dev", "fp32_dev_mixed", "fp32_dev_f32"])
+def test_d1q3_tunings_bitwise(dtype):
+    lbm = _lbm()
+    rho0, u0 = workloads.random_field((512,), seed=92, umax=0.2)
+    wide = 4 if dtype != "fp64" else 2
+    tunings = [lbm.make_tuning(64, 1, -1, 1, 0), lbm.make_tuning(256, 1, -1, 1, 0), lbm.make_tuning(128, 2, -1, 1, 0),
+               lbm.make_tuning(64, 1, -1, 2, 1), lbm.make_tuning(64, 4, -1, wide, 0),
+               lbm.make_tuning(0, 0, -1, 0, -1, lbm.LBM_LAYOUT_PLANES), None]
+    ref = None
+    for t in tunings:
+        out = run_gpu(rho0, u0, 0.53, 17, dtype, True, tuning=t, populations=True)
+        if ref is None:
+            ref = out
+        assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]) and np.array_equal(out[3], ref[3])
+
+
+def test_d1q3_populations_match_oracle():
+    """f*_i(x, n) = f_i(x + c_i, n + 1) on the oracle's pre-collision populations."""
+    rho0, u0 = workloads.random_field((23,), seed=93, umax=0.4)
+    _, _, _, f_gpu = run_gpu(rho0, u0, 0.6, 4, "fp64", True, populations=True)
+    _, _, _, f_or = oracle.run(rho0, u0, 0.6, 5, corr="min", return_f=True)
+    c, _ = oracle.lattice(1)
+    for k, ck in enumerate(c):
+        i = int(ck[0] + 1)
+        back = np.roll(f_or[k], shift=-int(ck[0]))
+        assert np.max(np.abs(f_gpu[i] - back)) < 1e-13
+
+
+@pytest.mark.parametrize("width", [1, 3])
+def test_d1q3_embeds_in_d2q9_and_d3q27(width):
+    """A field uniform in y and z evolves on D2Q9 / D3Q27 as on D1Q3."""
+    rho1, u1 = workloads.random_field((70,), seed=94, umax=0.3)
+    r1, v1, _, _ = run_gpu(rho1, u1, 0.55, 30, "fp64", True)
+    rho2 = np.broadcast_to(rho1, (width, 70)).copy()
+    u2 = np.zeros((2, width, 70))
+    u2[0] = u1[0]
+    r2, v2, _, _ = run_gpu(rho2, u2, 0.55, 30, "fp64", True)
+    rho3 = np.broadcast_to(rho1, (width, width, 70)).copy()
+    u3 = np.zeros((3, width, width, 70))
+    u3[0] = u1[0]
+    r3, v3, _, _ = run_gpu(rho3, u3, 0.55, 30, "fp64", True)
+    for y in range(width):
+        assert rel_err(r2[y], r1) < 1e-13 and rel_err(v2[0, y], v1[0]) < 1e-12
+        assert np.max(np.abs(v2[1, y])) < 1e-15
+        for z in range(width):
+            assert rel_err(r3[z, y], r1) < 1e-13 and rel_err(v3[0, z, y], v1[0]) < 1e-12
+
+
+# --- acoustic energy -------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(300,), (33, 70), (11, 13, 19)])
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_energy_matches_oracle_moments(shape, dtype):
+    import torch
+    lbm = _lbm()
+    rho0, u0 = workloads.random_field(shape, seed=95, umax=0.2)
+    D = len(shape)
+    U = [0.1, -0.05, 0.02][:D]
+    r_ref, u_ref, _ = oracle.run(rho0, u0, 0.58, 12, corr="min")
+    e_ref = energy_np(r_ref, u_ref, U, rho_ref=1.1)
+    with lbm.Domain(rho0, u0, 0.58, dtype=dtype, bulk_correction=True) as d:
+        d.step(12)
+        e1 = d.energy(U, 1.1)
+        e2 = d.energy(U, 1.1)
+        torch.cuda.synchronize()
+        e1, e2 = float(e1.item()), float(e2.item())
+    assert e1 == e2  # fixed reduction order
+    assert abs(e1 - e_ref) / e_ref < (1e-12 if dtype == "fp64" else 1e-5)
+
+
+def test_energy_argument_checks():
+    import torch
+    lbm = _lbm()
+    rho0, u0 = workloads.random_field((64,), seed=96, umax=0.1)
+    out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    with lbm.Domain(rho0, u0, 0.6, dtype="fp64") as d:
+        for bad in (0.0, -1.0, float("nan")):
+            with pytest.raises(lbm.LBMError) as e:
+                d.energy([0.0], bad, out=out)
+            assert e.value.status == lbm.LBM_EINVAL
+        with pytest.raises(lbm.LBMError):
+            d.energy([float("inf")], 1.0, out=out)
+        d.energy(None, 1.0, out=out)  # U = NULL is the zero velocity
+        torch.cuda.synchronize()
+        assert float(out.item()) == pytest.approx(energy_np(rho0, u0, [0.0]), rel=1e-12)
+
+
+# --- pressure-wave workload --------------------------------------------------
+
+@pytest.mark.parametrize("eq", ["entropic", "product"])
+@pytest.mark.parametrize("corr", [False, True])
+def test_wave_energy_history_matches_oracle(eq, corr):
+    wave = _wave()
+    nx, drho, U0, tau = 64, 1e-3, 0.2, 0.65
+    t, E, diag = wave.energy_history(nx, drho, U0, tau, 600, every=100, bulk_correction=corr, equilibrium=eq)
+    assert diag["steps"] == 600 and not diag["domain_error"]
+    rho0, u0 = workloads.pressure_wave(nx, drho, U0)
+    for k, tk in enumerate(t):
+        r, u, _ = oracle.run(rho0, u0, tau, int(tk), corr="min" if corr else "off", kind=eq)
+        e_ref = energy_np(r, u, [U0])
+        assert abs(E[k] - e_ref) / e_ref < 1e-10, (k, E[k], e_ref)
+
+
+def test_wave_embeddings_give_the_same_energy():
+    """D2Q9 (width 4) and D3Q27 (width 2 x 2) waves carry width^(D-1) copies of the D1Q3 energy."""
+    wave = _wave()
+    _, E1, _ = wave.energy_history(64, 1e-3, 0.15, 0.65, 400, every=100, bulk_correction=True)
+    _, E2, _ = wave.energy_history(64, 1e-3, 0.15, 0.65, 400, every=100, bulk_correction=True, dim=2, width=4)
+    _, E3, _ = wave.energy_history(64, 1e-3, 0.15, 0.65, 400, every=100, bulk_correction=True, dim=3, width=2)
+    assert np.max(np.abs(E2 / 4 - E1) / E1) < 1e-10
+    assert np.max(np.abs(E3 / 4 - E1) / E1) < 1e-10
+
+
+def test_wave_effective_viscosity_follows_A_and_the_correction_restores_it():
+    """Sec. "Validation via dissipation of isothermal pressure waves": without
+    the correction nu_eff / nu_eff(0) follows A(U0) (entropic: eq. entropic_bulk;
+    product form: eq. LBGK_bulk); with it, it returns to within 2 % of 1, and
+    the product form deviates more than the entropic equilibrium."""
+    wave = _wave()
+    rows = wave.sweep([-0.3, -0.1, 0.2, 0.3])
+    by = {(r["equilibrium"], r["bulk_correction"], r["U0"]): r for r in rows}
+    for U0 in (-0.3, -0.1, 0.2, 0.3):
+        for eq in ("entropic", "product"):
+            A = oracle.bulk_A(U0, "entropic" if eq == "entropic" else "poly2")
+            off, on = by[eq, False, U0]["normalised"], by[eq, True, U0]["normalised"]
+            print(f"[wave] {eq} U0={U0:+.2f}: off {off:.4f} (A {A:.4f})  on {on:.4f}", flush=True)
+            assert off == pytest.approx(A, rel=0.015)
+            assert on == pytest.approx(1.0, abs=0.02)
+            assert abs(on - 1.0) < abs(off - 1.0)
+        assert by["product", False, U0]["normalised"] < by["entropic", False, U0]["normalised"]
+    nu0 = by["entropic", False, 0.0]["ratio"]
+    assert nu0 == pytest.approx(1.0, rel=0.005)  # the fit recovers nu at rest
+
+
+def test_wave_fit_matches_oracle_fit():
+    """The GPU's fitted viscosity equals the one fitted to the oracle's energies
+    at the same sample times."""
+    wave = _wave()
+    nx, drho, U0, tau = 64, 1e-3, -0.25, 0.65
+    t, E, _ = wave.energy_history(nx, drho, U0, tau, 1200, every=100, bulk_correction=True)
+    rho0, u0 = workloads.pressure_wave(nx, drho, U0)
+    E_ref = []
+    for tk in t:
+        r, u, _ = oracle.run(rho0, u0, tau, int(tk), corr="min")
+        E_ref.append(energy_np(r, u, [U0]))
+    g = wave.decay_rate(t, E, 200)
+    o = wave.decay_rate(t, E_ref, 200)
+    assert abs(g - o) / o < 1e-8
+    k = 2 * math.pi / nx
+    assert wave.effective_viscosity(g, nx) == pytest.approx(g / (2 * k * k))
