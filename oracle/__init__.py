@@ -72,6 +72,9 @@ def _load():
                                       ctypes.c_double, ctypes.c_int, ctypes.c_int, dp, dp,
                                       ctypes.c_long, ctypes.c_long, lp, lp, lp, dp, dp]
     lib.oracle_run_sample.restype = ctypes.c_long
+    lib.oracle_jacobian.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                    dp, dp]
+    lib.oracle_jacobian.restype = ctypes.c_int
     lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_set_threads.restype = ctypes.c_int
     _lib = lib
@@ -123,6 +126,17 @@ def equilibrium(rho: float, u, kind: str = "entropic"):
 def bulk_A(u: float, kind: str = "entropic") -> float:
     """Effective-viscosity factor A(u) of a 1-D velocity."""
     return _load().oracle_bulk_A(EQ_KINDS[kind], float(u))
+
+
+def jacobian(tau: float, u, corr="off", kind: str = "entropic", rho: float = 1.0) -> np.ndarray:
+    """Jacobian (Q, Q) of the collision operator at f = f^eq(rho, u), oracle ordering."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    D = u.shape[0]
+    J = np.zeros(27 * 27)
+    Q = _load().oracle_jacobian(D, EQ_KINDS[kind], CORR_MODES[corr], float(tau), float(rho), _dptr(u), _dptr(J))
+    if Q < 0:
+        raise ValueError("bad arguments")
+    return J[: Q * Q].reshape(Q, Q).copy()
 
 
 def beta(tau: float, u, corr="off", kind: str = "entropic") -> float:

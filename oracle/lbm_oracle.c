@@ -419,3 +419,96 @@ int oracle_set_threads(int n)
     return 1;
 #endif
 }
+
+/* Sec. "von Neumann spectral analysis: introduction" and the appendix
+ * "Jacobian of entropic equilibrium": the Jacobian J_ij = d Omega_i / d f_j
+ * of the collision operator Omega_i = 2 beta (f_i^eq - f_i), evaluated at the
+ * equilibrium state f = f^eq(rho, u).
+ *
+ * At that state f^eq - f = 0, so the velocity dependence of beta under the
+ * bulk correction contributes nothing: J = 2 beta(u) (d f^eq / d f - I).
+ * d f^eq / d f follows from the chain rule through the moments,
+ *     d rho / d f_j = 1,   d u_a / d f_j = (c_ja - u_a) / rho.
+ * Entropic equilibrium, written as f_i^eq = w_i rho prod_a Lambda_a Gamma_ia
+ * with Lambda_a = 2 - S_a, Gamma_ia = Z_a^{c_ia}, Z_a = (2 u_a + S_a) / (1 - u_a):
+ *     d f_i^eq / d f_j = f_i^eq [ d ln rho + sum_a (d ln Lambda_a + d ln Gamma_ia) ],
+ *     d S_a / d f_j = ((c_ja u_a / varsigma^2 + 1) / S_a - S_a) / rho,
+ *     d ln Lambda_a / d f_j = -(d S_a / d f_j) / Lambda_a,
+ *     d ln Gamma_ia / d f_j = c_ia [ (2 d u_a + d S_a) / (2 u_a + S_a) + d u_a / (1 - u_a) ].
+ * (The printed derivative of Gamma is garbled; the last line is the
+ * derivative of c_ia ln Z_a.)
+ * Second-order polynomial equilibrium: its closed form differentiated in rho
+ * and u.  Product form: f_i^eq = rho prod_a phi_{c_ia}(u_a) with
+ * phi_0 = 1 - varsigma^2 - u^2 and phi_{+-1} = (+-u + varsigma^2 + u^2) / 2, so
+ * d phi_0 / du = -2 u and d phi_{+-1} / du = (+-1 + 2 u) / 2.
+ *
+ * J is written row-major (J[i * Q + j]) in the oracle's population order.
+ * Returns Q, or -1 for bad arguments. */
+int oracle_jacobian(int D, int kind, int corr_mode, double tau, double rho, const double *u, double *J)
+{
+    int c[27 * 3];
+    double w[27], feq[27];
+    int Q = oracle_lattice(D, c, w);
+    if (Q < 0 || !(rho > 0.0) || !(tau > 0.5))
+        return -1;
+    if (equilibrium_on(D, Q, c, w, kind, rho, u, feq) < 0)
+        return -1;
+    double two_beta = 2.0 * oracle_beta(D, kind, corr_mode, tau, u);
+
+    for (int j = 0; j < Q; j++) {
+        double du[3] = {0.0, 0.0, 0.0}; /* d u_a / d f_j */
+        for (int a = 0; a < D; a++)
+            du[a] = (c[3 * j + a] - u[a]) / rho;
+        for (int i = 0; i < Q; i++) {
+            double dfeq;
+            if (kind == ORACLE_EQ_ENTROPIC) {
+                double dlog = 1.0 / rho; /* d ln rho / d f_j */
+                for (int a = 0; a < D; a++) {
+                    double S = sqrt((u[a] * u[a]) / CS2 + 1.0);
+                    double dS = ((c[3 * j + a] * u[a] / CS2 + 1.0) / S - S) / rho;
+                    double Lambda = 2.0 - S;
+                    dlog += -dS / Lambda;
+                    dlog += c[3 * i + a] * ((2.0 * du[a] + dS) / (2.0 * u[a] + S) + du[a] / (1.0 - u[a]));
+                }
+                dfeq = feq[i] * dlog;
+            } else if (kind == ORACLE_EQ_POLY2) {
+                double cu = 0.0, usq = 0.0;
+                for (int a = 0; a < D; a++) {
+                    cu += c[3 * i + a] * u[a];
+                    usq += u[a] * u[a];
+                }
+                double bracket = 1.0 + cu / CS2 + (cu * cu) / (2.0 * CS2 * CS2) - usq / (2.0 * CS2);
+                dfeq = w[i] * bracket; /* d rho / d f_j = 1 */
+                for (int a = 0; a < D; a++) {
+                    double dbracket_du = c[3 * i + a] / CS2 + cu * c[3 * i + a] / (CS2 * CS2) - u[a] / CS2;
+                    dfeq += w[i] * rho * dbracket_du * du[a];
+                }
+            } else {
+                double phi[3], dphi[3];
+                for (int a = 0; a < D; a++) {
+                    int ca = c[3 * i + a];
+                    if (ca == 0) {
+                        phi[a] = 1.0 - CS2 - u[a] * u[a];
+                        dphi[a] = -2.0 * u[a];
+                    } else {
+                        phi[a] = (ca * u[a] + CS2 + u[a] * u[a]) / 2.0;
+                        dphi[a] = (ca + 2.0 * u[a]) / 2.0;
+                    }
+                }
+                double prod = 1.0;
+                for (int a = 0; a < D; a++)
+                    prod *= phi[a];
+                dfeq = prod; /* d rho / d f_j = 1 */
+                for (int a = 0; a < D; a++) {
+                    double others = 1.0;
+                    for (int b = 0; b < D; b++)
+                        if (b != a)
+                            others *= phi[b];
+                    dfeq += rho * others * dphi[a] * du[a];
+                }
+            }
+            J[i * Q + j] = two_beta * (dfeq - (i == j ? 1.0 : 0.0));
+        }
+    }
+    return Q;
+}
