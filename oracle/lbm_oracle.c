@@ -46,7 +46,9 @@
  *
  * Compiled with gcc -O2 -ffp-contract=off (no fast-math), optionally with
  * OpenMP over nodes; each node is computed independently, so the result does
- * not depend on the thread count.
+ * not depend on the thread count.  The state, moments, relaxation and
+ * streaming are IEEE double; the equilibrium's closed forms are evaluated in
+ * extended precision and rounded once per population (see equilibrium_on).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -104,56 +106,70 @@ int oracle_lattice(int D, int *c, double *w)
  *       + 1)), then f_i = w_i X^{-1} prod_alpha Z_alpha^{c_ia};
  *   ORACLE_EQ_POLY2: eq. (Poly2_isothermal_EDF);
  *   ORACLE_EQ_PRODUCT: eq. (Product_isothermal_EDF).
+ * The closed forms are evaluated in extended precision (long double, 64-bit
+ * significand on x86-64) and each f_i is rounded once to double.  The
+ * equilibrium meets the mass and momentum constraints exactly (Sec. "Discrete
+ * entropic equilibrium construction"); a double evaluation of the multiplier
+ * form misses the momentum constraint by a few units in the last place with a
+ * sign that stays the same from one step to the next, so under repeated
+ * collisions it acts as a small spurious force and the velocity drifts
+ * linearly in time.  One rounding per population keeps that below the
+ * rounding of the state itself.
  * Returns 0, or 1 when (rho, u) lies outside the entropic equilibrium's domain
  * (rho <= 0, |u_alpha| >= 1, or a non-finite input); the values are still
  * written, whatever they evaluate to. */
+typedef long double xreal;
+
 static int equilibrium_on(int D, int Q, const int *c, const double *w, int kind, double rho,
                           const double *u, double *feq)
 {
+    const xreal cs2 = 1.0L / 3.0L;
     int bad = !(rho > 0.0) || !isfinite(rho);
     for (int a = 0; a < D; a++)
         if (!(fabs(u[a]) < 1.0))
             bad = 1;
 
     if (kind == ORACLE_EQ_ENTROPIC) {
-        double Z[3], Xinv = rho;
+        xreal Z[3], Xinv = rho;
         for (int a = 0; a < D; a++) {
-            double root = sqrt((u[a] * u[a]) / CS2 + 1.0);
-            Z[a] = (2.0 * u[a] + root) / (1.0 - u[a]);
-            Xinv *= (2.0 - root);
+            xreal ua = u[a];
+            xreal root = sqrtl((ua * ua) / cs2 + 1.0L);
+            Z[a] = (2.0L * ua + root) / (1.0L - ua);
+            Xinv *= (2.0L - root);
         }
         for (int i = 0; i < Q; i++) {
-            double prod = 1.0;
+            xreal prod = 1.0L;
             for (int a = 0; a < D; a++) {
                 if (c[3 * i + a] == 1)
                     prod *= Z[a];
                 else if (c[3 * i + a] == -1)
                     prod /= Z[a];
             }
-            feq[i] = w[i] * Xinv * prod;
+            feq[i] = (double)((xreal)w[i] * Xinv * prod);
         }
     } else if (kind == ORACLE_EQ_POLY2) {
-        double usq = 0.0;
+        xreal usq = 0.0L;
         for (int a = 0; a < D; a++)
-            usq += u[a] * u[a];
+            usq += (xreal)u[a] * u[a];
         for (int i = 0; i < Q; i++) {
-            double cu = 0.0;
+            xreal cu = 0.0L;
             for (int a = 0; a < D; a++)
-                cu += c[3 * i + a] * u[a];
-            feq[i] = w[i] * rho *
-                     (1.0 + cu / CS2 + (cu * cu) / (2.0 * CS2 * CS2) - usq / (2.0 * CS2));
+                cu += c[3 * i + a] * (xreal)u[a];
+            feq[i] = (double)((xreal)w[i] * rho *
+                              (1.0L + cu / cs2 + (cu * cu) / (2.0L * cs2 * cs2) - usq / (2.0L * cs2)));
         }
     } else if (kind == ORACLE_EQ_PRODUCT) {
         for (int i = 0; i < Q; i++) {
-            double prod = rho;
+            xreal prod = rho;
             for (int a = 0; a < D; a++) {
                 int ca = c[3 * i + a];
+                xreal ua = u[a];
                 if (ca == 0)
-                    prod *= (1.0 - CS2 - u[a] * u[a]);
+                    prod *= (1.0L - cs2 - ua * ua);
                 else
-                    prod *= (ca * u[a] + CS2 + u[a] * u[a]) / 2.0;
+                    prod *= (ca * ua + cs2 + ua * ua) / 2.0L;
             }
-            feq[i] = prod;
+            feq[i] = (double)prod;
         }
     } else {
         return -1;
