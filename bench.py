@@ -15,6 +15,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -188,6 +189,92 @@ def bench_wave(steps: int = 2000) -> dict:
             "runs": len(rows), "wall_s": round(wall, 3)}
 
 
+# FP64 operations of one D2Q9 amplification-matrix eigensolve as written in
+# the kernel (a fused multiply-add counts 2; divisions, square roots and
+# transcendentals 1): building M (about 800), the Householder reduction
+# (sum over m = 8..2 of 16 m^2 + 150 m + 32 = 8722), norm and radius (about
+# 200), and 2124 per QR step.
+VN_FLOPS_FIXED = 9718
+VN_FLOPS_PER_STEP = 2124
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def bench_stability(cpu_budget_s: float = 5.0, with_cpu: bool = True) -> dict:
+    """Linear-stability domains of the three equilibria over the paper's 15
+    viscosities and 19 directions (D2Q9, k grid 33 x 33 on [0, pi]^2, 24
+    bisection steps), and the eigensolver kernel's FP64 rate."""
+    import numpy as np
+    import torch
+
+    from paper_2303_08163_amd import vonneumann as vn
+
+    thetas = [math.radians(5 * a) for a in range(19)]
+    out = {"workload": "D2Q9 von Neumann stability domains: 15 nu x 19 theta x 3 equilibria, "
+                       "k grid 33^2 on [0, pi]^2, 24 bisection steps, FP64"}
+    table = {}
+    total_m = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for eq in ("entropic", "poly2", "product"):
+        umax, st = vn.stability_domain(vn.PAPER_NUS, thetas, equilibrium=eq, nk=33, iters=24)
+        total_m += st["matrices"]
+        table[eq] = {"u_max_theta0": [round(float(v), 5) for v in umax[:, 0]],
+                     "u_max_theta45": [round(float(v), 5) for v in umax[:, 9]],
+                     "unconverged": st["unconverged"]}
+    wall = time.perf_counter() - t0
+    out.update({"nu": vn.PAPER_NUS, "domains": table, "matrices": total_m, "wall_s": round(wall, 3),
+                "matrices_per_s": round(total_m / wall, 1)})
+
+    # kernel rate: one launch of the spectra kernel over 2^20 cases drawn like the sweep's
+    rng = np.random.default_rng(5)
+    n = 1 << 20
+    nus = np.exp(rng.uniform(math.log(1e-6), math.log(1.2), n))
+    sp, th = rng.uniform(0, 0.95, n), rng.uniform(0, math.pi / 2, n)
+    cases = np.stack([0.5 + 3 * nus, sp * np.cos(th), sp * np.sin(th), rng.uniform(0, math.pi, n),
+                      rng.uniform(0, math.pi, n)], axis=1)
+    dev = torch.device("cuda:0")
+    c = torch.from_numpy(cases).to(dev)
+    radius = torch.empty(n, dtype=torch.float64, device=dev)
+    info = torch.empty(n, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    from paper_2303_08163_amd import lbm
+    call = lambda: lbm.lbm_vn_spectra(lbm.LBM_D2Q9, "product", False, c.data_ptr(), n, radius.data_ptr(), None,
+                                      info.data_ptr(), stream.cuda_stream)
+    call()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record(stream)
+    for _ in range(reps):
+        call()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    per_launch = e0.elapsed_time(e1) / 1e3 / reps
+    steps = info.cpu().numpy().astype(np.int64)
+    flops = VN_FLOPS_FIXED * n + VN_FLOPS_PER_STEP * int(steps[steps > 0].sum())
+    achieved = flops / per_launch / 1e12
+    out["kernel"] = {"kernel": "k_vn_spectra<D2Q9, product form, no correction>", "cases": n,
+                     "launch_avg_ms": round(per_launch * 1e3, 4), "matrices_per_s": round(n / per_launch, 1),
+                     "qr_steps_mean": round(float(steps.mean()), 2), "unconverged": int((steps < 0).sum()),
+                     "roofline": {"bound": "alu", "achieved": round(achieved, 3),
+                                  "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                                  "flops_per_launch": flops}}
+    if with_cpu:
+        from oracle import stability as ost
+        ks = ost.k_grid(33)
+        t0 = time.perf_counter()
+        m = 0
+        while time.perf_counter() - t0 < cpu_budget_s:
+            ost.batch_spectral_radius(0.5 + 3 * 1e-3, [0.3, 0.2], ks, kind="product")
+            m += len(ks)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(m / dt, 1), "unit": "matrices/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{m} D2Q9 amplification matrices (oracle Jacobian + LAPACK "
+                                         f"eigenvalues), {dt:.1f} s"}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -195,8 +282,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256, help="grid side (headline: 256)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sections", default="headline,batched,serving,wave",
-                    help="comma list of headline, batched, serving, wave")
+    ap.add_argument("--sections", default="headline,batched,serving,wave,stability",
+                    help="comma list of headline, batched, serving, wave, stability")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--serve-requests", type=int, default=120)
@@ -297,6 +384,8 @@ def main() -> int:
         out["serving"] = bench_serving(args.serve_requests, args.serve_rate, args.serve_light_requests)
     if "wave" in sections:
         out["wave"] = bench_wave()
+    if "stability" in sections:
+        out["stability"] = bench_stability(with_cpu=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

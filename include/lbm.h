@@ -310,6 +310,55 @@ int lbm_pool_slot_info(lbm_pool *pool, int32_t slot, lbm_slot_info *info);
  * lbm_pool_destroy(NULL) returns LBM_OK. */
 int lbm_pool_destroy(lbm_pool *pool);
 
+/* ---------------------------------------------------------------------------
+ * Linear (von Neumann) stability: Sec. "Linear stability analysis".
+ *
+ * A plane-wave perturbation f'_i = F_i exp(i (k . r - omega t)) of the uniform
+ * equilibrium state (rho = 1, u) evolves by eq. (PerturbedDiscreteLBE); its
+ * amplification matrix is M = E (I + J) (eq. VN_eigen), E_ii = exp(-i c_i . k),
+ * J the Jacobian of the collision operator at that state, and every
+ * eigenvalue is lambda = exp(-i omega): a mode grows when |lambda| > 1.
+ * With the bulk correction the node's relaxation rate is taken at u (its
+ * derivative does not enter J, because f^eq - f = 0 at the reference state).
+ * Lattices: LBM_D1Q3 and LBM_D2Q9 (the paper's analysis is 2-D).  All
+ * arithmetic is FP64; eigenvalues come from a Householder reduction to
+ * Hessenberg form and shifted QR steps, one matrix per GPU thread.
+ * -------------------------------------------------------------------------*/
+
+/* Spectra of `count` independent cases.
+ *   cases   device pointer, count records of 5 doubles: tau, u_x, u_y, k_x, k_y
+ *           (u_y and k_y are ignored for D1Q3).  tau > 1/2 is not checked
+ *           per case; a non-finite record gives non-finite results.
+ *   radius  device pointer to count doubles: max |lambda| (NULL: not written).
+ *   eig     device pointer to count * Q * 2 doubles: the Q eigenvalues of
+ *           each case as (re, im), in no particular order (NULL: not written).
+ *   info    device pointer to count int32: QR steps taken, or -1 when the
+ *           iteration limit (30 Q steps) was reached first (NULL: not written).
+ *   stream  hipStream_t (NULL = the null stream).
+ * Enqueues one kernel and returns without synchronising.  Errors: LBM_EINVAL
+ * (lattice other than D1Q3/D2Q9, bad equilibrium or bulk_correction, count < 0,
+ * cases NULL with count > 0); LBM_EDEVICE. */
+int lbm_vn_spectra(int32_t lattice, int32_t equilibrium, int32_t bulk_correction, const double *cases,
+                   int64_t count, double *radius, double *eig, int32_t *info, void *stream);
+
+/* Largest spectral radius over a wave-vector grid, for n_states states: for
+ * state s = (tau, u_x, u_y) (device array of n_states * 3 doubles) the
+ * maximum of max |lambda| over k = (pi a / (nk - 1), pi b / (nk - 1)),
+ * a, b = 0..nk-1 (k_x only for D1Q3; k = 0 when nk = 1), the grid over
+ * [0, pi]^2 of Sec. "Linear stability domain".
+ *   max_radius   device pointer to n_states doubles (written).
+ *   scratch      device pointer to n_states * 8 bytes, 8-byte aligned
+ *                (caller-owned; overwritten).
+ *   unconverged  device pointer to one int32: number of matrices whose QR
+ *                iteration hit the limit (written).
+ * Enqueues three kernels and returns without synchronising.  The maximum does
+ * not depend on the order of evaluation.  Errors: LBM_EINVAL (as for
+ * lbm_vn_spectra; nk < 1 or > 65536; NULL pointers; n_states * nk^D above
+ * 2^31 * 64); LBM_EDEVICE. */
+int lbm_vn_max_radius(int32_t lattice, int32_t equilibrium, int32_t bulk_correction, const double *states,
+                      int64_t n_states, int32_t nk, double *max_radius, void *scratch, int32_t *unconverged,
+                      void *stream);
+
 /* Message of the last error raised on the calling thread (static storage,
  * empty if none). */
 const char *lbm_last_error(void);

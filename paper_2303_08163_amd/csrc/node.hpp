@@ -101,7 +101,7 @@ __device__ __forceinline__ void node_moments(const double (&f)[Lattice<DIM>::Q],
 }
 
 // Per-axis equilibrium factors g_{-1}, g_0, g_{+1} and S = sqrt(1 + 3 u^2).
-__device__ __forceinline__ void axis_factors(double u, double (&g)[3], double &S) {
+__host__ __device__ __forceinline__ void axis_factors(double u, double (&g)[3], double &S) {
     S = sqrt(fma(3.0 * u, u, 1.0));
     const double twoS_m1 = fma(2.0, S, -1.0);
     const double three_u = 3.0 * u;
@@ -111,7 +111,7 @@ __device__ __forceinline__ void axis_factors(double u, double (&g)[3], double &S
 }
 
 // 2 beta with the bulk-viscosity correction at the node's largest |u_a|.
-__device__ __forceinline__ double corrected_omega(double umax, double Smax, double two_tau_m1) {
+__host__ __device__ __forceinline__ double corrected_omega(double umax, double Smax, double two_tau_m1) {
     const double v2 = 3.0 * umax * umax;
     const double sp1 = Smax + 1.0;
     const double q = 2.0 * (Smax * Smax) * (sp1 * sp1);
@@ -127,7 +127,7 @@ __device__ __forceinline__ double corrected_omega(double umax, double Smax, doub
 //                phi_0 = 1 - s2 - u^2 and phi_{+-1} = (+-u + s2 + u^2) / 2.
 constexpr int kEqEntropic = 0, kEqPoly2 = 1, kEqProduct = 2;
 
-__device__ __forceinline__ void product_factors(double u, double (&g)[3]) {
+__host__ __device__ __forceinline__ void product_factors(double u, double (&g)[3]) {
     const double u2 = u * u;
     const double base = 1.0 / 3.0 + u2;
     g[0] = (base - u) * 0.5;
@@ -138,7 +138,7 @@ __device__ __forceinline__ void product_factors(double u, double (&g)[3]) {
 // 2 beta with the correction for polynomial equilibria, eq. (redefined_relaxation
 // rate_poly): A = 1 - (3/2) u^2 / s2 (eq. LBGK_bulk) at the node's largest |u_a|.
 // A < 0 beyond |u| = s2^(1/2) (2/3)^(1/2) and beta leaves [0, 1]; nothing is clamped.
-__device__ __forceinline__ double corrected_omega_poly(double umax, double two_tau_m1) {
+__host__ __device__ __forceinline__ double corrected_omega_poly(double umax, double two_tau_m1) {
     const double A = fma(-4.5 * umax, umax, 1.0);
     return (2.0 * A) / (A + two_tau_m1);
 }

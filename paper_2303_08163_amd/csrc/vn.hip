@@ -1,0 +1,220 @@
+// vn.hip -- von Neumann spectra on the GPU: one amplification matrix per
+// thread (see vn.hpp), batched over cases, and the largest spectral radius
+// over a grid of wave vectors for many states at once (the inner loop of the
+// linear-stability-domain search of Sec. "Linear stability domain").
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "lbm.h"
+#include "lbm_internal.hpp"
+#include "vn.hpp"
+
+namespace lbm {
+
+constexpr int kVnThreads = 64;
+
+struct VnSpectraArgs {
+    const double *cases;  // count x 5: tau, u_x, u_y, k_x, k_y
+    int64_t count;
+    double *radius;  // count, or null
+    double *eig;     // count x N x 2, or null
+    int *info;       // count, or null: QR steps taken, -1 if the limit was reached
+};
+
+template <int DIM, int EQ, bool CORR>
+__global__ __launch_bounds__(kVnThreads) void k_vn_spectra(VnSpectraArgs a) {
+    constexpr int N = DIM == 1 ? 3 : 9;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.count)
+        return;
+    const double *p = a.cases + 5 * t;
+    const double tau = p[0];
+    const double u[2] = {p[1], DIM == 2 ? p[2] : 0.0};
+    const double k[2] = {p[3], DIM == 2 ? p[4] : 0.0};
+    cplx H[N][N];
+    vn_matrix<DIM, EQ, CORR>(tau, u, k, H);
+    hessenberg<N>(H);
+    const int steps = hessenberg_eigenvalues<N>(H);
+    double r = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        r = fmax(r, cabs(H[i][i]));
+        if (a.eig) {
+            a.eig[(t * N + i) * 2 + 0] = H[i][i].re;
+            a.eig[(t * N + i) * 2 + 1] = H[i][i].im;
+        }
+    }
+    if (a.radius)
+        a.radius[t] = r;
+    if (a.info)
+        a.info[t] = steps;
+}
+
+struct VnMaxArgs {
+    const double *states;  // n_states x 3: tau, u_x, u_y
+    int64_t n_states;
+    int nk;                    // wave-vector points per axis on [0, pi]
+    int64_t per_state;         // nk^DIM
+    unsigned long long *rmax;  // n_states: bit pattern of the largest radius (non-negative doubles order as integers)
+    int *unconverged;          // one counter
+};
+
+template <int DIM, int EQ, bool CORR>
+__global__ __launch_bounds__(kVnThreads) void k_vn_max_radius(VnMaxArgs a) {
+    constexpr int N = DIM == 1 ? 3 : 9;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.n_states * a.per_state)
+        return;
+    const int64_t s = t / a.per_state;
+    const int64_t q = t - s * a.per_state;
+    const double dk = a.nk > 1 ? 3.141592653589793 / (double)(a.nk - 1) : 0.0;
+    const int ix = (int)(q % a.nk), iy = DIM == 2 ? (int)(q / a.nk) : 0;
+    const double *p = a.states + 3 * s;
+    const double tau = p[0];
+    const double u[2] = {p[1], DIM == 2 ? p[2] : 0.0};
+    const double k[2] = {ix * dk, iy * dk};
+    cplx H[N][N];
+    vn_matrix<DIM, EQ, CORR>(tau, u, k, H);
+    hessenberg<N>(H);
+    const int steps = hessenberg_eigenvalues<N>(H);
+    double r = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        r = fmax(r, cabs(H[i][i]));
+    if (steps < 0)
+        atomicAdd(a.unconverged, 1);
+    atomicMax(a.rmax + s, (unsigned long long)__double_as_longlong(r));
+}
+
+static __global__ void k_vn_clear(unsigned long long *p, int64_t n, int *counter) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n)
+        p[t] = 0ull;
+    if (t == 0)
+        *counter = 0;
+}
+
+static __global__ void k_vn_bits_to_double(const unsigned long long *bits, int64_t n, double *out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n)
+        out[t] = __longlong_as_double((long long)bits[t]);
+}
+
+using SpectraFn = void (*)(VnSpectraArgs);
+using MaxFn = void (*)(VnMaxArgs);
+
+template <int DIM, int EQ>
+static void pick(bool corr, SpectraFn &sf, MaxFn &mf) {
+    sf = corr ? k_vn_spectra<DIM, EQ, true> : k_vn_spectra<DIM, EQ, false>;
+    mf = corr ? k_vn_max_radius<DIM, EQ, true> : k_vn_max_radius<DIM, EQ, false>;
+}
+
+template <int DIM>
+static void pick_eq(int eq, bool corr, SpectraFn &sf, MaxFn &mf) {
+    if (eq == LBM_EQ_POLY2)
+        pick<DIM, kEqPoly2>(corr, sf, mf);
+    else if (eq == LBM_EQ_PRODUCT)
+        pick<DIM, kEqProduct>(corr, sf, mf);
+    else
+        pick<DIM, kEqEntropic>(corr, sf, mf);
+}
+
+static int vn_select(int32_t lattice, int32_t equilibrium, int32_t corr, SpectraFn &sf, MaxFn &mf, int &dim) {
+    if (lattice != LBM_D1Q3 && lattice != LBM_D2Q9) {
+        set_error("von Neumann spectra: lattice must be LBM_D1Q3 or LBM_D2Q9");
+        return LBM_EINVAL;
+    }
+    if (equilibrium != LBM_EQ_ENTROPIC && equilibrium != LBM_EQ_POLY2 && equilibrium != LBM_EQ_PRODUCT) {
+        set_error("von Neumann spectra: bad equilibrium");
+        return LBM_EINVAL;
+    }
+    if (corr != 0 && corr != 1) {
+        set_error("von Neumann spectra: bulk_correction must be 0 or 1");
+        return LBM_EINVAL;
+    }
+    dim = lattice == LBM_D1Q3 ? 1 : 2;
+    if (dim == 1)
+        pick_eq<1>(equilibrium, corr != 0, sf, mf);
+    else
+        pick_eq<2>(equilibrium, corr != 0, sf, mf);
+    return LBM_OK;
+}
+
+}  // namespace lbm
+
+using namespace lbm;
+
+extern "C" {
+
+int lbm_vn_spectra(int32_t lattice, int32_t equilibrium, int32_t bulk_correction, const double *cases,
+                   int64_t count, double *radius, double *eig, int32_t *info, void *stream) {
+    SpectraFn sf;
+    MaxFn mf;
+    int dim;
+    int rc = vn_select(lattice, equilibrium, bulk_correction, sf, mf, dim);
+    if (rc != LBM_OK)
+        return rc;
+    if (count < 0 || (count > 0 && !cases) || count > ((int64_t)1 << 40)) {
+        set_error("von Neumann spectra: NULL cases or bad count");
+        return LBM_EINVAL;
+    }
+    if (count == 0)
+        return LBM_OK;
+    VnSpectraArgs a{cases, count, radius, eig, info};
+    const int64_t blocks = (count + kVnThreads - 1) / kVnThreads;
+    if (blocks > INT32_MAX) {
+        set_error("von Neumann spectra: too many cases");
+        return LBM_EINVAL;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(sf, dim3((unsigned)blocks), dim3(kVnThreads), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return hip_fail(e, "von Neumann spectra launch");
+    return LBM_OK;
+}
+
+int lbm_vn_max_radius(int32_t lattice, int32_t equilibrium, int32_t bulk_correction, const double *states,
+                      int64_t n_states, int32_t nk, double *max_radius, void *scratch, int32_t *unconverged,
+                      void *stream) {
+    SpectraFn sf;
+    MaxFn mf;
+    int dim;
+    int rc = vn_select(lattice, equilibrium, bulk_correction, sf, mf, dim);
+    if (rc != LBM_OK)
+        return rc;
+    if (n_states < 0 || nk < 1 || nk > 65536 || (n_states > 0 && (!states || !max_radius || !scratch)) ||
+        !unconverged) {
+        set_error("von Neumann max radius: NULL pointer or bad sizes");
+        return LBM_EINVAL;
+    }
+    if ((reinterpret_cast<uintptr_t>(scratch) & 7u) != 0) {
+        set_error("von Neumann max radius: scratch must be 8-byte aligned");
+        return LBM_EINVAL;
+    }
+    const int64_t per = dim == 1 ? (int64_t)nk : (int64_t)nk * nk;
+    const int64_t total = n_states * per;
+    if (total > ((int64_t)INT32_MAX - 1) * kVnThreads) {
+        set_error("von Neumann max radius: too many matrices per call");
+        return LBM_EINVAL;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto *bits = static_cast<unsigned long long *>(scratch);
+    const int64_t nclear = n_states > 0 ? n_states : 1;
+    hipLaunchKernelGGL(k_vn_clear, dim3((unsigned)((nclear + 255) / 256)), dim3(256), 0, s, bits, n_states,
+                       unconverged);
+    if (total > 0) {
+        VnMaxArgs a{states, n_states, nk, per, bits, unconverged};
+        hipLaunchKernelGGL(mf, dim3((unsigned)((total + kVnThreads - 1) / kVnThreads)), dim3(kVnThreads), 0, s, a);
+        hipLaunchKernelGGL(k_vn_bits_to_double, dim3((unsigned)((n_states + 255) / 256)), dim3(256), 0, s,
+                           (const unsigned long long *)bits, n_states, max_radius);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return hip_fail(e, "von Neumann max radius launch");
+    return LBM_OK;
+}
+
+}  // extern "C"

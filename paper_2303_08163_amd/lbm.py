@@ -98,7 +98,8 @@ EXPORTS = ("lbm_workspace_bytes", "lbm_workspace_bytes_tuned", "lbm_create", "lb
            "lbm_step", "lbm_moments", "lbm_get_populations", "lbm_energy", "lbm_destroy", "lbm_status_string",
            "lbm_last_error", "lbm_version", "lbm_pool_table_bytes", "lbm_pool_slot_bytes", "lbm_pool_create",
            "lbm_pool_admit", "lbm_pool_run", "lbm_pool_poll", "lbm_pool_moments", "lbm_pool_get_populations",
-           "lbm_pool_release", "lbm_pool_stats_get", "lbm_pool_slot_info", "lbm_pool_destroy")
+           "lbm_pool_release", "lbm_pool_stats_get", "lbm_pool_slot_info", "lbm_pool_destroy",
+           "lbm_vn_spectra", "lbm_vn_max_radius")
 
 
 def load_library(path: str = LIB_PATH):
@@ -128,6 +129,9 @@ def load_library(path: str = LIB_PATH):
         "lbm_moments": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(lbm_diag)]),
         "lbm_get_populations": (ctypes.c_int, [vp, vp]),
         "lbm_energy": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_double, vp]),
+        "lbm_vn_spectra": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, i64, vp, vp, vp, vp]),
+        "lbm_vn_max_radius": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, i64,
+                                             ctypes.c_int32, vp, vp, vp, vp]),
         "lbm_destroy": (ctypes.c_int, [vp]),
         "lbm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "lbm_last_error": (ctypes.c_char_p, []),
@@ -226,6 +230,20 @@ def lbm_energy(h, U, rho_ref: float, out: int) -> None:
     """Enqueue E about (rho_ref, U) into the device double at address out."""
     arr = None if U is None else (ctypes.c_double * 3)(*[float(v) for v in U] + [0.0] * (3 - len(U)))
     _check(load_library().lbm_energy(h, arr, float(rho_ref), out), "lbm_energy")
+
+
+def lbm_vn_spectra(lattice: int, equilibrium, bulk_correction, cases: int, count: int, radius, eig, info,
+                   stream=None) -> None:
+    _check(load_library().lbm_vn_spectra(int(lattice), EQUILIBRIA.get(equilibrium, equilibrium),
+                                          int(bool(bulk_correction)), cases, int(count), radius, eig, info, stream),
+           "lbm_vn_spectra")
+
+
+def lbm_vn_max_radius(lattice: int, equilibrium, bulk_correction, states: int, n_states: int, nk: int,
+                      max_radius: int, scratch: int, unconverged: int, stream=None) -> None:
+    _check(load_library().lbm_vn_max_radius(int(lattice), EQUILIBRIA.get(equilibrium, equilibrium),
+                                             int(bool(bulk_correction)), states, int(n_states), int(nk),
+                                             max_radius, scratch, unconverged, stream), "lbm_vn_max_radius")
 
 
 def lbm_destroy(h) -> None:

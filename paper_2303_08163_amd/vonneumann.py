@@ -1,0 +1,136 @@
+"""Linear (von Neumann) stability analysis on the GPU (Sec. "Linear stability
+analysis" of arXiv:2303.08163).
+
+spectra():           eigenvalues of the amplification matrix M = E (I + J) for
+                     a batch of (tau, u, k) cases (lbm_vn_spectra).
+max_radius():        largest spectral radius over the [0, pi]^2 wave-vector grid
+                     for a batch of states (lbm_vn_max_radius).
+stability_domain():  largest stable speed |u| per (nu, theta), theta the angle
+                     of u from the x axis, found by bisection run for every
+                     (nu, theta) pair at once: each bisection step is one
+                     lbm_vn_max_radius call over all pairs (Sec. "Linear
+                     stability domain": stable when no mode grows for any k in
+                     [0, pi]^2; here |lambda| <= 1 + tol, tol absorbing
+                     rounding).  The stable set along a direction is read as
+                     the interval [0, u_max).
+Every matrix and eigenvalue is computed in the library's kernels; the host
+only forms the inputs and keeps the bisection brackets.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import lbm
+
+NU_PER_TAU = 1.0 / 3.0
+
+
+def tau_of_nu(nu: float) -> float:
+    return 0.5 + nu / NU_PER_TAU
+
+
+def _lattice(dim: int) -> int:
+    if dim == 1:
+        return lbm.LBM_D1Q3
+    if dim == 2:
+        return lbm.LBM_D2Q9
+    raise ValueError("von Neumann spectra run on D1Q3 or D2Q9")
+
+
+def spectra(cases, dim: int = 2, equilibrium="entropic", bulk_correction=False, device="cuda:0"):
+    """cases (n, 5): tau, u_x, u_y, k_x, k_y.  Returns (radius (n,), eigenvalues
+    (n, Q) complex, info (n,) QR steps or -1) as numpy arrays."""
+    import torch
+    lbm.load_library()
+    c = torch.as_tensor(np.ascontiguousarray(cases, dtype=np.float64)).to(device)
+    n = c.shape[0]
+    if c.ndim != 2 or c.shape[1] != 5:
+        raise ValueError("cases must have shape (n, 5)")
+    Q = 3 ** dim
+    radius = torch.empty(n, dtype=torch.float64, device=device)
+    eig = torch.empty((n, Q, 2), dtype=torch.float64, device=device)
+    info = torch.empty(n, dtype=torch.int32, device=device)
+    stream = torch.cuda.current_stream(device)
+    lbm.lbm_vn_spectra(_lattice(dim), equilibrium, bulk_correction, c.data_ptr(), n, radius.data_ptr(),
+                       eig.data_ptr(), info.data_ptr(), stream.cuda_stream)
+    stream.synchronize()
+    e = eig.cpu().numpy()
+    return radius.cpu().numpy(), e[..., 0] + 1j * e[..., 1], info.cpu().numpy()
+
+
+class RadiusEvaluator:
+    """Device buffers for repeated lbm_vn_max_radius calls over up to n_states states."""
+
+    def __init__(self, n_states: int, dim: int = 2, equilibrium="entropic", bulk_correction=False, nk: int = 33,
+                 device="cuda:0"):
+        import torch
+        lbm.load_library()
+        self.dim, self.eq, self.corr, self.nk = dim, equilibrium, bulk_correction, nk
+        self.device = torch.device(device)
+        self.capacity = n_states
+        self.states = torch.empty((n_states, 3), dtype=torch.float64, device=self.device)
+        self.rmax = torch.empty(n_states, dtype=torch.float64, device=self.device)
+        self.scratch = torch.empty(n_states, dtype=torch.int64, device=self.device)
+        self.unconverged = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.matrices = 0
+
+    def __call__(self, states: np.ndarray):
+        """states (n, 3): tau, u_x, u_y.  Returns (max radius (n,), unconverged count)."""
+        import torch
+        n = states.shape[0]
+        if n > self.capacity:
+            raise ValueError("more states than the evaluator holds")
+        self.states[:n].copy_(torch.from_numpy(np.ascontiguousarray(states, dtype=np.float64)))
+        lbm.lbm_vn_max_radius(_lattice(self.dim), self.eq, self.corr, self.states.data_ptr(), n, self.nk,
+                              self.rmax.data_ptr(), self.scratch.data_ptr(), self.unconverged.data_ptr(),
+                              self.stream.cuda_stream)
+        self.matrices += n * self.nk ** self.dim
+        r = self.rmax[:n].cpu().numpy()  # synchronises the stream
+        return r, int(self.unconverged.item())
+
+
+def max_radius(states, dim: int = 2, equilibrium="entropic", bulk_correction=False, nk: int = 33,
+               device="cuda:0"):
+    states = np.asarray(states, dtype=np.float64)
+    ev = RadiusEvaluator(states.shape[0], dim, equilibrium, bulk_correction, nk, device)
+    return ev(states)
+
+
+def stability_domain(nus, thetas, equilibrium="entropic", bulk_correction=False, nk: int = 33, iters: int = 24,
+                     tol: float = 1e-9, device="cuda:0"):
+    """Largest stable speed for every (nu, theta) pair; returns (u_max array of
+    shape (len(nus), len(thetas)), stats dict)."""
+    nus = np.asarray(nus, dtype=np.float64)
+    thetas = np.asarray(thetas, dtype=np.float64)
+    P = len(nus) * len(thetas)
+    nu_p = np.repeat(nus, len(thetas))
+    th_p = np.tile(thetas, len(nus))
+    tau_p = 0.5 + nu_p / NU_PER_TAU
+    s_max = 1.0 / np.maximum(np.abs(np.cos(th_p)), np.abs(np.sin(th_p)))
+    ev = RadiusEvaluator(P, 2, equilibrium, bulk_correction, nk, device)
+    unconverged = 0
+
+    def stable(speed):
+        nonlocal unconverged
+        st = np.stack([tau_p, speed * np.cos(th_p), speed * np.sin(th_p)], axis=1)
+        r, bad = ev(st)
+        unconverged += bad
+        return r <= 1.0 + tol
+
+    lo = np.zeros(P)
+    hi = s_max.copy()
+    ok0 = stable(np.zeros(P))
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        s = stable(mid)
+        lo = np.where(s, mid, lo)
+        hi = np.where(s, hi, mid)
+    lo = np.where(ok0, lo, 0.0)
+    return lo.reshape(len(nus), len(thetas)), {"matrices": ev.matrices, "unconverged": unconverged,
+                                                "calls": iters + 1}
+
+
+PAPER_NUS = [1e-6, 5e-6, 1e-5, 5e-5, 1e-4, 5e-4, 1e-3, 5e-3, 1e-2, 5e-2, 0.1, 0.5, 1.0, 1.1, 1.2]
