@@ -189,6 +189,97 @@ def bench_wave(steps: int = 2000) -> dict:
             "runs": len(rows), "wall_s": round(wall, 3)}
 
 
+def host_cpu() -> dict:
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(), "threads_used": cpu_threads()}
+
+
+def bench_oracle_timing(budget_s: float = 6.0) -> dict:
+    """The oracle on the host, one thread and all threads, on bounded samples of
+    C1 (full), C2 (full grid, a few steps), C3 at 64^3 and four C4 domains."""
+    import oracle
+    from paper_2303_08163_amd import workloads
+
+    cases = [("C1 D2Q9 64^2 Taylor-Green, tau 0.51", workloads.taylor_green_2d(64, u0=0.05), 0.51),
+             ("C2 D2Q9 4096^2 double shear, tau 0.5001", workloads.double_shear_layer(4096), 0.5001),
+             ("C3 D3Q27 64^3 Taylor-Green, tau 0.5005", workloads.taylor_green_3d(64, u0=0.05), 0.5005)]
+    for sp in workloads.batch_domains(512, 2303)[:4]:
+        cases.append((f"C4 D2Q9 {sp['nx']}x{sp['ny']} shear wave, tau {sp['tau']:.4f}",
+                      workloads.shear_wave(sp["nx"], sp["ny"], sp["amp"]), sp["tau"]))
+    out = {"host": host_cpu(), "runs": []}
+    for threads in (1, cpu_threads()):
+        oracle.set_threads(threads)
+        for name, (r0, u0), tau in cases:
+            for corr in ("off", "min"):
+                n = r0.size
+                t0 = time.perf_counter()
+                oracle.run(r0, u0, tau, 1, corr=corr)
+                one = max(time.perf_counter() - t0, 1e-6)
+                steps = max(1, min(2000, int(budget_s / one)))
+                t0 = time.perf_counter()
+                oracle.run(r0, u0, tau, steps, corr=corr)
+                dt = time.perf_counter() - t0
+                out["runs"].append({"case": name, "correction": corr, "threads": threads, "steps": steps,
+                                    "seconds": round(dt, 2), "mlups": round(n * steps / dt / 1e6, 2)})
+    return out
+
+
+def bench_variants(steps: int = 50, warmup: int = 5) -> dict:
+    """Throughput of the other equilibria and of the correction on the headline
+    grid (D3Q27 256^3 Taylor-Green, FP32 deviation storage, default vector
+    kernel), and of a D1Q3 row of 2^27 nodes."""
+    import numpy as np
+    import torch
+
+    from paper_2303_08163_amd import lbm, workloads
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+
+    def timed(dom, nodes, bytes_per_lup):
+        dom.step(warmup)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        dom.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3
+        _, _, d = dom.moments(fields=False)
+        mlups = nodes * steps / sec / 1e6
+        return {"mlups": round(mlups, 1), "gbs": round(mlups * 1e6 * bytes_per_lup / 1e9, 1),
+                "frac": round(mlups * 1e6 * bytes_per_lup / 1e9 / HBM_PEAK_GBS, 4), "domain_error": d["domain_error"]}
+
+    rho0, u0 = workloads.taylor_green_3d(256, u0=0.05)
+    rd = torch.from_numpy(rho0).to(dev)
+    ud = torch.from_numpy(u0).to(dev)
+    del rho0, u0
+    for eq in ("entropic", "poly2", "product"):
+        for corr in (False, True):
+            dom = lbm.Domain(rd, ud, 0.5005, dtype="fp32_dev", bulk_correction=corr, equilibrium=eq, stream=stream)
+            out[f"d3q27_256_fp32_{eq}{'_corrected' if corr else ''}"] = timed(dom, 256 ** 3, 216)
+            dom.close()
+    del rd, ud
+    n1 = 1 << 27
+    x = np.arange(n1, dtype=np.float64)
+    r1 = torch.from_numpy(1.0 + 1e-3 * np.sin(2 * math.pi * x / n1)).to(dev)
+    u1 = torch.full((1, n1), 0.1, dtype=torch.float64, device=dev)
+    del x
+    for dt, s in (("fp32_dev", 4), ("fp64", 8)):
+        dom = lbm.Domain(r1, u1, 0.6, dtype=dt, bulk_correction=True, stream=stream)
+        out[f"d1q3_2^27_{dt}_corrected"] = timed(dom, n1, 2 * 3 * s)
+        dom.close()
+    return {"steps": steps, "results": out}
+
+
 # FP64 operations of one D2Q9 amplification-matrix eigensolve as written in
 # the kernel (a fused multiply-add counts 2; divisions, square roots and
 # transcendentals 1): building M (about 800), the Householder reduction
@@ -282,8 +373,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256, help="grid side (headline: 256)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sections", default="headline,batched,serving,wave,stability",
-                    help="comma list of headline, batched, serving, wave, stability")
+    ap.add_argument("--sections", default="headline,batched,serving,wave,stability,variants",
+                    help="comma list of headline, batched, serving, wave, stability, variants, "
+                         "oracle_timing (not in the default run: several minutes of host time)")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--serve-requests", type=int, default=120)
@@ -320,6 +412,14 @@ def main() -> int:
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
     ms = start.elapsed_time(stop)
+    # four more repetitions of the same K steps (median of five reported beside)
+    reps = [ms / args.steps]
+    for _ in range(4):
+        start.record(stream)
+        dom.step(args.steps)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        reps.append(start.elapsed_time(stop) / args.steps)
     _, _, diag = dom.moments(fields=False)
     dom.close()
 
@@ -375,6 +475,8 @@ def main() -> int:
         "copy_bandwidth_gbs": round(copy_gbs, 1),
         "frac_of_copy": round(achieved / copy_gbs, 4),
         "wall_s_timed_region": round(t_wall, 4),
+        "repetitions_ms_per_step": [round(v, 5) for v in reps],
+        "median_of_5_mlups": round(nodes / (sorted(reps)[2] / 1e3) / 1e6, 1),
         "mass_drift": abs(diag["mass"] / (nodes * 1.0) - 1.0),
         "kernel_source_digest": kernel_source_digest(),
     }
@@ -384,6 +486,10 @@ def main() -> int:
         out["serving"] = bench_serving(args.serve_requests, args.serve_rate, args.serve_light_requests)
     if "wave" in sections:
         out["wave"] = bench_wave()
+    if "oracle_timing" in sections:
+        out["oracle_timing"] = bench_oracle_timing()
+    if "variants" in sections:
+        out["variants"] = bench_variants()
     if "stability" in sections:
         out["stability"] = bench_stability(with_cpu=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:

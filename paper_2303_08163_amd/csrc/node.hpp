@@ -12,7 +12,12 @@
 //       g_0 = 2 (2 - S) / 3,  g_{+1} = (2 S - 1 + 3 u) / 6,  g_{-1} = (2 S - 1 - 3 u) / 6
 //     because, with S^2 = 1 + 3 u^2, (2 - S)(2 u + S) = (1 - u)(2 S - 1 + 3 u) and
 //     (2 - S)(1 - u) = (2 u + S)(2 S - 1 - 3 u) hold identically.  This needs
-//     one square root per axis and no power, exponential or division.
+//     one square root per axis and no power, exponential or division.  The
+//     factors are formed as h +- u/2 and 1 - 2 h with h = (2 S - 1) / 6, so
+//     that g_{+1} - g_{-1} = u and g_{-1} + g_0 + g_{+1} = 1 hold up to
+//     value-dependent rounding: multiplying every factor by a rounded constant
+//     (1/6, 2/3) would remove the same fraction of mass and momentum at every
+//     node and step, a bias that adds up over long runs.
 //   Sec. "Correction of leading-order bulk viscosity error", eq.
 //     (redefined_relaxation rate) with A from eq. (entropic_bulk):
 //     2 beta = 2 A / (A + 2 tau - 1).  A node uses A = min_a A(u_a); A is even
@@ -103,11 +108,11 @@ __device__ __forceinline__ void node_moments(const double (&f)[Lattice<DIM>::Q],
 // Per-axis equilibrium factors g_{-1}, g_0, g_{+1} and S = sqrt(1 + 3 u^2).
 __host__ __device__ __forceinline__ void axis_factors(double u, double (&g)[3], double &S) {
     S = sqrt(fma(3.0 * u, u, 1.0));
-    const double twoS_m1 = fma(2.0, S, -1.0);
-    const double three_u = 3.0 * u;
-    g[0] = (twoS_m1 - three_u) * (1.0 / 6.0);
-    g[1] = (2.0 - S) * (2.0 / 3.0);
-    g[2] = (twoS_m1 + three_u) * (1.0 / 6.0);
+    const double h = fma(2.0, S, -1.0) * (1.0 / 6.0);
+    const double half_u = 0.5 * u;
+    g[0] = h - half_u;
+    g[1] = fma(-2.0, h, 1.0);
+    g[2] = h + half_u;
 }
 
 // 2 beta with the bulk-viscosity correction at the node's largest |u_a|.
@@ -127,13 +132,18 @@ __host__ __device__ __forceinline__ double corrected_omega(double umax, double S
 //                phi_0 = 1 - s2 - u^2 and phi_{+-1} = (+-u + s2 + u^2) / 2.
 constexpr int kEqEntropic = 0, kEqPoly2 = 1, kEqProduct = 2;
 
+// (phi_0 is formed as 1 - (s2 + u^2) so that the factors sum to 1 up to rounding.)
 __host__ __device__ __forceinline__ void product_factors(double u, double (&g)[3]) {
-    const double u2 = u * u;
-    const double base = 1.0 / 3.0 + u2;
+    const double base = fma(u, u, 1.0 / 3.0);
     g[0] = (base - u) * 0.5;
-    g[1] = (2.0 / 3.0) - u2;
+    g[1] = 1.0 - base;
     g[2] = (base + u) * 0.5;
 }
+
+// 6^D w_i: the lattice weights as integers (1-D: 1, 4, 1).  The second-order
+// polynomial equilibrium scales them by rho / 6^D, one correctly rounded
+// division per node, so that the weights sum to 1 exactly.
+__host__ __device__ constexpr double w1_int(int k) { return k == 1 ? 4.0 : 1.0; }
 
 // 2 beta with the correction for polynomial equilibria, eq. (redefined_relaxation
 // rate_poly): A = 1 - (3/2) u^2 / s2 (eq. LBGK_bulk) at the node's largest |u_a|.
@@ -207,6 +217,7 @@ __device__ __forceinline__ bool collide(T (&v)[Lattice<DIM>::Q], const Relax &r)
     }
 
     const double base_poly = fma(-1.5, usq, 1.0);
+    const double rho_w = EQ == kEqPoly2 ? rho / (DIM == 1 ? 6.0 : (DIM == 2 ? 36.0 : 216.0)) : 0.0;
 #pragma unroll
     for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
 #pragma unroll
@@ -221,7 +232,8 @@ __device__ __forceinline__ bool collide(T (&v)[Lattice<DIM>::Q], const Relax &r)
                 if constexpr (EQ == kEqPoly2) {
                     const double cu = (cx - 1) * u[0] + (DIM >= 2 ? (cy - 1) * u[1] : 0.0) +
                                       (DIM == 3 ? (cz - 1) * u[2] : 0.0);
-                    feq = (Lattice<DIM>::weight(i) * rho) * fma(cu, fma(4.5, cu, 3.0), base_poly);
+                    const double wint = w1_int(cx) * (DIM >= 2 ? w1_int(cy) : 1.0) * (DIM == 3 ? w1_int(cz) : 1.0);
+                    feq = (wint * rho_w) * fma(cu, fma(4.5, cu, 3.0), base_poly);
                 } else {
                     feq = t * g[0][cx];
                 }
@@ -354,6 +366,7 @@ __device__ __forceinline__ bool equilibrium_stored(double rho, const double (&u)
             usq = fma(u[a], u[a], usq);
     }
     const double base_poly = fma(-1.5, usq, 1.0);
+    const double rho_w = EQ == kEqPoly2 ? rho / (DIM == 1 ? 6.0 : (DIM == 2 ? 36.0 : 216.0)) : 0.0;
 #pragma unroll
     for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
 #pragma unroll
@@ -368,7 +381,8 @@ __device__ __forceinline__ bool equilibrium_stored(double rho, const double (&u)
                 if constexpr (EQ == kEqPoly2) {
                     const double cu = (cx - 1) * u[0] + (DIM >= 2 ? (cy - 1) * u[1] : 0.0) +
                                       (DIM == 3 ? (cz - 1) * u[2] : 0.0);
-                    feq = (Lattice<DIM>::weight(i) * rho) * fma(cu, fma(4.5, cu, 3.0), base_poly);
+                    const double wint = w1_int(cx) * (DIM >= 2 ? w1_int(cy) : 1.0) * (DIM == 3 ? w1_int(cz) : 1.0);
+                    feq = (wint * rho_w) * fma(cu, fma(4.5, cu, 3.0), base_poly);
                 } else {
                     feq = t * g[0][cx];
                 }
