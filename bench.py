@@ -142,25 +142,28 @@ def bench_serving(n_requests: int, rate: float, light_requests: int) -> dict:
     from paper_2303_08163_amd import serve, workloads
     res = {}
     trace = workloads.serving_trace(n_requests=n_requests, rate=rate, seed=8163)
-    be = serve.PoolBackend(96 << 30, max_slots=512)
-    try:
-        pool_out = serve.Server(be).serve(trace)
-    finally:
-        be.close()
-    base_out = serve.serial_serve(trace)
-    ps, bs = serve.summarize(pool_out), serve.summarize(base_out)
-    res["stated_rate"] = {"rate_req_s": rate, "requests": n_requests, "continuous_batching": ps, "serial": bs}
+    def pooled(tr, policy):
+        be = serve.PoolBackend(96 << 30, max_slots=512)
+        try:
+            kw = {"policy": "swf", "lookahead": 1 << 30} if policy == "swf" else {"policy": "fifo", "lookahead": 8}
+            return serve.summarize(serve.Server(be, **kw).serve(tr))
+        finally:
+            be.close()
+
+    ps = pooled(trace, "fifo")
+    pw = pooled(trace, "swf")
+    bs = serve.summarize(serve.serial_serve(trace))
+    res["stated_rate"] = {"rate_req_s": rate, "requests": n_requests, "continuous_batching": ps,
+                          "continuous_batching_shortest_work_first": pw, "serial": bs}
     cap = ps["solves_per_s"] or 1.0
     light_rate = max(0.5, 0.5 * cap)
     trace_l = workloads.serving_trace(n_requests=light_requests, rate=light_rate, seed=8164)
-    be = serve.PoolBackend(96 << 30, max_slots=512)
-    try:
-        pl = serve.summarize(serve.Server(be).serve(trace_l))
-    finally:
-        be.close()
+    pl = pooled(trace_l, "fifo")
+    plw = pooled(trace_l, "swf")
     bl = serve.summarize(serve.serial_serve(trace_l))
     res["half_capacity_rate"] = {"rate_req_s": round(light_rate, 2), "requests": light_requests,
-                                 "continuous_batching": pl, "serial": bl}
+                                 "continuous_batching": pl, "continuous_batching_shortest_work_first": plw,
+                                 "serial": bl}
     return res
 
 

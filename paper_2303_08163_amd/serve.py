@@ -90,14 +90,15 @@ class PoolBackend:
         self.slot_req[slot] = req
         return slot
 
+    @staticmethod
+    def step_bytes(req) -> int:
+        """HBM bytes of one step of a request (2 Q 4 bytes per node, FP32 storage)."""
+        q, nodes = (9, req["n"] ** 2) if req["lattice"] == 9 else (27, req["n"] ** 3)
+        return 2 * q * 4 * nodes
+
     def step_seconds(self, slots) -> float:
         """Estimated GPU time of one step of the given slots (memory-bound)."""
-        b = 0
-        for s in slots:
-            r = self.slot_req[s]
-            q, nodes = (9, r["n"] ** 2) if r["lattice"] == 9 else (27, r["n"] ** 3)
-            b += 2 * q * 4 * nodes
-        return b / self.bytes_per_s
+        return sum(self.step_bytes(self.slot_req[s]) for s in slots) / self.bytes_per_s
 
     def remaining(self, slot) -> int:
         return int(self.pool.slot_info(slot)["steps_remaining"])
@@ -125,17 +126,34 @@ class Server:
 
     chunk_s: target GPU time of one run (bounds how long a newly arrived
     request waits before it joins); lookahead: how many queued requests are
-    tried per admission pass (first-fit within the window, arrival order).
+    tried per admission pass (first fit within the window).
+    policy:
+      "fifo"  the window is taken in arrival order and every request that fits
+              in memory is admitted (all admitted requests share the GPU);
+      "swf"   (default) shortest work first: the queue is ordered by estimated work
+              (bytes per step x steps), and admission stops once the admitted
+              requests move `saturate_bytes` per step -- enough to keep the GPU
+              busy -- so that short requests finish first instead of sharing
+              the device with everything queued.  Admitted requests are never
+              paused, so this approximates shortest-remaining-work order.
     """
 
-    def __init__(self, backend, chunk_s: float = 0.02, lookahead: int = 8, max_chunk: int = 2000,
-                 clock=time.perf_counter, sleep=time.sleep):
+    def __init__(self, backend, chunk_s: float = 0.02, lookahead: int = 64, max_chunk: int = 2000,
+                 clock=time.perf_counter, sleep=time.sleep, policy: str = "swf",
+                 saturate_bytes: float = 512e6):
+        if policy not in ("fifo", "swf"):
+            raise ValueError("policy must be 'fifo' or 'swf'")
         self.b = backend
         self.chunk_s = chunk_s
         self.lookahead = lookahead
         self.max_chunk = max_chunk
         self.clock = clock
         self.sleep = sleep
+        self.policy = policy
+        self.saturate_bytes = saturate_bytes
+
+    def _work(self, req) -> float:
+        return float(self.b.step_bytes(req)) * req["steps"]
 
     def serve(self, trace):
         """Serve a list of requests (dicts with 'arrival' seconds from start).
@@ -155,15 +173,25 @@ class Server:
                 queue.append(trace[i])
                 i += 1
             # admission: first fit within the look-ahead window, in arrival order
+            # (fifo) or in order of estimated work up to the saturation traffic (swf)
             tried = 0
-            for req in list(queue):
+            if self.policy == "swf":
+                order = sorted(queue, key=lambda r: (self._work(r), r["arrival"]))
+                load = sum(b.step_bytes(r) for r, _ in active.values())
+            else:
+                order = list(queue)
+                load = 0.0
+            for req in order:
                 if tried >= self.lookahead:
+                    break
+                if self.policy == "swf" and active and load >= self.saturate_bytes:
                     break
                 tried += 1
                 slot = b.try_admit(req)
                 if slot is not None:
                     active[slot] = (req, now())
                     queue.remove(req)
+                    load += b.step_bytes(req)
             if not active:
                 if i < len(trace):
                     wait = trace[i]["arrival"] - now()

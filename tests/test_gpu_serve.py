@@ -8,14 +8,16 @@ from paper_2303_08163_amd import workloads
 pytestmark = pytest.mark.gpu
 
 
-def test_served_results_equal_alone():
+@pytest.mark.parametrize("policy", ["fifo", "swf"])
+def test_served_results_equal_alone(policy):
     import torch
     from paper_2303_08163_amd import lbm, serve
     trace = workloads.serving_trace(n_requests=14, rate=400.0, seed=11, d2_range=(64, 160), d3_range=(16, 40),
                                     steps_range=(20, 300))
     be = serve.PoolBackend(1 << 30, max_slots=5)
     try:
-        out = serve.Server(be, chunk_s=0.002).serve(trace)
+        kw = {"policy": "swf", "lookahead": 64, "saturate_bytes": 2e6} if policy == "swf" else {"policy": "fifo"}
+        out = serve.Server(be, chunk_s=0.002, **kw).serve(trace)
     finally:
         be.close()
     assert sorted(r["id"] for r in out) == list(range(len(trace)))
