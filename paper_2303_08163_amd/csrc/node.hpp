@@ -218,6 +218,7 @@ __device__ __forceinline__ bool collide(T (&v)[Lattice<DIM>::Q], const Relax &r)
 
     const double base_poly = fma(-1.5, usq, 1.0);
     const double rho_w = EQ == kEqPoly2 ? rho / (DIM == 1 ? 6.0 : (DIM == 2 ? 36.0 : 216.0)) : 0.0;
+    const double ux2_45 = (4.5 * u[0]) * u[0];
 #pragma unroll
     for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
 #pragma unroll
@@ -225,15 +226,23 @@ __device__ __forceinline__ bool collide(T (&v)[Lattice<DIM>::Q], const Relax &r)
             const double t = EQ == kEqPoly2 || DIM == 1
                                  ? rho
                                  : (DIM == 3 ? (rho * g[1][cy]) * g[2][cz] : rho * g[1][cy]);
+            // second-order polynomial along the row: with p = c_y u_y + c_z u_z,
+            // 1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u^2 = pp + c_x odd + c_x^2 4.5 u_x^2,
+            // pp = 1 - 1.5 u^2 + 3 p + 4.5 p^2, odd = 3 u_x (1 + 3 p)
+            double pp = 0.0, odd = 0.0, row_w = 0.0;
+            if constexpr (EQ == kEqPoly2) {
+                const double p = (DIM >= 2 ? (cy - 1) * u[1] : 0.0) + (DIM == 3 ? (cz - 1) * u[2] : 0.0);
+                pp = fma(p, fma(4.5, p, 3.0), base_poly);
+                odd = (3.0 * u[0]) * fma(3.0, p, 1.0);
+                row_w = rho_w * ((DIM >= 2 ? w1_int(cy) : 1.0) * (DIM == 3 ? w1_int(cz) : 1.0));
+            }
 #pragma unroll
             for (int cx = 0; cx < 3; ++cx) {
                 const int i = cx + 3 * cy + 9 * cz;
                 double feq;
                 if constexpr (EQ == kEqPoly2) {
-                    const double cu = (cx - 1) * u[0] + (DIM >= 2 ? (cy - 1) * u[1] : 0.0) +
-                                      (DIM == 3 ? (cz - 1) * u[2] : 0.0);
-                    const double wint = w1_int(cx) * (DIM >= 2 ? w1_int(cy) : 1.0) * (DIM == 3 ? w1_int(cz) : 1.0);
-                    feq = (wint * rho_w) * fma(cu, fma(4.5, cu, 3.0), base_poly);
+                    const double P = cx == 1 ? pp : (cx == 2 ? (pp + ux2_45) + odd : (pp + ux2_45) - odd);
+                    feq = (w1_int(cx) * row_w) * P;
                 } else {
                     feq = t * g[0][cx];
                 }
@@ -367,6 +376,7 @@ __device__ __forceinline__ bool equilibrium_stored(double rho, const double (&u)
     }
     const double base_poly = fma(-1.5, usq, 1.0);
     const double rho_w = EQ == kEqPoly2 ? rho / (DIM == 1 ? 6.0 : (DIM == 2 ? 36.0 : 216.0)) : 0.0;
+    const double ux2_45 = (4.5 * u[0]) * u[0];
 #pragma unroll
     for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
 #pragma unroll
@@ -374,15 +384,23 @@ __device__ __forceinline__ bool equilibrium_stored(double rho, const double (&u)
             const double t = EQ == kEqPoly2 || DIM == 1
                                  ? rho
                                  : (DIM == 3 ? (rho * g[1][cy]) * g[2][cz] : rho * g[1][cy]);
+            // second-order polynomial along the row: with p = c_y u_y + c_z u_z,
+            // 1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u^2 = pp + c_x odd + c_x^2 4.5 u_x^2,
+            // pp = 1 - 1.5 u^2 + 3 p + 4.5 p^2, odd = 3 u_x (1 + 3 p)
+            double pp = 0.0, odd = 0.0, row_w = 0.0;
+            if constexpr (EQ == kEqPoly2) {
+                const double p = (DIM >= 2 ? (cy - 1) * u[1] : 0.0) + (DIM == 3 ? (cz - 1) * u[2] : 0.0);
+                pp = fma(p, fma(4.5, p, 3.0), base_poly);
+                odd = (3.0 * u[0]) * fma(3.0, p, 1.0);
+                row_w = rho_w * ((DIM >= 2 ? w1_int(cy) : 1.0) * (DIM == 3 ? w1_int(cz) : 1.0));
+            }
 #pragma unroll
             for (int cx = 0; cx < 3; ++cx) {
                 const int i = cx + 3 * cy + 9 * cz;
                 double feq;
                 if constexpr (EQ == kEqPoly2) {
-                    const double cu = (cx - 1) * u[0] + (DIM >= 2 ? (cy - 1) * u[1] : 0.0) +
-                                      (DIM == 3 ? (cz - 1) * u[2] : 0.0);
-                    const double wint = w1_int(cx) * (DIM >= 2 ? w1_int(cy) : 1.0) * (DIM == 3 ? w1_int(cz) : 1.0);
-                    feq = (wint * rho_w) * fma(cu, fma(4.5, cu, 3.0), base_poly);
+                    const double P = cx == 1 ? pp : (cx == 2 ? (pp + ux2_45) + odd : (pp + ux2_45) - odd);
+                    feq = (w1_int(cx) * row_w) * P;
                 } else {
                     feq = t * g[0][cx];
                 }
