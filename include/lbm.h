@@ -334,12 +334,15 @@ int lbm_pool_destroy(lbm_pool *pool);
  *           each case as (re, im), in no particular order (NULL: not written).
  *   info    device pointer to count int32: QR steps taken, or -1 when the
  *           iteration limit (30 Q steps) was reached first (NULL: not written).
+ *   flops   device pointer to count doubles: FP64 operations the solver spent
+ *           on the case, counting its own active block at every QR step (a
+ *           fused multiply-add counts 2) (NULL: not written).
  *   stream  hipStream_t (NULL = the null stream).
  * Enqueues one kernel and returns without synchronising.  Errors: LBM_EINVAL
  * (lattice other than D1Q3/D2Q9, bad equilibrium or bulk_correction, count < 0,
  * cases NULL with count > 0); LBM_EDEVICE. */
 int lbm_vn_spectra(int32_t lattice, int32_t equilibrium, int32_t bulk_correction, const double *cases,
-                   int64_t count, double *radius, double *eig, int32_t *info, void *stream);
+                   int64_t count, double *radius, double *eig, int32_t *info, double *flops, void *stream);
 
 /* Largest spectral radius over a wave-vector grid, for n_states states: for
  * state s = (tau, u_x, u_y) (device array of n_states * 3 doubles) the

@@ -13,7 +13,15 @@
 
 namespace lbm {
 
-constexpr int kVnThreads = 64;
+constexpr int kVnThreads = 64;  // one wavefront per workgroup
+
+// Largest v over the wavefront (all 64 lanes take part).
+__device__ __forceinline__ int wave_max_int(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
 
 struct VnSpectraArgs {
     const double *cases;  // count x 5: tau, u_x, u_y, k_x, k_y
@@ -21,14 +29,17 @@ struct VnSpectraArgs {
     double *radius;  // count, or null
     double *eig;     // count x N x 2, or null
     int *info;       // count, or null: QR steps taken, -1 if the limit was reached
+    double *flops;   // count, or null: FP64 operations spent on the case
 };
 
 template <int DIM, int EQ, bool CORR>
 __global__ __launch_bounds__(kVnThreads) void k_vn_spectra(VnSpectraArgs a) {
     constexpr int N = DIM == 1 ? 3 : 9;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.count)
-        return;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // lanes past the end repeat the last case (every lane must reach the
+    // wavefront-wide reductions of the eigensolver) and write nothing
+    const bool live = t0 < a.count;
+    const int64_t t = live ? t0 : a.count - 1;
     const double *p = a.cases + 5 * t;
     const double tau = p[0];
     const double u[2] = {p[1], DIM == 2 ? p[2] : 0.0};
@@ -36,7 +47,10 @@ __global__ __launch_bounds__(kVnThreads) void k_vn_spectra(VnSpectraArgs a) {
     cplx H[N][N];
     vn_matrix<DIM, EQ, CORR>(tau, u, k, H);
     hessenberg<N>(H);
-    const int steps = hessenberg_eigenvalues<N>(H);
+    double work = vn_fixed_flops<N>();
+    const int steps = hessenberg_eigenvalues<N>(H, wave_max_int, &work);
+    if (!live)
+        return;
     double r = 0.0;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -50,6 +64,8 @@ __global__ __launch_bounds__(kVnThreads) void k_vn_spectra(VnSpectraArgs a) {
         a.radius[t] = r;
     if (a.info)
         a.info[t] = steps;
+    if (a.flops)
+        a.flops[t] = work;
 }
 
 struct VnMaxArgs {
@@ -64,9 +80,10 @@ struct VnMaxArgs {
 template <int DIM, int EQ, bool CORR>
 __global__ __launch_bounds__(kVnThreads) void k_vn_max_radius(VnMaxArgs a) {
     constexpr int N = DIM == 1 ? 3 : 9;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.n_states * a.per_state)
-        return;
+    const int64_t total = a.n_states * a.per_state;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = t0 < total;  // lanes past the end repeat the last matrix, write nothing
+    const int64_t t = live ? t0 : total - 1;
     const int64_t s = t / a.per_state;
     const int64_t q = t - s * a.per_state;
     const double dk = a.nk > 1 ? 3.141592653589793 / (double)(a.nk - 1) : 0.0;
@@ -78,7 +95,9 @@ __global__ __launch_bounds__(kVnThreads) void k_vn_max_radius(VnMaxArgs a) {
     cplx H[N][N];
     vn_matrix<DIM, EQ, CORR>(tau, u, k, H);
     hessenberg<N>(H);
-    const int steps = hessenberg_eigenvalues<N>(H);
+    const int steps = hessenberg_eigenvalues<N>(H, wave_max_int);
+    if (!live)
+        return;
     double r = 0.0;
 #pragma unroll
     for (int i = 0; i < N; ++i)
@@ -149,7 +168,7 @@ using namespace lbm;
 extern "C" {
 
 int lbm_vn_spectra(int32_t lattice, int32_t equilibrium, int32_t bulk_correction, const double *cases,
-                   int64_t count, double *radius, double *eig, int32_t *info, void *stream) {
+                   int64_t count, double *radius, double *eig, int32_t *info, double *flops, void *stream) {
     SpectraFn sf;
     MaxFn mf;
     int dim;
@@ -162,7 +181,7 @@ int lbm_vn_spectra(int32_t lattice, int32_t equilibrium, int32_t bulk_correction
     }
     if (count == 0)
         return LBM_OK;
-    VnSpectraArgs a{cases, count, radius, eig, info};
+    VnSpectraArgs a{cases, count, radius, eig, info, flops};
     const int64_t blocks = (count + kVnThreads - 1) / kVnThreads;
     if (blocks > INT32_MAX) {
         set_error("von Neumann spectra: too many cases");

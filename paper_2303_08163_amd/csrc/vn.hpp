@@ -22,9 +22,9 @@
 // unreduced block, exceptional shifts after 10 and 20 steps without
 // deflation) until every subdiagonal entry is negligible.  All loops run
 // over compile-time index ranges so the matrix stays in registers; a QR step
-// always sweeps the whole matrix (rotations against a zero subdiagonal are
-// exact identities, so deflated blocks stay decoupled), and the active block
-// only selects the shift.
+// sweeps the leading block that still holds unconverged eigenvalues of any
+// thread of the wavefront (rotations against a zero subdiagonal are exact
+// identities, so deflated blocks stay decoupled).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -231,14 +231,86 @@ __host__ __device__ __forceinline__ void hessenberg(cplx (&A)[N][N]) {
     });
 }
 
-// Eigenvalues of an upper Hessenberg matrix (overwritten; the diagonal holds
-// them on return).  Returns the number of QR steps, or -1 if the iteration
-// limit (30 N steps) was reached first.
+// One explicit shifted QR step on the leading M x M block of H:
+// H - mu I = Q R, H <- R Q + mu I, with the shift applied to rows 0..hi only
+// (hi >= M - 1 never happens: M - 1 is the wavefront's largest hi).  Rows
+// below hi are deflated (zero subdiagonal), the rotations there are exact
+// identities, so without the shift they are left bit-for-bit unchanged.
+template <int N, int M>
+__host__ __device__ __forceinline__ void qr_step(cplx (&H)[N][N], cplx mu, int hi) {
+    static_for<0, M>([&](auto kk) {
+        constexpr int k = decltype(kk)::value;
+        if (k <= hi)
+            H[k][k] = csub(H[k][k], mu);
+    });
+    double cs[M - 1];
+    cplx sn[M - 1];
+    static_for<0, M - 1>([&](auto kk) {
+        constexpr int k = decltype(kk)::value;
+        givens(H[k][k], H[k + 1][k], cs[k], sn[k]);
+        static_for<k, M>([&](auto jj) {
+            constexpr int j = decltype(jj)::value;
+            const cplx x = H[k][j], y = H[k + 1][j];
+            // row k <- c x + s y ; row k+1 <- -conj(s) x + c y
+            H[k][j] = cadd(cscale(cs[k], x), cmul(sn[k], y));
+            H[k + 1][j] = csub(cscale(cs[k], y), cmulc(sn[k], x));
+        });
+        H[k + 1][k] = {0.0, 0.0};
+    });
+    static_for<0, M - 1>([&](auto kk) {
+        constexpr int k = decltype(kk)::value;
+        static_for<0, k + 2>([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            const cplx x = H[i][k], y = H[i][k + 1];
+            // columns k, k+1 times G^H: col k <- c x + conj(s) y ; col k+1 <- -s x + c y
+            H[i][k] = cadd(cscale(cs[k], x), cmulc(sn[k], y));
+            H[i][k + 1] = csub(cscale(cs[k], y), cmul(sn[k], x));
+        });
+    });
+    static_for<0, M>([&](auto kk) {
+        constexpr int k = decltype(kk)::value;
+        if (k <= hi)
+            H[k][k] = cadd(H[k][k], mu);
+    });
+}
+
+// FP64 operations (a fused multiply-add counts 2; divisions, square roots and
+// transcendentals 1) of the solver as written: building M, the Householder
+// reduction and the norm (fixed), and one QR step on an active block of M
+// rows (its rotations, the shift on M rows, the deflation scan and the shift
+// choice).  Used to report the arithmetic rate; they count each matrix's own
+// active block, not the wavefront's common one.
 template <int N>
-__host__ __device__ __forceinline__ int hessenberg_eigenvalues(cplx (&H)[N][N]) {
+__host__ __device__ constexpr double vn_fixed_flops() {
+    double h = 0.0;
+    for (int m = 2; m <= N - 1; ++m)
+        h += 16.0 * m * m + (6.0 + 16.0 * N) * m + 2.0 * N + 14.0;
+    const double build = 9.0 * N * N + 20.0 * N + 40.0;
+    const double norm = 3.0 * (N * (N + 1) / 2 + N - 1) + 4.0 * N;
+    return h + build + norm;
+}
+__host__ __device__ constexpr double vn_step_flops(int M) {
+    return (M - 1) * (20.0 * M + 62.0) + 4.0 * M + 150.0;
+}
+
+// Eigenvalues of an upper Hessenberg matrix (overwritten; the diagonal holds
+// them on return).  Returns the number of QR steps taken, or -1 if the
+// iteration limit (30 N steps) was reached first.
+//
+// For eigenvalues only, once the rows below hi have deflated the leading
+// (hi + 1) x (hi + 1) block carries every remaining eigenvalue, so a step
+// sweeps only the leading M x M block.  group_max(v) returns the largest v
+// over the threads that execute in lockstep (a wavefront on the GPU, the
+// thread itself on the host); M is taken from it so that every thread of a
+// wavefront runs the same compile-time block size.  Every thread must call
+// this function (none may have left early), and the loop runs until every
+// thread of the group is done; a finished thread's steps are exact no-ops.
+template <int N, typename GroupMax>
+__host__ __device__ __forceinline__ int hessenberg_eigenvalues(cplx (&H)[N][N], GroupMax group_max,
+                                                               double *work = nullptr) {
     constexpr double kUlp = 2.220446049250313e-16;
     // scale below which a subdiagonal entry is negligible in any case:
-    // ulp times the largest |entry| (1-norm of the complex value)
+    // ulp times 1e-2 times the largest |entry| (1-norm of the complex value)
     double norm = 0.0;
     static_for<0, N>([&](auto ii) {
         constexpr int i = decltype(ii)::value;
@@ -247,8 +319,9 @@ __host__ __device__ __forceinline__ int hessenberg_eigenvalues(cplx (&H)[N][N]) 
             norm = fmax(norm, cabs1(H[i][j]));
         });
     });
-    norm *= 1e-2;  // kUlp * norm * 1e-2: well below the eigenvalues' own rounding
+    norm *= 1e-2;
     int steps = 0, since_deflation = 0, last_hi = N;
+    bool failed = false;
     for (;;) {
         // deflate negligible subdiagonal entries (relative to their diagonal
         // neighbours, or to the matrix norm when those are tiny); hi = lowest
@@ -262,75 +335,54 @@ __host__ __device__ __forceinline__ int hessenberg_eigenvalues(cplx (&H)[N][N]) 
             if (H[k][k - 1].re != 0.0 || H[k][k - 1].im != 0.0)
                 hi = k;
         });
-        if (hi == 0)
-            return steps;
-        if (steps >= 30 * N)
-            return -1;
-        if (hi != last_hi) {
-            last_hi = hi;
-            since_deflation = 0;
+        if (hi > 0 && steps >= 30 * N) {
+            failed = true;
+            hi = 0;  // give up: stop stepping this matrix
         }
-        // trailing 2 x 2 of the active block: [[a, b], [c, d]] at rows hi-1, hi
-        cplx a = {0.0, 0.0}, b = a, c = a, d = a, e = a;  // e = H[hi-1][hi-2] (0 if hi = 1)
-        static_for<1, N>([&](auto kk) {
-            constexpr int k = decltype(kk)::value;
-            if (k == hi) {
-                a = H[k - 1][k - 1];
-                b = H[k - 1][k];
-                c = H[k][k - 1];
-                d = H[k][k];
-                if constexpr (k >= 2)
-                    e = H[k - 1][k - 2];
+        const int wave_hi = group_max(hi);
+        if (wave_hi == 0)
+            return failed ? -1 : steps;
+        cplx mu = {0.0, 0.0};
+        if (hi > 0) {
+            if (hi != last_hi) {
+                last_hi = hi;
+                since_deflation = 0;
             }
-        });
-        cplx mu;
-        if (since_deflation == 10 || since_deflation == 20) {
-            // exceptional shift
-            const double t = cabs1(c) + cabs1(e);
-            mu = {d.re + 0.75 * t, d.im};
-        } else {
-            // Wilkinson: eigenvalue of the 2 x 2 closer to d
-            const cplx half = cscale(0.5, csub(a, d));
-            const cplx disc = csqrt_(cadd(cmul(half, half), cmul(b, c)));
-            const cplx m1 = cadd(half, disc), m2 = csub(half, disc);
-            const cplx den = cabs1(m1) >= cabs1(m2) ? m1 : m2;  // larger root for stability
-            // d - b c / (half + sign * disc)
-            mu = (den.re == 0.0 && den.im == 0.0) ? d : csub(d, cdiv(cmul(b, c), den));
+            // trailing 2 x 2 of the active block: [[a, b], [c, d]] at rows hi-1, hi
+            cplx a = {0.0, 0.0}, b = a, c = a, d = a, e = a;  // e = H[hi-1][hi-2] (0 if hi = 1)
+            static_for<1, N>([&](auto kk) {
+                constexpr int k = decltype(kk)::value;
+                if (k == hi) {
+                    a = H[k - 1][k - 1];
+                    b = H[k - 1][k];
+                    c = H[k][k - 1];
+                    d = H[k][k];
+                    if constexpr (k >= 2)
+                        e = H[k - 1][k - 2];
+                }
+            });
+            if (since_deflation == 10 || since_deflation == 20) {
+                // exceptional shift
+                const double t = cabs1(c) + cabs1(e);
+                mu = {d.re + 0.75 * t, d.im};
+            } else {
+                // Wilkinson: eigenvalue of the 2 x 2 closer to d
+                const cplx half = cscale(0.5, csub(a, d));
+                const cplx disc = csqrt_(cadd(cmul(half, half), cmul(b, c)));
+                const cplx m1 = cadd(half, disc), m2 = csub(half, disc);
+                const cplx den = cabs1(m1) >= cabs1(m2) ? m1 : m2;  // larger root for stability
+                mu = (den.re == 0.0 && den.im == 0.0) ? d : csub(d, cdiv(cmul(b, c), den));
+            }
+            ++steps;
+            ++since_deflation;
+            if (work)
+                *work += vn_step_flops(hi + 1);
         }
-        ++steps;
-        ++since_deflation;
-        // one explicit shifted QR step over the whole matrix: H - mu I = Q R, H <- R Q + mu I
-        static_for<0, N>([&](auto kk) {
-            constexpr int k = decltype(kk)::value;
-            H[k][k] = csub(H[k][k], mu);
-        });
-        double cs[N - 1];
-        cplx sn[N - 1];
-        static_for<0, N - 1>([&](auto kk) {
-            constexpr int k = decltype(kk)::value;
-            givens(H[k][k], H[k + 1][k], cs[k], sn[k]);
-            static_for<k, N>([&](auto jj) {
-                constexpr int j = decltype(jj)::value;
-                const cplx x = H[k][j], y = H[k + 1][j];
-                // row k <- c x + s y ; row k+1 <- -conj(s) x + c y
-                H[k][j] = cadd(cscale(cs[k], x), cmul(sn[k], y));
-                H[k + 1][j] = csub(cscale(cs[k], y), cmulc(sn[k], x));
-            });
-            H[k + 1][k] = {0.0, 0.0};
-        });
-        static_for<0, N - 1>([&](auto kk) {
-            constexpr int k = decltype(kk)::value;
-            static_for<0, k + 2>([&](auto ii) {
-                constexpr int i = decltype(ii)::value;
-                const cplx x = H[i][k], y = H[i][k + 1];
-                // columns k, k+1 times G^H: col k <- c x + conj(s) y ; col k+1 <- -s x + c y
-                H[i][k] = cadd(cscale(cs[k], x), cmulc(sn[k], y));
-                H[i][k + 1] = csub(cscale(cs[k], y), cmul(sn[k], x));
-            });
-        });
-        static_for<0, N>([&](auto kk) {
-            constexpr int k = decltype(kk)::value;
-            H[k][k] = cadd(H[k][k], mu);
+        // one QR step on the leading (wave_hi + 1) block, the same size for the group
+        static_for<2, N + 1>([&](auto mm) {
+            constexpr int M = decltype(mm)::value;
+            if (wave_hi + 1 == M)
+                qr_step<N, M>(H, mu, hi);
         });
     }
 }

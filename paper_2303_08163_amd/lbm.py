@@ -129,7 +129,8 @@ def load_library(path: str = LIB_PATH):
         "lbm_moments": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(lbm_diag)]),
         "lbm_get_populations": (ctypes.c_int, [vp, vp]),
         "lbm_energy": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_double, vp]),
-        "lbm_vn_spectra": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, i64, vp, vp, vp, vp]),
+        "lbm_vn_spectra": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, i64, vp, vp, vp, vp,
+                                          vp]),
         "lbm_vn_max_radius": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, i64,
                                              ctypes.c_int32, vp, vp, vp, vp]),
         "lbm_destroy": (ctypes.c_int, [vp]),
@@ -233,10 +234,10 @@ def lbm_energy(h, U, rho_ref: float, out: int) -> None:
 
 
 def lbm_vn_spectra(lattice: int, equilibrium, bulk_correction, cases: int, count: int, radius, eig, info,
-                   stream=None) -> None:
+                   flops=None, stream=None) -> None:
     _check(load_library().lbm_vn_spectra(int(lattice), EQUILIBRIA.get(equilibrium, equilibrium),
-                                          int(bool(bulk_correction)), cases, int(count), radius, eig, info, stream),
-           "lbm_vn_spectra")
+                                          int(bool(bulk_correction)), cases, int(count), radius, eig, info, flops,
+                                          stream), "lbm_vn_spectra")
 
 
 def lbm_vn_max_radius(lattice: int, equilibrium, bulk_correction, states: int, n_states: int, nk: int,

@@ -54,7 +54,7 @@ def spectra(cases, dim: int = 2, equilibrium="entropic", bulk_correction=False, 
     info = torch.empty(n, dtype=torch.int32, device=device)
     stream = torch.cuda.current_stream(device)
     lbm.lbm_vn_spectra(_lattice(dim), equilibrium, bulk_correction, c.data_ptr(), n, radius.data_ptr(),
-                       eig.data_ptr(), info.data_ptr(), stream.cuda_stream)
+                       eig.data_ptr(), info.data_ptr(), None, stream.cuda_stream)
     stream.synchronize()
     e = eig.cpu().numpy()
     return radius.cpu().numpy(), e[..., 0] + 1j * e[..., 1], info.cpu().numpy()

@@ -143,12 +143,12 @@ def test_d1q3_configs(lbm):
 def test_vn_argument_checks(lbm):
     lib = lbm.load_library()
     E = lbm.LBM_EINVAL
-    assert lib.lbm_vn_spectra(27, 0, 0, 256, 1, None, None, None, None) == E  # D3Q27 not offered
-    assert lib.lbm_vn_spectra(9, 3, 0, 256, 1, None, None, None, None) == E
-    assert lib.lbm_vn_spectra(9, 0, 2, 256, 1, None, None, None, None) == E
-    assert lib.lbm_vn_spectra(9, 0, 0, None, 1, None, None, None, None) == E
-    assert lib.lbm_vn_spectra(9, 0, 0, 256, -1, None, None, None, None) == E
-    assert lib.lbm_vn_spectra(3, 1, 1, 256, 0, None, None, None, None) == lbm.LBM_OK  # nothing to do
+    assert lib.lbm_vn_spectra(27, 0, 0, 256, 1, None, None, None, None, None) == E  # D3Q27 not offered
+    assert lib.lbm_vn_spectra(9, 3, 0, 256, 1, None, None, None, None, None) == E
+    assert lib.lbm_vn_spectra(9, 0, 2, 256, 1, None, None, None, None, None) == E
+    assert lib.lbm_vn_spectra(9, 0, 0, None, 1, None, None, None, None, None) == E
+    assert lib.lbm_vn_spectra(9, 0, 0, 256, -1, None, None, None, None, None) == E
+    assert lib.lbm_vn_spectra(3, 1, 1, 256, 0, None, None, None, None, None) == lbm.LBM_OK  # nothing to do
     assert lib.lbm_vn_max_radius(9, 0, 0, 256, 4, 0, 256, 256, 256, None) == E  # nk < 1
     assert lib.lbm_vn_max_radius(9, 0, 0, 256, 4, 33, 256, 260, 256, None) == E  # misaligned scratch
     assert lib.lbm_vn_max_radius(9, 0, 0, 256, 4, 33, 256, 256, None, None) == E
