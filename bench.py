@@ -146,13 +146,20 @@ def bench_serving(n_requests: int, rate: float, light_requests: int) -> dict:
         be = serve.PoolBackend(96 << 30, max_slots=512)
         try:
             kw = {"policy": "swf", "lookahead": 1 << 30} if policy == "swf" else {"policy": "fifo", "lookahead": 8}
-            return serve.summarize(serve.Server(be, **kw).serve(tr))
+            out = serve.summarize(serve.Server(be, **kw).serve(tr))
         finally:
             be.close()
+        progress(f"serving {len(tr)} requests, continuous batching {policy}: {out}")
+        return out
+
+    def serial(tr):
+        out = serve.summarize(serve.serial_serve(tr))
+        progress(f"serving {len(tr)} requests, serial: {out}")
+        return out
 
     ps = pooled(trace, "fifo")
     pw = pooled(trace, "swf")
-    bs = serve.summarize(serve.serial_serve(trace))
+    bs = serial(trace)
     res["stated_rate"] = {"rate_req_s": rate, "requests": n_requests, "continuous_batching": ps,
                           "continuous_batching_shortest_work_first": pw, "serial": bs}
     cap = ps["solves_per_s"] or 1.0
@@ -160,7 +167,7 @@ def bench_serving(n_requests: int, rate: float, light_requests: int) -> dict:
     trace_l = workloads.serving_trace(n_requests=light_requests, rate=light_rate, seed=8164)
     pl = pooled(trace_l, "fifo")
     plw = pooled(trace_l, "swf")
-    bl = serve.summarize(serve.serial_serve(trace_l))
+    bl = serial(trace_l)
     res["half_capacity_rate"] = {"rate_req_s": round(light_rate, 2), "requests": light_requests,
                                  "continuous_batching": pl, "continuous_batching_shortest_work_first": plw,
                                  "serial": bl}
@@ -190,6 +197,11 @@ def bench_wave(steps: int = 2000) -> dict:
             "U0": sorted(set(U0s) | {0.0}), "nu_eff_over_nu_eff_at_rest": table,
             "nu_eff_over_nu_at_rest": round(next(r["ratio"] for r in rows if r["U0"] == 0.0), 5),
             "runs": len(rows), "wall_s": round(wall, 3)}
+
+
+def progress(msg: str) -> None:
+    """A progress line on stderr (the JSON result line goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def host_cpu() -> dict:
@@ -481,16 +493,21 @@ def main() -> int:
     }
     if "batched" in sections:
         out["batched"] = bench_batched(args.batch_count, args.batch_steps)
+        progress("batched done")
     if "serving" in sections:
         out["serving"] = bench_serving(args.serve_requests, args.serve_rate, args.serve_light_requests)
     if "wave" in sections:
         out["wave"] = bench_wave()
+        progress("wave done")
     if "oracle_timing" in sections:
         out["oracle_timing"] = bench_oracle_timing()
+        progress("oracle_timing done")
     if "variants" in sections:
         out["variants"] = bench_variants()
+        progress("variants done")
     if "stability" in sections:
         out["stability"] = bench_stability(with_cpu=not args.no_cpu_baseline)
+        progress("stability done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

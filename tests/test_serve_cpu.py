@@ -207,3 +207,18 @@ def test_policy_is_checked():
     clk = VirtualClock()
     with pytest.raises(ValueError):
         serve.Server(FakeBackend(clk, 1 << 30, 4), policy="lifo")
+
+
+def test_thousand_request_trace():
+    """The full-length serving trace (1000 Poisson arrivals at 200 req/s):
+    every request served once within the budget under both policies, and
+    shortest-work-first keeps the median well below FIFO batching."""
+    tr = _trace(n=1000, rate=200.0)
+    res = {}
+    for policy in ("fifo", "swf"):
+        clk = VirtualClock()
+        be = FakeBackend(clk, budget=96 << 30, max_slots=512)
+        out = serve.Server(be, clock=clk.clock, sleep=clk.sleep, policy=policy).serve(tr)
+        assert sorted(r["id"] for r in out) == list(range(1000)) and be.peak <= 96 << 30
+        res[policy] = serve.summarize(out)
+    assert res["swf"]["p50_latency_s"] < 0.25 * res["fifo"]["p50_latency_s"]
