@@ -14,7 +14,11 @@ has shape ``(D, *grid)``.
 Parity status: every function here is pinned by tests in
 ``tests/test_oracle_*.py`` (conservation, entropy minimisation by brute force,
 closed forms printed in the paper, low-Mach limits, shear-wave viscosity,
-symmetries and embeddings); none is "parity unpinned".
+symmetries and embeddings); none is "parity unpinned".  The collision
+Jacobian and the von Neumann analysis built on it (``oracle.stability``) are
+pinned in ``tests/test_oracle_stability.py`` (finite differences, collision
+invariants, the k = 0 spectrum, sound speeds and dissipation at k -> 0, and
+the stability limits printed in the paper).
 """
 from __future__ import annotations
 
