@@ -244,7 +244,10 @@ typedef struct lbm_pool_tuning {
     int32_t persistent; /* 1: one cooperative launch per run and class; 0: one launch per step */
     int32_t workgroups; /* persistent grid size (0 = as many as are co-resident) */
     int32_t layout;     /* LBM_LAYOUT_* of the slots (0 = row-interleaved) */
-    int32_t reserved[3];/* must be 0 */
+    int32_t flat;       /* 0: a workgroup covers tile_x nodes of tile_y rows; 1: it covers
+                           tile_x * tile_y consecutive nodes of its slot in x-fastest order,
+                           across rows and planes (no idle lanes at ragged row ends) */
+    int32_t reserved[2];/* must be 0 */
 } lbm_pool_tuning;
 
 typedef struct lbm_pool_stats {

@@ -1,8 +1,9 @@
 """Autotuner for pool launch shapes.
 
 For a set of domains (lattice, grid, storage), it times a short run of each
-candidate pool tuning -- workgroup tile shape (one node per thread) and launch
-form (one launch per step, or one persistent cooperative launch per run) -- on
+candidate pool tuning -- workgroup tile shape (one node per thread; rows of
+tile_x nodes, or runs of consecutive nodes across rows) and launch form (one
+launch per step, or one persistent cooperative launch per run) -- on
 a scratch pool holding domains of exactly those sizes, and returns the
 fastest.  Results do not depend on the tuning (the per-node arithmetic is the
 same in every kernel), so only time is compared.  Choices are cached in a JSON
@@ -25,8 +26,13 @@ TILES = [(64, 4), (64, 2), (64, 1), (32, 8), (32, 2), (128, 2), (128, 1), (256, 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "lbm_entropic", "autotune.json")
 
 
+FLAT_TILES = [(64, 4), (64, 2), (64, 1)]  # flat mode: 256, 128 or 64 consecutive nodes per workgroup
+
+
 def candidates():
-    return [dict(tile_x=tx, tile_y=ty, persistent=p) for (tx, ty) in TILES for p in (0, 1)]
+    rows = [dict(tile_x=tx, tile_y=ty, persistent=p) for (tx, ty) in TILES for p in (0, 1)]
+    flat = [dict(tile_x=tx, tile_y=ty, persistent=p, flat=1) for (tx, ty) in FLAT_TILES for p in (0, 1)]
+    return rows + flat
 
 
 def signature(domains) -> str:
@@ -97,7 +103,7 @@ def tune_pool(domains, steps: int = 20, cands=None, cache_path: str | None = DEF
               use_cache: bool = True, verbose: bool = False):
     """domains: list of (lattice, (nx, ny[, nz]), dtype).  Returns (tuning dict,
     report) where report lists every candidate's time per step."""
-    key = f"{_device_key()}|{signature(domains)}"
+    key = f"candidates-v2|{_device_key()}|{signature(domains)}"
     cache = _load_cache(cache_path) if cache_path else {}
     if use_cache and key in cache:
         return cache[key]["tuning"], {"cached": True, "key": key, "times": cache[key].get("times")}

@@ -111,6 +111,21 @@ __device__ __forceinline__ void step_node(const store_t<DT> *__restrict__ src, s
         dst[self + i * ps] = f[i];
 }
 
+// A lane past the end of a row (nx <= x < ps) in the row-interleaved layout
+// stores zeros into the row's padding, so that the workgroup writes whole
+// cache lines: partial-line stores at ragged row ends cost as much again in
+// memory traffic.  The padding is never read.
+template <int DIM, int DT>
+__device__ __forceinline__ void store_padding(store_t<DT> *__restrict__ dst, int ny, int64_t ps, int64_t rs,
+                                              int x, int y, int z) {
+    if (rs != (int64_t)Lattice<DIM>::Q * ps || x >= ps)  // plane layout, or past the pitch
+        return;
+    const int64_t self = (int64_t)(z * ny + y) * rs + x;
+#pragma unroll
+    for (int i = 0; i < Lattice<DIM>::Q; ++i)
+        dst[self + i * ps] = store_t<DT>(0);
+}
+
 // One LBGK step over the whole domain.  1-D grid of tiles_x * tiles_y * nz
 // workgroups of blockDim.x * blockDim.y threads, one node per thread.
 template <int DIM, int DT, bool CORR, int EQ = kEqEntropic>
@@ -121,8 +136,12 @@ __global__ __launch_bounds__(256) void k_stream_collide(StepArgs a) {
     const int z = t / (a.tiles_x * a.tiles_y);
     const int x = tx * (int)blockDim.x + (int)threadIdx.x;
     const int y = ty * (int)blockDim.y + (int)threadIdx.y;
-    if (x >= a.nx || y >= a.ny)
+    if (y >= a.ny)
         return;
+    if (x >= a.nx) {
+        store_padding<DIM, DT>(static_cast<store_t<DT> *>(a.dst), a.ny, a.ps, a.rs, x, y, z);
+        return;
+    }
     step_node<DIM, DT, CORR, EQ>(static_cast<const store_t<DT> *>(a.src), static_cast<store_t<DT> *>(a.dst), a.nx,
                                  a.ny, a.nz, a.ps, a.rs, a.relax, a.flag, x, y, z);
 }

@@ -30,7 +30,7 @@ static int resolve_tuning(const lbm_pool_tuning *t, lbm_pool_tuning *out) {
     lbm_pool_tuning r{};
     if (t)
         r = *t;
-    if (r.reserved[0] || r.reserved[1] || r.reserved[2]) {
+    if (r.reserved[0] || r.reserved[1]) {
         set_error("lbm_pool_tuning.reserved must be 0");
         return LBM_EINVAL;
     }
@@ -48,6 +48,10 @@ static int resolve_tuning(const lbm_pool_tuning *t, lbm_pool_tuning *out) {
     }
     if (r.workgroups < 0) {
         set_error("pool tuning: workgroups must be >= 0");
+        return LBM_EINVAL;
+    }
+    if (r.flat != 0 && r.flat != 1) {
+        set_error("pool tuning: flat must be 0 or 1");
         return LBM_EINVAL;
     }
     if (r.layout == LBM_LAYOUT_DEFAULT)
@@ -314,7 +318,8 @@ int lbm_pool_admit(lbm_pool *p, const lbm_config *cfg, const double *rho, const 
     s.reported = false;
     s.tiles_x = (int)((cfg->nx + L.block_x - 1) / L.block_x);
     s.tiles_y = (int)((cfg->ny + L.block_y - 1) / L.block_y);
-    const int64_t tiles = (int64_t)s.tiles_x * s.tiles_y * cfg->nz;
+    const int64_t block = (int64_t)L.block_x * L.block_y;
+    const int64_t tiles = p->tun.flat ? (L.n + block - 1) / block : (int64_t)s.tiles_x * s.tiles_y * cfg->nz;
     if (tiles > (int64_t)1 << 30) {
         pool_free(p, off, bytes);
         s = Slot{};
@@ -403,6 +408,7 @@ int lbm_pool_run(lbm_pool *p, int64_t k) {
         a.barrier = p->barrier;
         a.error = p->error;
         a.spin_limit = kSpinLimit;
+        a.flat = p->tun.flat;
         const int dim = c >= 8 ? 3 : 2, dtype = (c % 8) / 2;
         const bool corr = (c & 1) != 0;
         PoolStepFn fn = dim == 3 ? pool_kernel<3>(dtype, corr, p->tun.persistent)

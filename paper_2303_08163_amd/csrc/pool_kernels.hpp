@@ -50,6 +50,7 @@ struct PoolRunArgs {
     unsigned *barrier;        // persistent form: arrival counter, zero at launch
     int *error;               // persistent form: set on a barrier timeout
     long long spin_limit;
+    int flat;                 // 1: a tile is blockDim.x * blockDim.y consecutive nodes of its slot
 };
 
 // Active tiles at step s: the tile count of the slots with remaining > s.
@@ -89,13 +90,29 @@ __device__ __forceinline__ void pool_tile(const PoolRunArgs &a, int t, int s) {
     const T *src = static_cast<const T *>(dd.buf[p]);
     T *dst = static_cast<T *>(dd.buf[p ^ 1]);
     const int tile = t - a.tile_start[lo];
-    const int tx = tile % tiles_x;
-    const int ty = (tile / tiles_x) % tiles_y;
-    const int z = tile / (tiles_x * tiles_y);
-    const int x = tx * (int)blockDim.x + (int)threadIdx.x;
-    const int y = ty * (int)blockDim.y + (int)threadIdx.y;
-    if (x >= nx || y >= ny)
-        return;
+    int x, y, z;
+    if (a.flat) {
+        // consecutive nodes of the slot, x fastest, across rows and planes
+        const int64_t n = (int64_t)tile * (blockDim.x * blockDim.y) + threadIdx.y * blockDim.x + threadIdx.x;
+        if (n >= (int64_t)nx * ny * nz)
+            return;
+        const int row = (int)(n / nx);
+        x = (int)(n - (int64_t)row * nx);
+        y = row % ny;
+        z = row / ny;
+    } else {
+        const int tx = tile % tiles_x;
+        const int ty = (tile / tiles_x) % tiles_y;
+        z = tile / (tiles_x * tiles_y);
+        x = tx * (int)blockDim.x + (int)threadIdx.x;
+        y = ty * (int)blockDim.y + (int)threadIdx.y;
+        if (y >= ny)
+            return;
+        if (x >= nx) {
+            store_padding<DIM, DT>(dst, ny, ps, rs, x, y, z);
+            return;
+        }
+    }
     step_node<DIM, DT, CORR>(src, dst, nx, ny, nz, ps, rs, relax, flag, x, y, z);
 }
 

@@ -48,11 +48,14 @@ def alone_results():
 
 
 @pytest.mark.parametrize("persistent", [0, 1])
-@pytest.mark.parametrize("tile", [(64, 4), (32, 2), (256, 1)])
+@pytest.mark.parametrize("tile", [(64, 4), (32, 2), (256, 1), ("flat", 64, 4), ("flat", 64, 1)])
 @pytest.mark.parametrize("chunk", [1000, 7])
 def test_pool_mix_equals_alone_bitwise(alone_results, persistent, tile, chunk):
     lbm = _lbm()
-    tun = lbm.make_pool_tuning(tile[0], tile[1], persistent)
+    if tile[0] == "flat":
+        tun = lbm.make_pool_tuning(tile[1], tile[2], persistent, flat=1)
+    else:
+        tun = lbm.make_pool_tuning(tile[0], tile[1], persistent)
     with lbm.Pool(GiB // 4, max_slots=16, tuning=tun) as pool:
         slots = []
         for (make, tau, steps, dtype, corr), (rho0, u0, _) in zip(MIX, alone_results):
