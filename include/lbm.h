@@ -123,8 +123,8 @@ enum { LBM_TUNE_NT_STORE = 1, LBM_TUNE_NT_LOAD = 2 };
 /* Population layouts in device memory (the library's private format; results
  * do not depend on it).  Rows run along x; row = z ny + y.
  *   LBM_LAYOUT_ROWS:   each row holds its Q population runs back to back,
- *                      each run padded to a multiple of 64 elements
- *                      ([z][y][i][x]).
+ *                      each run padded to a multiple of 16 elements (rows
+ *                      narrower than 16 are not padded) ([z][y][i][x]).
  *   LBM_LAYOUT_PLANES: one plane of N nodes per population ([i][z][y][x]),
  *                      planes padded to 64 elements plus plane_pad. */
 enum { LBM_LAYOUT_DEFAULT = 0, LBM_LAYOUT_ROWS = 1, LBM_LAYOUT_PLANES = 2 };

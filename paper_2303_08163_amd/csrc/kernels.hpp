@@ -6,7 +6,7 @@
 // Population i of node (x, row) lives at buf[i * ps + row * rs + x], where
 //   - row-interleaved layout (default): ps = pitch, rs = Q * pitch, i.e. each
 //     row stores its Q population runs back to back ([z][y][i][x]); pitch is
-//     nx rounded up to 64 elements (nx itself below 64);
+//     nx rounded up to 16 elements (nx itself below 16);
 //   - plane layout: ps = plane stride (>= N, a multiple of 64 plus optional
 //     padding), rs = nx ([i][z][y][x], one plane per population).
 // With the row-interleaved layout a row update reads 9 (D3Q27) or 3 (D2Q9)

@@ -70,13 +70,13 @@ def test_workspace_bytes_layout(lbm):
     # plane layout: padding adds whole 64-element blocks per plane
     t = lbm.make_tuning(0, 0, 100, layout=lbm.LBM_LAYOUT_PLANES)
     assert lbm.lbm_workspace_bytes(_cfg(lbm), t) == expect + 2 * 9 * 128 * 8
-    # row-interleaved layout (default): each population run padded to 64 elements
+    # row-interleaved layout (default): each population run padded to 16 elements
     e70 = lbm.lbm_workspace_bytes(_cfg(lbm, shape=(70, 32)))
-    assert e70 == 2 * 9 * 128 * 32 * 8 + 256 + 256 + ((9 * 7 * 8 + 255) // 256) * 256
+    assert e70 == 2 * 9 * 80 * 32 * 8 + 256 + 256 + ((9 * 7 * 8 + 255) // 256) * 256
     # D1Q3: one row of 3 runs; 64 x 3 doubles per buffer, one reduction block
     assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(64,))) == 2 * 3 * 64 * 8 + 256 + 256 + 256
-    assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(70,))) == 2 * 3 * 128 * 8 + 256 + 256 + 256
-    # below 64 the run is not padded
+    assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(70,))) == 2 * ((3 * 80 * 8 + 255) // 256) * 256 + 768
+    # below 16 the run is not padded
     assert lbm.lbm_workspace_bytes(_cfg(lbm, shape=(5, 3))) == 2 * 1280 + 256 + 256 + 256  # 1080 B buffers, 256-aligned
 
 
