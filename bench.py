@@ -82,7 +82,8 @@ def cpu_baseline(budget_s: float = 12.0) -> dict:
             "sample": f"D3Q27 64^3 Taylor-Green, FP64, {steps} steps, {dt:.1f} s, {threads} OpenMP threads"}
 
 
-def bench_batched(count: int, steps: int, dtypes=("fp32_dev", "fp64"), baseline: bool = True) -> dict:
+def bench_batched(count: int, steps: int, dtypes=("fp32_dev", "fp64"), baseline: bool = True,
+                  fixed_tuning: dict | None = None) -> dict:
     """Batched workload: `count` independent D2Q9 shear-wave domains (Nx, Ny
     uniform in 32..512, amplitude U[0.01, 0.2], nu log-uniform 1e-5..1e-1),
     `steps` steps each, all advanced by one persistent launch (or one launch
@@ -98,7 +99,10 @@ def bench_batched(count: int, steps: int, dtypes=("fp32_dev", "fp64"), baseline:
            "nodes": nodes}
     for dtype in dtypes:
         doms = [(9, (sp["nx"], sp["ny"]), dtype) for sp in specs]
-        tuning, rep = autotune.tune_pool(doms, steps=10)
+        if fixed_tuning is not None:
+            tuning, rep = dict(fixed_tuning), {"cached": False, "fixed": True}
+        else:
+            tuning, rep = autotune.tune_pool(doms, steps=10)
         tun = lbm.make_pool_tuning(**tuning)
         arena = lbm.lbm_pool_table_bytes(count) + sum(
             lbm.lbm_pool_slot_bytes(lbm.make_config(9, (sp["nx"], sp["ny"]), sp["tau"], dtype), tun) for sp in specs)
@@ -390,6 +394,8 @@ def main() -> int:
                          "oracle_timing (not in the default run: several minutes of host time)")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--batch-tuning", default="",
+                    help="TXxTY[,persistent][,flat]: fixed pool tile instead of the autotuner's choice")
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-light-requests", type=int, default=40)
@@ -493,7 +499,14 @@ def main() -> int:
         "kernel_source_digest": kernel_source_digest(),
     }
     if "batched" in sections:
-        out["batched"] = bench_batched(args.batch_count, args.batch_steps)
+        fixed = None
+        if args.batch_tuning:
+            parts = args.batch_tuning.split(",")
+            tx, ty = (int(v) for v in parts[0].lower().split("x"))
+            fixed = {"tile_x": tx, "tile_y": ty, "persistent": int("persistent" in parts[1:])}
+            if "flat" in parts[1:]:
+                fixed["flat"] = 1
+        out["batched"] = bench_batched(args.batch_count, args.batch_steps, fixed_tuning=fixed)
         progress("batched done")
     if "serving" in sections:
         out["serving"] = bench_serving(args.serve_requests, args.serve_rate, args.serve_light_requests)
