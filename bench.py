@@ -394,6 +394,8 @@ def main() -> int:
                          "oracle_timing (not in the default run: several minutes of host time)")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--no-batch-baseline", action="store_true",
+                    help="skip the one-domain-per-launch baseline of the batched section")
     ap.add_argument("--batch-tuning", default="",
                     help="TXxTY[,persistent][,flat]: fixed pool tile instead of the autotuner's choice")
     ap.add_argument("--serve-requests", type=int, default=120)
@@ -506,7 +508,8 @@ def main() -> int:
             fixed = {"tile_x": tx, "tile_y": ty, "persistent": int("persistent" in parts[1:])}
             if "flat" in parts[1:]:
                 fixed["flat"] = 1
-        out["batched"] = bench_batched(args.batch_count, args.batch_steps, fixed_tuning=fixed)
+        out["batched"] = bench_batched(args.batch_count, args.batch_steps, baseline=not args.no_batch_baseline,
+                                       fixed_tuning=fixed)
         progress("batched done")
     if "serving" in sections:
         out["serving"] = bench_serving(args.serve_requests, args.serve_rate, args.serve_light_requests)
