@@ -111,7 +111,9 @@ typedef struct lbm_tuning {
     int32_t plane_pad;        /* LBM_LAYOUT_PLANES only: extra elements between population
                                  planes (>= 0; < 0 selects the default, 0) */
     int32_t nodes_per_thread; /* consecutive x nodes per thread: 1, 2 or 4 (4 for FP32 storage
-                                 only); > 1 needs nx % (block_x * nodes_per_thread) == 0 */
+                                 only); > 1 needs nx % (block_x * nodes_per_thread) == 0.
+                                 0 = default: 4 floats or 2 doubles when nx allows, except
+                                 1 for FP32 storage on D2Q9 */
     int32_t flags;            /* LBM_TUNE_* bits for the vector kernels; < 0 selects the default */
     int32_t layout;           /* LBM_LAYOUT_*; 0 = default (row-interleaved) */
     int32_t reserved;         /* must be 0 */
