@@ -139,3 +139,16 @@ def test_pool_refuses_polynomial_equilibria():
                                 lbm.ctypes.byref(slot))
         assert rc == lbm.LBM_EINVAL
         assert pool.stats()["used_slots"] == 0
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("shape", [(21, 34), (6, 7, 9)])
+def test_polynomial_correction_beyond_positivity(kind, shape):
+    """Where A = 1 - 4.5 u^2 < 0 (|u| > 0.471) the corrected 2 beta of eq.
+    (redefined_relaxation rate_poly) is negative; nothing is clamped, so the
+    GPU follows the oracle there too (tau = 0.9 keeps A + 2 tau - 1 >= 0.67)."""
+    rho0, u0 = workloads.random_field(shape, seed=85, umax=0.5)
+    assert np.any(4.5 * np.max(np.abs(u0), axis=0) ** 2 > 1.0)
+    rho, u, diag, _ = run_gpu(rho0, u0, 0.9, 3, "fp64", True, kind)
+    r_ref, u_ref, _ = oracle.run(rho0, u0, 0.9, 3, corr="min", kind=kind)
+    assert rel_err(rho, r_ref) < 1e-12 and rel_err(u, u_ref) < 1e-12
