@@ -81,14 +81,24 @@ __device__ __forceinline__ void source_rows(int y, int z, int ny, int nz, int64_
 }
 
 // One node's pull-stream, collision and store.  src/dst are population
-// buffers of one domain; (x, y, z) must lie inside the grid.
+// buffers of one domain; (x, y, z) must lie inside the grid, or, with pad set,
+// in the row padding of the row-interleaved layout (nx <= x < ps).  A padding
+// lane goes through the same instructions as the nodes of its wavefront --
+// it reads the row's last node, and its result is discarded -- and stores
+// zeros into the padding with the same store instructions, so that the lines
+// at a ragged row end are written whole, by one instruction per population.
+// (A separate branch for the padding lanes diverges: the wavefront then issues
+// a second set of Q stores, each line at the row end is written in two parts,
+// and a step on a ragged width took up to 1.6 times as long.)  The padding is
+// never read.
 template <int DIM, int DT, bool CORR, int EQ = kEqEntropic>
 __device__ __forceinline__ void step_node(const store_t<DT> *__restrict__ src, store_t<DT> *__restrict__ dst,
                                           int nx, int ny, int nz, int64_t ps, int64_t rs, const Relax &relax,
-                                          int *flag, int x, int y, int z) {
+                                          int *flag, int x, int y, int z, bool pad = false) {
     using T = store_t<DT>;
     constexpr int Q = Lattice<DIM>::Q;
-    const int xs[3] = {x + 1 == nx ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};  // x - c_x
+    const int xn = pad ? nx - 1 : x;  // node whose sources are read
+    const int xs[3] = {xn + 1 == nx ? 0 : xn + 1, xn, xn == 0 ? nx - 1 : xn - 1};  // x - c_x
     int64_t rowoff[3][3];
     source_rows<DIM>(y, z, ny, nz, rs, rowoff);
     T f[Q];
@@ -103,27 +113,19 @@ __device__ __forceinline__ void step_node(const store_t<DT> *__restrict__ src, s
             }
 
     const bool bad = collide_dt<DIM, DT, CORR, EQ>(f, relax);
-    raise_flag(flag, bad);
+    raise_flag(flag, bad && !pad);
 
     const int64_t self = (int64_t)(z * ny + y) * rs + x;
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-        dst[self + i * ps] = f[i];
+        dst[self + i * ps] = pad ? T(0) : f[i];
 }
 
-// A lane past the end of a row (nx <= x < ps) in the row-interleaved layout
-// stores zeros into the row's padding, so that the workgroup writes whole
-// cache lines: partial-line stores at ragged row ends cost as much again in
-// memory traffic.  The padding is never read.
-template <int DIM, int DT>
-__device__ __forceinline__ void store_padding(store_t<DT> *__restrict__ dst, int ny, int64_t ps, int64_t rs,
-                                              int x, int y, int z) {
-    if (rs != (int64_t)Lattice<DIM>::Q * ps || x >= ps)  // plane layout, or past the pitch
-        return;
-    const int64_t self = (int64_t)(z * ny + y) * rs + x;
-#pragma unroll
-    for (int i = 0; i < Lattice<DIM>::Q; ++i)
-        dst[self + i * ps] = store_t<DT>(0);
+// Whether a lane at x >= nx has a padding position to fill (row-interleaved
+// layout, x below the pitch); other lanes past the row end do nothing.
+template <int DIM>
+__device__ __forceinline__ bool in_padding(int64_t ps, int64_t rs, int x) {
+    return rs == (int64_t)Lattice<DIM>::Q * ps && x < ps;
 }
 
 // One LBGK step over the whole domain.  1-D grid of tiles_x * tiles_y * nz
@@ -136,14 +138,11 @@ __global__ __launch_bounds__(256) void k_stream_collide(StepArgs a) {
     const int z = t / (a.tiles_x * a.tiles_y);
     const int x = tx * (int)blockDim.x + (int)threadIdx.x;
     const int y = ty * (int)blockDim.y + (int)threadIdx.y;
-    if (y >= a.ny)
+    const bool pad = x >= a.nx;
+    if (y >= a.ny || (pad && !in_padding<DIM>(a.ps, a.rs, x)))
         return;
-    if (x >= a.nx) {
-        store_padding<DIM, DT>(static_cast<store_t<DT> *>(a.dst), a.ny, a.ps, a.rs, x, y, z);
-        return;
-    }
     step_node<DIM, DT, CORR, EQ>(static_cast<const store_t<DT> *>(a.src), static_cast<store_t<DT> *>(a.dst), a.nx,
-                                 a.ny, a.nz, a.ps, a.rs, a.relax, a.flag, x, y, z);
+                                 a.ny, a.nz, a.ps, a.rs, a.relax, a.flag, x, y, z, pad);
 }
 
 // ---------------------------------------------------------------------------

@@ -91,6 +91,7 @@ __device__ __forceinline__ void pool_tile(const PoolRunArgs &a, int t, int s) {
     T *dst = static_cast<T *>(dd.buf[p ^ 1]);
     const int tile = t - a.tile_start[lo];
     int x, y, z;
+    bool pad = false;
     if (a.flat) {
         // consecutive nodes of the slot, x fastest, across rows and planes
         const int64_t n = (int64_t)tile * (blockDim.x * blockDim.y) + threadIdx.y * blockDim.x + threadIdx.x;
@@ -106,14 +107,11 @@ __device__ __forceinline__ void pool_tile(const PoolRunArgs &a, int t, int s) {
         z = tile / (tiles_x * tiles_y);
         x = tx * (int)blockDim.x + (int)threadIdx.x;
         y = ty * (int)blockDim.y + (int)threadIdx.y;
-        if (y >= ny)
+        pad = x >= nx;
+        if (y >= ny || (pad && !in_padding<DIM>(ps, rs, x)))
             return;
-        if (x >= nx) {
-            store_padding<DIM, DT>(dst, ny, ps, rs, x, y, z);
-            return;
-        }
     }
-    step_node<DIM, DT, CORR>(src, dst, nx, ny, nz, ps, rs, relax, flag, x, y, z);
+    step_node<DIM, DT, CORR>(src, dst, nx, ny, nz, ps, rs, relax, flag, x, y, z, pad);
 }
 
 // One step (a.step0) over the active prefix; grid = its tile count.
