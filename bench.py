@@ -118,7 +118,7 @@ def bench_batched(count: int, steps: int, dtypes=("fp32_dev", "fp64"), baseline:
         assert len(done) == count
         rec = {"solves_per_s": round(count / dt, 2), "seconds": round(dt, 4), "mlups": round(nodes * steps / dt / 1e6, 1),
                "tuning": tuning, "launches": st["launches"], "autotune_cached": rep.get("cached", False),
-               "autotune_fastest": (rep.get("times") or [])[:4]}
+               "autotune_fastest": (rep.get("times") or [])[:4], "autotune_failed": rep.get("failed", [])}
         if baseline and dtype == dtypes[0]:
             doms_alone = [lbm.Domain(r0, u0, sp["tau"], dtype=dtype) for sp, (r0, u0) in zip(specs, fields)]
             torch.cuda.synchronize()

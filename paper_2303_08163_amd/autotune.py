@@ -102,16 +102,22 @@ def time_tuning(domains, tuning: dict, steps: int = 20, warmup: int = 3) -> floa
 def tune_pool(domains, steps: int = 20, cands=None, cache_path: str | None = DEFAULT_CACHE,
               use_cache: bool = True, verbose: bool = False):
     """domains: list of (lattice, (nx, ny[, nz]), dtype).  Returns (tuning dict,
-    report) where report lists every candidate's time per step."""
+    report) where report lists every candidate's time per step and, under
+    "failed", each candidate that the library refused or that raised an error
+    while it ran (for instance a persistent run whose grid barrier timed out),
+    with the error text."""
     key = f"candidates-v2|{_device_key()}|{signature(domains)}"
     cache = _load_cache(cache_path) if cache_path else {}
     if use_cache and key in cache:
         return cache[key]["tuning"], {"cached": True, "key": key, "times": cache[key].get("times")}
-    times = []
+    times, failed = [], []
     for c in (cands or candidates()):
         try:
             dt = time_tuning(domains, c, steps=steps)
-        except (ValueError, lbm.LBMError):
+        except (ValueError, lbm.LBMError) as err:
+            failed.append([c, str(err)])
+            if verbose:
+                print(f"  autotune {c}: failed: {err}", flush=True)
             continue
         times.append((dt, c))
         if verbose:
@@ -120,7 +126,7 @@ def tune_pool(domains, steps: int = 20, cands=None, cache_path: str | None = DEF
         raise RuntimeError("no tuning candidate ran")
     times.sort(key=lambda x: x[0])
     best = times[0][1]
-    report = {"cached": False, "key": key, "times": [[round(t * 1e3, 4), c] for t, c in times]}
+    report = {"cached": False, "key": key, "times": [[round(t * 1e3, 4), c] for t, c in times], "failed": failed}
     if cache_path:
         cache[key] = {"tuning": best, "times": report["times"], "when": time.strftime("%Y-%m-%d %H:%M:%S")}
         _save_cache(cache_path, cache)

@@ -16,7 +16,7 @@ def test_autotune_small_batch(tmp_path):
     cands = [dict(tile_x=64, tile_y=4, persistent=0), dict(tile_x=32, tile_y=8, persistent=1),
              dict(tile_x=128, tile_y=2, persistent=1)]
     best, rep = autotune.tune_pool(doms, steps=5, cands=cands, cache_path=cache)
-    assert best in cands and not rep["cached"] and len(rep["times"]) == 3
+    assert best in cands and not rep["cached"] and len(rep["times"]) == 3 and rep["failed"] == []
     best2, rep2 = autotune.tune_pool(doms, steps=5, cands=cands, cache_path=cache)
     assert best2 == best and rep2["cached"]
     results = []
