@@ -397,7 +397,7 @@ def main() -> int:
     ap.add_argument("--no-batch-baseline", action="store_true",
                     help="skip the one-domain-per-launch baseline of the batched section")
     ap.add_argument("--batch-tuning", default="",
-                    help="TXxTY[,persistent][,flat]: fixed pool tile instead of the autotuner's choice")
+                    help="TXxTY[,persistent][,flat][,fit]: fixed pool tile instead of the autotuner's choice")
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-light-requests", type=int, default=40)
@@ -508,6 +508,8 @@ def main() -> int:
             fixed = {"tile_x": tx, "tile_y": ty, "persistent": int("persistent" in parts[1:])}
             if "flat" in parts[1:]:
                 fixed["flat"] = 1
+            if "fit" in parts[1:]:
+                fixed["row_fit"] = 1
         out["batched"] = bench_batched(args.batch_count, args.batch_steps, baseline=not args.no_batch_baseline,
                                        fixed_tuning=fixed)
         progress("batched done")

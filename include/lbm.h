@@ -249,7 +249,13 @@ typedef struct lbm_pool_tuning {
     int32_t flat;       /* 0: a workgroup covers tile_x nodes of tile_y rows; 1: it covers
                            tile_x * tile_y consecutive nodes of its slot in x-fastest order,
                            across rows and planes (no idle lanes at ragged row ends) */
-    int32_t reserved[2];/* must be 0 */
+    int32_t row_fit;    /* 1: each slot maps the workgroup's tile_x * tile_y threads onto rows
+                           of w threads, w the narrowest of 64, 128, 256 (dividing the
+                           workgroup) that covers the slot's padded row, or the widest such w
+                           when none does, with tile_x * tile_y / w rows per workgroup; a
+                           wavefront always stays within one row.  0: every slot uses
+                           tile_x x tile_y.  Not with flat; other values are LBM_EINVAL */
+    int32_t reserved;   /* must be 0 */
 } lbm_pool_tuning;
 
 typedef struct lbm_pool_stats {

@@ -2,8 +2,9 @@
 
 For a set of domains (lattice, grid, storage), it times a short run of each
 candidate pool tuning -- workgroup tile shape (one node per thread; rows of
-tile_x nodes, or runs of consecutive nodes across rows) and launch form (one
-launch per step, or one persistent cooperative launch per run) -- on
+tile_x nodes, rows fitted to each slot's width, or runs of consecutive nodes
+across rows) and launch form (one launch per step, or one persistent
+cooperative launch per run) -- on
 a scratch pool holding domains of exactly those sizes, and returns the
 fastest.  Results do not depend on the tuning (the per-node arithmetic is the
 same in every kernel), so only time is compared.  Choices are cached in a JSON
@@ -32,7 +33,8 @@ FLAT_TILES = [(64, 4), (64, 2), (64, 1)]  # flat mode: 256, 128 or 64 consecutiv
 def candidates():
     rows = [dict(tile_x=tx, tile_y=ty, persistent=p) for (tx, ty) in TILES for p in (0, 1)]
     flat = [dict(tile_x=tx, tile_y=ty, persistent=p, flat=1) for (tx, ty) in FLAT_TILES for p in (0, 1)]
-    return rows + flat
+    fit = [dict(tile_x=64, tile_y=4, persistent=p, row_fit=1) for p in (0, 1)]
+    return rows + flat + fit
 
 
 def signature(domains) -> str:
@@ -106,7 +108,7 @@ def tune_pool(domains, steps: int = 20, cands=None, cache_path: str | None = DEF
     "failed", each candidate that the library refused or that raised an error
     while it ran (for instance a persistent run whose grid barrier timed out),
     with the error text."""
-    key = f"candidates-v2|{_device_key()}|{signature(domains)}"
+    key = f"candidates-v3|{_device_key()}|{signature(domains)}"
     cache = _load_cache(cache_path) if cache_path else {}
     if use_cache and key in cache:
         return cache[key]["tuning"], {"cached": True, "key": key, "times": cache[key].get("times")}

@@ -30,7 +30,7 @@ static int resolve_tuning(const lbm_pool_tuning *t, lbm_pool_tuning *out) {
     lbm_pool_tuning r{};
     if (t)
         r = *t;
-    if (r.reserved[0] || r.reserved[1]) {
+    if (r.reserved) {
         set_error("lbm_pool_tuning.reserved must be 0");
         return LBM_EINVAL;
     }
@@ -52,6 +52,14 @@ static int resolve_tuning(const lbm_pool_tuning *t, lbm_pool_tuning *out) {
     }
     if (r.flat != 0 && r.flat != 1) {
         set_error("pool tuning: flat must be 0 or 1");
+        return LBM_EINVAL;
+    }
+    if (r.row_fit != 0 && r.row_fit != 1) {
+        set_error("pool tuning: row_fit must be 0 or 1");
+        return LBM_EINVAL;
+    }
+    if (r.row_fit && r.flat) {
+        set_error("pool tuning: row_fit and flat exclude each other");
         return LBM_EINVAL;
     }
     if (r.layout == LBM_LAYOUT_DEFAULT)
@@ -119,6 +127,7 @@ struct Slot {
     int64_t remaining = 0;
     bool failed = false;  // retired at poll: its state left the equilibrium's domain
     int tiles_x = 0, tiles_y = 0, tiles = 0;
+    int tw_shift = 0;  // row_fit: tile rows of 1 << tw_shift threads; 0: the workgroup's own shape
     int cls = 0;
 };
 
@@ -316,9 +325,21 @@ int lbm_pool_admit(lbm_pool *p, const lbm_config *cfg, const double *rho, const 
     s.bytes = bytes;
     s.remaining = nsteps;
     s.reported = false;
-    s.tiles_x = (int)((cfg->nx + L.block_x - 1) / L.block_x);
-    s.tiles_y = (int)((cfg->ny + L.block_y - 1) / L.block_y);
     const int64_t block = (int64_t)L.block_x * L.block_y;
+    int64_t tw = L.block_x, th = L.block_y;
+    s.tw_shift = 0;
+    if (p->tun.row_fit) {
+        // narrowest power-of-two row width from 64 that covers the padded row
+        const int64_t pitch = L.layout == LBM_LAYOUT_ROWS ? L.ps : cfg->nx;
+        int shift = 6;
+        while ((int64_t)1 << shift < pitch && shift < 8 && block % ((int64_t)2 << shift) == 0)
+            ++shift;
+        s.tw_shift = shift;
+        tw = (int64_t)1 << shift;
+        th = block / tw;
+    }
+    s.tiles_x = (int)((cfg->nx + tw - 1) / tw);
+    s.tiles_y = (int)((cfg->ny + th - 1) / th);
     const int64_t tiles = p->tun.flat ? (L.n + block - 1) / block : (int64_t)s.tiles_x * s.tiles_y * cfg->nz;
     if (tiles > (int64_t)1 << 30) {
         pool_free(p, off, bytes);
@@ -383,6 +404,7 @@ int lbm_pool_run(lbm_pool *p, int64_t k) {
             d.nz = (int)s.d.cfg.nz;
             d.tiles_x = s.tiles_x;
             d.tiles_y = s.tiles_y;
+            d.tw_shift = s.tw_shift;
             d.parity = s.d.cur;
             d.ps = s.d.L.ps;
             d.rs = s.d.L.rs;

@@ -33,8 +33,9 @@ struct SlotDesc {
     void *buf[2];
     int nx, ny, nz;
     int tiles_x, tiles_y;
-    int parity;  // buffer holding the state at the start of the run
-    int pad_[2];
+    int parity;    // buffer holding the state at the start of the run
+    int tw_shift;  // > 0: tiles are rows of 1 << tw_shift threads (row fit); 0: blockDim's shape
+    int pad_;
     int64_t ps, rs;
     Relax relax;
     int *flag;
@@ -82,6 +83,7 @@ __device__ __forceinline__ void pool_tile(const PoolRunArgs &a, int t, int s) {
     // (124 VGPRs instead of 70 for D3Q27).
     const SlotDesc &dd = a.slots[lo];
     const int nx = dd.nx, ny = dd.ny, nz = dd.nz, tiles_x = dd.tiles_x, tiles_y = dd.tiles_y;
+    const int tw_shift = dd.tw_shift;
     const int64_t ps = dd.ps, rs = dd.rs;
     const Relax relax = dd.relax;
     int *flag = dd.flag;
@@ -105,8 +107,16 @@ __device__ __forceinline__ void pool_tile(const PoolRunArgs &a, int t, int s) {
         const int tx = tile % tiles_x;
         const int ty = (tile / tiles_x) % tiles_y;
         z = tile / (tiles_x * tiles_y);
-        x = tx * (int)blockDim.x + (int)threadIdx.x;
-        y = ty * (int)blockDim.y + (int)threadIdx.y;
+        int lx = (int)threadIdx.x, ly = (int)threadIdx.y, bw = (int)blockDim.x, bh = (int)blockDim.y;
+        if (tw_shift > 0) {  // the slot's own row width: consecutive threads along x
+            const int tid = (int)(threadIdx.y * blockDim.x + threadIdx.x);
+            lx = tid & ((1 << tw_shift) - 1);
+            ly = tid >> tw_shift;
+            bw = 1 << tw_shift;
+            bh = (int)(blockDim.x * blockDim.y) >> tw_shift;
+        }
+        x = tx * bw + lx;
+        y = ty * bh + ly;
         pad = x >= nx;
         if (y >= ny || (pad && !in_padding<DIM>(ps, rs, x)))
             return;

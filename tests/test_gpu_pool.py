@@ -48,12 +48,16 @@ def alone_results():
 
 
 @pytest.mark.parametrize("persistent", [0, 1])
-@pytest.mark.parametrize("tile", [(64, 4), (32, 2), (256, 1), ("flat", 64, 4), ("flat", 64, 1)])
+@pytest.mark.parametrize("tile", [(64, 4), (32, 2), (256, 1), ("flat", 64, 4), ("flat", 64, 1), ("fit", 64, 4),
+                                  ("fit", 64, 2), ("fit-planes", 64, 4)])
 @pytest.mark.parametrize("chunk", [1000, 7])
 def test_pool_mix_equals_alone_bitwise(alone_results, persistent, tile, chunk):
     lbm = _lbm()
     if tile[0] == "flat":
         tun = lbm.make_pool_tuning(tile[1], tile[2], persistent, flat=1)
+    elif tile[0] in ("fit", "fit-planes"):
+        layout = lbm.LBM_LAYOUT_PLANES if tile[0] == "fit-planes" else 0
+        tun = lbm.make_pool_tuning(tile[1], tile[2], persistent, layout=layout, row_fit=1)
     else:
         tun = lbm.make_pool_tuning(tile[0], tile[1], persistent)
     with lbm.Pool(GiB // 4, max_slots=16, tuning=tun) as pool:
