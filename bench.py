@@ -179,6 +179,58 @@ def bench_serving(n_requests: int, rate: float, light_requests: int) -> dict:
     return res
 
 
+def bench_slab(steps: int = 200, nz: int = 32, n: int = 256) -> dict:
+    """One GPU's share of the headline domain split along z over 8 GPUs: an
+    n x n x nz FP32 slab of the n^3 Taylor-Green field with halo planes, its
+    own neighbour on both sides (pack both faces, unpack both faces after
+    every step; between GPUs the two packed buffers would travel over xGMI).
+    HIP events on the slab's stream split each step into the stream-collide
+    kernel and the four halo copies; nothing is skipped."""
+    import torch
+
+    from paper_2303_08163_amd import lbm, workloads
+
+    rho0, u0 = workloads.taylor_green_3d(n, u0=0.05, planes=(0, nz))
+    with lbm.Domain(rho0, u0, 0.5005, dtype="fp32_dev", z_halo=True) as s:
+        nb = s.halo_bytes()
+        lo = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
+        hi = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
+
+        def exchange():
+            s.halo_pack(0, lo)
+            s.halo_pack(1, hi)
+            s.halo_unpack(0, hi)
+            s.halo_unpack(1, lo)
+
+        exchange()
+        for _ in range(20):
+            s.step(1)
+            exchange()
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        s.stream.synchronize()
+        t0 = time.perf_counter()
+        for e in ev:
+            e[0].record(s.stream)
+            s.step(1)
+            e[1].record(s.stream)
+            exchange()
+            e[2].record(s.stream)
+        s.stream.synchronize()
+        wall = time.perf_counter() - t0
+        k_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
+        x_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
+        diag = s.moments(fields=False)[2]
+    nodes = n * n * nz
+    return {"workload": f"D3Q27 {n}x{n}x{nz} z-slab of the {n}^3 Taylor-Green field (u0 = 0.05, tau = 0.5005), "
+                        "FP32 deviations, halo planes exchanged with itself after every step",
+            "steps": steps, "ms_per_step": round(k_ms + x_ms, 5), "stream_collide_ms": round(k_ms, 5),
+            "halo_exchange_ms": round(x_ms, 5),
+            "mlups": round(nodes / ((k_ms + x_ms) * 1e-3) / 1e6, 1),
+            "stream_collide_gbs": round(nodes * 216 / (k_ms * 1e-3) / 1e9, 1),
+            "stream_collide_frac_of_8tbs": round(nodes * 216 / (k_ms * 1e-3) / 8e12, 4),
+            "halo_bytes_per_face": nb, "wall_s": round(wall, 4), "mass": diag["mass"]}
+
+
 def bench_wave(steps: int = 2000) -> dict:
     """Isothermal pressure-wave sweep: effective viscosity vs U0 for the
     entropic and product-form equilibria, with and without the bulk correction
@@ -389,7 +441,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256, help="grid side (headline: 256)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sections", default="headline,batched,serving,wave,stability,variants",
+    ap.add_argument("--sections", default="headline,batched,serving,wave,stability,variants,slab",
                     help="comma list of headline, batched, serving, wave, stability, variants, "
                          "oracle_timing (not in the default run: several minutes of host time)")
     ap.add_argument("--batch-count", type=int, default=512)
@@ -524,6 +576,9 @@ def main() -> int:
     if "variants" in sections:
         out["variants"] = bench_variants()
         progress("variants done")
+    if "slab" in sections:
+        out["slab"] = bench_slab()
+        progress("slab done")
     if "stability" in sections:
         out["stability"] = bench_stability(with_cpu=not args.no_cpu_baseline)
         progress("stability done")

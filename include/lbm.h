@@ -99,6 +99,11 @@ typedef struct lbm_config {
     int32_t bulk_correction; /* 0 = off, 1 = eq. (redefined_relaxation rate) */
     int32_t equilibrium;     /* LBM_EQ_ENTROPIC, LBM_EQ_POLY2 or LBM_EQ_PRODUCT */
     double rho0;             /* reference density of the FP32 deviation storage (> 0); ignored for FP64 */
+    int32_t z_halo;          /* 0: periodic in every direction.  1: a z-slab, nz planes of a larger
+                                domain that is split along z (D3Q27, row-interleaved layout only):
+                                no wrap in z; the planes below plane 0 and above plane nz - 1 are
+                                halo planes that lbm_halo_unpack fills (see there) */
+    int32_t reserved;        /* must be 0 */
 } lbm_config;
 
 /* Launch tuning (optional).  Zero fields take the library default.  Results do
@@ -178,9 +183,43 @@ int lbm_create_tuned(const lbm_config *cfg, const lbm_tuning *tuning, void *work
 
 /* Enqueue nsteps time steps (one fused stream-and-collide kernel launch each)
  * on the handle's stream and return without synchronising.  nsteps = 0 is a
- * no-op.  Errors: LBM_EINVAL (h NULL, nsteps < 0); LBM_EDEVICE (launch
- * failure). */
+ * no-op.  Errors: LBM_EINVAL (h NULL, nsteps < 0, nsteps > 1 on a z-slab,
+ * which needs a halo exchange between steps); LBM_EDEVICE (launch failure). */
 int lbm_step(lbm_handle *h, int64_t nsteps);
+
+/* Halo exchange of a z-slab (lbm_config.z_halo = 1).  A periodic domain split
+ * along z into slabs advances exactly as the whole domain when, between two
+ * steps, each slab receives the populations that stream into it across its
+ * two faces (the streaming of the lattice BGK equation, Sec. "Basic concepts":
+ * f_i at r comes from r - c_i; only populations with c_z = +1 cross a face
+ * upwards and c_z = -1 downwards).  With populations numbered
+ * i = (c_x + 1) + 3 (c_y + 1) + 9 (c_z + 1), the 9 with c_z = -1 are i = 0..8
+ * and the 9 with c_z = +1 are i = 18..26.
+ *
+ * A packed buffer holds one face: 9 nx ny stored values (FP64 or FP32
+ * deviations, the domain's storage type; lbm_halo_bytes bytes) in the order
+ * [y][k][x], k = 0..8 the 9 populations in increasing i.  Its contents are the
+ * library's stored values, meant to be moved unchanged (RCCL send/recv, peer
+ * copy) to the slab that unpacks them.
+ *
+ *   lbm_halo_pack(h, 0, buf): plane 0, populations c_z = -1, for the slab below.
+ *   lbm_halo_pack(h, 1, buf): plane nz - 1, populations c_z = +1, for the slab above.
+ *   lbm_halo_unpack(h, 0, buf): into the halo plane below plane 0 (populations
+ *       c_z = +1), from the slab below's face-1 pack.
+ *   lbm_halo_unpack(h, 1, buf): into the halo plane above plane nz - 1
+ *       (populations c_z = -1), from the slab above's face-0 pack.
+ *
+ * Sequence per step for every slab: lbm_step(h, 1); pack both faces; move the
+ * buffers; unpack both faces.  Before the first step the halo planes must be
+ * filled the same way (they start as zeros).  A slab that is its own
+ * neighbour on both sides (pack face 1 -> unpack face 0, pack face 0 -> unpack
+ * face 1) advances as the periodic domain of its nz planes.  buf is a device
+ * pointer owned by the caller; the copy is enqueued on the handle's stream
+ * without synchronising.  Errors: LBM_EINVAL (h or buf NULL, the domain is not
+ * a z-slab, face not 0 or 1); LBM_EDEVICE. */
+size_t lbm_halo_bytes(const lbm_config *cfg); /* 0 for a config that is not a valid z-slab */
+int lbm_halo_pack(lbm_handle *h, int32_t face, void *buf);
+int lbm_halo_unpack(lbm_handle *h, int32_t face, const void *buf);
 
 /* Moments of the current state: rho (N doubles) and u (D * N doubles) into
  * device pointers, and diagnostics into a host struct.  Any of rho, u, diag may

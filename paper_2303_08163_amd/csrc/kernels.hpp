@@ -37,6 +37,7 @@ struct StepArgs {
     int64_t ps, rs;        // population and row strides (elements)
     Relax relax;
     int *flag;
+    int zhalo;  // 1: z-slab, planes -1 and nz are halo planes (no periodic wrap in z)
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs (workgroup w runs on
@@ -64,14 +65,17 @@ __device__ __forceinline__ void raise_flag(int *flag, bool bad) {
 }
 
 // Source rows r - c for c_y, c_z = -1, 0, +1 on the periodic grid, as element
-// offsets of population 0.
+// offsets of population 0.  In a z-slab (zhalo) the planes z - 1 and z + 1 are
+// taken as they are: at the slab's faces they are the halo planes -1 and nz,
+// which hold the neighbouring slabs' populations.
 template <int DIM>
-__device__ __forceinline__ void source_rows(int y, int z, int ny, int nz, int64_t rs, int64_t (&rowoff)[3][3]) {
+__device__ __forceinline__ void source_rows(int y, int z, int ny, int nz, int64_t rs, int64_t (&rowoff)[3][3],
+                                            bool zhalo = false) {
     const int ys[3] = {y + 1 == ny ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
     int zs[3] = {z, z, z};
     if (DIM == 3) {
-        zs[0] = z + 1 == nz ? 0 : z + 1;
-        zs[2] = z == 0 ? nz - 1 : z - 1;
+        zs[0] = z + 1 == nz && !zhalo ? 0 : z + 1;
+        zs[2] = z == 0 && !zhalo ? nz - 1 : z - 1;
     }
 #pragma unroll
     for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
@@ -94,13 +98,13 @@ __device__ __forceinline__ void source_rows(int y, int z, int ny, int nz, int64_
 template <int DIM, int DT, bool CORR, int EQ = kEqEntropic>
 __device__ __forceinline__ void step_node(const store_t<DT> *__restrict__ src, store_t<DT> *__restrict__ dst,
                                           int nx, int ny, int nz, int64_t ps, int64_t rs, const Relax &relax,
-                                          int *flag, int x, int y, int z, bool pad = false) {
+                                          int *flag, int x, int y, int z, bool pad = false, bool zhalo = false) {
     using T = store_t<DT>;
     constexpr int Q = Lattice<DIM>::Q;
     const int xn = pad ? nx - 1 : x;  // node whose sources are read
     const int xs[3] = {xn + 1 == nx ? 0 : xn + 1, xn, xn == 0 ? nx - 1 : xn - 1};  // x - c_x
     int64_t rowoff[3][3];
-    source_rows<DIM>(y, z, ny, nz, rs, rowoff);
+    source_rows<DIM>(y, z, ny, nz, rs, rowoff, zhalo);
     T f[Q];
 #pragma unroll
     for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
@@ -142,7 +146,7 @@ __global__ __launch_bounds__(256) void k_stream_collide(StepArgs a) {
     if (y >= a.ny || (pad && !in_padding<DIM>(a.ps, a.rs, x)))
         return;
     step_node<DIM, DT, CORR, EQ>(static_cast<const store_t<DT> *>(a.src), static_cast<store_t<DT> *>(a.dst), a.nx,
-                                 a.ny, a.nz, a.ps, a.rs, a.relax, a.flag, x, y, z, pad);
+                                 a.ny, a.nz, a.ps, a.rs, a.relax, a.flag, x, y, z, pad, a.zhalo != 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -208,7 +212,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_vec(StepArgs a) {
     T *__restrict__ dst = static_cast<T *>(a.dst);
 
     int64_t rowoff[3][3];
-    source_rows<DIM>(y, z, a.ny, a.nz, a.rs, rowoff);
+    source_rows<DIM>(y, z, a.ny, a.nz, a.rs, rowoff, a.zhalo != 0);
     // neighbours of the run at the wavefront's ends (periodic in x)
     const int x_left = x0 == 0 ? nx - 1 : x0 - 1;
     const int x_right = x0 + NPT == nx ? 0 : x0 + NPT;
@@ -276,6 +280,24 @@ __global__ __launch_bounds__(256) void k_stream_collide_vec(StepArgs a) {
 static __global__ void k_clear_words(int *p, int count) {
     for (int k = threadIdx.x; k < count; k += blockDim.x)
         p[k] = 0;
+}
+
+// Halo exchange of a z-slab: copy the 9 population runs with one sign of c_z
+// of every row of one plane between the slab's buffer and a packed buffer
+// [y][k][x] (k = 0..8 in population order, nx elements per run).  Element
+// (y, k, x) is at src[y * s_row + k * s_run + x] and dst[y * d_row + k * d_run + x].
+// A bit copy (E = element width), so the stored values move unchanged.
+template <typename E>
+__global__ __launch_bounds__(256) void k_halo_copy(const E *__restrict__ src, E *__restrict__ dst, int nx,
+                                                   int64_t count, int64_t s_row, int64_t s_run, int64_t d_row,
+                                                   int64_t d_run) {
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < count;
+         n += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = n / nx;  // run index y * 9 + k
+        const int x = (int)(n - r * nx);
+        const int64_t y = r / 9, k = r - y * 9;
+        dst[y * d_row + k * d_run + x] = src[y * s_row + k * s_run + x];
+    }
 }
 
 // Element offset of population 0 of node n (x fastest) in a buffer.

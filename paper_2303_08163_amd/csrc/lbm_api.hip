@@ -85,6 +85,19 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
         set_error("nz must be 1 for D2Q9");
         return LBM_EINVAL;
     }
+    if (cfg->z_halo != 0 && cfg->z_halo != 1) {
+        set_error("z_halo must be 0 or 1");
+        return LBM_EINVAL;
+    }
+    if (cfg->reserved != 0) {
+        set_error("lbm_config.reserved must be 0");
+        return LBM_EINVAL;
+    }
+    if (cfg->z_halo && L.dim != 3) {
+        set_error("z_halo needs LBM_D3Q27");
+        return LBM_EINVAL;
+    }
+    L.zhalo = cfg->z_halo != 0;
     if (cfg->nx > INT32_MAX || cfg->ny > INT32_MAX || cfg->nz > INT32_MAX) {
         set_error("grid extent beyond 2^31 - 1");
         return LBM_EINVAL;
@@ -190,6 +203,10 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
         return LBM_EINVAL;
     }
     L.layout = layout;
+    if (L.zhalo && layout != LBM_LAYOUT_ROWS) {
+        set_error("z_halo needs the row-interleaved layout");
+        return LBM_EINVAL;
+    }
     if (layout == LBM_LAYOUT_PLANES) {
         L.ps = round_up(L.n, 64) + round_up(pad, 64);
         L.rs = cfg->nx;
@@ -200,7 +217,10 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
         L.ps = pitch;
         L.rs = (int64_t)L.q * pitch;
     }
-    const int64_t elems = layout == LBM_LAYOUT_PLANES ? (int64_t)L.q * L.ps : L.rs * (L.n / cfg->nx);
+    L.plane = layout == LBM_LAYOUT_PLANES ? 0 : L.rs * cfg->ny;
+    // a z-slab's buffers also hold the two halo planes, -1 below plane 0 and nz above nz - 1
+    const int64_t elems =
+        layout == LBM_LAYOUT_PLANES ? (int64_t)L.q * L.ps : L.rs * (L.n / cfg->nx) + (L.zhalo ? 2 * L.plane : 0);
     if (elems > ((int64_t)1 << 40)) {
         set_error("domain too large");
         return LBM_EINVAL;
@@ -309,9 +329,22 @@ int domain_bind_and_init(DomainState &d, const lbm_config *cfg, const Layout &L,
     d.cfg = *cfg;
     d.L = L;
     d.ws = static_cast<char *>(workspace);
-    d.buf[0] = d.ws + L.off_buf[0];
-    d.buf[1] = d.ws + L.off_buf[1];
+    // a z-slab's buffer pointers address plane 0, one halo plane into the buffer
+    const size_t halo_bytes = L.zhalo ? (size_t)L.plane * L.elem : 0;
+    d.buf[0] = d.ws + L.off_buf[0] + halo_bytes;
+    d.buf[1] = d.ws + L.off_buf[1] + halo_bytes;
     d.cur = 0;
+    if (L.zhalo) {
+        // defined contents (zeros) in the halo planes until the first exchange fills them
+        for (int k = 0; k < 2; ++k) {
+            char *b = d.ws + L.off_buf[k];
+            hipError_t e = hipMemsetAsync(b, 0, halo_bytes, s);
+            if (e == hipSuccess)
+                e = hipMemsetAsync(b + halo_bytes * (size_t)(cfg->nz + 1), 0, halo_bytes, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "halo plane clear");
+        }
+    }
     d.flag = reinterpret_cast<int *>(d.ws + L.off_flag);
     d.diag_dev = reinterpret_cast<double *>(d.ws + L.off_diag);
     d.partials = reinterpret_cast<double *>(d.ws + L.off_partials);
@@ -495,12 +528,16 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
         return LBM_EINVAL;
     }
     DomainState &d = h->d;
+    if (d.L.zhalo && nsteps > 1) {
+        set_error("a z-slab takes one step between halo exchanges");
+        return LBM_EINVAL;
+    }
     const bool corr = d.cfg.bulk_correction != 0;
     const int tiles_x = (int)((d.cfg.nx + (int64_t)d.L.block_x * d.L.npt - 1) / ((int64_t)d.L.block_x * d.L.npt));
     const int tiles_y = (int)((d.cfg.ny + d.L.block_y - 1) / d.L.block_y);
     for (int64_t s = 0; s < nsteps; ++s) {
         StepArgs a{d.buf[d.cur], d.buf[d.cur ^ 1], (int)d.cfg.nx, (int)d.cfg.ny, (int)d.cfg.nz, tiles_x, tiles_y,
-                   d.L.ps, d.L.rs, d.relax, d.flag};
+                   d.L.ps, d.L.rs, d.relax, d.flag, d.L.zhalo ? 1 : 0};
         int rc = launch_step(d.L, a, d.cfg.dtype, corr, h->stream, (int)d.cfg.nz);
         if (rc != LBM_OK)
             return rc;
@@ -509,6 +546,69 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
     }
     return LBM_OK;
 }
+
+size_t lbm_halo_bytes(const lbm_config *cfg) {
+    Layout L;
+    if (validate_config(cfg, nullptr, &L) != LBM_OK || !L.zhalo)
+        return 0;
+    return (size_t)9 * (size_t)cfg->nx * (size_t)cfg->ny * L.elem;
+}
+
+// Face 0 (plane 0, populations with c_z = -1) or face 1 (plane nz - 1, c_z = +1)
+// into a packed buffer; unpack fills halo plane -1 (face 0, c_z = +1) or nz
+// (face 1, c_z = -1) from one.  Populations are numbered i = (c_x + 1) +
+// 3 (c_y + 1) + 9 (c_z + 1), so each row's 9 runs of one sign of c_z are
+// adjacent.
+static int halo_copy(lbm_handle *h, int32_t face, const void *in, void *out, bool pack) {
+    if (!h || (pack ? !out : !in)) {
+        set_error("NULL handle or buffer");
+        return LBM_EINVAL;
+    }
+    DomainState &d = h->d;
+    if (!d.L.zhalo) {
+        set_error("the domain is not a z-slab (z_halo = 0)");
+        return LBM_EINVAL;
+    }
+    if (face != 0 && face != 1) {
+        set_error("face must be 0 (lower) or 1 (upper)");
+        return LBM_EINVAL;
+    }
+    const int64_t nx = d.cfg.nx, ny = d.cfg.ny, nz = d.cfg.nz;
+    int64_t plane, first;  // plane of the slab and first population of the 9
+    if (pack) {
+        plane = face == 0 ? 0 : nz - 1;
+        first = face == 0 ? 0 : 18;
+    } else {
+        plane = face == 0 ? -1 : nz;
+        first = face == 0 ? 18 : 0;
+    }
+    const int64_t off = (plane * ny) * d.L.rs + first * d.L.ps;  // elements from plane 0
+    const int64_t count = 9 * nx * ny;
+    const int blocks = (int)std::min<int64_t>((count + 255) / 256, 8192);
+    const int64_t s_row = pack ? d.L.rs : 9 * nx, s_run = pack ? d.L.ps : nx;
+    const int64_t d_row = pack ? 9 * nx : d.L.rs, d_run = pack ? nx : d.L.ps;
+    if (d.L.elem == 8) {
+        uint64_t *b = static_cast<uint64_t *>(d.buf[d.cur]) + off;
+        const uint64_t *src = pack ? b : static_cast<const uint64_t *>(in);
+        uint64_t *dst = pack ? static_cast<uint64_t *>(out) : b;
+        hipLaunchKernelGGL(k_halo_copy<uint64_t>, dim3(blocks), dim3(256), 0, h->stream, src, dst, (int)nx, count,
+                           s_row, s_run, d_row, d_run);
+    } else {
+        uint32_t *b = static_cast<uint32_t *>(d.buf[d.cur]) + off;
+        const uint32_t *src = pack ? b : static_cast<const uint32_t *>(in);
+        uint32_t *dst = pack ? static_cast<uint32_t *>(out) : b;
+        hipLaunchKernelGGL(k_halo_copy<uint32_t>, dim3(blocks), dim3(256), 0, h->stream, src, dst, (int)nx, count,
+                           s_row, s_run, d_row, d_run);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return hip_fail(e, pack ? "halo pack launch" : "halo unpack launch");
+    return LBM_OK;
+}
+
+int lbm_halo_pack(lbm_handle *h, int32_t face, void *buf) { return halo_copy(h, face, nullptr, buf, true); }
+
+int lbm_halo_unpack(lbm_handle *h, int32_t face, const void *buf) { return halo_copy(h, face, buf, nullptr, false); }
 
 int lbm_moments(lbm_handle *h, double *rho, double *u, lbm_diag *diag) {
     if (!h) {

@@ -23,6 +23,8 @@ struct Layout {
     int npt;           // nodes per thread along x
     int flags;         // LBM_TUNE_* bits
     bool rowwave;      // one wavefront spans a whole row (vector kernels)
+    bool zhalo;        // z-slab: each buffer holds halo planes -1 and nz around the nz planes
+    int64_t plane;     // elements of one plane (rows layout: ny * rs)
     int red_blocks;    // workgroups of the moments reduction
     size_t buf_bytes;  // one population buffer
     size_t off_buf[2], off_flag, off_diag, off_partials, ws_bytes;

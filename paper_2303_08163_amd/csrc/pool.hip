@@ -79,6 +79,10 @@ static int slot_layout(const lbm_config *cfg, const lbm_pool_tuning &t, Layout *
         set_error("pool slots run the entropic equilibrium only");
         return LBM_EINVAL;
     }
+    if (cfg && cfg->z_halo) {
+        set_error("pool slots are periodic domains (z_halo = 0)");
+        return LBM_EINVAL;
+    }
     if (cfg && cfg->lattice != LBM_D2Q9 && cfg->lattice != LBM_D3Q27) {
         set_error("pool slots run D2Q9 or D3Q27");
         return LBM_EINVAL;

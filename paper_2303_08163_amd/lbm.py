@@ -36,7 +36,8 @@ class lbm_config(ctypes.Structure):
     _fields_ = [("lattice", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
                 ("tau", ctypes.c_double), ("bulk_correction", ctypes.c_int32),
-                ("equilibrium", ctypes.c_int32), ("rho0", ctypes.c_double)]
+                ("equilibrium", ctypes.c_int32), ("rho0", ctypes.c_double),
+                ("z_halo", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class lbm_tuning(ctypes.Structure):
@@ -130,6 +131,9 @@ def load_library(path: str = LIB_PATH):
         "lbm_moments": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(lbm_diag)]),
         "lbm_get_populations": (ctypes.c_int, [vp, vp]),
         "lbm_energy": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_double, vp]),
+        "lbm_halo_bytes": (sz, [cfgp]),
+        "lbm_halo_pack": (ctypes.c_int, [vp, ctypes.c_int32, vp]),
+        "lbm_halo_unpack": (ctypes.c_int, [vp, ctypes.c_int32, vp]),
         "lbm_vn_spectra": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, i64, vp, vp, vp, vp,
                                           vp]),
         "lbm_vn_max_radius": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, i64,
@@ -171,14 +175,16 @@ def _check(status: int, where: str) -> int:
 
 
 def make_config(lattice: int, shape, tau: float, dtype="fp32_dev", bulk_correction=False,
-                rho0: float = 1.0, equilibrium="entropic") -> lbm_config:
+                rho0: float = 1.0, equilibrium="entropic", z_halo=False) -> lbm_config:
     """shape = (nx,) for D1Q3, (nx, ny) for D2Q9 or (nx, ny, nz) for D3Q27 (x first);
-    equilibrium: "entropic", "poly2", "product" or an LBM_EQ_* value."""
+    equilibrium: "entropic", "poly2", "product" or an LBM_EQ_* value; z_halo: a
+    z-slab of a domain split along z (halo planes instead of the wrap in z)."""
     nx = int(shape[0])
     ny = int(shape[1]) if len(shape) > 1 else 1
     nz = int(shape[2]) if len(shape) > 2 else 1
     return lbm_config(int(lattice), DTYPES.get(dtype, dtype), nx, ny, nz, float(tau),
-                      int(bool(bulk_correction)), EQUILIBRIA.get(equilibrium, equilibrium), float(rho0))
+                      int(bool(bulk_correction)), EQUILIBRIA.get(equilibrium, equilibrium), float(rho0),
+                      int(z_halo), 0)
 
 
 LBM_TUNE_NT_STORE, LBM_TUNE_NT_LOAD = 1, 2
@@ -226,6 +232,18 @@ def lbm_moments(h, rho: int | None, u: int | None, raise_on_domain: bool = True)
 
 def lbm_get_populations(h, out: int) -> None:
     _check(load_library().lbm_get_populations(h, out), "lbm_get_populations")
+
+
+def lbm_halo_bytes(cfg: lbm_config) -> int:
+    return int(load_library().lbm_halo_bytes(ctypes.byref(cfg)))
+
+
+def lbm_halo_pack(h, face: int, buf: int) -> None:
+    _check(load_library().lbm_halo_pack(h, int(face), buf), "lbm_halo_pack")
+
+
+def lbm_halo_unpack(h, face: int, buf: int) -> None:
+    _check(load_library().lbm_halo_unpack(h, int(face), buf), "lbm_halo_unpack")
 
 
 def lbm_energy(h, U, rho_ref: float, out: int) -> None:
@@ -347,7 +365,8 @@ class Domain:
     """
 
     def __init__(self, rho, u, tau: float, dtype="fp32_dev", bulk_correction=False, rho0: float = 1.0,
-                 stream=None, tuning: lbm_tuning | None = None, device="cuda:0", equilibrium="entropic"):
+                 stream=None, tuning: lbm_tuning | None = None, device="cuda:0", equilibrium="entropic",
+                 z_halo: bool = False):
         import torch
         load_library()
         on_device = isinstance(rho, torch.Tensor) and rho.is_cuda
@@ -363,7 +382,9 @@ class Domain:
         self.Q = 3 ** D
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.cfg = make_config(self.lattice, rho.shape[::-1], tau, dtype, bulk_correction, rho0, equilibrium)
+        self.cfg = make_config(self.lattice, rho.shape[::-1], tau, dtype, bulk_correction, rho0, equilibrium,
+                               z_halo)
+        self.z_halo = bool(z_halo)
         self.tuning = tuning
         nbytes = lbm_workspace_bytes(self.cfg, tuning)
         if nbytes == 0:
@@ -396,6 +417,22 @@ class Domain:
 
     def step(self, nsteps: int) -> None:
         lbm_step(self.handle, nsteps)
+
+    def halo_bytes(self) -> int:
+        """Bytes of one packed face of a z-slab (0 for a periodic domain)."""
+        return lbm_halo_bytes(self.cfg)
+
+    def halo_pack(self, face: int, buf) -> None:
+        """Enqueue the face's outgoing populations into buf (a CUDA tensor of
+        at least halo_bytes() bytes): face 0 = plane 0 (c_z = -1), face 1 =
+        plane nz - 1 (c_z = +1)."""
+        lbm_halo_pack(self.handle, face, buf.data_ptr())
+
+    def halo_unpack(self, face: int, buf) -> None:
+        """Enqueue buf into the halo plane below plane 0 (face 0; the lower
+        slab's face-1 pack) or above plane nz - 1 (face 1; the upper slab's
+        face-0 pack)."""
+        lbm_halo_unpack(self.handle, face, buf.data_ptr())
 
     def moments(self, fields: bool = True, raise_on_domain: bool = True):
         """(rho, u, diag) with rho, u as numpy float64 arrays (None if fields=False)."""

@@ -62,13 +62,16 @@ def double_shear_layer(n: int, width: float = 80.0, u0: float = 0.1, delta: floa
     return np.ones((n, n)), np.stack([ux, uy])
 
 
-def taylor_green_3d(n: int, u0: float = 0.05, rho0: float = 1.0):
+def taylor_green_3d(n: int, u0: float = 0.05, rho0: float = 1.0, planes: tuple | None = None):
     """3-D Taylor-Green vortex on an n^3 periodic grid, wavenumber 2 pi / n.
 
     u_x = u0 sin kx cos ky cos kz, u_y = -u0 cos kx sin ky cos kz, u_z = 0,
     rho = rho0 + (3 rho0 u0^2 / 16)(cos 2kx + cos 2ky)(cos 2kz + 2).
+    planes = (z0, z1): only the planes z0 <= z < z1 (a z-slab of the field).
     """
-    x, y, z = _axes3(n, n, n)
+    z0, z1 = (0, n) if planes is None else planes
+    z, y, x = np.meshgrid(np.arange(z0, z1, dtype=np.float64), np.arange(n, dtype=np.float64),
+                          np.arange(n, dtype=np.float64), indexing="ij")
     k = 2.0 * math.pi / n
     ux = u0 * np.sin(k * x) * np.cos(k * y) * np.cos(k * z)
     uy = -u0 * np.cos(k * x) * np.sin(k * y) * np.cos(k * z)

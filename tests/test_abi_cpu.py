@@ -224,3 +224,32 @@ def test_pool_host_logic(lbm):
     assert lib.lbm_pool_release(None, 0) == lbm.LBM_EINVAL
     assert lib.lbm_pool_stats_get(None, None) == lbm.LBM_EINVAL
     assert lib.lbm_pool_destroy(None) == lbm.LBM_OK
+
+
+def test_slab_configs(lbm):
+    """z-slabs: two halo planes per population buffer, packed faces of 9 nx ny
+    stored values, and the configurations a slab refuses."""
+    nx, ny, nz = 70, 5, 4
+    for dtype, s in (("fp64", 8), ("fp32_dev", 4)):
+        per = lbm.make_config(27, (nx, ny, nz), 0.6, dtype)
+        slab = lbm.make_config(27, (nx, ny, nz), 0.6, dtype, z_halo=True)
+        plane_bytes = 27 * 80 * ny * s  # rows of 27 runs of pitch 80
+        grow = lbm.lbm_workspace_bytes(slab) - lbm.lbm_workspace_bytes(per)
+        assert 2 * 2 * plane_bytes <= grow <= 2 * 2 * plane_bytes + 2 * 256
+        assert lbm.lbm_halo_bytes(slab) == 9 * nx * ny * s
+        assert lbm.lbm_halo_bytes(per) == 0
+    assert lbm.lbm_workspace_bytes(lbm.make_config(9, (64, 32), 0.6, "fp64", z_halo=True)) == 0
+    assert lbm.lbm_workspace_bytes(lbm.make_config(3, (64,), 0.6, "fp64", z_halo=True)) == 0
+    bad = lbm.make_config(27, (8, 8, 8), 0.6, "fp64")
+    bad.z_halo = 2
+    assert lbm.lbm_workspace_bytes(bad) == 0
+    bad = lbm.make_config(27, (8, 8, 8), 0.6, "fp64")
+    bad.reserved = 1
+    assert lbm.lbm_workspace_bytes(bad) == 0
+    slab = lbm.make_config(27, (8, 8, 8), 0.6, "fp64", z_halo=True)
+    planes = lbm.make_tuning(layout=lbm.LBM_LAYOUT_PLANES)
+    assert lbm.lbm_workspace_bytes(slab, planes) == 0
+    assert lbm.lbm_pool_slot_bytes(slab) == 0
+    lib = lbm.load_library()
+    assert lib.lbm_halo_pack(None, 0, 256) == lbm.LBM_EINVAL
+    assert lib.lbm_halo_unpack(None, 1, 256) == lbm.LBM_EINVAL

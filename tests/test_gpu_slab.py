@@ -1,0 +1,139 @@
+"""z-slabs with halo exchange (lbm_config.z_halo, lbm_halo_pack/unpack): a
+periodic D3Q27 domain split along z into slabs that exchange the populations
+crossing their faces after every step advances bitwise as the whole domain
+(streaming of the LBGK equation, Sec. "Basic concepts": only populations with
+c_z = +1 cross a face upwards, c_z = -1 downwards).  Slabs here live on one
+GPU and exchange through device buffers, which is what a send/recv between
+GPUs would carry."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2303_08163_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _lbm():
+    from paper_2303_08163_amd import lbm
+    return lbm
+
+
+def ring_run(rho0, u0, splits, tau, steps, dtype, corr, eq="entropic", tuning=None):
+    """Advance slabs of the given plane counts (a ring, periodic in z) and return
+    (rho, u, populations) gathered along z, and the slabs' diagnostics."""
+    import torch
+    lbm = _lbm()
+    assert sum(splits) == rho0.shape[0]
+    bounds = np.cumsum([0] + list(splits))
+    slabs = [lbm.Domain(rho0[a:b], u0[:, a:b], tau, dtype=dtype, bulk_correction=corr, equilibrium=eq,
+                        tuning=tuning, z_halo=True) for a, b in zip(bounds[:-1], bounds[1:])]
+    S = len(slabs)
+    nb = slabs[0].halo_bytes()
+    assert nb == 9 * rho0.shape[1] * rho0.shape[2] * (8 if dtype == "fp64" else 4)
+    lo = [torch.empty(nb, dtype=torch.uint8, device="cuda:0") for _ in range(S)]
+    hi = [torch.empty(nb, dtype=torch.uint8, device="cuda:0") for _ in range(S)]
+
+    def exchange():
+        for k, s in enumerate(slabs):
+            s.halo_pack(0, lo[k])
+            s.halo_pack(1, hi[k])
+        for k, s in enumerate(slabs):
+            s.halo_unpack(0, hi[(k - 1) % S])
+            s.halo_unpack(1, lo[(k + 1) % S])
+
+    try:
+        exchange()
+        for _ in range(steps):
+            for s in slabs:
+                s.step(1)
+            exchange()
+        out = [s.moments(raise_on_domain=False) for s in slabs]
+        pops = [s.populations().reshape(27, -1, rho0.shape[1], rho0.shape[2]) for s in slabs]
+    finally:
+        for s in slabs:
+            s.close()
+    rho = np.concatenate([o[0] for o in out], axis=0)
+    u = np.concatenate([o[1] for o in out], axis=1)
+    return rho, u, np.concatenate(pops, axis=1), [o[2] for o in out]
+
+
+def whole_run(rho0, u0, tau, steps, dtype, corr, eq="entropic", tuning=None):
+    lbm = _lbm()
+    with lbm.Domain(rho0, u0, tau, dtype=dtype, bulk_correction=corr, equilibrium=eq, tuning=tuning) as d:
+        d.step(steps)
+        rho, u, diag = d.moments(raise_on_domain=False)
+        f = d.populations().reshape(27, *rho0.shape)
+    return rho, u, f, diag
+
+
+CASES = [  # (grid (nz, ny, nx), splits, tau, steps, dtype, corr)
+    ((8, 13, 19), [5, 3], 0.56, 7, "fp64", False),
+    ((8, 13, 19), [5, 3], 0.56, 7, "fp32_dev", True),
+    ((7, 10, 24), [7], 0.6, 6, "fp64", True),
+    ((8, 9, 20), [1, 2, 3, 2], 0.53, 5, "fp32_dev", False),
+    ((6, 4, 256), [2, 4], 0.51, 5, "fp32_dev", False),   # vector kernel, one wavefront per row
+    ((6, 3, 128), [3, 3], 0.58, 4, "fp64", True),        # vector kernel, FP64 pairs
+    ((5, 3, 512), [2, 3], 0.52, 3, "fp32_dev", True),    # vector kernel across wavefronts
+]
+
+
+@pytest.mark.parametrize("grid,splits,tau,steps,dtype,corr", CASES)
+def test_slab_ring_equals_whole_domain_bitwise(grid, splits, tau, steps, dtype, corr):
+    rho0, u0 = workloads.random_field(grid, seed=91, umax=0.15)
+    r1, u1, f1, diags = ring_run(rho0, u0, splits, tau, steps, dtype, corr)
+    r2, u2, f2, diag = whole_run(rho0, u0, tau, steps, dtype, corr)
+    print(f"[slab] {grid} splits {splits} {dtype} corr={corr}: max |drho| {np.max(np.abs(r1 - r2)):.3e}", flush=True)
+    assert np.array_equal(r1, r2) and np.array_equal(u1, u2) and np.array_equal(f1, f2)
+    assert all(d["steps"] == steps and not d["domain_error"] for d in diags)
+    assert abs(sum(d["mass"] for d in diags) - diag["mass"]) < 1e-9 * diag["mass"]
+
+
+@pytest.mark.parametrize("eq", ["poly2", "product"])
+def test_slab_ring_polynomial_equilibria(eq):
+    rho0, u0 = workloads.random_field((6, 7, 33), seed=92, umax=0.12)
+    r1, u1, f1, _ = ring_run(rho0, u0, [4, 2], 0.55, 5, "fp64", True, eq=eq)
+    r2, u2, f2, _ = whole_run(rho0, u0, 0.55, 5, "fp64", True, eq=eq)
+    assert np.array_equal(r1, r2) and np.array_equal(u1, u2) and np.array_equal(f1, f2)
+
+
+def test_slab_ring_scalar_tuning_equals_vector():
+    """A ring of slabs run with one node per thread equals the default vector kernels."""
+    lbm = _lbm()
+    rho0, u0 = workloads.random_field((4, 4, 256), seed=93, umax=0.1)
+    a = ring_run(rho0, u0, [1, 3], 0.52, 4, "fp32_dev", False, tuning=lbm.make_tuning(64, 4, -1, 1, 0))
+    b = ring_run(rho0, u0, [1, 3], 0.52, 4, "fp32_dev", False)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
+
+
+def test_slab_ring_matches_oracle():
+    """The gathered slabs against the FP64 oracle of the whole periodic domain."""
+    rho0, u0 = workloads.random_field((9, 11, 17), seed=94, umax=0.15)
+    r1, u1, _, _ = ring_run(rho0, u0, [4, 5], 0.57, 10, "fp64", True)
+    r_ref, u_ref, bad = oracle.run(rho0, u0, 0.57, 10, corr="min")
+    assert bad == 0
+    assert np.max(np.abs(r1 - r_ref)) / np.max(np.abs(r_ref)) < 1e-12
+    assert np.max(np.abs(u1 - u_ref)) / np.max(np.abs(u_ref)) < 1e-12
+
+
+def test_slab_errors():
+    import torch
+    lbm = _lbm()
+    rho0, u0 = workloads.random_field((4, 5, 6), seed=95, umax=0.1)
+    buf = torch.empty(9 * 5 * 6 * 8, dtype=torch.uint8, device="cuda:0")
+    with lbm.Domain(rho0, u0, 0.6, dtype="fp64", z_halo=True) as s:
+        with pytest.raises(lbm.LBMError):
+            s.step(2)  # a slab needs an exchange between steps
+        for face in (-1, 2):
+            with pytest.raises(lbm.LBMError):
+                s.halo_pack(face, buf)
+            with pytest.raises(lbm.LBMError):
+                s.halo_unpack(face, buf)
+        s.step(0)
+        s.step(1)
+        assert s.moments(raise_on_domain=False)[2]["steps"] == 1
+    with lbm.Domain(rho0, u0, 0.6, dtype="fp64") as d:
+        assert d.halo_bytes() == 0
+        with pytest.raises(lbm.LBMError):
+            d.halo_pack(0, buf)
+        d.step(3)  # periodic domains take any step count
