@@ -185,7 +185,8 @@ def bench_slab(steps: int = 200, nz: int = 32, n: int = 256) -> dict:
     own neighbour on both sides (pack both faces, unpack both faces after
     every step; between GPUs the two packed buffers would travel over xGMI).
     HIP events on the slab's stream split each step into the stream-collide
-    kernel and the four halo copies; nothing is skipped."""
+    kernel and the two halo launches (pack both faces, unpack both);
+    nothing is skipped."""
     import torch
 
     from paper_2303_08163_amd import lbm, workloads
@@ -197,10 +198,8 @@ def bench_slab(steps: int = 200, nz: int = 32, n: int = 256) -> dict:
         hi = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
 
         def exchange():
-            s.halo_pack(0, lo)
-            s.halo_pack(1, hi)
-            s.halo_unpack(0, hi)
-            s.halo_unpack(1, lo)
+            s.halo_pack(lo, hi)
+            s.halo_unpack(hi, lo)
 
         exchange()
         for _ in range(20):

@@ -202,24 +202,26 @@ int lbm_step(lbm_handle *h, int64_t nsteps);
  * library's stored values, meant to be moved unchanged (RCCL send/recv, peer
  * copy) to the slab that unpacks them.
  *
- *   lbm_halo_pack(h, 0, buf): plane 0, populations c_z = -1, for the slab below.
- *   lbm_halo_pack(h, 1, buf): plane nz - 1, populations c_z = +1, for the slab above.
- *   lbm_halo_unpack(h, 0, buf): into the halo plane below plane 0 (populations
- *       c_z = +1), from the slab below's face-1 pack.
- *   lbm_halo_unpack(h, 1, buf): into the halo plane above plane nz - 1
- *       (populations c_z = -1), from the slab above's face-0 pack.
+ *   lbm_halo_pack(h, lower, upper): plane 0's populations with c_z = -1 into
+ *       `lower` (for the slab below), plane nz - 1's with c_z = +1 into
+ *       `upper` (for the slab above).
+ *   lbm_halo_unpack(h, lower, upper): `lower` (the slab below's `upper` pack)
+ *       into the halo plane below plane 0, `upper` (the slab above's `lower`
+ *       pack) into the halo plane above plane nz - 1.
+ * Each call moves both faces in one kernel launch; a NULL buffer skips its
+ * face (not both).
  *
- * Sequence per step for every slab: lbm_step(h, 1); pack both faces; move the
- * buffers; unpack both faces.  Before the first step the halo planes must be
- * filled the same way (they start as zeros).  A slab that is its own
- * neighbour on both sides (pack face 1 -> unpack face 0, pack face 0 -> unpack
- * face 1) advances as the periodic domain of its nz planes.  buf is a device
- * pointer owned by the caller; the copy is enqueued on the handle's stream
- * without synchronising.  Errors: LBM_EINVAL (h or buf NULL, the domain is not
- * a z-slab, face not 0 or 1); LBM_EDEVICE. */
+ * Sequence per step for every slab: lbm_step(h, 1); pack; move the buffers;
+ * unpack.  Before the first step the halo planes must be filled the same way
+ * (they start as zeros).  A slab that is its own neighbour on both sides
+ * (lbm_halo_pack(h, a, b); lbm_halo_unpack(h, b, a)) advances as the periodic
+ * domain of its nz planes.  The buffers are device pointers owned by the
+ * caller; the copies are enqueued on the handle's stream without
+ * synchronising.  Errors: LBM_EINVAL (h NULL, both buffers NULL, the domain is
+ * not a z-slab); LBM_EDEVICE. */
 size_t lbm_halo_bytes(const lbm_config *cfg); /* 0 for a config that is not a valid z-slab */
-int lbm_halo_pack(lbm_handle *h, int32_t face, void *buf);
-int lbm_halo_unpack(lbm_handle *h, int32_t face, const void *buf);
+int lbm_halo_pack(lbm_handle *h, void *lower, void *upper);
+int lbm_halo_unpack(lbm_handle *h, const void *lower, const void *upper);
 
 /* Moments of the current state: rho (N doubles) and u (D * N doubles) into
  * device pointers, and diagnostics into a host struct.  Any of rho, u, diag may

@@ -286,18 +286,30 @@ static __global__ void k_clear_words(int *p, int count) {
 // of every row of one plane between the slab's buffer and a packed buffer
 // [y][k][x] (k = 0..8 in population order, nx elements per run).  Element
 // (y, k, x) is at src[y * s_row + k * s_run + x] and dst[y * d_row + k * d_run + x].
-// A bit copy (E = element width), so the stored values move unchanged.
+// A bit copy (E = element width), so the stored values move unchanged.  Up to
+// two faces per launch (blockIdx.y); a face with a null dst is skipped.  One
+// workgroup per run (blockIdx.x = y * 9 + k), threads along x: no per-element
+// index division.
 template <typename E>
-__global__ __launch_bounds__(256) void k_halo_copy(const E *__restrict__ src, E *__restrict__ dst, int nx,
-                                                   int64_t count, int64_t s_row, int64_t s_run, int64_t d_row,
-                                                   int64_t d_run) {
-    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < count;
-         n += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = n / nx;  // run index y * 9 + k
-        const int x = (int)(n - r * nx);
-        const int64_t y = r / 9, k = r - y * 9;
-        dst[y * d_row + k * d_run + x] = src[y * s_row + k * s_run + x];
-    }
+struct HaloCopy {
+    const E *src[2];
+    E *dst[2];
+    int nx;
+    int64_t s_row, s_run, d_row, d_run;
+};
+
+template <typename E>
+__global__ __launch_bounds__(256) void k_halo_copy(HaloCopy<E> a) {
+    const int f = (int)blockIdx.y;
+    const E *__restrict__ src = a.src[f];
+    E *__restrict__ dst = a.dst[f];
+    if (dst == nullptr)
+        return;
+    const int64_t y = blockIdx.x / 9, k = blockIdx.x - y * 9;
+    const E *__restrict__ s = src + y * a.s_row + k * a.s_run;
+    E *__restrict__ d = dst + y * a.d_row + k * a.d_run;
+    for (int x = (int)threadIdx.x; x < a.nx; x += (int)blockDim.x)
+        d[x] = s[x];
 }
 
 // Element offset of population 0 of node n (x fastest) in a buffer.

@@ -97,6 +97,10 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
         set_error("z_halo needs LBM_D3Q27");
         return LBM_EINVAL;
     }
+    if (cfg->z_halo && cfg->ny > (int64_t)INT32_MAX / 9) {
+        set_error("z_halo needs 9 ny < 2^31 (one workgroup per packed run)");
+        return LBM_EINVAL;
+    }
     L.zhalo = cfg->z_halo != 0;
     if (cfg->nx > INT32_MAX || cfg->ny > INT32_MAX || cfg->nz > INT32_MAX) {
         set_error("grid extent beyond 2^31 - 1");
@@ -465,6 +469,46 @@ struct lbm_handle {
     hipStream_t stream;
 };
 
+// Pack: plane 0's populations with c_z = -1 into `lower`, plane nz - 1's with
+// c_z = +1 into `upper`.  Unpack: `lower` into the halo plane below plane 0
+// (populations c_z = +1), `upper` into the halo plane above plane nz - 1
+// (c_z = -1).  Populations are numbered i = (c_x + 1) + 3 (c_y + 1) +
+// 9 (c_z + 1), so each row's 9 runs of one sign of c_z are adjacent.  Both
+// faces go in one launch; a NULL buffer skips its face.
+template <typename E>
+static void launch_halo_copy(const DomainState &d, const void *lower, const void *upper, bool pack,
+                             hipStream_t stream) {
+    const int64_t nx = d.cfg.nx, ny = d.cfg.ny, nz = d.cfg.nz;
+    HaloCopy<E> a{};
+    a.nx = (int)nx;
+    a.s_row = pack ? d.L.rs : 9 * nx;
+    a.s_run = pack ? d.L.ps : nx;
+    a.d_row = pack ? 9 * nx : d.L.rs;
+    a.d_run = pack ? nx : d.L.ps;
+    E *base = static_cast<E *>(d.buf[d.cur]);
+    const void *ext[2] = {lower, upper};
+    for (int f = 0; f < 2; ++f) {
+        // plane of the slab and first population of the 9
+        const int64_t plane = pack ? (f == 0 ? 0 : nz - 1) : (f == 0 ? -1 : nz);
+        const int64_t first = pack ? (f == 0 ? 0 : 18) : (f == 0 ? 18 : 0);
+        E *slab = base + (plane * ny) * d.L.rs + first * d.L.ps;  // elements from plane 0
+        if (ext[f] == nullptr) {
+            a.src[f] = nullptr;
+            a.dst[f] = nullptr;
+        } else if (pack) {
+            a.src[f] = slab;
+            a.dst[f] = static_cast<E *>(const_cast<void *>(ext[f]));
+        } else {
+            a.src[f] = static_cast<const E *>(ext[f]);
+            a.dst[f] = slab;
+        }
+    }
+    // one workgroup per run of nx elements: 9 ny runs per face (ny < 2^31 / 9
+    // is checked at configuration)
+    const unsigned threads = (unsigned)std::min<int64_t>(256, (nx + 63) / 64 * 64);
+    hipLaunchKernelGGL(k_halo_copy<E>, dim3((unsigned)(9 * ny), 2), dim3(threads), 0, stream, a);
+}
+
 extern "C" {
 
 size_t lbm_workspace_bytes_tuned(const lbm_config *cfg, const lbm_tuning *tuning) {
@@ -554,14 +598,9 @@ size_t lbm_halo_bytes(const lbm_config *cfg) {
     return (size_t)9 * (size_t)cfg->nx * (size_t)cfg->ny * L.elem;
 }
 
-// Face 0 (plane 0, populations with c_z = -1) or face 1 (plane nz - 1, c_z = +1)
-// into a packed buffer; unpack fills halo plane -1 (face 0, c_z = +1) or nz
-// (face 1, c_z = -1) from one.  Populations are numbered i = (c_x + 1) +
-// 3 (c_y + 1) + 9 (c_z + 1), so each row's 9 runs of one sign of c_z are
-// adjacent.
-static int halo_copy(lbm_handle *h, int32_t face, const void *in, void *out, bool pack) {
-    if (!h || (pack ? !out : !in)) {
-        set_error("NULL handle or buffer");
+static int halo_copy(lbm_handle *h, const void *lower, const void *upper, bool pack) {
+    if (!h || (!lower && !upper)) {
+        set_error("NULL handle, or both buffers NULL");
         return LBM_EINVAL;
     }
     DomainState &d = h->d;
@@ -569,46 +608,21 @@ static int halo_copy(lbm_handle *h, int32_t face, const void *in, void *out, boo
         set_error("the domain is not a z-slab (z_halo = 0)");
         return LBM_EINVAL;
     }
-    if (face != 0 && face != 1) {
-        set_error("face must be 0 (lower) or 1 (upper)");
-        return LBM_EINVAL;
-    }
-    const int64_t nx = d.cfg.nx, ny = d.cfg.ny, nz = d.cfg.nz;
-    int64_t plane, first;  // plane of the slab and first population of the 9
-    if (pack) {
-        plane = face == 0 ? 0 : nz - 1;
-        first = face == 0 ? 0 : 18;
-    } else {
-        plane = face == 0 ? -1 : nz;
-        first = face == 0 ? 18 : 0;
-    }
-    const int64_t off = (plane * ny) * d.L.rs + first * d.L.ps;  // elements from plane 0
-    const int64_t count = 9 * nx * ny;
-    const int blocks = (int)std::min<int64_t>((count + 255) / 256, 8192);
-    const int64_t s_row = pack ? d.L.rs : 9 * nx, s_run = pack ? d.L.ps : nx;
-    const int64_t d_row = pack ? 9 * nx : d.L.rs, d_run = pack ? nx : d.L.ps;
-    if (d.L.elem == 8) {
-        uint64_t *b = static_cast<uint64_t *>(d.buf[d.cur]) + off;
-        const uint64_t *src = pack ? b : static_cast<const uint64_t *>(in);
-        uint64_t *dst = pack ? static_cast<uint64_t *>(out) : b;
-        hipLaunchKernelGGL(k_halo_copy<uint64_t>, dim3(blocks), dim3(256), 0, h->stream, src, dst, (int)nx, count,
-                           s_row, s_run, d_row, d_run);
-    } else {
-        uint32_t *b = static_cast<uint32_t *>(d.buf[d.cur]) + off;
-        const uint32_t *src = pack ? b : static_cast<const uint32_t *>(in);
-        uint32_t *dst = pack ? static_cast<uint32_t *>(out) : b;
-        hipLaunchKernelGGL(k_halo_copy<uint32_t>, dim3(blocks), dim3(256), 0, h->stream, src, dst, (int)nx, count,
-                           s_row, s_run, d_row, d_run);
-    }
+    if (d.L.elem == 8)
+        launch_halo_copy<uint64_t>(d, lower, upper, pack, h->stream);
+    else
+        launch_halo_copy<uint32_t>(d, lower, upper, pack, h->stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return hip_fail(e, pack ? "halo pack launch" : "halo unpack launch");
     return LBM_OK;
 }
 
-int lbm_halo_pack(lbm_handle *h, int32_t face, void *buf) { return halo_copy(h, face, nullptr, buf, true); }
+int lbm_halo_pack(lbm_handle *h, void *lower, void *upper) { return halo_copy(h, lower, upper, true); }
 
-int lbm_halo_unpack(lbm_handle *h, int32_t face, const void *buf) { return halo_copy(h, face, buf, nullptr, false); }
+int lbm_halo_unpack(lbm_handle *h, const void *lower, const void *upper) {
+    return halo_copy(h, lower, upper, false);
+}
 
 int lbm_moments(lbm_handle *h, double *rho, double *u, lbm_diag *diag) {
     if (!h) {

@@ -132,8 +132,8 @@ def load_library(path: str = LIB_PATH):
         "lbm_get_populations": (ctypes.c_int, [vp, vp]),
         "lbm_energy": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_double, vp]),
         "lbm_halo_bytes": (sz, [cfgp]),
-        "lbm_halo_pack": (ctypes.c_int, [vp, ctypes.c_int32, vp]),
-        "lbm_halo_unpack": (ctypes.c_int, [vp, ctypes.c_int32, vp]),
+        "lbm_halo_pack": (ctypes.c_int, [vp, vp, vp]),
+        "lbm_halo_unpack": (ctypes.c_int, [vp, vp, vp]),
         "lbm_vn_spectra": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, i64, vp, vp, vp, vp,
                                           vp]),
         "lbm_vn_max_radius": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, i64,
@@ -238,12 +238,12 @@ def lbm_halo_bytes(cfg: lbm_config) -> int:
     return int(load_library().lbm_halo_bytes(ctypes.byref(cfg)))
 
 
-def lbm_halo_pack(h, face: int, buf: int) -> None:
-    _check(load_library().lbm_halo_pack(h, int(face), buf), "lbm_halo_pack")
+def lbm_halo_pack(h, lower: int | None, upper: int | None) -> None:
+    _check(load_library().lbm_halo_pack(h, lower, upper), "lbm_halo_pack")
 
 
-def lbm_halo_unpack(h, face: int, buf: int) -> None:
-    _check(load_library().lbm_halo_unpack(h, int(face), buf), "lbm_halo_unpack")
+def lbm_halo_unpack(h, lower: int | None, upper: int | None) -> None:
+    _check(load_library().lbm_halo_unpack(h, lower, upper), "lbm_halo_unpack")
 
 
 def lbm_energy(h, U, rho_ref: float, out: int) -> None:
@@ -422,17 +422,19 @@ class Domain:
         """Bytes of one packed face of a z-slab (0 for a periodic domain)."""
         return lbm_halo_bytes(self.cfg)
 
-    def halo_pack(self, face: int, buf) -> None:
-        """Enqueue the face's outgoing populations into buf (a CUDA tensor of
-        at least halo_bytes() bytes): face 0 = plane 0 (c_z = -1), face 1 =
-        plane nz - 1 (c_z = +1)."""
-        lbm_halo_pack(self.handle, face, buf.data_ptr())
+    def halo_pack(self, lower, upper) -> None:
+        """Enqueue the outgoing populations of both faces (CUDA tensors of at
+        least halo_bytes() bytes, or None to skip a face): plane 0's c_z = -1
+        populations into lower, plane nz - 1's c_z = +1 into upper."""
+        lbm_halo_pack(self.handle, None if lower is None else lower.data_ptr(),
+                      None if upper is None else upper.data_ptr())
 
-    def halo_unpack(self, face: int, buf) -> None:
-        """Enqueue buf into the halo plane below plane 0 (face 0; the lower
-        slab's face-1 pack) or above plane nz - 1 (face 1; the upper slab's
-        face-0 pack)."""
-        lbm_halo_unpack(self.handle, face, buf.data_ptr())
+    def halo_unpack(self, lower, upper) -> None:
+        """Enqueue lower (the slab below's upper pack) into the halo plane
+        below plane 0 and upper (the slab above's lower pack) into the halo
+        plane above plane nz - 1; None skips a face."""
+        lbm_halo_unpack(self.handle, None if lower is None else lower.data_ptr(),
+                        None if upper is None else upper.data_ptr())
 
     def moments(self, fields: bool = True, raise_on_domain: bool = True):
         """(rho, u, diag) with rho, u as numpy float64 arrays (None if fields=False)."""

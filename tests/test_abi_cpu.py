@@ -251,5 +251,5 @@ def test_slab_configs(lbm):
     assert lbm.lbm_workspace_bytes(slab, planes) == 0
     assert lbm.lbm_pool_slot_bytes(slab) == 0
     lib = lbm.load_library()
-    assert lib.lbm_halo_pack(None, 0, 256) == lbm.LBM_EINVAL
-    assert lib.lbm_halo_unpack(None, 1, 256) == lbm.LBM_EINVAL
+    assert lib.lbm_halo_pack(None, 256, 512) == lbm.LBM_EINVAL
+    assert lib.lbm_halo_unpack(None, 256, None) == lbm.LBM_EINVAL

@@ -19,7 +19,7 @@ def _lbm():
     return lbm
 
 
-def ring_run(rho0, u0, splits, tau, steps, dtype, corr, eq="entropic", tuning=None):
+def ring_run(rho0, u0, splits, tau, steps, dtype, corr, eq="entropic", tuning=None, split_faces=False):
     """Advance slabs of the given plane counts (a ring, periodic in z) and return
     (rho, u, populations) gathered along z, and the slabs' diagnostics."""
     import torch
@@ -36,11 +36,17 @@ def ring_run(rho0, u0, splits, tau, steps, dtype, corr, eq="entropic", tuning=No
 
     def exchange():
         for k, s in enumerate(slabs):
-            s.halo_pack(0, lo[k])
-            s.halo_pack(1, hi[k])
+            if split_faces:  # one face per call
+                s.halo_pack(lo[k], None)
+                s.halo_pack(None, hi[k])
+            else:
+                s.halo_pack(lo[k], hi[k])
         for k, s in enumerate(slabs):
-            s.halo_unpack(0, hi[(k - 1) % S])
-            s.halo_unpack(1, lo[(k + 1) % S])
+            if split_faces:
+                s.halo_unpack(hi[(k - 1) % S], None)
+                s.halo_unpack(None, lo[(k + 1) % S])
+            else:
+                s.halo_unpack(hi[(k - 1) % S], lo[(k + 1) % S])
 
     try:
         exchange()
@@ -92,7 +98,7 @@ def test_slab_ring_equals_whole_domain_bitwise(grid, splits, tau, steps, dtype, 
 @pytest.mark.parametrize("eq", ["poly2", "product"])
 def test_slab_ring_polynomial_equilibria(eq):
     rho0, u0 = workloads.random_field((6, 7, 33), seed=92, umax=0.12)
-    r1, u1, f1, _ = ring_run(rho0, u0, [4, 2], 0.55, 5, "fp64", True, eq=eq)
+    r1, u1, f1, _ = ring_run(rho0, u0, [4, 2], 0.55, 5, "fp64", True, eq=eq, split_faces=(eq == "product"))
     r2, u2, f2, _ = whole_run(rho0, u0, 0.55, 5, "fp64", True, eq=eq)
     assert np.array_equal(r1, r2) and np.array_equal(u1, u2) and np.array_equal(f1, f2)
 
@@ -124,16 +130,15 @@ def test_slab_errors():
     with lbm.Domain(rho0, u0, 0.6, dtype="fp64", z_halo=True) as s:
         with pytest.raises(lbm.LBMError):
             s.step(2)  # a slab needs an exchange between steps
-        for face in (-1, 2):
-            with pytest.raises(lbm.LBMError):
-                s.halo_pack(face, buf)
-            with pytest.raises(lbm.LBMError):
-                s.halo_unpack(face, buf)
+        with pytest.raises(lbm.LBMError):
+            s.halo_pack(None, None)
+        with pytest.raises(lbm.LBMError):
+            s.halo_unpack(None, None)
         s.step(0)
         s.step(1)
         assert s.moments(raise_on_domain=False)[2]["steps"] == 1
     with lbm.Domain(rho0, u0, 0.6, dtype="fp64") as d:
         assert d.halo_bytes() == 0
         with pytest.raises(lbm.LBMError):
-            d.halo_pack(0, buf)
+            d.halo_pack(buf, buf)
         d.step(3)  # periodic domains take any step count
