@@ -101,7 +101,7 @@ EXPORTS = ("lbm_workspace_bytes", "lbm_workspace_bytes_tuned", "lbm_create", "lb
            "lbm_last_error", "lbm_version", "lbm_pool_table_bytes", "lbm_pool_slot_bytes", "lbm_pool_create",
            "lbm_pool_admit", "lbm_pool_run", "lbm_pool_poll", "lbm_pool_moments", "lbm_pool_get_populations",
            "lbm_pool_release", "lbm_pool_stats_get", "lbm_pool_slot_info", "lbm_pool_destroy",
-           "lbm_vn_spectra", "lbm_vn_max_radius")
+           "lbm_vn_spectra", "lbm_vn_max_radius", "lbm_halo_bytes", "lbm_halo_pack", "lbm_halo_unpack")
 
 
 def load_library(path: str = LIB_PATH):
