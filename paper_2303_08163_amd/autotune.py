@@ -3,13 +3,13 @@
 For a set of domains (lattice, grid, storage), it times a short run of each
 candidate pool tuning -- workgroup tile shape (one node per thread; rows of
 tile_x nodes, rows fitted to each slot's width, or runs of consecutive nodes
-across rows) and launch form (one launch per step, or one persistent
-cooperative launch per run) -- on
-a scratch pool holding domains of exactly those sizes, and returns the
-fastest.  Results do not depend on the tuning (the per-node arithmetic is the
-same in every kernel), so only time is compared.  Choices are cached in a JSON
-file keyed by device name, HIP runtime version and a coarse signature of the
-domain sizes.
+across rows) and launch form (one launch per step; on request also one
+persistent cooperative launch per run) -- on a scratch pool holding domains
+of exactly those sizes, and returns the fastest.  Results do not depend on
+the tuning (the per-node arithmetic is the same in every kernel), so only
+time is compared.  Choices are cached in a JSON file keyed by the candidate
+set, device name, HIP runtime version and a coarse signature of the domain
+sizes.
 """
 from __future__ import annotations
 
@@ -30,10 +30,17 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "lbm_entropic", 
 FLAT_TILES = [(64, 4), (64, 2), (64, 1)]  # flat mode: 256, 128 or 64 consecutive nodes per workgroup
 
 
-def candidates():
-    rows = [dict(tile_x=tx, tile_y=ty, persistent=p) for (tx, ty) in TILES for p in (0, 1)]
-    flat = [dict(tile_x=tx, tile_y=ty, persistent=p, flat=1) for (tx, ty) in FLAT_TILES for p in (0, 1)]
-    fit = [dict(tile_x=64, tile_y=4, persistent=p, row_fit=1) for p in (0, 1)]
+def candidates(persistent: bool = False):
+    """Tile shapes with one launch per step; with persistent, each also as one
+    cooperative launch per run.  The persistent form is left out by default:
+    its grid barrier cost 200-260 us per step on MI355X (every workgroup polls
+    one device-coherent counter and does an agent-scope release and acquire),
+    against a few microseconds between back-to-back launches, and it was the
+    slower form on every workload measured."""
+    forms = (0, 1) if persistent else (0,)
+    rows = [dict(tile_x=tx, tile_y=ty, persistent=p) for (tx, ty) in TILES for p in forms]
+    flat = [dict(tile_x=tx, tile_y=ty, persistent=p, flat=1) for (tx, ty) in FLAT_TILES for p in forms]
+    fit = [dict(tile_x=64, tile_y=4, persistent=p, row_fit=1) for p in forms]
     return rows + flat + fit
 
 
@@ -108,7 +115,9 @@ def tune_pool(domains, steps: int = 20, cands=None, cache_path: str | None = DEF
     "failed", each candidate that the library refused or that raised an error
     while it ran (for instance a persistent run whose grid barrier timed out),
     with the error text."""
-    key = f"candidates-v3|{_device_key()}|{signature(domains)}"
+    key = f"candidates-v4|{_device_key()}|{signature(domains)}" if cands is None else \
+        f"custom-{hashlib.sha256(json.dumps(cands, sort_keys=True).encode()).hexdigest()[:12]}|{_device_key()}|" \
+        f"{signature(domains)}"
     cache = _load_cache(cache_path) if cache_path else {}
     if use_cache and key in cache:
         return cache[key]["tuning"], {"cached": True, "key": key, "times": cache[key].get("times")}

@@ -38,3 +38,29 @@ def test_all_candidates_failing_raises(monkeypatch):
     monkeypatch.setattr(autotune, "_device_key", lambda: "test-device")
     with pytest.raises(RuntimeError):
         autotune.tune_pool([(9, (40, 50), "fp64")], cands=[dict(tile_x=64, tile_y=4, persistent=0)], cache_path=None)
+
+
+def test_candidate_sets():
+    default = autotune.candidates()
+    assert default and all(c["persistent"] == 0 for c in default)
+    both = autotune.candidates(persistent=True)
+    assert len(both) == 2 * len(default)
+    assert sorted(map(str, (c for c in both if c["persistent"] == 0))) == sorted(map(str, default))
+
+
+def test_custom_candidates_do_not_share_the_default_cache(monkeypatch, tmp_path):
+    calls = []
+
+    def fake_time(domains, c, steps=20, warmup=3):
+        calls.append(c)
+        return 1e-3 if c["tile_x"] == 128 else 2e-3
+
+    monkeypatch.setattr(autotune, "time_tuning", fake_time)
+    monkeypatch.setattr(autotune, "_device_key", lambda: "test-device")
+    cache = str(tmp_path / "tune.json")
+    doms = [(9, (40, 50), "fp32_dev")]
+    only64 = [dict(tile_x=64, tile_y=4, persistent=0)]
+    best, _ = autotune.tune_pool(doms, cands=only64, cache_path=cache)
+    assert best == only64[0]
+    best2, rep2 = autotune.tune_pool(doms, cache_path=cache)  # default set: timed afresh
+    assert not rep2["cached"] and best2["tile_x"] == 128
