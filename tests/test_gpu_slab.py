@@ -142,3 +142,50 @@ def test_slab_errors():
         with pytest.raises(lbm.LBMError):
             d.halo_pack(buf, buf)
         d.step(3)  # periodic domains take any step count
+
+
+def _moments_ring(rho0, u0, splits, tau, steps, dtype):
+    """Moments only (full-size grids): rings of slabs as in ring_run."""
+    import torch
+    lbm = _lbm()
+    bounds = np.cumsum([0] + list(splits))
+    slabs = [lbm.Domain(rho0[a:b], u0[:, a:b], tau, dtype=dtype, z_halo=True)
+             for a, b in zip(bounds[:-1], bounds[1:])]
+    S = len(slabs)
+    nb = slabs[0].halo_bytes()
+    lo = [torch.empty(nb, dtype=torch.uint8, device="cuda:0") for _ in range(S)]
+    hi = [torch.empty(nb, dtype=torch.uint8, device="cuda:0") for _ in range(S)]
+
+    def exchange():
+        for k, s in enumerate(slabs):
+            s.halo_pack(lo[k], hi[k])
+        for k, s in enumerate(slabs):
+            s.halo_unpack(hi[(k - 1) % S], lo[(k + 1) % S])
+
+    try:
+        exchange()
+        for _ in range(steps):
+            for s in slabs:
+                s.step(1)
+            exchange()
+        out = [s.moments(raise_on_domain=False) for s in slabs]
+    finally:
+        for s in slabs:
+            s.close()
+    return np.concatenate([o[0] for o in out], axis=0), np.concatenate([o[1] for o in out], axis=1)
+
+
+@pytest.mark.parametrize("planes,splits", [(32, [32]), (64, [32, 32])])
+def test_slab_full_size_bench_shape(planes, splits):
+    """The benchmark's slab (256 x 256 x 32, FP32, default launch shape, planes
+    of the 256^3 Taylor-Green field): as its own neighbour it advances as the
+    periodic 256 x 256 x 32 domain, and two such slabs as the 256 x 256 x 64
+    domain, bitwise."""
+    lbm = _lbm()
+    rho0, u0 = workloads.taylor_green_3d(256, u0=0.05, planes=(0, planes))
+    r1, u1 = _moments_ring(rho0, u0, splits, 0.5005, 4, "fp32_dev")
+    with lbm.Domain(rho0, u0, 0.5005, dtype="fp32_dev") as d:
+        d.step(4)
+        r2, u2, _ = d.moments()
+    print(f"[slab full size] 256x256x{planes} splits {splits}: max |du| {np.max(np.abs(u1 - u2)):.3e}", flush=True)
+    assert np.array_equal(r1, r2) and np.array_equal(u1, u2)
