@@ -86,9 +86,9 @@ def bench_batched(count: int, steps: int, dtypes=("fp32_dev", "fp64"), baseline:
                   fixed_tuning: dict | None = None) -> dict:
     """Batched workload: `count` independent D2Q9 shear-wave domains (Nx, Ny
     uniform in 32..512, amplitude U[0.01, 0.2], nu log-uniform 1e-5..1e-1),
-    `steps` steps each, all advanced by one persistent launch (or one launch
-    per step, whichever the autotuner picks), against the plain path: one
-    domain at a time, one kernel launch per step (count * steps launches)."""
+    `steps` steps each, all advanced together by one pool kernel launch per
+    step (tile shape from the autotuner), against the plain path: one domain
+    at a time, one kernel launch per step (count * steps launches)."""
     import torch
 
     from paper_2303_08163_amd import autotune, lbm, workloads

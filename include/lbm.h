@@ -270,9 +270,11 @@ const char *lbm_status_string(int status);
  * divides into a table region and slot workspaces (first-fit, coalescing free
  * list).  A slot is one periodic domain (any lattice and dtype; its own tau,
  * correction and step budget).  lbm_pool_run advances every active slot; one
- * step of all slots of a (lattice, dtype) class is one kernel launch, or all
- * steps of a run are one persistent cooperative launch with a device-side
- * grid barrier between steps.  A slot's populations are bitwise the same as
+ * step of all slots of a (lattice, dtype) class is one kernel launch (the
+ * default), or all steps of a run are one persistent cooperative launch with
+ * a device-side grid barrier between steps (on MI355X the barrier costs more
+ * than a kernel boundary, 0.2-0.3 ms per step at full occupancy, so the
+ * persistent form is an option, not the default).  A slot's populations are bitwise the same as
  * those of a single domain (lbm_create) with the same configuration and
  * layout: every kernel uses the same per-node arithmetic.  Pools are not
  * thread-safe; slots of one pool share its stream.

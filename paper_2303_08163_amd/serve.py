@@ -4,8 +4,8 @@ Requests (lattice, grid, initial field, u0, tau, step count) arrive over time.
 The server keeps the populations of admitted requests resident in HBM as slots
 of one pool, admits queued requests whenever a slot and a large enough block
 of the arena are free (admission by memory footprint), advances every active
-slot in chunks of K steps (one pool run: one kernel launch per step, or one
-persistent launch, covering all active requests of a class), and returns a
+slot in chunks of K steps (one pool run: one kernel launch per step covering
+all active requests of a class, with the pool's default tuning), and returns a
 result as soon as a request's steps are done.  Requests arriving while others
 run join the next chunk, so their work overlaps on the device.
 
