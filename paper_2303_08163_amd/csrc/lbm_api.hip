@@ -689,6 +689,6 @@ const char *lbm_status_string(int status) {
 
 const char *lbm_last_error(void) { return g_last_error; }
 
-const char *lbm_version(void) { return "lbm-entropic 0.3 (gfx950)"; }
+const char *lbm_version(void) { return "lbm-entropic 0.4 (gfx950)"; }
 
 }  // extern "C"

@@ -253,3 +253,14 @@ def test_slab_configs(lbm):
     lib = lbm.load_library()
     assert lib.lbm_halo_pack(None, 256, 512) == lbm.LBM_EINVAL
     assert lib.lbm_halo_unpack(None, 256, None) == lbm.LBM_EINVAL
+
+
+def test_c_abi_demo_compiles_and_links(tmp_path):
+    """The plain-C caller (tests/c/abi_demo.c) builds with gcc -std=c99 -Werror
+    against include/lbm.h and links against the library (run by a GPU test)."""
+    import subprocess
+    import __graft_entry__ as entry
+    out = str(tmp_path / "abi_demo")
+    r = subprocess.run(entry.c_demo_command(out), capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    assert os.path.exists(out)
