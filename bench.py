@@ -455,8 +455,9 @@ def main() -> int:
     args = ap.parse_args()
     sections = set(args.sections.split(","))
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs each domain on a single GPU "
-              "(multi-GPU slab decomposition is a design, not built).", file=sys.stderr)
+        print("bench.py measures one GPU only: every workload runs on a single GPU (z-slabs "
+              "with halo exchange model one GPU's share; the transfer between GPUs is not built).",
+              file=sys.stderr)
         return 2
 
     import numpy as np
