@@ -304,3 +304,25 @@ def test_invalid_arguments_raise():
             d.step(-1)
         d.step(0)
         assert d.moments(fields=False)[2]["steps"] == 0
+
+
+@pytest.mark.parametrize("rho_ref", [2.5, 1.0])
+@pytest.mark.parametrize("shape", [(23, 41), (7, 9, 13)])
+def test_fp32_reference_density(shape, rho_ref):
+    """FP32 deviation storage keeps f_i - w_i rho0 with the caller's reference
+    density rho0.  Fields of mean density 2.5 are run with rho0 = 2.5 (matched)
+    and rho0 = 1 (mismatched: larger stored deviations, fewer significant bits
+    in them); both meet the FP32 tolerance against the FP64 oracle."""
+    lbm = _lbm()
+    rho0, u0 = workloads.random_field(shape, seed=96, umax=0.12)
+    rho0 = 2.5 * rho0
+    steps = 20
+    with lbm.Domain(rho0, u0, 0.55, dtype="fp32_dev", bulk_correction=True, rho0=rho_ref) as d:
+        d.step(steps)
+        rho, u, diag = d.moments(raise_on_domain=False)
+    r_ref, u_ref, bad = oracle.run(rho0, u0, 0.55, steps, corr="min")
+    er, eu = rel_err(rho, r_ref), rel_err(u, u_ref)
+    report(f"{shape} FP32 rho0 = {rho_ref}, mean density 2.5", er, eu)
+    assert bad == 0 and not diag["domain_error"]
+    assert er < TOL["fp32_dev"] and eu < TOL["fp32_dev"]
+    assert abs(diag["mass"] / rho0.sum() - 1) < 1e-6
