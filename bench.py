@@ -186,7 +186,9 @@ def bench_slab(steps: int = 200, nz: int = 32, n: int = 256) -> dict:
     every step; between GPUs the two packed buffers would travel over xGMI).
     HIP events on the slab's stream split each step into the stream-collide
     kernel and the two halo launches (pack both faces, unpack both);
-    nothing is skipped."""
+    nothing is skipped.  Then the same slab with the exchange fused into the
+    step kernel (lbm_step_halo: one launch per step, which reads the entering
+    populations from the packed buffers and writes the leaving ones)."""
     import torch
 
     from paper_2303_08163_amd import lbm, workloads
@@ -219,6 +221,22 @@ def bench_slab(steps: int = 200, nz: int = 32, n: int = 256) -> dict:
         k_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
         x_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
         diag = s.moments(fields=False)[2]
+        # the same slab with the exchange fused into the step (lbm_step_halo):
+        # two sets of send buffers alternate, each step reads the other set
+        bufs = [[torch.empty(nb, dtype=torch.uint8, device="cuda:0") for _ in range(2)] for _ in range(2)]
+        s.halo_pack(bufs[1][0], bufs[1][1])
+        for t in range(20):
+            p = t % 2
+            s.step_halo(bufs[1 - p][1], bufs[1 - p][0], bufs[p][0], bufs[p][1])
+        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.stream.synchronize()
+        f0.record(s.stream)
+        for t in range(steps):
+            p = t % 2
+            s.step_halo(bufs[1 - p][1], bufs[1 - p][0], bufs[p][0], bufs[p][1])
+        f1.record(s.stream)
+        s.stream.synchronize()
+        fused_ms = f0.elapsed_time(f1) / steps
     nodes = n * n * nz
     return {"workload": f"D3Q27 {n}x{n}x{nz} z-slab of the {n}^3 Taylor-Green field (u0 = 0.05, tau = 0.5005), "
                         "FP32 deviations, halo planes exchanged with itself after every step",
@@ -227,7 +245,9 @@ def bench_slab(steps: int = 200, nz: int = 32, n: int = 256) -> dict:
             "mlups": round(nodes / ((k_ms + x_ms) * 1e-3) / 1e6, 1),
             "stream_collide_gbs": round(nodes * 216 / (k_ms * 1e-3) / 1e9, 1),
             "stream_collide_frac_of_8tbs": round(nodes * 216 / (k_ms * 1e-3) / 8e12, 4),
-            "halo_bytes_per_face": nb, "wall_s": round(wall, 4), "mass": diag["mass"]}
+            "halo_bytes_per_face": nb, "wall_s": round(wall, 4), "mass": diag["mass"],
+            "fused_exchange": {"ms_per_step": round(fused_ms, 5), "mlups": round(nodes / (fused_ms * 1e-3) / 1e6, 1),
+                               "frac_of_8tbs": round(nodes * 216 / (fused_ms * 1e-3) / 8e12, 4)}}
 
 
 def bench_wave(steps: int = 2000) -> dict:

@@ -220,6 +220,26 @@ int lbm_step(lbm_handle *h, int64_t nsteps);
  * synchronising.  Errors: LBM_EINVAL (h NULL, both buffers NULL, the domain is
  * not a z-slab); LBM_EDEVICE. */
 size_t lbm_halo_bytes(const lbm_config *cfg); /* 0 for a config that is not a valid z-slab */
+
+/* One step of a z-slab with the halo exchange fused into the stream-collide
+ * kernel (no pack or unpack launch): the populations entering across the two
+ * faces are read from recv_lower (the slab below's outgoing upper face) and
+ * recv_upper (the slab above's outgoing lower face) instead of the halo
+ * planes, and the populations leaving are written to send_lower (plane 0,
+ * c_z = -1) and send_upper (plane nz - 1, c_z = +1) while the step stores the
+ * slab's own state.  All four buffers are packed as for lbm_halo_pack (the
+ * two forms interoperate: a first step can read buffers lbm_halo_pack
+ * filled), lbm_halo_bytes each, device pointers owned by the caller; a
+ * receive buffer must not overlap a send buffer of the same call, so
+ * neighbours on one device alternate two sets of send buffers.  The halo
+ * planes are neither read nor written.  Enqueued without synchronising.
+ * Runs with LBM_FP64 or LBM_FP32_DEV storage and one node per thread or the
+ * default vector width (with the default cache hints).  Errors: LBM_EINVAL (h
+ * or a buffer NULL, a receive buffer equal to a send buffer, equal send
+ * buffers, the domain is not a z-slab, another storage type or tuning);
+ * LBM_EDEVICE. */
+int lbm_step_halo(lbm_handle *h, const void *recv_lower, const void *recv_upper, void *send_lower,
+                  void *send_upper);
 int lbm_halo_pack(lbm_handle *h, void *lower, void *upper);
 int lbm_halo_unpack(lbm_handle *h, const void *lower, const void *upper);
 

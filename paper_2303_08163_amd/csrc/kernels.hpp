@@ -40,6 +40,23 @@ struct StepArgs {
     int zhalo;  // 1: z-slab, planes -1 and nz are halo planes (no periodic wrap in z)
 };
 
+// Fused halo exchange of a z-slab, the extra argument of the *_halo step
+// kernels (a separate parameter, so that the plain kernels keep their
+// argument layout).  recv[0] / recv[1]: packed [y][k][x] runs of the
+// populations entering across the lower face (c_z = +1, i = 18..26) / upper
+// face (c_z = -1, i = 0..8), read instead of the halo planes; send[0] /
+// send[1]: the same packing of the populations leaving across the lower face
+// (plane 0, i = 0..8) / upper face (plane nz - 1, i = 18..26), written besides
+// the slab's own buffer.
+struct HaloArgs {
+    const void *recv[2];
+    void *send[2];
+};
+
+// Row y' of the packed halo buffer: population k of the face's 9 starts at
+// (y' * 9 + k) * nx.
+__device__ __forceinline__ int64_t packed_run(int yrow, int k, int nx) { return ((int64_t)yrow * 9 + k) * nx; }
+
 // Workgroups are dispatched round-robin over the 8 XCDs (workgroup w runs on
 // XCD w mod 8).  Give each XCD one contiguous range of tiles, walked in order,
 // so that tiles adjacent in x (which share the cache lines at their boundary
@@ -95,16 +112,25 @@ __device__ __forceinline__ void source_rows(int y, int z, int ny, int nz, int64_
 // a second set of Q stores, each line at the row end is written in two parts,
 // and a step on a ragged width took up to 1.6 times as long.)  The padding is
 // never read.
-template <int DIM, int DT, bool CORR, int EQ = kEqEntropic>
+// With HALO (a fused z-slab step, recv/send non-null) the populations
+// entering across a face are read from the packed buffers and those leaving
+// are also written to send.  Without it the halo arguments are ignored and
+// the code is that of the plain step.
+template <int DIM, int DT, bool CORR, int EQ = kEqEntropic, bool HALO = false>
 __device__ __forceinline__ void step_node(const store_t<DT> *__restrict__ src, store_t<DT> *__restrict__ dst,
                                           int nx, int ny, int nz, int64_t ps, int64_t rs, const Relax &relax,
-                                          int *flag, int x, int y, int z, bool pad = false, bool zhalo = false) {
+                                          int *flag, int x, int y, int z, bool pad = false, bool zhalo = false,
+                                          const void *recv_lo = nullptr, const void *recv_hi = nullptr,
+                                          void *send_lo = nullptr, void *send_hi = nullptr) {
     using T = store_t<DT>;
     constexpr int Q = Lattice<DIM>::Q;
     const int xn = pad ? nx - 1 : x;  // node whose sources are read
     const int xs[3] = {xn + 1 == nx ? 0 : xn + 1, xn, xn == 0 ? nx - 1 : xn - 1};  // x - c_x
     int64_t rowoff[3][3];
     source_rows<DIM>(y, z, ny, nz, rs, rowoff, zhalo);
+    const int ys[3] = {y + 1 == ny ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};  // y - c_y
+    const T *from_lo = HALO && DIM == 3 && z == 0 ? static_cast<const T *>(recv_lo) : nullptr;
+    const T *from_hi = HALO && DIM == 3 && z == nz - 1 ? static_cast<const T *>(recv_hi) : nullptr;
     T f[Q];
 #pragma unroll
     for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
@@ -113,7 +139,12 @@ __device__ __forceinline__ void step_node(const store_t<DT> *__restrict__ src, s
 #pragma unroll
             for (int cx = 0; cx < 3; ++cx) {
                 const int i = cx + 3 * cy + 9 * cz;
-                f[i] = src[rowoff[cz][cy] + i * ps + xs[cx]];
+                if (HALO && cz == 2 && from_lo)
+                    f[i] = from_lo[packed_run(ys[cy], i - 18, nx) + xs[cx]];
+                else if (HALO && cz == 0 && from_hi)
+                    f[i] = from_hi[packed_run(ys[cy], i, nx) + xs[cx]];
+                else
+                    f[i] = src[rowoff[cz][cy] + i * ps + xs[cx]];
             }
 
     const bool bad = collide_dt<DIM, DT, CORR, EQ>(f, relax);
@@ -123,6 +154,16 @@ __device__ __forceinline__ void step_node(const store_t<DT> *__restrict__ src, s
 #pragma unroll
     for (int i = 0; i < Q; ++i)
         dst[self + i * ps] = pad ? T(0) : f[i];
+    if (HALO && DIM == 3 && !pad) {
+        if (z == 0 && send_lo)
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                static_cast<T *>(send_lo)[packed_run(y, i, nx) + x] = f[i];
+        if (z == nz - 1 && send_hi)
+#pragma unroll
+            for (int i = 18; i < Q; ++i)
+                static_cast<T *>(send_hi)[packed_run(y, i - 18, nx) + x] = f[i];
+    }
 }
 
 // Whether a lane at x >= nx has a padding position to fill (row-interleaved
@@ -134,19 +175,33 @@ __device__ __forceinline__ bool in_padding(int64_t ps, int64_t rs, int x) {
 
 // One LBGK step over the whole domain.  1-D grid of tiles_x * tiles_y * nz
 // workgroups of blockDim.x * blockDim.y threads, one node per thread.
-template <int DIM, int DT, bool CORR, int EQ = kEqEntropic>
-__global__ __launch_bounds__(256) void k_stream_collide(StepArgs a) {
-    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+// (The launch dimensions come from the kernel: read there, the workgroup size
+// is known to be uniform, which spares a load per thread.)
+template <int DIM, int DT, bool CORR, int EQ, bool HALO>
+__device__ __forceinline__ void stream_collide(const StepArgs &a, const HaloArgs &h, int bdx, int bdy, int gdx) {
+    const int t = xcd_tile((int)blockIdx.x, gdx);
     const int tx = t % a.tiles_x;
     const int ty = (t / a.tiles_x) % a.tiles_y;
     const int z = t / (a.tiles_x * a.tiles_y);
-    const int x = tx * (int)blockDim.x + (int)threadIdx.x;
-    const int y = ty * (int)blockDim.y + (int)threadIdx.y;
+    const int x = tx * bdx + (int)threadIdx.x;
+    const int y = ty * bdy + (int)threadIdx.y;
     const bool pad = x >= a.nx;
     if (y >= a.ny || (pad && !in_padding<DIM>(a.ps, a.rs, x)))
         return;
-    step_node<DIM, DT, CORR, EQ>(static_cast<const store_t<DT> *>(a.src), static_cast<store_t<DT> *>(a.dst), a.nx,
-                                 a.ny, a.nz, a.ps, a.rs, a.relax, a.flag, x, y, z, pad, a.zhalo != 0);
+    step_node<DIM, DT, CORR, EQ, HALO>(static_cast<const store_t<DT> *>(a.src), static_cast<store_t<DT> *>(a.dst),
+                                       a.nx, a.ny, a.nz, a.ps, a.rs, a.relax, a.flag, x, y, z, pad, a.zhalo != 0,
+                                       h.recv[0], h.recv[1], h.send[0], h.send[1]);
+}
+
+template <int DIM, int DT, bool CORR, int EQ = kEqEntropic>
+__global__ __launch_bounds__(256) void k_stream_collide(StepArgs a) {
+    stream_collide<DIM, DT, CORR, EQ, false>(a, HaloArgs{}, (int)blockDim.x, (int)blockDim.y, (int)gridDim.x);
+}
+
+// A z-slab step with the halo exchange fused in.
+template <int DIM, int DT, bool CORR, int EQ = kEqEntropic>
+__global__ __launch_bounds__(256) void k_stream_collide_halo(StepArgs a, HaloArgs h) {
+    stream_collide<DIM, DT, CORR, EQ, true>(a, h, (int)blockDim.x, (int)blockDim.y, (int)gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -192,27 +247,32 @@ __device__ __forceinline__ void store_vec(V v, V *p) {
         *p = v;
 }
 
-template <int DIM, int DT, bool CORR, int NPT, bool ROWWAVE, int FLAGS, int EQ = kEqEntropic>
-__global__ __launch_bounds__(256) void k_stream_collide_vec(StepArgs a) {
+template <int DIM, int DT, bool CORR, int NPT, bool ROWWAVE, int FLAGS, int EQ, bool HALO>
+__device__ __forceinline__ void stream_collide_vec(const StepArgs &a, const HaloArgs &h, int bdx, int bdy, int gdx) {
     using T = store_t<DT>;
     using V = typename VecT<T, NPT>::type;
     constexpr int Q = Lattice<DIM>::Q;
-    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int t = xcd_tile((int)blockIdx.x, gdx);
     const int tx = t % a.tiles_x;
     const int ty = (t / a.tiles_x) % a.tiles_y;
     const int z = t / (a.tiles_x * a.tiles_y);
-    const int y = ty * (int)blockDim.y + (int)threadIdx.y;
+    const int y = ty * bdy + (int)threadIdx.y;
     if (y >= a.ny)  // uniform per wavefront
         return;
     const int nx = a.nx;
     const int64_t ps = a.ps;
     const int lane = (int)threadIdx.x & 63;
-    const int x0 = (tx * (int)blockDim.x + (int)threadIdx.x) * NPT;  // first node of this thread
+    const int x0 = (tx * bdx + (int)threadIdx.x) * NPT;  // first node of this thread
     const T *__restrict__ src = static_cast<const T *>(a.src);
     T *__restrict__ dst = static_cast<T *>(a.dst);
 
     int64_t rowoff[3][3];
     source_rows<DIM>(y, z, a.ny, a.nz, a.rs, rowoff, a.zhalo != 0);
+    // fused z-slab step: the face planes' entering runs come from the packed
+    // buffers (wavefront-uniform choice)
+    const int ys[3] = {y + 1 == a.ny ? 0 : y + 1, y, y == 0 ? a.ny - 1 : y - 1};  // y - c_y
+    const T *from_lo = HALO && DIM == 3 && z == 0 ? static_cast<const T *>(h.recv[0]) : nullptr;
+    const T *from_hi = HALO && DIM == 3 && z == a.nz - 1 ? static_cast<const T *>(h.recv[1]) : nullptr;
     // neighbours of the run at the wavefront's ends (periodic in x)
     const int x_left = x0 == 0 ? nx - 1 : x0 - 1;
     const int x_right = x0 + NPT == nx ? 0 : x0 + NPT;
@@ -225,7 +285,9 @@ __global__ __launch_bounds__(256) void k_stream_collide_vec(StepArgs a) {
 #pragma unroll
             for (int cx = 0; cx < 3; ++cx) {
                 const int i = cx + 3 * cy + 9 * cz;
-                const T *__restrict__ run = src + rowoff[cz][cy] + i * ps;
+                const T *__restrict__ run = HALO && cz == 2 && from_lo   ? from_lo + packed_run(ys[cy], i - 18, nx)
+                                            : HALO && cz == 0 && from_hi ? from_hi + packed_run(ys[cy], i, nx)
+                                                                         : src + rowoff[cz][cy] + i * ps;
                 const V v = load_vec<V, FLAGS>(reinterpret_cast<const V *>(run + x0));
                 if (cx == 1) {  // c_x = 0: aligned
 #pragma unroll
@@ -273,6 +335,41 @@ __global__ __launch_bounds__(256) void k_stream_collide_vec(StepArgs a) {
             v[k] = g[i][k];
         store_vec<V, FLAGS>(v, reinterpret_cast<V *>(dst + self + i * ps));
     }
+    if (HALO && DIM == 3 && z == 0 && h.send[0]) {  // leaving across the lower face: i = 0..8
+        T *out = static_cast<T *>(h.send[0]);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            V v;
+#pragma unroll
+            for (int k = 0; k < NPT; ++k)
+                v[k] = g[i][k];
+            store_vec<V, FLAGS>(v, reinterpret_cast<V *>(out + packed_run(y, i, nx) + x0));
+        }
+    }
+    if (HALO && DIM == 3 && z == a.nz - 1 && h.send[1]) {  // leaving across the upper face: i = 18..26
+        T *out = static_cast<T *>(h.send[1]);
+#pragma unroll
+        for (int i = 18; i < Q; ++i) {
+            V v;
+#pragma unroll
+            for (int k = 0; k < NPT; ++k)
+                v[k] = g[i][k];
+            store_vec<V, FLAGS>(v, reinterpret_cast<V *>(out + packed_run(y, i - 18, nx) + x0));
+        }
+    }
+}
+
+template <int DIM, int DT, bool CORR, int NPT, bool ROWWAVE, int FLAGS, int EQ = kEqEntropic>
+__global__ __launch_bounds__(256) void k_stream_collide_vec(StepArgs a) {
+    stream_collide_vec<DIM, DT, CORR, NPT, ROWWAVE, FLAGS, EQ, false>(a, HaloArgs{}, (int)blockDim.x, (int)blockDim.y,
+                                                                      (int)gridDim.x);
+}
+
+// A z-slab step with the halo exchange fused in.
+template <int DIM, int DT, bool CORR, int NPT, bool ROWWAVE, int FLAGS, int EQ = kEqEntropic>
+__global__ __launch_bounds__(256) void k_stream_collide_vec_halo(StepArgs a, HaloArgs h) {
+    stream_collide_vec<DIM, DT, CORR, NPT, ROWWAVE, FLAGS, EQ, true>(a, h, (int)blockDim.x, (int)blockDim.y,
+                                                                     (int)gridDim.x);
 }
 
 // Zero `count` 32-bit words (a kernel rather than a memset, so that the call

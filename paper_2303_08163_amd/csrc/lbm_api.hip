@@ -305,6 +305,38 @@ static StepFn step_kernel(const Layout &L, int dtype, bool corr) {
     }
 }
 
+// Fused-halo z-slab steps (D3Q27): FP64 or FP32-deviation storage, one node
+// per thread or the default vector width, with the default cache hints
+// (results never depend on the hints).  lbm_step_halo refuses the rest.
+static bool halo_supported(const Layout &L, int dtype) {
+    if (L.dim != 3 || (dtype != kF64 && dtype != kDevF64))
+        return false;
+    return L.npt == 1 || L.npt == (dtype == kF64 ? 2 : 4);
+}
+using HaloStepFn = void (*)(StepArgs, HaloArgs);
+template <int DT, bool CORR, int EQ>
+static HaloStepFn halo_kernel_eq(const Layout &L) {
+    constexpr int NPT = DT == kF64 ? 2 : 4;
+    constexpr int FL = DT == kF64 ? kNtStore : kNtStore | kNtLoad;
+    if (L.npt == 1)
+        return k_stream_collide_halo<3, DT, CORR, EQ>;
+    return L.rowwave ? k_stream_collide_vec_halo<3, DT, CORR, NPT, true, FL, EQ>
+                     : k_stream_collide_vec_halo<3, DT, CORR, NPT, false, FL, EQ>;
+}
+template <int DT, bool CORR>
+static HaloStepFn halo_kernel_for(const Layout &L) {
+    if (L.eq == LBM_EQ_POLY2)
+        return halo_kernel_eq<DT, CORR, kEqPoly2>(L);
+    if (L.eq == LBM_EQ_PRODUCT)
+        return halo_kernel_eq<DT, CORR, kEqProduct>(L);
+    return halo_kernel_eq<DT, CORR, kEqEntropic>(L);
+}
+static HaloStepFn halo_kernel(const Layout &L, int dtype, bool corr) {
+    if (dtype == kF64)
+        return corr ? halo_kernel_for<kF64, true>(L) : halo_kernel_for<kF64, false>(L);
+    return corr ? halo_kernel_for<kDevF64, true>(L) : halo_kernel_for<kDevF64, false>(L);
+}
+
 using InitFn = void (*)(InitArgs);
 template <int DIM, bool DEV>
 static InitFn init_kernel(int eq) {
@@ -315,9 +347,17 @@ static InitFn init_kernel(int eq) {
     return k_init<DIM, DEV, kEqEntropic>;
 }
 
-int launch_step(const Layout &L, const StepArgs &args, int dtype, bool corr, hipStream_t s, int nz) {
+int launch_step(const Layout &L, const StepArgs &args, int dtype, bool corr, hipStream_t s, int nz,
+                const HaloArgs *halo) {
     dim3 block(L.block_x, L.block_y, 1);
     dim3 grid((unsigned)(args.tiles_x * args.tiles_y * nz));
+    if (halo) {
+        hipLaunchKernelGGL(halo_kernel(L, dtype, corr), grid, block, 0, s, args, *halo);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return hip_fail(e, "stream-collide launch");
+        return LBM_OK;
+    }
     StepFn fn = L.dim == 1   ? step_kernel<1>(L, dtype, corr)
                 : L.dim == 2 ? step_kernel<2>(L, dtype, corr)
                              : step_kernel<3>(L, dtype, corr);
@@ -582,12 +622,54 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
     for (int64_t s = 0; s < nsteps; ++s) {
         StepArgs a{d.buf[d.cur], d.buf[d.cur ^ 1], (int)d.cfg.nx, (int)d.cfg.ny, (int)d.cfg.nz, tiles_x, tiles_y,
                    d.L.ps, d.L.rs, d.relax, d.flag, d.L.zhalo ? 1 : 0};
-        int rc = launch_step(d.L, a, d.cfg.dtype, corr, h->stream, (int)d.cfg.nz);
+        int rc = launch_step(d.L, a, d.cfg.dtype, corr, h->stream, (int)d.cfg.nz, nullptr);
         if (rc != LBM_OK)
             return rc;
         d.cur ^= 1;
         d.steps++;
     }
+    return LBM_OK;
+}
+
+int lbm_step_halo(lbm_handle *h, const void *recv_lower, const void *recv_upper, void *send_lower,
+                  void *send_upper) {
+    if (!h || !recv_lower || !recv_upper || !send_lower || !send_upper) {
+        set_error("NULL handle or halo buffer");
+        return LBM_EINVAL;
+    }
+    DomainState &d = h->d;
+    if (!d.L.zhalo) {
+        set_error("the domain is not a z-slab (z_halo = 0)");
+        return LBM_EINVAL;
+    }
+    if (!halo_supported(d.L, d.cfg.dtype)) {
+        set_error("fused halo steps take FP64 or FP32_DEV storage and one node per thread or the default "
+                  "vector width");
+        return LBM_EINVAL;
+    }
+    const void *recv[2] = {recv_lower, recv_upper};
+    const void *send[2] = {send_lower, send_upper};
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            if (recv[a] == send[b]) {
+                set_error("a receive buffer is also a send buffer");
+                return LBM_EINVAL;
+            }
+    if (send_lower == send_upper) {
+        set_error("the two send buffers are the same");
+        return LBM_EINVAL;
+    }
+    const bool corr = d.cfg.bulk_correction != 0;
+    const int tiles_x = (int)((d.cfg.nx + (int64_t)d.L.block_x * d.L.npt - 1) / ((int64_t)d.L.block_x * d.L.npt));
+    const int tiles_y = (int)((d.cfg.ny + d.L.block_y - 1) / d.L.block_y);
+    StepArgs a{d.buf[d.cur], d.buf[d.cur ^ 1], (int)d.cfg.nx, (int)d.cfg.ny, (int)d.cfg.nz, tiles_x, tiles_y,
+               d.L.ps, d.L.rs, d.relax, d.flag, 1};
+    const HaloArgs ha{{recv_lower, recv_upper}, {send_lower, send_upper}};
+    int rc = launch_step(d.L, a, d.cfg.dtype, corr, h->stream, (int)d.cfg.nz, &ha);
+    if (rc != LBM_OK)
+        return rc;
+    d.cur ^= 1;
+    d.steps++;
     return LBM_OK;
 }
 

@@ -47,7 +47,8 @@ struct DomainState {
 void set_error(const char *msg);
 int hip_fail(hipError_t e, const char *what);
 int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out);
-int launch_step(const Layout &L, const StepArgs &args, int dtype, bool corr, hipStream_t s, int nz);
+int launch_step(const Layout &L, const StepArgs &args, int dtype, bool corr, hipStream_t s, int nz,
+                const HaloArgs *halo);
 
 // Bind a domain to its workspace and enqueue f = f^eq(rho, u) plus the flag
 // clear; the caller synchronises and reads the flag (domain_read_flag).

@@ -101,7 +101,8 @@ EXPORTS = ("lbm_workspace_bytes", "lbm_workspace_bytes_tuned", "lbm_create", "lb
            "lbm_last_error", "lbm_version", "lbm_pool_table_bytes", "lbm_pool_slot_bytes", "lbm_pool_create",
            "lbm_pool_admit", "lbm_pool_run", "lbm_pool_poll", "lbm_pool_moments", "lbm_pool_get_populations",
            "lbm_pool_release", "lbm_pool_stats_get", "lbm_pool_slot_info", "lbm_pool_destroy",
-           "lbm_vn_spectra", "lbm_vn_max_radius", "lbm_halo_bytes", "lbm_halo_pack", "lbm_halo_unpack")
+           "lbm_vn_spectra", "lbm_vn_max_radius", "lbm_halo_bytes", "lbm_halo_pack", "lbm_halo_unpack",
+           "lbm_step_halo")
 
 
 def load_library(path: str = LIB_PATH):
@@ -134,6 +135,7 @@ def load_library(path: str = LIB_PATH):
         "lbm_halo_bytes": (sz, [cfgp]),
         "lbm_halo_pack": (ctypes.c_int, [vp, vp, vp]),
         "lbm_halo_unpack": (ctypes.c_int, [vp, vp, vp]),
+        "lbm_step_halo": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "lbm_vn_spectra": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, i64, vp, vp, vp, vp,
                                           vp]),
         "lbm_vn_max_radius": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, i64,
@@ -244,6 +246,10 @@ def lbm_halo_pack(h, lower: int | None, upper: int | None) -> None:
 
 def lbm_halo_unpack(h, lower: int | None, upper: int | None) -> None:
     _check(load_library().lbm_halo_unpack(h, lower, upper), "lbm_halo_unpack")
+
+
+def lbm_step_halo(h, recv_lower: int, recv_upper: int, send_lower: int, send_upper: int) -> None:
+    _check(load_library().lbm_step_halo(h, recv_lower, recv_upper, send_lower, send_upper), "lbm_step_halo")
 
 
 def lbm_energy(h, U, rho_ref: float, out: int) -> None:
@@ -417,6 +423,14 @@ class Domain:
 
     def step(self, nsteps: int) -> None:
         lbm_step(self.handle, nsteps)
+
+    def step_halo(self, recv_lower, recv_upper, send_lower, send_upper) -> None:
+        """One z-slab step with the halo exchange fused into the kernel: reads
+        the entering populations from recv_lower / recv_upper (the neighbours'
+        outgoing faces) and writes the leaving ones to send_lower /
+        send_upper (CUDA tensors of halo_bytes() bytes each)."""
+        lbm_step_halo(self.handle, recv_lower.data_ptr(), recv_upper.data_ptr(), send_lower.data_ptr(),
+                      send_upper.data_ptr())
 
     def halo_bytes(self) -> int:
         """Bytes of one packed face of a z-slab (0 for a periodic domain)."""

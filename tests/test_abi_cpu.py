@@ -253,6 +253,7 @@ def test_slab_configs(lbm):
     lib = lbm.load_library()
     assert lib.lbm_halo_pack(None, 256, 512) == lbm.LBM_EINVAL
     assert lib.lbm_halo_unpack(None, 256, None) == lbm.LBM_EINVAL
+    assert lib.lbm_step_halo(None, 256, 512, 768, 1024) == lbm.LBM_EINVAL
 
 
 def test_c_abi_demo_compiles_and_links(tmp_path):
