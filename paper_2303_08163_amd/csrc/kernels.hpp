@@ -25,6 +25,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "node.hpp"
 
 namespace lbm {
@@ -177,12 +179,23 @@ __device__ __forceinline__ bool in_padding(int64_t ps, int64_t rs, int x) {
 // workgroups of blockDim.x * blockDim.y threads, one node per thread.
 // (The launch dimensions come from the kernel: read there, the workgroup size
 // is known to be uniform, which spares a load per thread.)
+//
+// Plane of tile-plane p: in a fused z-slab step the two face planes, which
+// also write the send buffers, go first (p = 0 -> plane 0, p = 1 -> plane
+// nz - 1), so that their extra stores overlap the interior planes rather than
+// trailing the grid, and the sends are complete early.
+template <bool HALO>
+__device__ __forceinline__ int plane_of(int p, int nz) {
+    if (!HALO || nz < 2)
+        return p;
+    return p == 0 ? 0 : p == 1 ? nz - 1 : p - 1;
+}
 template <int DIM, int DT, bool CORR, int EQ, bool HALO>
 __device__ __forceinline__ void stream_collide(const StepArgs &a, const HaloArgs &h, int bdx, int bdy, int gdx) {
     const int t = xcd_tile((int)blockIdx.x, gdx);
     const int tx = t % a.tiles_x;
     const int ty = (t / a.tiles_x) % a.tiles_y;
-    const int z = t / (a.tiles_x * a.tiles_y);
+    const int z = plane_of<HALO>(t / (a.tiles_x * a.tiles_y), a.nz);
     const int x = tx * bdx + (int)threadIdx.x;
     const int y = ty * bdy + (int)threadIdx.y;
     const bool pad = x >= a.nx;
@@ -247,6 +260,36 @@ __device__ __forceinline__ void store_vec(V v, V *p) {
         *p = v;
 }
 
+// One population run of the vector step: an aligned NPT-wide load and, for the
+// x-shifted populations (cx = 0: c_x = -1, cx = 2: c_x = +1), the element from
+// the neighbouring lane or, at the wavefront's ends, a single-lane load.
+template <typename T, typename V, int NPT, bool ROWWAVE, int FLAGS>
+__device__ __forceinline__ void pull_run(const T *__restrict__ run, int x0, int lane, int x_left, int x_right, int cx,
+                                         T (&gi)[NPT]) {
+    const V v = load_vec<V, FLAGS>(reinterpret_cast<const V *>(run + x0));
+    if (cx == 1) {
+#pragma unroll
+        for (int k = 0; k < NPT; ++k)
+            gi[k] = v[k];
+    } else if (cx == 2) {
+        T left = __shfl(v[NPT - 1], (lane + 63) & 63, 64);
+        if (!ROWWAVE && lane == 0)
+            left = run[x_left];
+        gi[0] = left;
+#pragma unroll
+        for (int k = 1; k < NPT; ++k)
+            gi[k] = v[k - 1];
+    } else {
+        T right = __shfl(v[0], (lane + 1) & 63, 64);
+        if (!ROWWAVE && lane == 63)
+            right = run[x_right];
+#pragma unroll
+        for (int k = 0; k < NPT - 1; ++k)
+            gi[k] = v[k + 1];
+        gi[NPT - 1] = right;
+    }
+}
+
 template <int DIM, int DT, bool CORR, int NPT, bool ROWWAVE, int FLAGS, int EQ, bool HALO>
 __device__ __forceinline__ void stream_collide_vec(const StepArgs &a, const HaloArgs &h, int bdx, int bdy, int gdx) {
     using T = store_t<DT>;
@@ -255,7 +298,7 @@ __device__ __forceinline__ void stream_collide_vec(const StepArgs &a, const Halo
     const int t = xcd_tile((int)blockIdx.x, gdx);
     const int tx = t % a.tiles_x;
     const int ty = (t / a.tiles_x) % a.tiles_y;
-    const int z = t / (a.tiles_x * a.tiles_y);
+    const int z = plane_of<HALO>(t / (a.tiles_x * a.tiles_y), a.nz);
     const int y = ty * bdy + (int)threadIdx.y;
     if (y >= a.ny)  // uniform per wavefront
         return;
@@ -278,39 +321,64 @@ __device__ __forceinline__ void stream_collide_vec(const StepArgs &a, const Halo
     const int x_right = x0 + NPT == nx ? 0 : x0 + NPT;
 
     T g[Q][NPT];  // g[i][k]: value population i pulls into node x0 + k
+    if constexpr (HALO) {
+        // fused z-slab step: `face` selects, per wavefront, the variant that
+        // reads the face planes' entering runs from the packed buffers, so
+        // that rows inside the slab run the plain loads
+        auto pull = [&](auto face) {
+            constexpr bool F = decltype(face)::value;
 #pragma unroll
-    for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
+            for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
 #pragma unroll
-        for (int cy = 0; cy < Lattice<DIM>::NY; ++cy)
+                for (int cy = 0; cy < Lattice<DIM>::NY; ++cy)
 #pragma unroll
-            for (int cx = 0; cx < 3; ++cx) {
-                const int i = cx + 3 * cy + 9 * cz;
-                const T *__restrict__ run = HALO && cz == 2 && from_lo   ? from_lo + packed_run(ys[cy], i - 18, nx)
-                                            : HALO && cz == 0 && from_hi ? from_hi + packed_run(ys[cy], i, nx)
-                                                                         : src + rowoff[cz][cy] + i * ps;
-                const V v = load_vec<V, FLAGS>(reinterpret_cast<const V *>(run + x0));
-                if (cx == 1) {  // c_x = 0: aligned
+                    for (int cx = 0; cx < 3; ++cx) {
+                        const int i = cx + 3 * cy + 9 * cz;
+                        const T *__restrict__ run = F && cz == 2 && from_lo   ? from_lo + packed_run(ys[cy], i - 18, nx)
+                                                    : F && cz == 0 && from_hi ? from_hi + packed_run(ys[cy], i, nx)
+                                                                              : src + rowoff[cz][cy] + i * ps;
+                        pull_run<T, V, NPT, ROWWAVE, FLAGS>(run, x0, lane, x_left, x_right, cx, g[i]);
+                    }
+        };
+        if (from_lo || from_hi)  // uniform per wavefront
+            pull(std::true_type{});
+        else
+            pull(std::false_type{});
+    } else {
+        // the plain step keeps its own loop (the generic lambda above compiles
+        // to a longer instruction stream)
 #pragma unroll
-                    for (int k = 0; k < NPT; ++k)
-                        g[i][k] = v[k];
-                } else if (cx == 2) {  // c_x = +1 pulls from x - 1
-                    T left = __shfl(v[NPT - 1], (lane + 63) & 63, 64);
-                    if (!ROWWAVE && lane == 0)
-                        left = run[x_left];
-                    g[i][0] = left;
+        for (int cz = 0; cz < Lattice<DIM>::NZ; ++cz)
 #pragma unroll
-                    for (int k = 1; k < NPT; ++k)
-                        g[i][k] = v[k - 1];
-                } else {  // c_x = -1 pulls from x + 1
-                    T right = __shfl(v[0], (lane + 1) & 63, 64);
-                    if (!ROWWAVE && lane == 63)
-                        right = run[x_right];
+            for (int cy = 0; cy < Lattice<DIM>::NY; ++cy)
 #pragma unroll
-                    for (int k = 0; k < NPT - 1; ++k)
-                        g[i][k] = v[k + 1];
-                    g[i][NPT - 1] = right;
+                for (int cx = 0; cx < 3; ++cx) {
+                    const int i = cx + 3 * cy + 9 * cz;
+                    const T *__restrict__ run = src + rowoff[cz][cy] + i * ps;
+                    const V v = load_vec<V, FLAGS>(reinterpret_cast<const V *>(run + x0));
+                    if (cx == 1) {  // c_x = 0: aligned
+#pragma unroll
+                        for (int k = 0; k < NPT; ++k)
+                            g[i][k] = v[k];
+                    } else if (cx == 2) {  // c_x = +1 pulls from x - 1
+                        T left = __shfl(v[NPT - 1], (lane + 63) & 63, 64);
+                        if (!ROWWAVE && lane == 0)
+                            left = run[x_left];
+                        g[i][0] = left;
+#pragma unroll
+                        for (int k = 1; k < NPT; ++k)
+                            g[i][k] = v[k - 1];
+                    } else {  // c_x = -1 pulls from x + 1
+                        T right = __shfl(v[0], (lane + 1) & 63, 64);
+                        if (!ROWWAVE && lane == 63)
+                            right = run[x_right];
+#pragma unroll
+                        for (int k = 0; k < NPT - 1; ++k)
+                            g[i][k] = v[k + 1];
+                        g[i][NPT - 1] = right;
+                    }
                 }
-            }
+    }
 
     bool bad = false;
 #pragma unroll

@@ -7,7 +7,8 @@
  *   2. argument errors (LBM_EINVAL) on the paths a C caller can take;
  *   3. a pool of two D2Q9 domains of different sizes run to completion;
  *   4. a z-slab that is its own neighbour equals the periodic domain of the
- *      same planes, bitwise.
+ *      same planes, bitwise, with the halo exchange through pack/unpack and
+ *      with it fused into the step (lbm_step_halo).
  * Prints "abi_demo ok" and returns 0 on success; prints the failed check and
  * returns 1 otherwise. */
 #include <hip/hip_runtime_api.h>
@@ -202,6 +203,23 @@ static int slab_self_ring(void) {
         CHECK(lbm_halo_pack(b, lo, hi) == LBM_OK && lbm_halo_unpack(b, hi, lo) == LBM_OK, "exchange");
     }
     CHECK(lbm_step(a, 6) == LBM_OK, "periodic steps");
+    /* a second slab stepped with the exchange fused in: two send sets, each
+       step reads the set the previous step wrote */
+    void *ws3, *fs[2][2];
+    HIPCHECK(hipMalloc(&ws3, wsl));
+    for (int p = 0; p < 2; ++p)
+        for (int f = 0; f < 2; ++f)
+            HIPCHECK(hipMalloc(&fs[p][f], hb));
+    lbm_handle *c = NULL;
+    CHECK(lbm_create(&slab, ws3, wsl, rho_d, u_d, NULL, &c) == LBM_OK, "create fused slab");
+    if (!c)
+        return 1;
+    CHECK(lbm_halo_pack(c, fs[1][0], fs[1][1]) == LBM_OK, "seed the fused exchange");
+    for (int s = 0; s < 6; ++s) {
+        const int p = s % 2;
+        CHECK(lbm_step_halo(c, fs[1 - p][1], fs[1 - p][0], fs[p][0], fs[p][1]) == LBM_OK, "fused step");
+    }
+    CHECK(lbm_step_halo(c, fs[0][1], fs[0][0], fs[0][1], fs[1][1]) == LBM_EINVAL, "fused step rejects aliasing");
     double *fa, *fb;
     HIPCHECK(hipMalloc((void **)&fa, sizeof(double) * 27 * (size_t)n));
     HIPCHECK(hipMalloc((void **)&fb, sizeof(double) * 27 * (size_t)n));
@@ -212,6 +230,14 @@ static int slab_self_ring(void) {
     HIPCHECK(hipMemcpy(ha, fa, sizeof(double) * 27 * (size_t)n, hipMemcpyDeviceToHost));
     HIPCHECK(hipMemcpy(hb_, fb, sizeof(double) * 27 * (size_t)n, hipMemcpyDeviceToHost));
     CHECK(memcmp(ha, hb_, sizeof(double) * 27 * (size_t)n) == 0, "slab self-ring equals periodic domain bitwise");
+    CHECK(lbm_get_populations(c, fb) == LBM_OK, "fused populations");
+    HIPCHECK(hipMemcpy(hb_, fb, sizeof(double) * 27 * (size_t)n, hipMemcpyDeviceToHost));
+    CHECK(memcmp(ha, hb_, sizeof(double) * 27 * (size_t)n) == 0, "fused self-ring equals periodic domain bitwise");
+    CHECK(lbm_destroy(c) == LBM_OK, "destroy fused slab");
+    HIPCHECK(hipFree(ws3));
+    for (int p = 0; p < 2; ++p)
+        for (int f = 0; f < 2; ++f)
+            HIPCHECK(hipFree(fs[p][f]));
     free(ha);
     free(hb_);
     CHECK(lbm_destroy(a) == LBM_OK && lbm_destroy(b) == LBM_OK, "destroy");
