@@ -81,6 +81,9 @@ CASES = [  # (grid (nz, ny, nx), splits, tau, steps, dtype, corr)
     ((6, 4, 256), [2, 4], 0.51, 5, "fp32_dev", False),   # vector kernel, one wavefront per row
     ((6, 3, 128), [3, 3], 0.58, 4, "fp64", True),        # vector kernel, FP64 pairs
     ((5, 3, 512), [2, 3], 0.52, 3, "fp32_dev", True),    # vector kernel across wavefronts
+    ((3, 1, 1), [1, 1, 1], 0.6, 4, "fp64", False),       # 1 x 1 cross-section, one-plane slabs
+    ((4, 2, 5), [2, 2], 0.55, 5, "fp32_dev", True),      # rows narrower than the 16-element pitch
+    ((4, 3, 300), [3, 1], 0.57, 4, "fp64", True),        # packed runs longer than a workgroup
 ]
 
 
@@ -235,6 +238,8 @@ FUSED_CASES = [  # (grid (nz, ny, nx), splits, tau, steps, dtype, corr, eq)
     ((6, 4, 256), [2, 4], 0.51, 5, "fp32_dev", False, "entropic"),  # vector kernel, one wavefront per row
     ((6, 3, 128), [3, 3], 0.58, 4, "fp64", True, "product"),       # vector kernel, FP64 pairs
     ((5, 3, 512), [2, 3], 0.52, 3, "fp32_dev", True, "entropic"),   # vector kernel across wavefronts
+    ((3, 1, 1), [1, 1, 1], 0.6, 4, "fp64", False, "entropic"),      # 1 x 1 cross-section
+    ((4, 3, 300), [3, 1], 0.57, 4, "fp32_dev", True, "product"),    # ragged rows over several tiles
 ]
 
 
