@@ -150,10 +150,31 @@ __host__ __device__ __forceinline__ void vn_matrix(double tau, const double (&u)
 
 // Unitary Givens rotation G = [[c, s], [-conj(s), c]] (c real) with
 // G (a, b)^T = (r, 0)^T; exactly the identity when b = 0.
+//
+// The rotations form the serial chain of a QR step, so they are computed from
+// the squared norms: two square roots and two divisions instead of three
+// hypot calls and three divisions.  Entries here are O(1) and deflation
+// zeroes any below ulp times its scale, so the squares neither overflow nor
+// underflow; should both underflow anyway, the rescaling form below runs.
 __host__ __device__ __forceinline__ void givens(cplx a, cplx b, double &c, cplx &s) {
     if (b.re == 0.0 && b.im == 0.0) {
         c = 1.0;
         s = {0.0, 0.0};
+        return;
+    }
+    const double na2 = fma(a.re, a.re, a.im * a.im), nb2 = fma(b.re, b.re, b.im * b.im);
+    const double r2 = na2 + nb2;
+    if (r2 > 0.0) {
+        const double inv_r = 1.0 / sqrt(r2);
+        if (na2 == 0.0) {
+            c = 0.0;
+            s = cscale(inv_r, {b.re, -b.im});  // conj(b) / |b|
+            return;
+        }
+        const double na = sqrt(na2);
+        c = na * inv_r;
+        // s = (a / |a|) conj(b) / r
+        s = cscale(inv_r / na, cmul(a, {b.re, -b.im}));
         return;
     }
     const double na = cabs(a), nb = cabs(b);
@@ -290,7 +311,9 @@ __host__ __device__ constexpr double vn_fixed_flops() {
     return h + build + norm;
 }
 __host__ __device__ constexpr double vn_step_flops(int M) {
-    return (M - 1) * (20.0 * M + 62.0) + 4.0 * M + 150.0;
+    // per rotation: applying it to two rows and two columns (20 M) and
+    // forming it from squared norms (20) with the rest of its bookkeeping (46)
+    return (M - 1) * (20.0 * M + 66.0) + 4.0 * M + 150.0;
 }
 
 // Eigenvalues of an upper Hessenberg matrix (overwritten; the diagonal holds
