@@ -152,10 +152,11 @@ __host__ __device__ __forceinline__ void vn_matrix(double tau, const double (&u)
 // G (a, b)^T = (r, 0)^T; exactly the identity when b = 0.
 //
 // The rotations form the serial chain of a QR step, so they are computed from
-// the squared norms: two square roots and two divisions instead of three
-// hypot calls and three divisions.  Entries here are O(1) and deflation
-// zeroes any below ulp times its scale, so the squares neither overflow nor
-// underflow; should both underflow anyway, the rescaling form below runs.
+// the squared norms with one square root and one division in sequence:
+// q = 1 / sqrt(|a|^2 r^2) gives c = |a| / r = |a|^2 q and |s| scale 1 / (|a| r)
+// = q.  Entries here are O(1) and deflation zeroes any below ulp times its
+// scale, so the products neither overflow nor underflow; should they reach
+// the underflow range anyway, the rescaling form below runs.
 __host__ __device__ __forceinline__ void givens(cplx a, cplx b, double &c, cplx &s) {
     if (b.re == 0.0 && b.im == 0.0) {
         c = 1.0;
@@ -164,17 +165,17 @@ __host__ __device__ __forceinline__ void givens(cplx a, cplx b, double &c, cplx 
     }
     const double na2 = fma(a.re, a.re, a.im * a.im), nb2 = fma(b.re, b.re, b.im * b.im);
     const double r2 = na2 + nb2;
-    if (r2 > 0.0) {
-        const double inv_r = 1.0 / sqrt(r2);
-        if (na2 == 0.0) {
-            c = 0.0;
-            s = cscale(inv_r, {b.re, -b.im});  // conj(b) / |b|
-            return;
-        }
-        const double na = sqrt(na2);
-        c = na * inv_r;
-        // s = (a / |a|) conj(b) / r
-        s = cscale(inv_r / na, cmul(a, {b.re, -b.im}));
+    if (na2 == 0.0 && r2 > 1e-300) {
+        c = 0.0;
+        s = cscale(1.0 / sqrt(r2), {b.re, -b.im});  // conj(b) / |b|
+        return;
+    }
+    const double p = na2 * r2;
+    if (p > 1e-300) {
+        const double q = 1.0 / sqrt(p);
+        c = na2 * q;
+        // s = (a / |a|) conj(b) / r = a conj(b) q
+        s = cscale(q, cmul(a, {b.re, -b.im}));
         return;
     }
     const double na = cabs(a), nb = cabs(b);
@@ -312,8 +313,8 @@ __host__ __device__ constexpr double vn_fixed_flops() {
 }
 __host__ __device__ constexpr double vn_step_flops(int M) {
     // per rotation: applying it to two rows and two columns (20 M) and
-    // forming it from squared norms (20) with the rest of its bookkeeping (46)
-    return (M - 1) * (20.0 * M + 66.0) + 4.0 * M + 150.0;
+    // forming it from squared norms (19) with the rest of its bookkeeping (46)
+    return (M - 1) * (20.0 * M + 65.0) + 4.0 * M + 150.0;
 }
 
 // Eigenvalues of an upper Hessenberg matrix (overwritten; the diagonal holds
