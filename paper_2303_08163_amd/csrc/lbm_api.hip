@@ -504,9 +504,21 @@ int domain_energy(DomainState &d, hipStream_t s, const double *U, double rho_ref
 
 using namespace lbm;
 
+// Steps of small domains are bound by the host's launch rate (about 3 us per
+// launch), so long runs replay a captured HIP graph of kGraphSteps launches
+// instead.  kGraphSteps is even: the population buffers are back in place
+// after each replay, so one graph per starting buffer serves every call.  The
+// graph holds the same kernels with the same arguments, so results are
+// bitwise those of plain launches.
+constexpr int kGraphSteps = 32;
+
 struct lbm_handle {
     DomainState d;
     hipStream_t stream;
+    hipStream_t capture = nullptr;            // private stream the graphs are captured on
+    hipGraph_t graph[2] = {nullptr, nullptr};  // by the buffer holding the state at the start
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    bool graphs_off = false;                   // a graph call failed once: plain launches only
 };
 
 // Pack: plane 0's populations with c_z = -1 into `lower`, plane nz - 1's with
@@ -606,6 +618,55 @@ int lbm_create(const lbm_config *cfg, void *workspace, size_t ws_bytes, const do
     return lbm_create_tuned(cfg, nullptr, workspace, ws_bytes, rho, u, stream, out);
 }
 
+// Enqueue one plain step launch with the state in buffer `cur` on stream s.
+static int enqueue_step(lbm_handle *h, int cur, hipStream_t s) {
+    DomainState &d = h->d;
+    const bool corr = d.cfg.bulk_correction != 0;
+    const int tiles_x = (int)((d.cfg.nx + (int64_t)d.L.block_x * d.L.npt - 1) / ((int64_t)d.L.block_x * d.L.npt));
+    const int tiles_y = (int)((d.cfg.ny + d.L.block_y - 1) / d.L.block_y);
+    StepArgs a{d.buf[cur], d.buf[cur ^ 1], (int)d.cfg.nx, (int)d.cfg.ny, (int)d.cfg.nz, tiles_x, tiles_y,
+               d.L.ps, d.L.rs, d.relax, d.flag, d.L.zhalo ? 1 : 0};
+    return launch_step(d.L, a, d.cfg.dtype, corr, s, (int)d.cfg.nz, nullptr);
+}
+
+// The graph of kGraphSteps steps starting from buffer `cur`, captured on first
+// use.  Returns false (and turns graphs off for the handle) if any graph call
+// fails; the caller then launches plainly.
+static bool step_graph(lbm_handle *h, int cur) {
+    if (h->graphs_off)
+        return false;
+    if (h->exec[cur])
+        return true;
+    hipError_t e = hipSuccess;
+    if (!h->capture)
+        e = hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        int rc = LBM_OK;
+        for (int k = 0; k < kGraphSteps && rc == LBM_OK; ++k)
+            rc = enqueue_step(h, cur ^ (k & 1), h->capture);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(h->capture, &g);
+        if (e == hipSuccess && rc == LBM_OK && g) {
+            h->graph[cur] = g;
+            e = hipGraphInstantiate(&h->exec[cur], g, nullptr, nullptr, 0);
+        } else {
+            if (g)
+                hipGraphDestroy(g);
+            if (e == hipSuccess)
+                e = hipErrorUnknown;
+        }
+    }
+    if (e != hipSuccess || !h->exec[cur]) {
+        (void)hipGetLastError();  // leave no sticky error behind for the next call
+        h->exec[cur] = nullptr;
+        h->graphs_off = true;
+        return false;
+    }
+    return true;
+}
+
 int lbm_step(lbm_handle *h, int64_t nsteps) {
     if (!h || nsteps < 0) {
         set_error("NULL handle or negative step count");
@@ -616,13 +677,17 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
         set_error("a z-slab takes one step between halo exchanges");
         return LBM_EINVAL;
     }
-    const bool corr = d.cfg.bulk_correction != 0;
-    const int tiles_x = (int)((d.cfg.nx + (int64_t)d.L.block_x * d.L.npt - 1) / ((int64_t)d.L.block_x * d.L.npt));
-    const int tiles_y = (int)((d.cfg.ny + d.L.block_y - 1) / d.L.block_y);
-    for (int64_t s = 0; s < nsteps; ++s) {
-        StepArgs a{d.buf[d.cur], d.buf[d.cur ^ 1], (int)d.cfg.nx, (int)d.cfg.ny, (int)d.cfg.nz, tiles_x, tiles_y,
-                   d.L.ps, d.L.rs, d.relax, d.flag, d.L.zhalo ? 1 : 0};
-        int rc = launch_step(d.L, a, d.cfg.dtype, corr, h->stream, (int)d.cfg.nz, nullptr);
+    int64_t s = 0;
+    if (nsteps >= 2 * kGraphSteps && step_graph(h, d.cur)) {
+        for (; s + kGraphSteps <= nsteps; s += kGraphSteps) {
+            hipError_t e = hipGraphLaunch(h->exec[d.cur], h->stream);
+            if (e != hipSuccess)
+                return hip_fail(e, "step graph launch");
+            d.steps += kGraphSteps;  // an even count: d.cur is unchanged
+        }
+    }
+    for (; s < nsteps; ++s) {
+        int rc = enqueue_step(h, d.cur, h->stream);
         if (rc != LBM_OK)
             return rc;
         d.cur ^= 1;
@@ -744,6 +809,14 @@ int lbm_destroy(lbm_handle *h) {
     if (!h)
         return LBM_OK;
     hipError_t e = hipStreamSynchronize(h->stream);
+    for (int k = 0; k < 2; ++k) {
+        if (h->exec[k])
+            hipGraphExecDestroy(h->exec[k]);
+        if (h->graph[k])
+            hipGraphDestroy(h->graph[k]);
+    }
+    if (h->capture)
+        hipStreamDestroy(h->capture);
     delete h;
     if (e != hipSuccess)
         return hip_fail(e, "destroy synchronise");
