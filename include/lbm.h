@@ -185,8 +185,7 @@ int lbm_create_tuned(const lbm_config *cfg, const lbm_tuning *tuning, void *work
  * on the handle's stream and return without synchronising.  Runs of 64 steps
  * or more replay a captured HIP graph of 32 launches (the same kernels and
  * arguments, so bitwise the same results) to relieve the host's launch rate;
- * the graph is captured on the handle's first such call.  nsteps = 0 is a
- * no-op.  Errors: LBM_EINVAL (h NULL, nsteps < 0, nsteps > 1 on a z-slab,
+ * the graphs are captured by lbm_create.  nsteps = 0 is a no-op.  Errors: LBM_EINVAL (h NULL, nsteps < 0, nsteps > 1 on a z-slab,
  * which needs a halo exchange between steps); LBM_EDEVICE (launch failure). */
 int lbm_step(lbm_handle *h, int64_t nsteps);
 

@@ -572,6 +572,8 @@ size_t lbm_workspace_bytes_tuned(const lbm_config *cfg, const lbm_tuning *tuning
 
 size_t lbm_workspace_bytes(const lbm_config *cfg) { return lbm_workspace_bytes_tuned(cfg, nullptr); }
 
+static void prepare_step_graphs(lbm_handle *h);
+
 int lbm_create_tuned(const lbm_config *cfg, const lbm_tuning *tuning, void *workspace, size_t ws_bytes,
                      const double *rho, const double *u, void *stream, lbm_handle **out) {
     Layout L;
@@ -609,6 +611,10 @@ int lbm_create_tuned(const lbm_config *cfg, const lbm_tuning *tuning, void *work
         set_error("initial state has a node with rho <= 0 or |u_alpha| >= 1");
         return LBM_EDOMAIN;
     }
+    // capture the step graphs now, so that no later call pays for it
+    if (!L.zhalo) {
+        prepare_step_graphs(h);
+    }
     *out = h;
     return LBM_OK;
 }
@@ -629,9 +635,10 @@ static int enqueue_step(lbm_handle *h, int cur, hipStream_t s) {
     return launch_step(d.L, a, d.cfg.dtype, corr, s, (int)d.cfg.nz, nullptr);
 }
 
-// The graph of kGraphSteps steps starting from buffer `cur`, captured on first
-// use.  Returns false (and turns graphs off for the handle) if any graph call
-// fails; the caller then launches plainly.
+// The graph of kGraphSteps steps starting from buffer `cur` (captured when the
+// handle is created; later calls find it).  Returns false (and turns graphs
+// off for the handle) if any graph call fails; the caller then launches
+// plainly.
 static bool step_graph(lbm_handle *h, int cur) {
     if (h->graphs_off)
         return false;
@@ -665,6 +672,13 @@ static bool step_graph(lbm_handle *h, int cur) {
         return false;
     }
     return true;
+}
+
+// Both graphs (one per starting buffer), captured when the handle is created.
+static void prepare_step_graphs(lbm_handle *h) {
+    for (int cur = 0; cur < 2; ++cur)
+        if (!step_graph(h, cur))
+            return;
 }
 
 int lbm_step(lbm_handle *h, int64_t nsteps) {
