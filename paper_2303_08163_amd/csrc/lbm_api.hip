@@ -674,11 +674,16 @@ static bool step_graph(lbm_handle *h, int cur) {
     return true;
 }
 
-// Both graphs (one per starting buffer), captured when the handle is created.
+// Both graphs (one per starting buffer), captured when the handle is created;
+// the capture stream is released afterwards (a handle keeps no extra stream).
 static void prepare_step_graphs(lbm_handle *h) {
     for (int cur = 0; cur < 2; ++cur)
         if (!step_graph(h, cur))
-            return;
+            break;
+    if (h->capture) {
+        hipStreamDestroy(h->capture);
+        h->capture = nullptr;
+    }
 }
 
 int lbm_step(lbm_handle *h, int64_t nsteps) {
