@@ -260,6 +260,22 @@ int lbm_moments(lbm_handle *h, double *rho, double *u, lbm_diag *diag);
  * pointer to Q * N doubles.  Synchronises the stream. */
 int lbm_get_populations(lbm_handle *h, double *out);
 
+/* Checkpoint and restart: the current state as the library stores it (its
+ * private format: the storage type, layout and padding of the handle's
+ * configuration and tuning), so that a restart is bit-exact for every storage
+ * type.  lbm_state_bytes: the size of a saved state (0 for h NULL).
+ * lbm_save_state copies the state into dst; lbm_load_state replaces the
+ * handle's state with src, sets its step count to `steps` and clears the
+ * domain flag (save a state only while lbm_moments reports no domain error).  dst / src are device pointers owned by the caller, of
+ * exactly lbm_state_bytes(h) bytes; a state is valid only for a handle with
+ * the same configuration and tuning.  Enqueued on the handle's stream without
+ * synchronising.  Errors: LBM_EINVAL (h or the buffer NULL, bytes not
+ * lbm_state_bytes(h), steps < 0); LBM_EDEVICE.  (lbm_get_populations gives
+ * the portable, canonical FP64 form.) */
+size_t lbm_state_bytes(const lbm_handle *h);
+int lbm_save_state(lbm_handle *h, void *dst, size_t bytes);
+int lbm_load_state(lbm_handle *h, const void *src, size_t bytes, int64_t steps);
+
 /* Quadratic acoustic energy of the current state about a reference state
  * (rho_ref, U), summed over the nodes:
  *     E = sum_r [ rho_ref |u - U|^2 / 2 + c_s^2 (rho - rho_ref)^2 / (2 rho_ref) ],

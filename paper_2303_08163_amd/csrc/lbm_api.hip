@@ -816,6 +816,43 @@ int lbm_energy(lbm_handle *h, const double *U, double rho_ref, double *out) {
     return domain_energy(h->d, h->stream, U, rho_ref, out);
 }
 
+// Checkpoint / restart: the stored population buffer holding the current
+// state (whole, including row padding and a z-slab's halo planes), copied
+// device to device on the handle's stream.
+size_t lbm_state_bytes(const lbm_handle *h) { return h ? h->d.L.buf_bytes : 0; }
+
+static char *state_base(const DomainState &d) {
+    const size_t halo_bytes = d.L.zhalo ? (size_t)d.L.plane * d.L.elem : 0;
+    return static_cast<char *>(d.buf[d.cur]) - halo_bytes;
+}
+
+int lbm_save_state(lbm_handle *h, void *dst, size_t bytes) {
+    if (!h || !dst || bytes != h->d.L.buf_bytes) {
+        set_error("NULL handle or buffer, or bytes != lbm_state_bytes()");
+        return LBM_EINVAL;
+    }
+    hipError_t e = hipMemcpyAsync(dst, state_base(h->d), bytes, hipMemcpyDeviceToDevice, h->stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "state save");
+    return LBM_OK;
+}
+
+int lbm_load_state(lbm_handle *h, const void *src, size_t bytes, int64_t steps) {
+    if (!h || !src || bytes != h->d.L.buf_bytes || steps < 0) {
+        set_error("NULL handle or buffer, bytes != lbm_state_bytes(), or negative step count");
+        return LBM_EINVAL;
+    }
+    hipError_t e = hipMemcpyAsync(state_base(h->d), src, bytes, hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(64), 0, h->stream, h->d.flag, 64);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess)
+        return hip_fail(e, "state load");
+    h->d.steps = steps;
+    return LBM_OK;
+}
+
 int lbm_get_populations(lbm_handle *h, double *out) {
     if (!h || !out) {
         set_error("NULL handle or output");

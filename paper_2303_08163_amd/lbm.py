@@ -102,7 +102,7 @@ EXPORTS = ("lbm_workspace_bytes", "lbm_workspace_bytes_tuned", "lbm_create", "lb
            "lbm_pool_admit", "lbm_pool_run", "lbm_pool_poll", "lbm_pool_moments", "lbm_pool_get_populations",
            "lbm_pool_release", "lbm_pool_stats_get", "lbm_pool_slot_info", "lbm_pool_destroy",
            "lbm_vn_spectra", "lbm_vn_max_radius", "lbm_halo_bytes", "lbm_halo_pack", "lbm_halo_unpack",
-           "lbm_step_halo")
+           "lbm_step_halo", "lbm_state_bytes", "lbm_save_state", "lbm_load_state")
 
 
 def load_library(path: str = LIB_PATH):
@@ -136,6 +136,9 @@ def load_library(path: str = LIB_PATH):
         "lbm_halo_pack": (ctypes.c_int, [vp, vp, vp]),
         "lbm_halo_unpack": (ctypes.c_int, [vp, vp, vp]),
         "lbm_step_halo": (ctypes.c_int, [vp, vp, vp, vp, vp]),
+        "lbm_state_bytes": (sz, [vp]),
+        "lbm_save_state": (ctypes.c_int, [vp, vp, sz]),
+        "lbm_load_state": (ctypes.c_int, [vp, vp, sz, i64]),
         "lbm_vn_spectra": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, i64, vp, vp, vp, vp,
                                           vp]),
         "lbm_vn_max_radius": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, i64,
@@ -234,6 +237,18 @@ def lbm_moments(h, rho: int | None, u: int | None, raise_on_domain: bool = True)
 
 def lbm_get_populations(h, out: int) -> None:
     _check(load_library().lbm_get_populations(h, out), "lbm_get_populations")
+
+
+def lbm_state_bytes(h) -> int:
+    return int(load_library().lbm_state_bytes(h))
+
+
+def lbm_save_state(h, dst: int, nbytes: int) -> None:
+    _check(load_library().lbm_save_state(h, dst, nbytes), "lbm_save_state")
+
+
+def lbm_load_state(h, src: int, nbytes: int, steps: int) -> None:
+    _check(load_library().lbm_load_state(h, src, nbytes, steps), "lbm_load_state")
 
 
 def lbm_halo_bytes(cfg: lbm_config) -> int:
@@ -431,6 +446,22 @@ class Domain:
         send_upper (CUDA tensors of halo_bytes() bytes each)."""
         lbm_step_halo(self.handle, recv_lower.data_ptr(), recv_upper.data_ptr(), send_lower.data_ptr(),
                       send_upper.data_ptr())
+
+    def save_state(self):
+        """Checkpoint: a CUDA uint8 tensor holding the stored state (bit-exact),
+        and the step count.  Raises LBMDomainError if the domain flag is set."""
+        import torch
+        n = lbm_state_bytes(self.handle)
+        buf = torch.empty(n, dtype=torch.uint8, device=self.device)
+        torch.cuda.current_stream(self.device).synchronize()  # buf comes from torch's current stream
+        lbm_save_state(self.handle, buf.data_ptr(), n)
+        steps = self.moments(fields=False)[2]["steps"]  # synchronises
+        return buf, steps
+
+    def load_state(self, buf, steps: int) -> None:
+        """Restart from a save_state() checkpoint of a domain with the same
+        configuration and tuning."""
+        lbm_load_state(self.handle, buf.data_ptr(), buf.numel() * buf.element_size(), int(steps))
 
     def halo_bytes(self) -> int:
         """Bytes of one packed face of a z-slab (0 for a periodic domain)."""

@@ -172,6 +172,9 @@ def test_create_argument_checks_precede_gpu_work(lbm):
     assert lib.lbm_step(None, 1) == lbm.LBM_EINVAL
     assert lib.lbm_moments(None, None, None, None) == lbm.LBM_EINVAL
     assert lib.lbm_get_populations(None, None) == lbm.LBM_EINVAL
+    assert lib.lbm_state_bytes(None) == 0
+    assert lib.lbm_save_state(None, 256, 0) == lbm.LBM_EINVAL
+    assert lib.lbm_load_state(None, 256, 0, 0) == lbm.LBM_EINVAL
     assert lib.lbm_energy(None, None, 1.0, 256) == lbm.LBM_EINVAL
     assert lib.lbm_destroy(None) == lbm.LBM_OK
     assert b"NULL" in lib.lbm_last_error()
