@@ -266,9 +266,10 @@ int lbm_get_populations(lbm_handle *h, double *out);
  * type.  lbm_state_bytes: the size of a saved state (0 for h NULL).
  * lbm_save_state copies the state into dst; lbm_load_state replaces the
  * handle's state with src, sets its step count to `steps` and clears the
- * domain flag (save a state only while lbm_moments reports no domain error).  dst / src are device pointers owned by the caller, of
- * exactly lbm_state_bytes(h) bytes; a state is valid only for a handle with
- * the same configuration and tuning.  Enqueued on the handle's stream without
+ * domain flag (save a state only while lbm_moments reports no domain error).
+ * dst / src are device pointers owned by the caller, of exactly
+ * lbm_state_bytes(h) bytes; a state is valid only for a handle with the same
+ * configuration and tuning.  Enqueued on the handle's stream without
  * synchronising.  Errors: LBM_EINVAL (h or the buffer NULL, bytes not
  * lbm_state_bytes(h), steps < 0); LBM_EDEVICE.  (lbm_get_populations gives
  * the portable, canonical FP64 form.) */
