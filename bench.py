@@ -325,7 +325,8 @@ def bench_oracle_timing(budget_s: float = 6.0) -> dict:
 def bench_variants(steps: int = 100, warmup: int = 10, steps_1d: int = 200, warmup_1d: int = 20) -> dict:
     """Throughput of the other equilibria and of the correction on the headline
     grid (D3Q27 256^3 Taylor-Green, FP32 deviation storage, default vector
-    kernel), and of a D1Q3 row of 2^27 nodes (more steps: one takes ~0.6 ms)."""
+    kernel), of a D1Q3 row of 2^27 nodes (more steps: one takes ~0.6 ms), and
+    of the D2Q9 4096^2 double shear layer with two or one steps per launch."""
     import numpy as np
     import torch
 
@@ -368,6 +369,16 @@ def bench_variants(steps: int = 100, warmup: int = 10, steps_1d: int = 200, warm
         dom = lbm.Domain(r1, u1, 0.6, dtype=dt, bulk_correction=True, stream=stream)
         out[f"d1q3_2^27_{dt}_corrected"] = timed(dom, n1, 2 * 3 * s, steps_1d, warmup_1d)
         dom.close()
+    del r1, u1
+    # D2Q9 4096^2 double shear layer: the default two steps per launch against one.
+    # gbs / frac count 2 Q s bytes per node update (what one step per launch moves);
+    # two steps per launch move about half of that.
+    r2, u2 = workloads.double_shear_layer(4096)
+    for dt, s in (("fp32_dev", 4), ("fp64", 8)):
+        for name, tun in (("", None), ("_one_step_per_launch", lbm.make_tuning(time_block=1))):
+            dom = lbm.Domain(r2, u2, 0.5001, dtype=dt, stream=stream, tuning=tun)
+            out[f"d2q9_4096_{dt}{name}"] = timed(dom, 4096 ** 2, 2 * 9 * s)
+            dom.close()
     return {"steps": steps, "steps_d1q3": steps_1d, "results": out}
 
 

@@ -121,6 +121,13 @@ typedef struct lbm_tuning {
                                  1 for FP32 storage on D2Q9 */
     int32_t flags;            /* LBM_TUNE_* bits for the vector kernels; < 0 selects the default */
     int32_t layout;           /* LBM_LAYOUT_*; 0 = default (row-interleaved) */
+    int32_t time_block;       /* LBGK steps per launch: 0 or 1 = one; 2 = two steps per sweep,
+                                 the intermediate state kept in LDS (D2Q9, LBM_FP64 or
+                                 LBM_FP32_DEV, entropic equilibrium, row-interleaved layout,
+                                 nx a multiple of 64; an odd step count ends with one
+                                 one-step launch of the kernel the other fields select) */
+    int32_t time_rows;        /* time_block = 2: rows swept per workgroup (>= 1; 0 = default);
+                                 must be 0 otherwise */
     int32_t reserved;         /* must be 0 */
 } lbm_tuning;
 

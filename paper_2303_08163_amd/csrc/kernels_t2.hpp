@@ -1,0 +1,151 @@
+// kernels_t2.hpp -- two LBGK steps per launch on D2Q9 (temporal blocking).
+//
+// A step reads and writes every population once, so a one-step kernel moves
+// 2 Q s bytes per node update whatever its tiling.  Two steps in one sweep
+// halve that: the intermediate state f*(t + 1) never leaves the chip.
+//
+// Each workgroup owns tx consecutive columns [x0, x0 + tx) of `rows`
+// consecutive rows [y0, y1) and sweeps its rows in y order.  At sweep row r
+// (r = y0 - 1 .. y1) it
+//   1. pulls f(t + 1) at row r for the tx + 2 columns [x0 - 1, x0 + tx + 1)
+//      from the source buffer, collides, and puts the post-collision values
+//      (rounded to the storage type, exactly what a one-step launch would
+//      store) into a ring of four LDS rows;
+//   2. once rows r - 2 .. r are in the ring, pulls f(t + 2) at row r - 1 for
+//      the tx owned columns from the ring, collides, and stores f*(t + 2).
+// A D2Q9 population moves at most one row and one column per step, so the
+// halo of one column on each side and one row above and below is all that
+// step 2 needs.  The halo nodes are also computed by the neighbouring
+// workgroups; every node runs the same collision code as in the one-step
+// kernels, so the results are bitwise those of two one-step launches.  A
+// workgroup reads the populations of (tx + 2) x (rows + 2) step-1 node
+// updates and writes those of its tx x rows nodes once.
+//
+// A D3Q27 node holds 27 populations, so the ring would need (tx + 2) x 27 x 4
+// rows of a 2-D tile (and the x-y halo grows the re-read area); in 160 KB of
+// LDS that does not fit at any useful tile size, so D3Q27 stays one step per
+// launch.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace lbm {
+
+struct Step2Args {
+    const void *src;  // f*(t), row-interleaved layout
+    void *dst;        // f*(t + 2)
+    int nx, ny;
+    int tx;           // owned columns per workgroup (blockDim.x - 64; nx % tx == 0)
+    int rows;         // owned rows per workgroup
+    int tiles_x, tiles_y;
+    int64_t ps, rs;
+    Relax relax;
+    int *flag;
+};
+
+constexpr int kT2Ring = 4;  // LDS rows in the ring (see the barrier note below)
+
+// LDS bytes of the ring for tx owned columns and elements of `elem` bytes.
+__host__ __device__ constexpr size_t t2_lds_bytes(int tx, size_t elem) {
+    return (size_t)kT2Ring * 9 * (size_t)(tx + 2) * elem;
+}
+
+// Pull f_i(x, y) = f*_i(x - c_x, y - c_y) of one D2Q9 node from a buffer
+// (periodic wrap; 0 <= x < nx, 0 <= y < ny).
+template <typename T>
+__device__ __forceinline__ void pull_d2q9(const T *__restrict__ src, int nx, int ny, int64_t ps, int64_t rs, int x,
+                                          int y, T (&f)[9]) {
+    const int xs[3] = {x + 1 == nx ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};  // x - c_x
+    const int ys[3] = {y + 1 == ny ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};  // y - c_y
+#pragma unroll
+    for (int cy = 0; cy < 3; ++cy)
+#pragma unroll
+        for (int cx = 0; cx < 3; ++cx) {
+            const int i = cx + 3 * cy;
+            f[i] = src[(int64_t)ys[cy] * rs + i * ps + xs[cx]];
+        }
+}
+
+// Grid: tiles_x * tiles_y workgroups of tx + 64 threads (the last wavefront
+// computes the two halo columns of step 1 beyond the first tx nodes), dynamic
+// LDS t2_lds_bytes(tx, sizeof(T)).
+template <int DT, bool CORR>
+__global__ __launch_bounds__(320) void k_stream_collide2(Step2Args a) {
+    using T = store_t<DT>;
+    extern __shared__ __align__(16) unsigned char t2_lds[];
+    T *ring = reinterpret_cast<T *>(t2_lds);
+    const T *__restrict__ src = static_cast<const T *>(a.src);
+    T *__restrict__ dst = static_cast<T *>(a.dst);
+
+    const int t = (int)threadIdx.x;
+    const int w1 = a.tx + 2;  // step-1 columns
+    const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int x0 = (tile % a.tiles_x) * a.tx;
+    const int y0 = (tile / a.tiles_x) * a.rows;
+    const int y1 = min(y0 + a.rows, a.ny);
+
+    // step-1 column of this lane: x0 - 1 + t, wrapped (tx <= nx, so one wrap
+    // suffices); lanes past the halo read column x0 and discard the result
+    const bool s1 = t < w1;
+    int x1 = s1 ? x0 - 1 + t : x0;
+    x1 = x1 < 0 ? x1 + a.nx : (x1 >= a.nx ? x1 - a.nx : x1);
+    const bool s2 = t < a.tx;
+    // sweep rows run from y0 - 1 to y1 <= ny: one wrap at either end
+    auto wrap_row = [&](int r) { return r < 0 ? r + a.ny : (r >= a.ny ? r - a.ny : r); };
+
+    // One sweep row: step 1 at row r from f (pulled two rows earlier), then
+    // the loads of row r + 2 into f, then step 2 at row r - 1.
+    auto sweep_row = [&](T (&f)[9], int r) {
+        // step 1 at sweep row r into ring slot (r - y0 + 1) mod 4
+        const bool bad1 = collide_dt<2, DT, CORR>(f, a.relax);
+        raise_flag(a.flag, bad1 && s1);
+        T *slot = ring + (size_t)((r - y0 + 1) & (kT2Ring - 1)) * 9 * w1;
+        if (s1) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                slot[i * w1 + t] = f[i];
+        }
+        // Slot r + 1 (written in the next row) is slot r - 3, last read by
+        // step 2 of row r - 2 in the previous row, which every lane finished
+        // before passing this barrier: one barrier per row suffices.
+        __syncthreads();
+        if (r + 2 <= y1)  // keep two rows of loads in flight
+            pull_d2q9<T>(src, a.nx, a.ny, a.ps, a.rs, x1, wrap_row(r + 2), f);
+        if (r > y0 && s2) {
+            // step 2 at row y = r - 1: f_i(x, y) = f*_i(x - c_x, y - c_y) from
+            // sweep row y + 1 - cy, step-1 column (x0 + t + 1 - cx) - (x0 - 1)
+            const int y = r - 1;
+            T g[9];
+#pragma unroll
+            for (int cy = 0; cy < 3; ++cy) {
+                const T *srow = ring + (size_t)((y + 2 - cy - y0) & (kT2Ring - 1)) * 9 * w1;
+#pragma unroll
+                for (int cx = 0; cx < 3; ++cx) {
+                    const int i = cx + 3 * cy;
+                    g[i] = srow[i * w1 + t + 2 - cx];
+                }
+            }
+            const bool bad2 = collide_dt<2, DT, CORR>(g, a.relax);
+            raise_flag(a.flag, bad2);
+            T *out = dst + (int64_t)y * a.rs + x0 + t;
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                out[i * a.ps] = g[i];
+        }
+    };
+
+    // sweep rows y0 - 1 .. y1 (at least three), alternating two register sets
+    T fa[9], fb[9];
+    pull_d2q9<T>(src, a.nx, a.ny, a.ps, a.rs, x1, wrap_row(y0 - 1), fa);
+    pull_d2q9<T>(src, a.nx, a.ny, a.ps, a.rs, x1, y0, fb);
+    for (int r = y0 - 1;;) {
+        sweep_row(fa, r);
+        if (++r > y1)
+            break;
+        sweep_row(fb, r);
+        if (++r > y1)
+            break;
+    }
+}
+
+}  // namespace lbm

@@ -8,6 +8,7 @@
 #include <new>
 
 #include "kernels.hpp"
+#include "kernels_t2.hpp"
 #include "lbm.h"
 #include "lbm_internal.hpp"
 
@@ -112,7 +113,7 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
         return LBM_EINVAL;
     }
     // tuning
-    int bx = 0, by = 0, pad = -1, npt = 0, flags = -1, layout = 0;
+    int bx = 0, by = 0, pad = -1, npt = 0, flags = -1, layout = 0, tblock = 0, trows = 0;
     if (tun) {
         if (tun->reserved != 0) {
             set_error("lbm_tuning.reserved must be 0");
@@ -124,7 +125,11 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
         npt = tun->nodes_per_thread;
         flags = tun->flags;
         layout = tun->layout;
+        tblock = tun->time_block;
+        trows = tun->time_rows;
     }
+    // the one-step kernel's shape left to the library (then the default may be two steps per launch)
+    const bool shape_default = bx == 0 && by == 0 && npt == 0 && flags < 0 && layout == 0;
     if (layout == LBM_LAYOUT_DEFAULT)
         layout = LBM_LAYOUT_ROWS;
     if (layout != LBM_LAYOUT_ROWS && layout != LBM_LAYOUT_PLANES) {
@@ -194,6 +199,67 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
             set_error("more than 2^31 - 1 workgroup tiles");
             return LBM_EINVAL;
         }
+    }
+    const bool t2_fits = L.dim == 2 && layout == LBM_LAYOUT_ROWS && L.eq == LBM_EQ_ENTROPIC &&
+                         (cfg->dtype == LBM_FP64 || cfg->dtype == LBM_FP32_DEV) && cfg->nx % 64 == 0;
+    if (tblock == 0) {
+        // default: two steps per launch for large D2Q9 domains.  A workgroup sweeps its
+        // rows one after another (about 1.4 us per row), so small grids lack the
+        // parallelism; measured break-even near 2048^2 nodes for FP32 storage (1536^2:
+        // 29.0 against 26.7 us per step; 2048^2: 39.0 against 49.0) and 1024^2 for FP64
+        // (512^2: 12.1 against 8.9; 1024^2: 16.0 against 29.6)
+        const int64_t big = fp32 ? (int64_t)2048 * 2048 : (int64_t)1024 * 1024;
+        tblock = t2_fits && shape_default && trows == 0 && L.n >= big ? 2 : 1;
+    }
+    if (tblock != 1 && tblock != 2) {
+        set_error("time_block must be 0, 1 or 2");
+        return LBM_EINVAL;
+    }
+    if (tblock == 1 && trows != 0) {
+        set_error("time_rows needs time_block = 2");
+        return LBM_EINVAL;
+    }
+    L.tblock = tblock;
+    L.t2_tx = L.t2_rows = 0;
+    if (tblock == 2) {
+        if (!t2_fits) {
+            set_error("time_block = 2 needs D2Q9, the row-interleaved layout, the entropic "
+                      "equilibrium, LBM_FP64 or LBM_FP32_DEV, and nx a multiple of 64");
+            return LBM_EINVAL;
+        }
+        if (trows < 0 || trows > cfg->ny) {
+            set_error("time_rows must lie in 0 .. ny");
+            return LBM_EINVAL;
+        }
+        // owned columns: the widest of 256 (FP32) or 128 (FP64), 128, 64 dividing nx, so
+        // that the LDS ring stays near 37 KB and four workgroups fit a compute unit
+        int tx = fp32 ? 256 : 128;
+        while (cfg->nx % tx != 0)
+            tx /= 2;
+        const int64_t tiles_x = cfg->nx / tx;
+        if (trows == 0) {
+            // Four workgroups fit a compute unit (LDS), 1024 the chip; a workgroup's time
+            // is about that of its rows + 2 sweep rows.  Take the row count with the least
+            // (rounds of 1024 workgroups) x (rows + 2), so that the last round is not
+            // mostly idle (3072^2 FP64: 36 rows, 2064 workgroups, 170.8 us per step;
+            // 16 rows: 139.9).
+            int64_t best = -1;
+            for (int cand : {16, 24, 32, 48, 64, 96, 128}) {
+                const int64_t rws = std::min<int64_t>(cand, cfg->ny);
+                const int64_t wgs = tiles_x * ((cfg->ny + rws - 1) / rws);
+                const int64_t cost = (wgs + 1023) / 1024 * (rws + 2);
+                if (best < 0 || cost < best) {
+                    best = cost;
+                    trows = (int)rws;
+                }
+            }
+        }
+        if (tiles_x * ((cfg->ny + trows - 1) / trows) > (int64_t)INT32_MAX) {
+            set_error("more than 2^31 - 1 workgroup tiles");
+            return LBM_EINVAL;
+        }
+        L.t2_tx = tx;
+        L.t2_rows = trows;
     }
     L.block_x = bx;
     L.block_y = by;
@@ -365,6 +431,20 @@ int launch_step(const Layout &L, const StepArgs &args, int dtype, bool corr, hip
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return hip_fail(e, "stream-collide launch");
+    return LBM_OK;
+}
+
+// Two steps in one launch (time_block = 2): src -> dst = f*(t + 2).
+int launch_step2(const Layout &L, const StepArgs &args, int dtype, bool corr, hipStream_t s) {
+    Step2Args a{args.src, args.dst, args.nx, args.ny, L.t2_tx, L.t2_rows, args.nx / L.t2_tx,
+                (args.ny + L.t2_rows - 1) / L.t2_rows, L.ps, L.rs, args.relax, args.flag};
+    void (*fn)(Step2Args) = dtype == kF64 ? (corr ? k_stream_collide2<kF64, true> : k_stream_collide2<kF64, false>)
+                                          : (corr ? k_stream_collide2<kDevF64, true> : k_stream_collide2<kDevF64, false>);
+    hipLaunchKernelGGL(fn, dim3((unsigned)(a.tiles_x * a.tiles_y)), dim3((unsigned)(a.tx + 64)),
+                       (unsigned)t2_lds_bytes(a.tx, L.elem), s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return hip_fail(e, "two-step launch");
     return LBM_OK;
 }
 
@@ -635,6 +715,14 @@ static int enqueue_step(lbm_handle *h, int cur, hipStream_t s) {
     return launch_step(d.L, a, d.cfg.dtype, corr, s, (int)d.cfg.nz, nullptr);
 }
 
+// Enqueue one two-step launch (time_block = 2) from buffer `cur`.
+static int enqueue_pair(lbm_handle *h, int cur, hipStream_t s) {
+    DomainState &d = h->d;
+    StepArgs a{d.buf[cur], d.buf[cur ^ 1], (int)d.cfg.nx, (int)d.cfg.ny, 1, 0, 0,
+               d.L.ps, d.L.rs, d.relax, d.flag, 0};
+    return launch_step2(d.L, a, d.cfg.dtype, d.cfg.bulk_correction != 0, s);
+}
+
 // The graph of kGraphSteps steps starting from buffer `cur` (captured when the
 // handle is created; later calls find it).  Returns false (and turns graphs
 // off for the handle) if any graph call fails; the caller then launches
@@ -651,8 +739,12 @@ static bool step_graph(lbm_handle *h, int cur) {
         e = hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         int rc = LBM_OK;
-        for (int k = 0; k < kGraphSteps && rc == LBM_OK; ++k)
-            rc = enqueue_step(h, cur ^ (k & 1), h->capture);
+        // kGraphSteps steps: as many launches, or half as many two-step launches;
+        // either way an even number of buffer swaps
+        const int launches = h->d.L.tblock == 2 ? kGraphSteps / 2 : kGraphSteps;
+        for (int k = 0; k < launches && rc == LBM_OK; ++k)
+            rc = h->d.L.tblock == 2 ? enqueue_pair(h, cur ^ (k & 1), h->capture)
+                                    : enqueue_step(h, cur ^ (k & 1), h->capture);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(h->capture, &g);
         if (e == hipSuccess && rc == LBM_OK && g) {
@@ -702,7 +794,16 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
             hipError_t e = hipGraphLaunch(h->exec[d.cur], h->stream);
             if (e != hipSuccess)
                 return hip_fail(e, "step graph launch");
-            d.steps += kGraphSteps;  // an even count: d.cur is unchanged
+            d.steps += kGraphSteps;  // an even count of swaps: d.cur is unchanged
+        }
+    }
+    if (d.L.tblock == 2) {
+        for (; s + 2 <= nsteps; s += 2) {
+            int rc = enqueue_pair(h, d.cur, h->stream);
+            if (rc != LBM_OK)
+                return rc;
+            d.cur ^= 1;
+            d.steps += 2;
         }
     }
     for (; s < nsteps; ++s) {

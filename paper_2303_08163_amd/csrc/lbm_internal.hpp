@@ -23,6 +23,8 @@ struct Layout {
     int npt;           // nodes per thread along x
     int flags;         // LBM_TUNE_* bits
     bool rowwave;      // one wavefront spans a whole row (vector kernels)
+    int tblock;        // LBGK steps per launch (1 or 2)
+    int t2_tx, t2_rows;  // two-step kernel: owned columns and rows per workgroup
     bool zhalo;        // z-slab: each buffer holds halo planes -1 and nz around the nz planes
     int64_t plane;     // elements of one plane (rows layout: ny * rs)
     int red_blocks;    // workgroups of the moments reduction
@@ -49,6 +51,7 @@ int hip_fail(hipError_t e, const char *what);
 int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out);
 int launch_step(const Layout &L, const StepArgs &args, int dtype, bool corr, hipStream_t s, int nz,
                 const HaloArgs *halo);
+int launch_step2(const Layout &L, const StepArgs &args, int dtype, bool corr, hipStream_t s);
 
 // Bind a domain to its workspace and enqueue f = f^eq(rho, u) plus the flag
 // clear; the caller synchronises and reads the flag (domain_read_flag).

@@ -43,7 +43,8 @@ class lbm_config(ctypes.Structure):
 class lbm_tuning(ctypes.Structure):
     _fields_ = [("block_x", ctypes.c_int32), ("block_y", ctypes.c_int32),
                 ("plane_pad", ctypes.c_int32), ("nodes_per_thread", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("layout", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("layout", ctypes.c_int32), ("time_block", ctypes.c_int32),
+                ("time_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class lbm_diag(ctypes.Structure):
@@ -196,9 +197,10 @@ LBM_TUNE_NT_STORE, LBM_TUNE_NT_LOAD = 1, 2
 LBM_LAYOUT_DEFAULT, LBM_LAYOUT_ROWS, LBM_LAYOUT_PLANES = 0, 1, 2
 
 
-def make_tuning(block_x=0, block_y=0, plane_pad=-1, nodes_per_thread=0, flags=-1, layout=0) -> lbm_tuning:
+def make_tuning(block_x=0, block_y=0, plane_pad=-1, nodes_per_thread=0, flags=-1, layout=0, time_block=0,
+                time_rows=0) -> lbm_tuning:
     return lbm_tuning(int(block_x), int(block_y), int(plane_pad), int(nodes_per_thread), int(flags),
-                      int(layout), 0)
+                      int(layout), int(time_block), int(time_rows), 0)
 
 
 def lbm_workspace_bytes(cfg: lbm_config, tuning: lbm_tuning | None = None) -> int:

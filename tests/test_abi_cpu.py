@@ -108,6 +108,30 @@ def test_valid_tunings_accepted(lbm):
         assert lbm.lbm_workspace_bytes(cfg, lbm.make_tuning(*tun)) > 0, tun
 
 
+def test_time_block_configs(lbm):
+    """Two steps per launch: D2Q9, FP64 or FP32_DEV, entropic, rows layout,
+    nx a multiple of 64; the workspace is that of the one-step domain."""
+    two = lbm.make_tuning(time_block=2)
+    for dt in ("fp64", "fp32_dev"):
+        for nx in (64, 192, 4096):
+            cfg = _cfg(lbm, shape=(nx, 5), dtype=dt)
+            assert lbm.lbm_workspace_bytes(cfg, two) == lbm.lbm_workspace_bytes(cfg) > 0
+            assert lbm.lbm_workspace_bytes(cfg, lbm.make_tuning(time_block=2, time_rows=5)) > 0
+            assert lbm.lbm_workspace_bytes(cfg, lbm.make_tuning(time_block=2, time_rows=6)) == 0
+            assert lbm.lbm_workspace_bytes(cfg, lbm.make_tuning(time_block=2, time_rows=-1)) == 0
+    refused = [_cfg(lbm, shape=(96, 8)), _cfg(lbm, shape=(100, 8), dtype="fp32_dev"),
+               _cfg(lbm, lattice=27, shape=(64, 8, 8)), _cfg(lbm, lattice=3, shape=(256,)),
+               _cfg(lbm, shape=(64, 8), dtype="fp32_dev_mixed"), _cfg(lbm, shape=(64, 8), equilibrium="poly2")]
+    for cfg in refused:
+        assert lbm.lbm_workspace_bytes(cfg, two) == 0
+    assert b"time_block" in lbm.load_library().lbm_last_error()
+    cfg = _cfg(lbm, shape=(64, 8))
+    assert lbm.lbm_workspace_bytes(cfg, lbm.make_tuning(layout=lbm.LBM_LAYOUT_PLANES, time_block=2)) == 0
+    assert lbm.lbm_workspace_bytes(cfg, lbm.make_tuning(time_block=3)) == 0
+    assert lbm.lbm_workspace_bytes(cfg, lbm.make_tuning(time_rows=4)) == 0  # rows without two steps
+    assert lbm.lbm_workspace_bytes(cfg, lbm.make_tuning(time_block=1)) > 0
+
+
 def test_polynomial_equilibria_configs(lbm):
     """The polynomial kinds take both production storage modes and the scalar
     or default vector kernel; other vector tunings are refused."""

@@ -1,0 +1,94 @@
+"""Two LBGK steps per launch on D2Q9 (lbm_tuning.time_block = 2): the
+intermediate state stays in LDS, and every node runs the same collision code
+as the one-step kernels, so results must be bitwise those of the default
+one-step path -- for both storage types, with and without the correction,
+on ragged row counts, degenerate grids (one or two rows, a single column
+tile), odd step counts (ending with one one-step launch) and graph replays.
+The domain flag must rise exactly when it rises on the one-step path; the
+oracle closes the loop at FP64 tolerance."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2303_08163_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _lbm():
+    from paper_2303_08163_amd import lbm
+    return lbm
+
+
+CASES = [  # (ny, nx), dtype, correction, time_rows, step chunks
+    ((64, 64), "fp32_dev", False, 0, (1, 2, 7, 100)),
+    ((100, 192), "fp64", True, 7, (65, 3)),
+    ((1, 128), "fp32_dev", True, 1, (6, 1)),
+    ((2, 64), "fp64", False, 0, (5,)),
+    ((3, 512), "fp32_dev", False, 2, (4, 64)),
+    ((37, 256), "fp32_dev", True, 37, (9,)),
+    ((48, 320), "fp64", False, 5, (2, 2, 131)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_two_step_equals_one_step_bitwise(case):
+    lbm = _lbm()
+    shape, dtype, corr, rows, chunks = CASES[case]
+    rho0, u0 = workloads.random_field(shape, seed=40 + case, umax=0.1)
+    two = lbm.make_tuning(time_block=2, time_rows=rows)
+    with lbm.Domain(rho0, u0, 0.55, dtype=dtype, bulk_correction=corr, tuning=two) as a, \
+            lbm.Domain(rho0, u0, 0.55, dtype=dtype, bulk_correction=corr) as b:
+        done = 0
+        for n in chunks:
+            a.step(n)
+            b.step(n)
+            done += n
+            ra, ua, da = a.moments()
+            rb, ub, db = b.moments()
+            assert da["steps"] == db["steps"] == done
+            assert np.array_equal(ra, rb) and np.array_equal(ua, ub), (shape, done)
+        assert np.array_equal(a.populations(), b.populations())
+
+
+def test_two_step_matches_oracle():
+    lbm = _lbm()
+    rho0, u0 = workloads.taylor_green_2d(64, u0=0.05)
+    for corr in (False, True):
+        r_ref, u_ref, bad = oracle.run(rho0, u0, 0.53, 50, corr="min" if corr else "off")
+        assert bad == 0
+        with lbm.Domain(rho0, u0, 0.53, dtype="fp64", bulk_correction=corr,
+                        tuning=lbm.make_tuning(time_block=2)) as d:
+            d.step(50)
+            rho, u, diag = d.moments()
+        assert np.max(np.abs(rho - r_ref)) / np.max(np.abs(r_ref)) < 1e-12
+        assert np.max(np.abs(u - u_ref)) / np.max(np.abs(u_ref)) < 1e-12
+
+
+def test_two_step_domain_flag_as_one_step():
+    """The flag is the OR over every node of both steps, halo duplicates
+    included: it must rise in the same call as on the one-step path."""
+    lbm = _lbm()
+    for seed in range(70, 74):
+        rho0, u0 = workloads.random_field((16, 64), seed=seed, umax=0.99, rho_lo=0.3, rho_hi=2.0)
+        with lbm.Domain(rho0, u0, 0.5001, dtype="fp64", tuning=lbm.make_tuning(time_block=2)) as a, \
+                lbm.Domain(rho0, u0, 0.5001, dtype="fp64") as b:
+            for n in (1, 2, 3, 6, 10):
+                a.step(n)
+                b.step(n)
+                fa = a.moments(fields=False, raise_on_domain=False)[2]["domain_error"]
+                fb = b.moments(fields=False, raise_on_domain=False)[2]["domain_error"]
+                assert fa == fb, (seed, n)
+
+
+@pytest.mark.parametrize("dtype", ["fp32_dev", "fp64"])
+def test_two_step_full_size_bitwise(dtype):
+    """D2Q9 4096^2 (the large 2-D workload), 4 steps in default tiles."""
+    lbm = _lbm()
+    rho0, u0 = workloads.random_field((4096, 4096), seed=50, umax=0.1)
+    with lbm.Domain(rho0, u0, 0.51, dtype=dtype, tuning=lbm.make_tuning(time_block=2)) as a:
+        a.step(4)
+        fa = a.populations()
+    with lbm.Domain(rho0, u0, 0.51, dtype=dtype) as b:
+        b.step(4)
+        assert np.array_equal(fa, b.populations())
