@@ -35,7 +35,7 @@ struct Step2Args {
     const void *src;  // f*(t), row-interleaved layout
     void *dst;        // f*(t + 2)
     int nx, ny;
-    int tx;           // owned columns per workgroup (blockDim.x - 64; nx % tx == 0)
+    int tx;           // owned columns per workgroup (blockDim.x; nx % tx == 0)
     int rows;         // owned rows per workgroup
     int tiles_x, tiles_y;
     int64_t ps, rs;
@@ -45,9 +45,22 @@ struct Step2Args {
 
 constexpr int kT2Ring = 4;  // LDS rows in the ring (see the barrier note below)
 
-// LDS bytes of the ring for tx owned columns and elements of `elem` bytes.
+// The two step-1 halo columns of a row: with float storage wavefront 0
+// computes them for a chunk of 32 sweep rows at a time (2 x 32 nodes, one
+// wavefront), into a small LDS area copied into the ring row by row; with
+// double storage an extra wavefront per workgroup computes them every row.
+// (Measured at 4096^2, us per step: float 143.2 with chunks against 148.3
+// with the extra wavefront; double 265.2 against 225.9 -- the double
+// workgroups of tx = 128 keep only two wavefronts without it, too few loads
+// in flight.)
+__host__ __device__ constexpr bool t2_halo_wave(size_t elem) { return elem == 8; }
+constexpr int kT2Chunk = 32;
+
+// Threads per workgroup and LDS bytes for tx owned columns and elements of
+// `elem` bytes: the ring [4][9][tx + 2], and the halo chunk [32][2][9].
+__host__ __device__ constexpr int t2_threads(int tx, size_t elem) { return tx + (t2_halo_wave(elem) ? 64 : 0); }
 __host__ __device__ constexpr size_t t2_lds_bytes(int tx, size_t elem) {
-    return (size_t)kT2Ring * 9 * (size_t)(tx + 2) * elem;
+    return ((size_t)kT2Ring * 9 * (size_t)(tx + 2) + (t2_halo_wave(elem) ? 0 : (size_t)kT2Chunk * 2 * 9)) * elem;
 }
 
 // Pull f_i(x, y) = f*_i(x - c_x, y - c_y) of one D2Q9 node from a buffer
@@ -66,54 +79,120 @@ __device__ __forceinline__ void pull_d2q9(const T *__restrict__ src, int nx, int
         }
 }
 
-// Grid: tiles_x * tiles_y workgroups of tx + 64 threads (the last wavefront
-// computes the two halo columns of step 1 beyond the first tx nodes), dynamic
-// LDS t2_lds_bytes(tx, sizeof(T)).
+// The same pull for a row y common to the wavefront: the (row, population)
+// bases are wavefront-uniform (scalar registers) and the lane's part is a
+// byte offset xb[cx] of its source column x - c_x, fixed for the whole sweep,
+// so the loads need no per-lane 64-bit address arithmetic.
+template <typename T>
+__device__ __forceinline__ void pull_row_d2q9(const T *__restrict__ src, int ny, int64_t ps, int64_t rs, int y,
+                                              const uint32_t (&xb)[3], T (&f)[9]) {
+    const int ys[3] = {y + 1 == ny ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};  // y - c_y
+#pragma unroll
+    for (int cy = 0; cy < 3; ++cy)
+#pragma unroll
+        for (int cx = 0; cx < 3; ++cx) {
+            const int i = cx + 3 * cy;
+            const char *base = reinterpret_cast<const char *>(src + (int64_t)ys[cy] * rs + (int64_t)i * ps);
+            f[i] = *reinterpret_cast<const T *>(base + xb[cx]);
+        }
+}
+
+// Grid: tiles_x * tiles_y workgroups of t2_threads(tx, sizeof(T)) threads,
+// dynamic LDS t2_lds_bytes(tx, sizeof(T)).  Ring column c holds step-1
+// column x0 - 1 + c.  With chunks, lane t computes step 1 and step 2 at
+// column x0 + t; with the halo wavefront, lane t < tx + 2 computes step 1 at
+// x0 - 1 + t and lane t < tx step 2 at x0 + t.
 template <int DT, bool CORR>
 __global__ __launch_bounds__(320) void k_stream_collide2(Step2Args a) {
     using T = store_t<DT>;
+    constexpr bool HW = t2_halo_wave(sizeof(T));
+    constexpr int CH = kT2Chunk;
     extern __shared__ __align__(16) unsigned char t2_lds[];
-    T *ring = reinterpret_cast<T *>(t2_lds);
     const T *__restrict__ src = static_cast<const T *>(a.src);
     T *__restrict__ dst = static_cast<T *>(a.dst);
 
     const int t = (int)threadIdx.x;
-    const int w1 = a.tx + 2;  // step-1 columns
+    const int w1 = a.tx + 2;  // ring columns: x0 - 1 .. x0 + tx
+    T *ring = reinterpret_cast<T *>(t2_lds);
+    T *hal = ring + (size_t)kT2Ring * 9 * w1;  // [CH][2][9]
     const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int x0 = (tile % a.tiles_x) * a.tx;
     const int y0 = (tile / a.tiles_x) * a.rows;
     const int y1 = min(y0 + a.rows, a.ny);
-
-    // step-1 column of this lane: x0 - 1 + t, wrapped (tx <= nx, so one wrap
-    // suffices); lanes past the halo read column x0 and discard the result
-    const bool s1 = t < w1;
-    int x1 = s1 ? x0 - 1 + t : x0;
-    x1 = x1 < 0 ? x1 + a.nx : (x1 >= a.nx ? x1 - a.nx : x1);
-    const bool s2 = t < a.tx;
+    const int nsweep = y1 - y0 + 2;  // sweep rows y0 - 1 .. y1 (offsets 0 .. nsweep - 1)
+    const int x = x0 + t;            // step-2 column
+    const bool s2 = !HW || t < a.tx;
+    // step-1 column: x0 + t, or with the halo wavefront x0 - 1 + t wrapped (tx <= nx:
+    // one wrap suffices; lanes past the halo read column x0 and discard the result)
+    const bool s1 = !HW || t < w1;
+    int x1 = x;
+    if (HW) {
+        x1 = s1 ? x0 - 1 + t : x0;
+        x1 = x1 < 0 ? x1 + a.nx : (x1 >= a.nx ? x1 - a.nx : x1);
+    }
+    // byte offsets of the step-1 lane's source columns x1 - c_x
+    const uint32_t xb[3] = {(uint32_t)((x1 + 1 == a.nx ? 0 : x1 + 1) * (int)sizeof(T)), (uint32_t)(x1 * (int)sizeof(T)),
+                            (uint32_t)((x1 == 0 ? a.nx - 1 : x1 - 1) * (int)sizeof(T))};
     // sweep rows run from y0 - 1 to y1 <= ny: one wrap at either end
     auto wrap_row = [&](int r) { return r < 0 ? r + a.ny : (r >= a.ny ? r - a.ny : r); };
 
-    // One sweep row: step 1 at row r from f (pulled two rows earlier), then
-    // the loads of row r + 2 into f, then step 2 at row r - 1.
+    // halo lanes of wavefront 0: sweep offset k0 + (t >> 1), column t & 1 (x0 - 1 or x0 + tx,
+    // wrapped; tx <= nx); lanes past the chunk or the sweep load a valid row and discard it
+    const bool w0 = !HW && t < 64;
+    const int hx = (t & 1) ? (x0 + a.tx == a.nx ? 0 : x0 + a.tx) : (x0 == 0 ? a.nx - 1 : x0 - 1);
+    T h[9];
+    auto halo_load = [&](int k0) {
+        const int k = min(k0 + ((t & 63) >> 1), nsweep - 1);
+        pull_d2q9<T>(src, a.nx, a.ny, a.ps, a.rs, hx, wrap_row(y0 - 1 + k), h);
+    };
+
+    // One sweep row: (at a chunk start, the halo chunk) step 1 at row r from f
+    // (pulled two rows earlier), then the loads of row r + 2 into f, then
+    // step 2 at row r - 1.
     auto sweep_row = [&](T (&f)[9], int r) {
-        // step 1 at sweep row r into ring slot (r - y0 + 1) mod 4
+        const int k = r - y0 + 1;  // sweep offset
+        if (!HW && k % CH == 0) {
+            if (w0) {
+                const bool valid = t < 2 * CH && k + (t >> 1) < nsweep;
+                const bool badh = collide_dt<2, DT, CORR>(h, a.relax);
+                raise_flag(a.flag, badh && valid);
+                if (valid) {
+#pragma unroll
+                    for (int i = 0; i < 9; ++i)
+                        hal[t * 9 + i] = h[i];
+                }
+                if (k + CH < nsweep)  // the next chunk's loads
+                    halo_load(k + CH);
+            }
+            // The chunk is complete before any lane copies from it; the
+            // previous chunk was last read before the barrier of row r - 1.
+            __syncthreads();
+        }
+        // step 1 at sweep row r into ring slot k mod 4 (column c <-> x0 - 1 + c)
         const bool bad1 = collide_dt<2, DT, CORR>(f, a.relax);
         raise_flag(a.flag, bad1 && s1);
-        T *slot = ring + (size_t)((r - y0 + 1) & (kT2Ring - 1)) * 9 * w1;
+        T *slot = ring + (size_t)(k & (kT2Ring - 1)) * 9 * w1;
         if (s1) {
 #pragma unroll
             for (int i = 0; i < 9; ++i)
-                slot[i * w1 + t] = f[i];
+                slot[i * w1 + (HW ? t : t + 1)] = f[i];
+        }
+        if (!HW && t < 2) {
+            const T *hv = hal + ((k % CH) * 2 + t) * 9;
+            const int c = t == 0 ? 0 : w1 - 1;
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                slot[i * w1 + c] = hv[i];
         }
         // Slot r + 1 (written in the next row) is slot r - 3, last read by
         // step 2 of row r - 2 in the previous row, which every lane finished
         // before passing this barrier: one barrier per row suffices.
         __syncthreads();
         if (r + 2 <= y1)  // keep two rows of loads in flight
-            pull_d2q9<T>(src, a.nx, a.ny, a.ps, a.rs, x1, wrap_row(r + 2), f);
+            pull_row_d2q9<T>(src, a.ny, a.ps, a.rs, wrap_row(r + 2), xb, f);
         if (r > y0 && s2) {
             // step 2 at row y = r - 1: f_i(x, y) = f*_i(x - c_x, y - c_y) from
-            // sweep row y + 1 - cy, step-1 column (x0 + t + 1 - cx) - (x0 - 1)
+            // sweep row y + 1 - cy, ring column (x + 1 - cx) - (x0 - 1)
             const int y = r - 1;
             T g[9];
 #pragma unroll
@@ -127,17 +206,21 @@ __global__ __launch_bounds__(320) void k_stream_collide2(Step2Args a) {
             }
             const bool bad2 = collide_dt<2, DT, CORR>(g, a.relax);
             raise_flag(a.flag, bad2);
-            T *out = dst + (int64_t)y * a.rs + x0 + t;
+            const uint32_t ob = (uint32_t)(x * (int)sizeof(T));
 #pragma unroll
-            for (int i = 0; i < 9; ++i)
-                out[i * a.ps] = g[i];
+            for (int i = 0; i < 9; ++i) {
+                char *base = reinterpret_cast<char *>(dst + (int64_t)y * a.rs + (int64_t)i * a.ps);
+                *reinterpret_cast<T *>(base + ob) = g[i];
+            }
         }
     };
 
     // sweep rows y0 - 1 .. y1 (at least three), alternating two register sets
     T fa[9], fb[9];
-    pull_d2q9<T>(src, a.nx, a.ny, a.ps, a.rs, x1, wrap_row(y0 - 1), fa);
-    pull_d2q9<T>(src, a.nx, a.ny, a.ps, a.rs, x1, y0, fb);
+    if (w0)
+        halo_load(0);
+    pull_row_d2q9<T>(src, a.ny, a.ps, a.rs, wrap_row(y0 - 1), xb, fa);
+    pull_row_d2q9<T>(src, a.ny, a.ps, a.rs, y0, xb, fb);
     for (int r = y0 - 1;;) {
         sweep_row(fa, r);
         if (++r > y1)

@@ -440,7 +440,7 @@ int launch_step2(const Layout &L, const StepArgs &args, int dtype, bool corr, hi
                 (args.ny + L.t2_rows - 1) / L.t2_rows, L.ps, L.rs, args.relax, args.flag};
     void (*fn)(Step2Args) = dtype == kF64 ? (corr ? k_stream_collide2<kF64, true> : k_stream_collide2<kF64, false>)
                                           : (corr ? k_stream_collide2<kDevF64, true> : k_stream_collide2<kDevF64, false>);
-    hipLaunchKernelGGL(fn, dim3((unsigned)(a.tiles_x * a.tiles_y)), dim3((unsigned)(a.tx + 64)),
+    hipLaunchKernelGGL(fn, dim3((unsigned)(a.tiles_x * a.tiles_y)), dim3((unsigned)t2_threads(a.tx, L.elem)),
                        (unsigned)t2_lds_bytes(a.tx, L.elem), s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
