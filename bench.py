@@ -325,8 +325,7 @@ def bench_oracle_timing(budget_s: float = 6.0) -> dict:
 def bench_variants(steps: int = 100, warmup: int = 10, steps_1d: int = 200, warmup_1d: int = 20) -> dict:
     """Throughput of the other equilibria and of the correction on the headline
     grid (D3Q27 256^3 Taylor-Green, FP32 deviation storage, default vector
-    kernel), of a D1Q3 row of 2^27 nodes (more steps: one takes ~0.6 ms), and
-    of the D2Q9 4096^2 double shear layer with two or one steps per launch."""
+    kernel), and of a D1Q3 row of 2^27 nodes (more steps: one takes ~0.6 ms)."""
     import numpy as np
     import torch
 
@@ -369,17 +368,41 @@ def bench_variants(steps: int = 100, warmup: int = 10, steps_1d: int = 200, warm
         dom = lbm.Domain(r1, u1, 0.6, dtype=dt, bulk_correction=True, stream=stream)
         out[f"d1q3_2^27_{dt}_corrected"] = timed(dom, n1, 2 * 3 * s, steps_1d, warmup_1d)
         dom.close()
-    del r1, u1
-    # D2Q9 4096^2 double shear layer: the default two steps per launch against one.
-    # gbs / frac count 2 Q s bytes per node update (what one step per launch moves);
-    # two steps per launch move about half of that.
-    r2, u2 = workloads.double_shear_layer(4096)
-    for dt, s in (("fp32_dev", 4), ("fp64", 8)):
-        for name, tun in (("", None), ("_one_step_per_launch", lbm.make_tuning(time_block=1))):
-            dom = lbm.Domain(r2, u2, 0.5001, dtype=dt, stream=stream, tuning=tun)
-            out[f"d2q9_4096_{dt}{name}"] = timed(dom, 4096 ** 2, 2 * 9 * s)
-            dom.close()
     return {"steps": steps, "steps_d1q3": steps_1d, "results": out}
+
+
+def bench_d2q9(steps: int = 100, warmup: int = 10) -> dict:
+    """The D2Q9 4096^2 double shear layer (tau 0.5001), FP32 deviations and FP64,
+    with the default two steps per launch and with one.  gbs / frac count
+    2 Q s bytes per node update (what one step per launch moves); two steps per
+    launch move about half of that, so for them these are equivalent rates."""
+    import torch
+
+    from paper_2303_08163_amd import lbm, workloads
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    r2, u2 = workloads.double_shear_layer(4096)
+    out = {}
+    for dt, s in (("fp32_dev", 4), ("fp64", 8)):
+        for name, tun in (("two_steps_per_launch", None), ("one_step_per_launch", lbm.make_tuning(time_block=1))):
+            dom = lbm.Domain(r2, u2, 0.5001, dtype=dt, stream=stream, tuning=tun)
+            dom.step(warmup)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            dom.step(steps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            sec = e0.elapsed_time(e1) / 1e3
+            _, _, d = dom.moments(fields=False)
+            dom.close()
+            mlups = 4096 ** 2 * steps / sec / 1e6
+            gbs = mlups * 1e6 * 2 * 9 * s / 1e9
+            out[f"{dt}_{name}"] = {"mlups": round(mlups, 1), "us_per_step": round(sec / steps * 1e6, 1),
+                                   "gbs_2Qs_per_update": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                   "domain_error": d["domain_error"]}
+    return {"workload": "D2Q9 4096^2 double shear layer, tau 0.5001", "steps": steps, "results": out}
 
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6
@@ -471,8 +494,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256, help="grid side (headline: 256)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sections", default="headline,batched,serving,wave,stability,variants,slab",
-                    help="comma list of headline, batched, serving, wave, stability, variants, "
+    ap.add_argument("--sections", default="headline,batched,serving,wave,stability,variants,slab,d2q9",
+                    help="comma list of headline, batched, serving, wave, stability, variants, slab, d2q9, "
                          "oracle_timing (not in the default run: several minutes of host time)")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=2000)
@@ -610,6 +633,9 @@ def main() -> int:
     if "slab" in sections:
         out["slab"] = bench_slab()
         progress("slab done")
+    if "d2q9" in sections:
+        out["d2q9"] = bench_d2q9()
+        progress("d2q9 done")
     if "stability" in sections:
         out["stability"] = bench_stability(with_cpu=not args.no_cpu_baseline)
         progress("stability done")
