@@ -752,13 +752,15 @@ static bool step_graph(lbm_handle *h, int cur) {
             e = hipGraphInstantiate(&h->exec[cur], g, nullptr, nullptr, 0);
         } else {
             if (g)
-                hipGraphDestroy(g);
+                (void)hipGraphDestroy(g);
             if (e == hipSuccess)
                 e = hipErrorUnknown;
         }
     }
     if (e != hipSuccess || !h->exec[cur]) {
         (void)hipGetLastError();  // leave no sticky error behind for the next call
+        if (h->exec[cur])
+            (void)hipGraphExecDestroy(h->exec[cur]);
         h->exec[cur] = nullptr;
         h->graphs_off = true;
         return false;

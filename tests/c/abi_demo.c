@@ -116,6 +116,19 @@ static int single_domain(void) {
     double f0;
     HIPCHECK(hipMemcpy(&f0, f_d, sizeof(double), hipMemcpyDeviceToHost));
     CHECK(f0 > 0.0 && f0 < 1.0, "population value");
+    /* checkpoint at step 50, run on, restart from it: the same bits again */
+    const size_t st_bytes = lbm_state_bytes(h);
+    void *st;
+    HIPCHECK(hipMalloc(&st, st_bytes));
+    CHECK(lbm_save_state(h, st, st_bytes) == LBM_OK, "save state");
+    lbm_diag d1, d2;
+    CHECK(lbm_step(h, 7) == LBM_OK && lbm_moments(h, NULL, NULL, &d1) == LBM_OK, "run on");
+    CHECK(lbm_load_state(h, st, st_bytes, 50) == LBM_OK, "load state");
+    CHECK(lbm_step(h, 7) == LBM_OK && lbm_moments(h, NULL, NULL, &d2) == LBM_OK, "run on again");
+    CHECK(d1.steps == 57 && d2.steps == 57 && d1.kinetic_energy == d2.kinetic_energy && d1.mass == d2.mass,
+          "restart is bit-exact");
+    CHECK(lbm_load_state(h, st, st_bytes - 1, 50) == LBM_EINVAL, "load refuses a wrong size");
+    HIPCHECK(hipFree(st));
     /* argument errors */
     CHECK(lbm_step(h, -1) == LBM_EINVAL, "negative step count");
     CHECK(lbm_step(NULL, 1) == LBM_EINVAL, "NULL handle");
