@@ -364,10 +364,13 @@ def bench_variants(steps: int = 100, warmup: int = 10, steps_1d: int = 200, warm
     r1 = torch.from_numpy(1.0 + 1e-3 * np.sin(2 * math.pi * x / n1)).to(dev)
     u1 = torch.full((1, n1), 0.1, dtype=torch.float64, device=dev)
     del x
+    # D1Q3: the default (eight steps per launch) and one step per launch; gbs / frac
+    # count 2 Q s bytes per node update, so for the former they are equivalent rates
     for dt, s in (("fp32_dev", 4), ("fp64", 8)):
-        dom = lbm.Domain(r1, u1, 0.6, dtype=dt, bulk_correction=True, stream=stream)
-        out[f"d1q3_2^27_{dt}_corrected"] = timed(dom, n1, 2 * 3 * s, steps_1d, warmup_1d)
-        dom.close()
+        for name, tun in (("", None), ("_one_step_per_launch", lbm.make_tuning(time_block=1))):
+            dom = lbm.Domain(r1, u1, 0.6, dtype=dt, bulk_correction=True, stream=stream, tuning=tun)
+            out[f"d1q3_2^27_{dt}_corrected{name}"] = timed(dom, n1, 2 * 3 * s, steps_1d, warmup_1d)
+            dom.close()
     return {"steps": steps, "steps_d1q3": steps_1d, "results": out}
 
 

@@ -121,11 +121,16 @@ typedef struct lbm_tuning {
                                  1 for FP32 storage on D2Q9 */
     int32_t flags;            /* LBM_TUNE_* bits for the vector kernels; < 0 selects the default */
     int32_t layout;           /* LBM_LAYOUT_*; 0 = default (row-interleaved) */
-    int32_t time_block;       /* LBGK steps per launch: 0 or 1 = one; 2 = two steps per sweep,
-                                 the intermediate state kept in LDS (D2Q9, LBM_FP64 or
-                                 LBM_FP32_DEV, entropic equilibrium, row-interleaved layout,
-                                 nx a multiple of 64; an odd step count ends with one
-                                 one-step launch of the kernel the other fields select) */
+    int32_t time_block;       /* LBGK steps per launch, the intermediate states kept in LDS
+                                 (LBM_FP64 or LBM_FP32_DEV, entropic equilibrium,
+                                 row-interleaved layout): 1 = one; 2 on D2Q9 with nx a
+                                 multiple of 64; 2, 4 or 8 on D1Q3 with nx >= 1032 (FP32) or
+                                 520 (FP64).  Step counts that are not a multiple end with
+                                 one-step launches of the kernel the other fields select.
+                                 0 = default: 2 for D2Q9 domains of >= 2048^2 nodes (FP32) or
+                                 1024^2 (FP64), 8 for D1Q3 where allowed, else 1 -- when
+                                 block_x, block_y, nodes_per_thread, flags and layout are
+                                 left at their defaults */
     int32_t time_rows;        /* time_block = 2: rows swept per workgroup (>= 1; 0 = default);
                                  must be 0 otherwise */
     int32_t reserved;         /* must be 0 */

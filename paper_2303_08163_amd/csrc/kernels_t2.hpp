@@ -231,4 +231,92 @@ __global__ __launch_bounds__(320) void k_stream_collide2(Step2Args a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// D1Q3, K steps per launch.  A workgroup owns tx consecutive nodes [x0, x0 +
+// tx) and keeps the segment [x0 - K, x0 + tx + K) in LDS, as two buffers
+// [3][tx + 2K] used in turn.  Step 1 pulls from HBM for the positions
+// 1 .. tx + 2K - 2 of the segment, step j for j .. tx + 2K - 1 - j from the
+// previous step's buffer, and step K, on the owned positions, stores to HBM:
+// a population moves one node per step, so K nodes of halo on each side are
+// all that K steps need.  The halo nodes are also computed by the
+// neighbouring workgroups, with the same per-node code, so the results are
+// bitwise those of K one-step launches.  Needs nx >= tx + K (one periodic
+// wrap); the last workgroup's positions past nx are the nodes from x = 0 on,
+// computed but not stored.
+struct StepKArgs {
+    const void *src;  // f*(t)
+    void *dst;        // f*(t + K)
+    int nx;
+    int tx;           // owned nodes per workgroup
+    int K;            // steps per launch (2 .. 8)
+    int64_t ps;       // population stride (the one row's pitch)
+    Relax relax;
+    int *flag;
+};
+
+constexpr int kT1MaxK = 8;
+
+__host__ __device__ constexpr size_t t1_lds_bytes(int tx, int K, size_t elem) {
+    return (size_t)2 * 3 * (size_t)(tx + 2 * K) * elem;
+}
+
+template <int DT, bool CORR>
+__global__ __launch_bounds__(256) void k_stream_collide_t1(StepKArgs a) {
+    using T = store_t<DT>;
+    extern __shared__ __align__(16) unsigned char t1_lds[];
+    const T *__restrict__ src = static_cast<const T *>(a.src);
+    T *__restrict__ dst = static_cast<T *>(a.dst);
+    const int w = a.tx + 2 * a.K;  // segment length
+    T *buf[2] = {reinterpret_cast<T *>(t1_lds), reinterpret_cast<T *>(t1_lds) + 3 * w};
+    const int x0 = (int)blockIdx.x * a.tx;
+    const int nthr = (int)blockDim.x;
+    auto wrap = [&](int x) { return x < 0 ? x + a.nx : (x >= a.nx ? x - a.nx : x); };
+
+    // step 1: positions m = 1 .. w - 2 (x = x0 - K + m) pull f*_i(x - c_i) from HBM
+    for (int m = 1 + (int)threadIdx.x; m < w - 1; m += nthr) {
+        const int x = x0 - a.K + m;
+        T f[3];
+#pragma unroll
+        for (int cx = 0; cx < 3; ++cx)
+            f[cx] = src[cx * a.ps + wrap(x + 1 - cx)];
+        const bool bad = collide_dt<1, DT, CORR>(f, a.relax);
+        raise_flag(a.flag, bad);
+        if (a.K == 1) {
+            if (m >= 1 && m < 1 + a.tx && x < a.nx)
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    dst[i * a.ps + x] = f[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                buf[0][i * w + m] = f[i];
+        }
+    }
+    // steps 2 .. K from LDS; the last one stores the owned positions
+    for (int j = 2; j <= a.K; ++j) {
+        __syncthreads();
+        const T *in = buf[j & 1 ? 1 : 0];
+        T *out = buf[j & 1 ? 0 : 1];
+        for (int m = j + (int)threadIdx.x; m < w - j; m += nthr) {
+            T f[3];
+#pragma unroll
+            for (int cx = 0; cx < 3; ++cx)
+                f[cx] = in[cx * w + m + 1 - cx];
+            const bool bad = collide_dt<1, DT, CORR>(f, a.relax);
+            raise_flag(a.flag, bad);
+            if (j == a.K) {
+                const int x = x0 - a.K + m;  // m in [K, K + tx): x0 <= x < x0 + tx
+                if (x < a.nx)
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+                        dst[i * a.ps + x] = f[i];
+            } else {
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    out[i * w + m] = f[i];
+            }
+        }
+    }
+}
+
 }  // namespace lbm

@@ -23,8 +23,8 @@ struct Layout {
     int npt;           // nodes per thread along x
     int flags;         // LBM_TUNE_* bits
     bool rowwave;      // one wavefront spans a whole row (vector kernels)
-    int tblock;        // LBGK steps per launch (1 or 2)
-    int t2_tx, t2_rows;  // two-step kernel: owned columns and rows per workgroup
+    int tblock;        // LBGK steps per launch (1; 2 on D2Q9; 2, 4 or 8 on D1Q3)
+    int t2_tx, t2_rows;  // multi-step kernels: owned columns (nodes) and rows per workgroup
     bool zhalo;        // z-slab: each buffer holds halo planes -1 and nz around the nz planes
     int64_t plane;     // elements of one plane (rows layout: ny * rs)
     int red_blocks;    // workgroups of the moments reduction

@@ -132,6 +132,25 @@ def test_time_block_configs(lbm):
     assert lbm.lbm_workspace_bytes(cfg, lbm.make_tuning(time_block=1)) > 0
 
 
+def test_d1q3_time_block_configs(lbm):
+    """K = 2, 4 or 8 steps per launch on D1Q3: FP64 or FP32_DEV, entropic, long
+    enough rows (nx >= 1032 FP32, 520 FP64); D2Q9 takes 2 only."""
+    for K in (2, 4, 8):
+        assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(1032,), dtype="fp32_dev"),
+                                       lbm.make_tuning(time_block=K)) > 0
+        assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(520,)), lbm.make_tuning(time_block=K)) > 0
+        assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(1031,), dtype="fp32_dev"),
+                                       lbm.make_tuning(time_block=K)) == 0
+        assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(519,)), lbm.make_tuning(time_block=K)) == 0
+    for K in (3, 5, 16):
+        assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(4096,)), lbm.make_tuning(time_block=K)) == 0
+    for K in (4, 8):
+        assert lbm.lbm_workspace_bytes(_cfg(lbm, shape=(4096, 64)), lbm.make_tuning(time_block=K)) == 0
+    assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(4096,), equilibrium="poly2"),
+                                   lbm.make_tuning(time_block=4)) == 0
+    assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(4096,)), lbm.make_tuning(time_block=4, time_rows=2)) == 0
+
+
 def test_polynomial_equilibria_configs(lbm):
     """The polynomial kinds take both production storage modes and the scalar
     or default vector kernel; other vector tunings are refused."""

@@ -1,4 +1,5 @@
-"""Two LBGK steps per launch on D2Q9 (lbm_tuning.time_block = 2): the
+"""Several LBGK steps per launch (lbm_tuning.time_block): two on D2Q9, and
+2, 4 or 8 on D1Q3.  On D2Q9 (time_block = 2) the
 intermediate state stays in LDS, and every node runs the same collision code
 as the one-step kernels, so results must be bitwise those of the default
 one-step path -- for both storage types, with and without the correction,
@@ -92,3 +93,59 @@ def test_two_step_full_size_bitwise(dtype):
     with lbm.Domain(rho0, u0, 0.51, dtype=dtype) as b:
         b.step(4)
         assert np.array_equal(fa, b.populations())
+
+
+D1Q3_CASES = [  # nx, dtype, correction, K, step chunks
+    (1032, "fp32_dev", False, 2, (1, 2, 7, 64)),
+    (1500, "fp32_dev", True, 4, (3, 70)),
+    (4096, "fp64", False, 8, (8, 9, 100)),
+    (520, "fp64", True, 8, (17,)),
+    (1 << 20, "fp32_dev", True, 8, (40,)),
+    (5000, "fp64", True, 4, (66,)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(D1Q3_CASES)))
+def test_d1q3_multi_step_equals_one_step_bitwise(case):
+    """K steps per launch on D1Q3 (LDS segments with K nodes of halo): bitwise
+    the one-step path, on ragged lengths, the smallest allowed length, graph
+    replays (>= 64 steps) and counts that leave a remainder."""
+    lbm = _lbm()
+    nx, dtype, corr, K, chunks = D1Q3_CASES[case]
+    rho0, u0 = workloads.random_field((nx,), seed=60 + case, umax=0.1)
+    with lbm.Domain(rho0, u0, 0.55, dtype=dtype, bulk_correction=corr,
+                    tuning=lbm.make_tuning(time_block=K)) as a, \
+            lbm.Domain(rho0, u0, 0.55, dtype=dtype, bulk_correction=corr,
+                       tuning=lbm.make_tuning(time_block=1)) as b:
+        done = 0
+        for n in chunks:
+            a.step(n)
+            b.step(n)
+            done += n
+            ra, ua, da = a.moments()
+            rb, ub, db = b.moments()
+            assert da["steps"] == db["steps"] == done
+            assert np.array_equal(ra, rb) and np.array_equal(ua, ub), (nx, K, done)
+        assert np.array_equal(a.populations(), b.populations())
+
+
+def test_d1q3_multi_step_matches_oracle_and_flags():
+    lbm = _lbm()
+    rho0, u0 = workloads.pressure_wave(2048, 1e-3, 0.1)
+    r_ref, u_ref, bad = oracle.run(rho0, u0, 0.6, 48, corr="min")
+    assert bad == 0
+    with lbm.Domain(rho0, u0, 0.6, dtype="fp64", bulk_correction=True, tuning=lbm.make_tuning(time_block=8)) as d:
+        d.step(48)
+        rho, u, _ = d.moments()
+    assert np.max(np.abs(rho - r_ref)) / np.max(np.abs(r_ref)) < 1e-12
+    assert np.max(np.abs(u - u_ref)) / np.max(np.abs(u_ref)) < 1e-12
+    for seed in range(80, 83):
+        rho0, u0 = workloads.random_field((2048,), seed=seed, umax=0.99, rho_lo=0.3, rho_hi=2.0)
+        with lbm.Domain(rho0, u0, 0.5001, dtype="fp64", tuning=lbm.make_tuning(time_block=4)) as a, \
+                lbm.Domain(rho0, u0, 0.5001, dtype="fp64", tuning=lbm.make_tuning(time_block=1)) as b:
+            for n in (1, 4, 5, 8):
+                a.step(n)
+                b.step(n)
+                fa = a.moments(fields=False, raise_on_domain=False)[2]["domain_error"]
+                fb = b.moments(fields=False, raise_on_domain=False)[2]["domain_error"]
+                assert fa == fb, (seed, n)
