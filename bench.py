@@ -322,11 +322,10 @@ def bench_oracle_timing(budget_s: float = 6.0) -> dict:
     return out
 
 
-def bench_variants(steps: int = 100, warmup: int = 10, steps_1d: int = 200, warmup_1d: int = 20) -> dict:
+def bench_variants(steps: int = 100, warmup: int = 10) -> dict:
     """Throughput of the other equilibria and of the correction on the headline
     grid (D3Q27 256^3 Taylor-Green, FP32 deviation storage, default vector
-    kernel), and of a D1Q3 row of 2^27 nodes (more steps: one takes ~0.6 ms)."""
-    import numpy as np
+    kernel)."""
     import torch
 
     from paper_2303_08163_amd import lbm, workloads
@@ -359,19 +358,52 @@ def bench_variants(steps: int = 100, warmup: int = 10, steps_1d: int = 200, warm
             out[f"d3q27_256_fp32_{eq}{'_corrected' if corr else ''}"] = timed(dom, 256 ** 3, 216)
             dom.close()
     del rd, ud
+    return {"steps": steps, "results": out}
+
+
+def bench_d1q3(steps: int = 200, warmup: int = 20) -> dict:
+    """A D1Q3 row of 2^27 nodes (a pressure wave, U = 0.1, tau 0.6, with the
+    correction), FP32 deviations and FP64, with the default eight steps per
+    launch and with one; more steps than elsewhere (one step takes ~0.6 ms,
+    50 steps read up to 7 % low)."""
+    import numpy as np
+    import torch
+
+    from paper_2303_08163_amd import lbm
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+
+    def timed(dom, nodes, bytes_per_lup):
+        dom.step(warmup)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        dom.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3
+        _, _, d = dom.moments(fields=False)
+        mlups = nodes * steps / sec / 1e6
+        return {"mlups": round(mlups, 1), "us_per_step": round(sec / steps * 1e6, 2),
+                "gbs_2Qs_per_update": round(mlups * 1e6 * bytes_per_lup / 1e9, 1),
+                "frac": round(mlups * 1e6 * bytes_per_lup / 1e9 / HBM_PEAK_GBS, 4), "domain_error": d["domain_error"]}
+
     n1 = 1 << 27
     x = np.arange(n1, dtype=np.float64)
     r1 = torch.from_numpy(1.0 + 1e-3 * np.sin(2 * math.pi * x / n1)).to(dev)
     u1 = torch.full((1, n1), 0.1, dtype=torch.float64, device=dev)
     del x
-    # D1Q3: the default (eight steps per launch) and one step per launch; gbs / frac
-    # count 2 Q s bytes per node update, so for the former they are equivalent rates
+    # the default (eight steps per launch) and one step per launch; gbs / frac count
+    # 2 Q s bytes per node update, so for the former they are equivalent rates
     for dt, s in (("fp32_dev", 4), ("fp64", 8)):
-        for name, tun in (("", None), ("_one_step_per_launch", lbm.make_tuning(time_block=1))):
+        for name, tun in (("eight_steps_per_launch", None), ("one_step_per_launch", lbm.make_tuning(time_block=1))):
             dom = lbm.Domain(r1, u1, 0.6, dtype=dt, bulk_correction=True, stream=stream, tuning=tun)
-            out[f"d1q3_2^27_{dt}_corrected{name}"] = timed(dom, n1, 2 * 3 * s, steps_1d, warmup_1d)
+            out[f"{dt}_{name}"] = timed(dom, n1, 2 * 3 * s)
             dom.close()
-    return {"steps": steps, "steps_d1q3": steps_1d, "results": out}
+    return {"workload": "D1Q3 2^27 nodes, pressure wave rho = 1 + 1e-3 sin(2 pi x / N), U = 0.1, tau 0.6, "
+                        "bulk correction on", "steps": steps, "results": out}
 
 
 def bench_d2q9(steps: int = 100, warmup: int = 10) -> dict:
@@ -502,8 +534,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256, help="grid side (headline: 256)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sections", default="headline,batched,serving,wave,stability,variants,slab,d2q9",
-                    help="comma list of headline, batched, serving, wave, stability, variants, slab, d2q9, "
+    ap.add_argument("--sections", default="headline,batched,serving,wave,stability,variants,slab,d2q9,d1q3",
+                    help="comma list of headline, batched, serving, wave, stability, variants, slab, d2q9, d1q3, "
                          "oracle_timing (not in the default run: several minutes of host time)")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=2000)
@@ -644,6 +676,9 @@ def main() -> int:
     if "d2q9" in sections:
         out["d2q9"] = bench_d2q9()
         progress("d2q9 done")
+    if "d1q3" in sections:
+        out["d1q3"] = bench_d1q3()
+        progress("d1q3 done")
     if "stability" in sections:
         out["stability"] = bench_stability(with_cpu=not args.no_cpu_baseline)
         progress("stability done")
