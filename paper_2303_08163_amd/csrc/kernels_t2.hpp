@@ -35,7 +35,7 @@ struct Step2Args {
     const void *src;  // f*(t), row-interleaved layout
     void *dst;        // f*(t + 2)
     int nx, ny;
-    int tx;           // owned columns per workgroup (blockDim.x; nx % tx == 0)
+    int tx;           // owned columns per workgroup (nx % tx == 0; 64 .. 512)
     int rows;         // owned rows per workgroup
     int tiles_x, tiles_y;
     int64_t ps, rs;
@@ -103,7 +103,7 @@ __device__ __forceinline__ void pull_row_d2q9(const T *__restrict__ src, int ny,
 // column x0 + t; with the halo wavefront, lane t < tx + 2 computes step 1 at
 // x0 - 1 + t and lane t < tx step 2 at x0 + t.
 template <int DT, bool CORR>
-__global__ __launch_bounds__(320) void k_stream_collide2(Step2Args a) {
+__global__ __launch_bounds__(512) void k_stream_collide2(Step2Args a) {
     using T = store_t<DT>;
     constexpr bool HW = t2_halo_wave(sizeof(T));
     constexpr int CH = kT2Chunk;

@@ -261,23 +261,27 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
             set_error("time_rows must lie in 0 .. ny");
             return LBM_EINVAL;
         }
-        // owned columns: the widest of 256 (FP32) or 128 (FP64), 128, 64 dividing nx, so
-        // that the LDS ring stays near 37 KB and four workgroups fit a compute unit
-        int tx = fp32 ? 256 : 128;
+        // owned columns: the widest of 512 (FP32) or 128 (FP64), then 256, 128, 64 that
+        // divides nx.  Measured at 4096^2 FP32, us per step: 512 columns 139.8 (76 KB of LDS,
+        // two workgroups per compute unit), 256 146.1 (39 KB, four), 128 156.2; FP64 takes
+        // 128 (37 KB, four workgroups of three wavefronts)
+        int tx = fp32 ? 512 : 128;
         while (cfg->nx % tx != 0)
             tx /= 2;
         const int64_t tiles_x = cfg->nx / tx;
+        // workgroups resident at once: 256 compute units x those that fit 160 KB of LDS
+        const int64_t per_cu = std::max<int64_t>(1, (int64_t)163840 / (int64_t)t2_lds_bytes(tx, L.elem));
+        const int64_t round = 256 * std::min<int64_t>(per_cu, 8);
         if (trows == 0) {
-            // Four workgroups fit a compute unit (LDS), 1024 the chip; a workgroup's time
-            // is about that of its rows + 2 sweep rows.  Take the row count with the least
-            // (rounds of 1024 workgroups) x (rows + 2), so that the last round is not
-            // mostly idle (3072^2 FP64: 36 rows, 2064 workgroups, 170.8 us per step;
-            // 16 rows: 139.9).
+            // A workgroup's time is about that of its rows + 2 sweep rows.  Take the row
+            // count with the least (rounds of resident workgroups) x (rows + 2), so that
+            // the last round is not mostly idle (3072^2 FP64, 1024 resident: 36 rows,
+            // 2064 workgroups, 170.8 us per step; 16 rows: 139.9).
             int64_t best = -1;
             for (int cand : {16, 24, 32, 48, 64, 96, 128}) {
                 const int64_t rws = std::min<int64_t>(cand, cfg->ny);
                 const int64_t wgs = tiles_x * ((cfg->ny + rws - 1) / rws);
-                const int64_t cost = (wgs + 1023) / 1024 * (rws + 2);
+                const int64_t cost = (wgs + round - 1) / round * (rws + 2);
                 if (best < 0 || cost < best) {
                     best = cost;
                     trows = (int)rws;
