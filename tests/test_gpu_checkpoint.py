@@ -26,6 +26,9 @@ CASES = [  # (fields, dtype, correction, tuning kwargs)
     (lambda: workloads.random_field((4, 6, 128), seed=14, umax=0.1), "fp64", False,
      dict(block_x=64, nodes_per_thread=2)),
     (lambda: workloads.random_field((100,), seed=15, umax=0.1), "fp64", True, None),
+    # multi-step launches: the saved state is the same stored buffer
+    (lambda: workloads.random_field((24, 192), seed=19, umax=0.1), "fp32_dev", True, dict(time_block=2)),
+    (lambda: workloads.random_field((3000,), seed=20, umax=0.1), "fp32_dev", False, dict(time_block=8)),
 ]
 
 
