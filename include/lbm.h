@@ -122,8 +122,8 @@ typedef struct lbm_tuning {
     int32_t flags;            /* LBM_TUNE_* bits for the vector kernels; < 0 selects the default */
     int32_t layout;           /* LBM_LAYOUT_*; 0 = default (row-interleaved) */
     int32_t time_block;       /* LBGK steps per launch, the intermediate states kept in LDS
-                                 (LBM_FP64 or LBM_FP32_DEV, entropic equilibrium,
-                                 row-interleaved layout): 1 = one; 2 on D2Q9 with nx a
+                                 (LBM_FP64 or LBM_FP32_DEV, any equilibrium, row-interleaved
+                                 layout): 1 = one; 2 on D2Q9 with nx a
                                  multiple of 64; 2, 4 or 8 on D1Q3 with nx >= 1032 (FP32) or
                                  520 (FP64).  Step counts that are not a multiple end with
                                  one-step launches of the kernel the other fields select.

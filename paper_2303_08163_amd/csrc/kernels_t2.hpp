@@ -102,7 +102,7 @@ __device__ __forceinline__ void pull_row_d2q9(const T *__restrict__ src, int ny,
 // column x0 - 1 + c.  With chunks, lane t computes step 1 and step 2 at
 // column x0 + t; with the halo wavefront, lane t < tx + 2 computes step 1 at
 // x0 - 1 + t and lane t < tx step 2 at x0 + t.
-template <int DT, bool CORR>
+template <int DT, bool CORR, int EQ = kEqEntropic>
 __global__ __launch_bounds__(512) void k_stream_collide2(Step2Args a) {
     using T = store_t<DT>;
     constexpr bool HW = t2_halo_wave(sizeof(T));
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(512) void k_stream_collide2(Step2Args a) {
         if (!HW && k % CH == 0) {
             if (w0) {
                 const bool valid = t < 2 * CH && k + (t >> 1) < nsweep;
-                const bool badh = collide_dt<2, DT, CORR>(h, a.relax);
+                const bool badh = collide_dt<2, DT, CORR, EQ>(h, a.relax);
                 raise_flag(a.flag, badh && valid);
                 if (valid) {
 #pragma unroll
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(512) void k_stream_collide2(Step2Args a) {
             __syncthreads();
         }
         // step 1 at sweep row r into ring slot k mod 4 (column c <-> x0 - 1 + c)
-        const bool bad1 = collide_dt<2, DT, CORR>(f, a.relax);
+        const bool bad1 = collide_dt<2, DT, CORR, EQ>(f, a.relax);
         raise_flag(a.flag, bad1 && s1);
         T *slot = ring + (size_t)(k & (kT2Ring - 1)) * 9 * w1;
         if (s1) {
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(512) void k_stream_collide2(Step2Args a) {
                     g[i] = srow[i * w1 + t + 2 - cx];
                 }
             }
-            const bool bad2 = collide_dt<2, DT, CORR>(g, a.relax);
+            const bool bad2 = collide_dt<2, DT, CORR, EQ>(g, a.relax);
             raise_flag(a.flag, bad2);
             const uint32_t ob = (uint32_t)(x * (int)sizeof(T));
 #pragma unroll
@@ -260,7 +260,7 @@ __host__ __device__ constexpr size_t t1_lds_bytes(int tx, int K, size_t elem) {
     return (size_t)2 * 3 * (size_t)(tx + 2 * K) * elem;
 }
 
-template <int DT, bool CORR>
+template <int DT, bool CORR, int EQ = kEqEntropic>
 __global__ __launch_bounds__(256) void k_stream_collide_t1(StepKArgs a) {
     using T = store_t<DT>;
     extern __shared__ __align__(16) unsigned char t1_lds[];
@@ -279,7 +279,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_t1(StepKArgs a) {
 #pragma unroll
         for (int cx = 0; cx < 3; ++cx)
             f[cx] = src[cx * a.ps + wrap(x + 1 - cx)];
-        const bool bad = collide_dt<1, DT, CORR>(f, a.relax);
+        const bool bad = collide_dt<1, DT, CORR, EQ>(f, a.relax);
         raise_flag(a.flag, bad);
         if (a.K == 1) {
             if (m >= 1 && m < 1 + a.tx && x < a.nx)
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_t1(StepKArgs a) {
 #pragma unroll
             for (int cx = 0; cx < 3; ++cx)
                 f[cx] = in[cx * w + m + 1 - cx];
-            const bool bad = collide_dt<1, DT, CORR>(f, a.relax);
+            const bool bad = collide_dt<1, DT, CORR, EQ>(f, a.relax);
             raise_flag(a.flag, bad);
             if (j == a.K) {
                 const int x = x0 - a.K + m;  // m in [K, K + tx): x0 <= x < x0 + tx

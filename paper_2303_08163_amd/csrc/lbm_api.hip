@@ -200,12 +200,12 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
             return LBM_EINVAL;
         }
     }
-    const bool t2_fits = L.dim == 2 && layout == LBM_LAYOUT_ROWS && L.eq == LBM_EQ_ENTROPIC &&
+    const bool t2_fits = L.dim == 2 && layout == LBM_LAYOUT_ROWS &&
                          (cfg->dtype == LBM_FP64 || cfg->dtype == LBM_FP32_DEV) && cfg->nx % 64 == 0;
     // D1Q3, K steps per launch: owned nodes per workgroup (the LDS segment is 2 x 3 x
     // (tx + 2K) elements, 25 KB at K = 8), and nx >= tx + K for a single periodic wrap
     const int t1_tx = fp32 ? 1024 : 512;
-    const bool t1_fits = L.dim == 1 && layout == LBM_LAYOUT_ROWS && L.eq == LBM_EQ_ENTROPIC &&
+    const bool t1_fits = L.dim == 1 && layout == LBM_LAYOUT_ROWS &&
                          (cfg->dtype == LBM_FP64 || cfg->dtype == LBM_FP32_DEV) && cfg->nx >= t1_tx + 8;
     if (tblock == 0) {
         // default: two steps per launch for large D2Q9 domains.  A workgroup sweeps its
@@ -227,9 +227,8 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
             return LBM_EINVAL;
         }
         if (!t1_fits || trows != 0) {
-            set_error("time_block > 1 on D1Q3 needs the row-interleaved layout, the entropic "
-                      "equilibrium, LBM_FP64 or LBM_FP32_DEV, nx >= 1032 (FP32) or 520 (FP64), "
-                      "and time_rows = 0");
+            set_error("time_block > 1 on D1Q3 needs the row-interleaved layout, LBM_FP64 or "
+                      "LBM_FP32_DEV, nx >= 1032 (FP32) or 520 (FP64), and time_rows = 0");
             return LBM_EINVAL;
         }
         L.tblock = tblock;
@@ -253,8 +252,8 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
     }
     if (tblock == 2) {
         if (!t2_fits) {
-            set_error("time_block = 2 needs D2Q9, the row-interleaved layout, the entropic "
-                      "equilibrium, LBM_FP64 or LBM_FP32_DEV, and nx a multiple of 64");
+            set_error("time_block = 2 needs D2Q9, the row-interleaved layout, LBM_FP64 or "
+                      "LBM_FP32_DEV, and nx a multiple of 64");
             return LBM_EINVAL;
         }
         if (trows < 0 || trows > cfg->ny) {
@@ -468,13 +467,25 @@ int launch_step(const Layout &L, const StepArgs &args, int dtype, bool corr, hip
     return LBM_OK;
 }
 
+// Multi-step kernels by storage, correction and equilibrium.
+template <int EQ>
+static void (*t1_kernel(int dtype, bool corr))(StepKArgs) {
+    return dtype == kF64 ? (corr ? k_stream_collide_t1<kF64, true, EQ> : k_stream_collide_t1<kF64, false, EQ>)
+                         : (corr ? k_stream_collide_t1<kDevF64, true, EQ> : k_stream_collide_t1<kDevF64, false, EQ>);
+}
+template <int EQ>
+static void (*t2_kernel(int dtype, bool corr))(Step2Args) {
+    return dtype == kF64 ? (corr ? k_stream_collide2<kF64, true, EQ> : k_stream_collide2<kF64, false, EQ>)
+                         : (corr ? k_stream_collide2<kDevF64, true, EQ> : k_stream_collide2<kDevF64, false, EQ>);
+}
+
 // Several steps in one launch (time_block > 1): src -> dst = f*(t + time_block).
 int launch_step2(const Layout &L, const StepArgs &args, int dtype, bool corr, hipStream_t s) {
     if (L.dim == 1) {
         StepKArgs a{args.src, args.dst, args.nx, L.t2_tx, L.tblock, L.ps, args.relax, args.flag};
-        void (*fn)(StepKArgs) = dtype == kF64
-                                    ? (corr ? k_stream_collide_t1<kF64, true> : k_stream_collide_t1<kF64, false>)
-                                    : (corr ? k_stream_collide_t1<kDevF64, true> : k_stream_collide_t1<kDevF64, false>);
+        void (*fn)(StepKArgs) = L.eq == LBM_EQ_POLY2     ? t1_kernel<kEqPoly2>(dtype, corr)
+                                : L.eq == LBM_EQ_PRODUCT ? t1_kernel<kEqProduct>(dtype, corr)
+                                                         : t1_kernel<kEqEntropic>(dtype, corr);
         hipLaunchKernelGGL(fn, dim3((unsigned)((args.nx + a.tx - 1) / a.tx)), dim3(256),
                            (unsigned)t1_lds_bytes(a.tx, a.K, L.elem), s, a);
         hipError_t e = hipGetLastError();
@@ -484,8 +495,9 @@ int launch_step2(const Layout &L, const StepArgs &args, int dtype, bool corr, hi
     }
     Step2Args a{args.src, args.dst, args.nx, args.ny, L.t2_tx, L.t2_rows, args.nx / L.t2_tx,
                 (args.ny + L.t2_rows - 1) / L.t2_rows, L.ps, L.rs, args.relax, args.flag};
-    void (*fn)(Step2Args) = dtype == kF64 ? (corr ? k_stream_collide2<kF64, true> : k_stream_collide2<kF64, false>)
-                                          : (corr ? k_stream_collide2<kDevF64, true> : k_stream_collide2<kDevF64, false>);
+    void (*fn)(Step2Args) = L.eq == LBM_EQ_POLY2     ? t2_kernel<kEqPoly2>(dtype, corr)
+                            : L.eq == LBM_EQ_PRODUCT ? t2_kernel<kEqProduct>(dtype, corr)
+                                                     : t2_kernel<kEqEntropic>(dtype, corr);
     hipLaunchKernelGGL(fn, dim3((unsigned)(a.tiles_x * a.tiles_y)), dim3((unsigned)t2_threads(a.tx, L.elem)),
                        (unsigned)t2_lds_bytes(a.tx, L.elem), s, a);
     hipError_t e = hipGetLastError();

@@ -109,8 +109,8 @@ def test_valid_tunings_accepted(lbm):
 
 
 def test_time_block_configs(lbm):
-    """Two steps per launch: D2Q9, FP64 or FP32_DEV, entropic, rows layout,
-    nx a multiple of 64; the workspace is that of the one-step domain."""
+    """Two steps per launch: D2Q9, FP64 or FP32_DEV, rows layout, nx a
+    multiple of 64; the workspace is that of the one-step domain."""
     two = lbm.make_tuning(time_block=2)
     for dt in ("fp64", "fp32_dev"):
         for nx in (64, 192, 4096):
@@ -121,7 +121,7 @@ def test_time_block_configs(lbm):
             assert lbm.lbm_workspace_bytes(cfg, lbm.make_tuning(time_block=2, time_rows=-1)) == 0
     refused = [_cfg(lbm, shape=(96, 8)), _cfg(lbm, shape=(100, 8), dtype="fp32_dev"),
                _cfg(lbm, lattice=27, shape=(64, 8, 8)), _cfg(lbm, lattice=3, shape=(256,)),
-               _cfg(lbm, shape=(64, 8), dtype="fp32_dev_mixed"), _cfg(lbm, shape=(64, 8), equilibrium="poly2")]
+               _cfg(lbm, shape=(64, 8), dtype="fp32_dev_mixed")]
     for cfg in refused:
         assert lbm.lbm_workspace_bytes(cfg, two) == 0
     assert b"time_block" in lbm.load_library().lbm_last_error()
@@ -133,8 +133,8 @@ def test_time_block_configs(lbm):
 
 
 def test_d1q3_time_block_configs(lbm):
-    """K = 2, 4 or 8 steps per launch on D1Q3: FP64 or FP32_DEV, entropic, long
-    enough rows (nx >= 1032 FP32, 520 FP64); D2Q9 takes 2 only."""
+    """K = 2, 4 or 8 steps per launch on D1Q3: FP64 or FP32_DEV, long enough
+    rows (nx >= 1032 FP32, 520 FP64); D2Q9 takes 2 only."""
     for K in (2, 4, 8):
         assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(1032,), dtype="fp32_dev"),
                                        lbm.make_tuning(time_block=K)) > 0
@@ -146,8 +146,10 @@ def test_d1q3_time_block_configs(lbm):
         assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(4096,)), lbm.make_tuning(time_block=K)) == 0
     for K in (4, 8):
         assert lbm.lbm_workspace_bytes(_cfg(lbm, shape=(4096, 64)), lbm.make_tuning(time_block=K)) == 0
-    assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(4096,), equilibrium="poly2"),
-                                   lbm.make_tuning(time_block=4)) == 0
+    for eq in ("poly2", "product"):  # every equilibrium, on both lattices
+        assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(4096,), equilibrium=eq),
+                                       lbm.make_tuning(time_block=4)) > 0
+        assert lbm.lbm_workspace_bytes(_cfg(lbm, shape=(128, 8), equilibrium=eq), lbm.make_tuning(time_block=2)) > 0
     assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(4096,)), lbm.make_tuning(time_block=4, time_rows=2)) == 0
 
 

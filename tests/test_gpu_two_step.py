@@ -149,3 +149,19 @@ def test_d1q3_multi_step_matches_oracle_and_flags():
                 fa = a.moments(fields=False, raise_on_domain=False)[2]["domain_error"]
                 fb = b.moments(fields=False, raise_on_domain=False)[2]["domain_error"]
                 assert fa == fb, (seed, n)
+
+
+@pytest.mark.parametrize("eq", ["poly2", "product"])
+def test_multi_step_polynomial_equilibria_bitwise(eq):
+    """The polynomial and product-form equilibria take the same multi-step
+    kernels: two steps on D2Q9, four on D1Q3, bitwise one step per launch."""
+    lbm = _lbm()
+    for shape, K, dtype in (((36, 256), 2, "fp32_dev"), ((40, 192), 2, "fp64"), ((3000,), 4, "fp32_dev"),
+                            ((1100,), 4, "fp64")):
+        rho0, u0 = workloads.random_field(shape, seed=90, umax=0.08)
+        kw = dict(dtype=dtype, bulk_correction=True, equilibrium=eq)
+        with lbm.Domain(rho0, u0, 0.56, tuning=lbm.make_tuning(time_block=K), **kw) as a, \
+                lbm.Domain(rho0, u0, 0.56, tuning=lbm.make_tuning(time_block=1), **kw) as b:
+            a.step(70)
+            b.step(70)
+            assert np.array_equal(a.populations(), b.populations()), (eq, shape)
