@@ -206,11 +206,13 @@ __global__ __launch_bounds__(512) void k_stream_collide2(Step2Args a) {
             }
             const bool bad2 = collide_dt<2, DT, CORR, EQ>(g, a.relax);
             raise_flag(a.flag, bad2);
+            // non-temporal stores: the output is not read again in this launch (4096^2, us
+            // per step: FP64 212.4 against 224.4 with plain stores, FP32 127.3 against 131.2)
             const uint32_t ob = (uint32_t)(x * (int)sizeof(T));
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 char *base = reinterpret_cast<char *>(dst + (int64_t)y * a.rs + (int64_t)i * a.ps);
-                *reinterpret_cast<T *>(base + ob) = g[i];
+                __builtin_nontemporal_store(g[i], reinterpret_cast<T *>(base + ob));
             }
         }
     };
@@ -309,7 +311,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_t1(StepKArgs a) {
                 if (x < a.nx)
 #pragma unroll
                     for (int i = 0; i < 3; ++i)
-                        dst[i * a.ps + x] = f[i];
+                        __builtin_nontemporal_store(f[i], dst + i * a.ps + x);
             } else {
 #pragma unroll
                 for (int i = 0; i < 3; ++i)
