@@ -43,6 +43,15 @@ struct Step2Args {
     int *flag;
 };
 
+// Non-temporal output stores pay when the two population buffers exceed the
+// 256 MB last-level (Infinity) cache: 4096^2 D2Q9, us per step, FP64 212.4
+// against 224.4 with plain stores.  When both fit, the next launch reads the
+// output from that cache, and non-temporal stores lose it (1024^2 FP64: 20.3
+// against 16.3).  A compile-time choice (the NT parameter of the kernels): as
+// a run-time branch the compiler merges the two store sequences and drops
+// the hint.
+__host__ __device__ constexpr bool t2_nt_stores(size_t buf_bytes) { return 2 * buf_bytes > ((size_t)192 << 20); }
+
 constexpr int kT2Ring = 4;  // LDS rows in the ring (see the barrier note below)
 
 // The two step-1 halo columns of a row: with float storage wavefront 0
@@ -102,7 +111,7 @@ __device__ __forceinline__ void pull_row_d2q9(const T *__restrict__ src, int ny,
 // column x0 - 1 + c.  With chunks, lane t computes step 1 and step 2 at
 // column x0 + t; with the halo wavefront, lane t < tx + 2 computes step 1 at
 // x0 - 1 + t and lane t < tx step 2 at x0 + t.
-template <int DT, bool CORR, int EQ = kEqEntropic>
+template <int DT, bool CORR, int EQ = kEqEntropic, bool NT = false>
 __global__ __launch_bounds__(512) void k_stream_collide2(Step2Args a) {
     using T = store_t<DT>;
     constexpr bool HW = t2_halo_wave(sizeof(T));
@@ -206,13 +215,19 @@ __global__ __launch_bounds__(512) void k_stream_collide2(Step2Args a) {
             }
             const bool bad2 = collide_dt<2, DT, CORR, EQ>(g, a.relax);
             raise_flag(a.flag, bad2);
-            // non-temporal stores: the output is not read again in this launch (4096^2, us
-            // per step: FP64 212.4 against 224.4 with plain stores, FP32 127.3 against 131.2)
             const uint32_t ob = (uint32_t)(x * (int)sizeof(T));
+            if constexpr (NT) {
 #pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                char *base = reinterpret_cast<char *>(dst + (int64_t)y * a.rs + (int64_t)i * a.ps);
-                __builtin_nontemporal_store(g[i], reinterpret_cast<T *>(base + ob));
+                for (int i = 0; i < 9; ++i) {
+                    char *base = reinterpret_cast<char *>(dst + (int64_t)y * a.rs + (int64_t)i * a.ps);
+                    __builtin_nontemporal_store(g[i], reinterpret_cast<T *>(base + ob));
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    char *base = reinterpret_cast<char *>(dst + (int64_t)y * a.rs + (int64_t)i * a.ps);
+                    *reinterpret_cast<T *>(base + ob) = g[i];
+                }
             }
         }
     };
@@ -262,7 +277,7 @@ __host__ __device__ constexpr size_t t1_lds_bytes(int tx, int K, size_t elem) {
     return (size_t)2 * 3 * (size_t)(tx + 2 * K) * elem;
 }
 
-template <int DT, bool CORR, int EQ = kEqEntropic>
+template <int DT, bool CORR, int EQ = kEqEntropic, bool NT = false>
 __global__ __launch_bounds__(256) void k_stream_collide_t1(StepKArgs a) {
     using T = store_t<DT>;
     extern __shared__ __align__(16) unsigned char t1_lds[];
@@ -308,10 +323,17 @@ __global__ __launch_bounds__(256) void k_stream_collide_t1(StepKArgs a) {
             raise_flag(a.flag, bad);
             if (j == a.K) {
                 const int x = x0 - a.K + m;  // m in [K, K + tx): x0 <= x < x0 + tx
-                if (x < a.nx)
+                if (x < a.nx) {
+                    if constexpr (NT) {
 #pragma unroll
-                    for (int i = 0; i < 3; ++i)
-                        __builtin_nontemporal_store(f[i], dst + i * a.ps + x);
+                        for (int i = 0; i < 3; ++i)
+                            __builtin_nontemporal_store(f[i], dst + i * a.ps + x);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i)
+                            dst[i * a.ps + x] = f[i];
+                    }
+                }
             } else {
 #pragma unroll
                 for (int i = 0; i < 3; ++i)

@@ -467,25 +467,35 @@ int launch_step(const Layout &L, const StepArgs &args, int dtype, bool corr, hip
     return LBM_OK;
 }
 
-// Multi-step kernels by storage, correction and equilibrium.
-template <int EQ>
-static void (*t1_kernel(int dtype, bool corr))(StepKArgs) {
-    return dtype == kF64 ? (corr ? k_stream_collide_t1<kF64, true, EQ> : k_stream_collide_t1<kF64, false, EQ>)
-                         : (corr ? k_stream_collide_t1<kDevF64, true, EQ> : k_stream_collide_t1<kDevF64, false, EQ>);
+// Multi-step kernels by storage, correction, equilibrium and store hint.
+template <int EQ, bool NT>
+static void (*t1_kernel_nt(int dtype, bool corr))(StepKArgs) {
+    return dtype == kF64 ? (corr ? k_stream_collide_t1<kF64, true, EQ, NT> : k_stream_collide_t1<kF64, false, EQ, NT>)
+                         : (corr ? k_stream_collide_t1<kDevF64, true, EQ, NT>
+                                 : k_stream_collide_t1<kDevF64, false, EQ, NT>);
 }
 template <int EQ>
-static void (*t2_kernel(int dtype, bool corr))(Step2Args) {
-    return dtype == kF64 ? (corr ? k_stream_collide2<kF64, true, EQ> : k_stream_collide2<kF64, false, EQ>)
-                         : (corr ? k_stream_collide2<kDevF64, true, EQ> : k_stream_collide2<kDevF64, false, EQ>);
+static void (*t1_kernel(int dtype, bool corr, bool nt))(StepKArgs) {
+    return nt ? t1_kernel_nt<EQ, true>(dtype, corr) : t1_kernel_nt<EQ, false>(dtype, corr);
+}
+template <int EQ, bool NT>
+static void (*t2_kernel_nt(int dtype, bool corr))(Step2Args) {
+    return dtype == kF64 ? (corr ? k_stream_collide2<kF64, true, EQ, NT> : k_stream_collide2<kF64, false, EQ, NT>)
+                         : (corr ? k_stream_collide2<kDevF64, true, EQ, NT> : k_stream_collide2<kDevF64, false, EQ, NT>);
+}
+template <int EQ>
+static void (*t2_kernel(int dtype, bool corr, bool nt))(Step2Args) {
+    return nt ? t2_kernel_nt<EQ, true>(dtype, corr) : t2_kernel_nt<EQ, false>(dtype, corr);
 }
 
 // Several steps in one launch (time_block > 1): src -> dst = f*(t + time_block).
 int launch_step2(const Layout &L, const StepArgs &args, int dtype, bool corr, hipStream_t s) {
     if (L.dim == 1) {
         StepKArgs a{args.src, args.dst, args.nx, L.t2_tx, L.tblock, L.ps, args.relax, args.flag};
-        void (*fn)(StepKArgs) = L.eq == LBM_EQ_POLY2     ? t1_kernel<kEqPoly2>(dtype, corr)
-                                : L.eq == LBM_EQ_PRODUCT ? t1_kernel<kEqProduct>(dtype, corr)
-                                                         : t1_kernel<kEqEntropic>(dtype, corr);
+        const bool nt = t2_nt_stores(L.buf_bytes);
+        void (*fn)(StepKArgs) = L.eq == LBM_EQ_POLY2     ? t1_kernel<kEqPoly2>(dtype, corr, nt)
+                                : L.eq == LBM_EQ_PRODUCT ? t1_kernel<kEqProduct>(dtype, corr, nt)
+                                                         : t1_kernel<kEqEntropic>(dtype, corr, nt);
         hipLaunchKernelGGL(fn, dim3((unsigned)((args.nx + a.tx - 1) / a.tx)), dim3(256),
                            (unsigned)t1_lds_bytes(a.tx, a.K, L.elem), s, a);
         hipError_t e = hipGetLastError();
@@ -495,9 +505,10 @@ int launch_step2(const Layout &L, const StepArgs &args, int dtype, bool corr, hi
     }
     Step2Args a{args.src, args.dst, args.nx, args.ny, L.t2_tx, L.t2_rows, args.nx / L.t2_tx,
                 (args.ny + L.t2_rows - 1) / L.t2_rows, L.ps, L.rs, args.relax, args.flag};
-    void (*fn)(Step2Args) = L.eq == LBM_EQ_POLY2     ? t2_kernel<kEqPoly2>(dtype, corr)
-                            : L.eq == LBM_EQ_PRODUCT ? t2_kernel<kEqProduct>(dtype, corr)
-                                                     : t2_kernel<kEqEntropic>(dtype, corr);
+    const bool nt = t2_nt_stores(L.buf_bytes);
+    void (*fn)(Step2Args) = L.eq == LBM_EQ_POLY2     ? t2_kernel<kEqPoly2>(dtype, corr, nt)
+                            : L.eq == LBM_EQ_PRODUCT ? t2_kernel<kEqProduct>(dtype, corr, nt)
+                                                     : t2_kernel<kEqEntropic>(dtype, corr, nt);
     hipLaunchKernelGGL(fn, dim3((unsigned)(a.tiles_x * a.tiles_y)), dim3((unsigned)t2_threads(a.tx, L.elem)),
                        (unsigned)t2_lds_bytes(a.tx, L.elem), s, a);
     hipError_t e = hipGetLastError();
