@@ -203,10 +203,11 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
     const bool t2_fits = L.dim == 2 && layout == LBM_LAYOUT_ROWS &&
                          (cfg->dtype == LBM_FP64 || cfg->dtype == LBM_FP32_DEV) && cfg->nx % 64 == 0;
     // D1Q3, K steps per launch: owned nodes per workgroup (the LDS segment is 2 x 3 x
-    // (tx + 2K) elements, 25 KB at K = 8), and nx >= tx + K for a single periodic wrap
-    const int t1_tx = fp32 ? 1024 : 512;
+    // (tx + 2K) elements, 25 KB at K = 8), and nx >= tx + K for a single periodic wrap:
+    // short rows take tx = nx - 8 (nx >= 16)
+    const int t1_tx = (int)std::min<int64_t>(fp32 ? 1024 : 512, cfg->nx - 8);
     const bool t1_fits = L.dim == 1 && layout == LBM_LAYOUT_ROWS &&
-                         (cfg->dtype == LBM_FP64 || cfg->dtype == LBM_FP32_DEV) && cfg->nx >= t1_tx + 8;
+                         (cfg->dtype == LBM_FP64 || cfg->dtype == LBM_FP32_DEV) && cfg->nx >= 16;
     if (tblock == 0) {
         // default: two steps per launch for large D2Q9 domains.  A workgroup sweeps its
         // rows one after another (about 1.4 us per row), so small grids lack the
@@ -215,9 +216,9 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
         // (512^2: 12.1 against 8.9; 1024^2: 16.0 against 29.6)
         const int64_t big = fp32 ? (int64_t)2048 * 2048 : (int64_t)1024 * 1024;
         tblock = t2_fits && shape_default && trows == 0 && L.n >= big ? 2 : 1;
-        // D1Q3: eight steps per launch whenever the row allows it (measured faster from
-        // 2^16 nodes up; 2^27 with the correction: FP32 297 against 229 GLUPS, FP64 295
-        // against 127)
+        // D1Q3: eight steps per launch whenever the row allows it (2^27 with the
+        // correction: FP32 297 against 229 GLUPS, FP64 295 against 127; short rows are
+        // bound by launches, and eight steps take one)
         if (t1_fits && shape_default && trows == 0)
             tblock = 8;
     }
@@ -228,7 +229,7 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
         }
         if (!t1_fits || trows != 0) {
             set_error("time_block > 1 on D1Q3 needs the row-interleaved layout, LBM_FP64 or "
-                      "LBM_FP32_DEV, nx >= 1032 (FP32) or 520 (FP64), and time_rows = 0");
+                      "LBM_FP32_DEV, nx >= 16, and time_rows = 0");
             return LBM_EINVAL;
         }
         L.tblock = tblock;

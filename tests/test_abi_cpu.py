@@ -120,7 +120,7 @@ def test_time_block_configs(lbm):
             assert lbm.lbm_workspace_bytes(cfg, lbm.make_tuning(time_block=2, time_rows=6)) == 0
             assert lbm.lbm_workspace_bytes(cfg, lbm.make_tuning(time_block=2, time_rows=-1)) == 0
     refused = [_cfg(lbm, shape=(96, 8)), _cfg(lbm, shape=(100, 8), dtype="fp32_dev"),
-               _cfg(lbm, lattice=27, shape=(64, 8, 8)), _cfg(lbm, lattice=3, shape=(256,)),
+               _cfg(lbm, lattice=27, shape=(64, 8, 8)), _cfg(lbm, lattice=3, shape=(15,)),
                _cfg(lbm, shape=(64, 8), dtype="fp32_dev_mixed")]
     for cfg in refused:
         assert lbm.lbm_workspace_bytes(cfg, two) == 0
@@ -133,15 +133,16 @@ def test_time_block_configs(lbm):
 
 
 def test_d1q3_time_block_configs(lbm):
-    """K = 2, 4 or 8 steps per launch on D1Q3: FP64 or FP32_DEV, long enough
-    rows (nx >= 1032 FP32, 520 FP64); D2Q9 takes 2 only."""
+    """K = 2, 4 or 8 steps per launch on D1Q3: FP64 or FP32_DEV, nx >= 16;
+    D2Q9 takes 2 only."""
     for K in (2, 4, 8):
-        assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(1032,), dtype="fp32_dev"),
-                                       lbm.make_tuning(time_block=K)) > 0
-        assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(520,)), lbm.make_tuning(time_block=K)) > 0
-        assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(1031,), dtype="fp32_dev"),
+        for nx in (16, 64, 1031, 1032, 5000):
+            for dt in ("fp32_dev", "fp64"):
+                assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(nx,), dtype=dt),
+                                               lbm.make_tuning(time_block=K)) > 0, (K, nx, dt)
+        assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(15,), dtype="fp32_dev"),
                                        lbm.make_tuning(time_block=K)) == 0
-        assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(519,)), lbm.make_tuning(time_block=K)) == 0
+        assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(15,)), lbm.make_tuning(time_block=K)) == 0
     for K in (3, 5, 16):
         assert lbm.lbm_workspace_bytes(_cfg(lbm, lattice=3, shape=(4096,)), lbm.make_tuning(time_block=K)) == 0
     for K in (4, 8):

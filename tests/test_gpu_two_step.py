@@ -102,6 +102,12 @@ D1Q3_CASES = [  # nx, dtype, correction, K, step chunks
     (520, "fp64", True, 8, (17,)),
     (1 << 20, "fp32_dev", True, 8, (40,)),
     (5000, "fp64", True, 4, (66,)),
+    # short rows: tx = nx - 8 owned nodes per workgroup, two workgroups
+    (16, "fp64", True, 8, (8, 3, 64)),
+    (17, "fp32_dev", False, 8, (9, 16)),
+    (64, "fp32_dev", True, 8, (10, 10, 70)),
+    (100, "fp64", False, 2, (5, 64)),
+    (255, "fp32_dev", True, 4, (13,)),
 ]
 
 
