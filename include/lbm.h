@@ -123,9 +123,10 @@ typedef struct lbm_tuning {
     int32_t layout;           /* LBM_LAYOUT_*; 0 = default (row-interleaved) */
     int32_t time_block;       /* LBGK steps per launch, the intermediate states kept in LDS
                                  (LBM_FP64 or LBM_FP32_DEV, any equilibrium, row-interleaved
-                                 layout): 1 = one; 2 on D2Q9 with nx a
-                                 multiple of 64; 2, 4 or 8 on D1Q3 with nx >= 16.  Step counts that are not a multiple end with
-                                 one-step launches of the kernel the other fields select.
+                                 layout): 1 = one; 2 on D2Q9 with nx >= 64; 2, 4 or 8 on
+                                 D1Q3 with nx >= 16.  Step counts that are not a multiple
+                                 end with one-step launches of the kernel the other fields
+                                 select.
                                  0 = default: 2 for D2Q9 domains of >= 2048^2 nodes (FP32) or
                                  1024^2 (FP64), 8 for D1Q3 where allowed, else 1 -- when
                                  block_x, block_y, nodes_per_thread, flags and layout are

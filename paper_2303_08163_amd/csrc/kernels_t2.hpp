@@ -35,7 +35,7 @@ struct Step2Args {
     const void *src;  // f*(t), row-interleaved layout
     void *dst;        // f*(t + 2)
     int nx, ny;
-    int tx;           // owned columns per workgroup (nx % tx == 0; 64 .. 512)
+    int tx;           // columns per workgroup tile (64 .. 512; the last tile of a row may be partial)
     int rows;         // owned rows per workgroup
     int tiles_x, tiles_y;
     int64_t ps, rs;
@@ -107,10 +107,12 @@ __device__ __forceinline__ void pull_row_d2q9(const T *__restrict__ src, int ny,
 }
 
 // Grid: tiles_x * tiles_y workgroups of t2_threads(tx, sizeof(T)) threads,
-// dynamic LDS t2_lds_bytes(tx, sizeof(T)).  Ring column c holds step-1
-// column x0 - 1 + c.  With chunks, lane t computes step 1 and step 2 at
-// column x0 + t; with the halo wavefront, lane t < tx + 2 computes step 1 at
-// x0 - 1 + t and lane t < tx step 2 at x0 + t.
+// dynamic LDS t2_lds_bytes(tx, sizeof(T)).  A tile owns nv = min(tx, nx - x0)
+// columns (fewer than tx in the last tile of a ragged row).  Ring column c
+// holds step-1 column x0 - 1 + c, c = 0 .. nv + 1.  With chunks, lane t < nv
+// computes step 1 and step 2 at column x0 + t; with the halo wavefront, lane
+// t < nv + 2 computes step 1 at x0 - 1 + t and lane t < nv step 2 at x0 + t.
+// Other lanes load a valid node, discard the result, and keep to the barriers.
 template <int DT, bool CORR, int EQ = kEqEntropic, bool NT = false>
 __global__ __launch_bounds__(512) void k_stream_collide2(Step2Args a) {
     using T = store_t<DT>;
@@ -129,12 +131,13 @@ __global__ __launch_bounds__(512) void k_stream_collide2(Step2Args a) {
     const int y0 = (tile / a.tiles_x) * a.rows;
     const int y1 = min(y0 + a.rows, a.ny);
     const int nsweep = y1 - y0 + 2;  // sweep rows y0 - 1 .. y1 (offsets 0 .. nsweep - 1)
-    const int x = x0 + t;            // step-2 column
-    const bool s2 = !HW || t < a.tx;
-    // step-1 column: x0 + t, or with the halo wavefront x0 - 1 + t wrapped (tx <= nx:
-    // one wrap suffices; lanes past the halo read column x0 and discard the result)
-    const bool s1 = !HW || t < w1;
-    int x1 = x;
+    const int nv = min(a.tx, a.nx - x0);  // owned columns of this tile
+    const int x = x0 + t;                  // step-2 column
+    const bool s2 = t < nv;
+    // step-1 column: x0 + t, or with the halo wavefront x0 - 1 + t wrapped (x0 + nv <= nx:
+    // one wrap suffices); lanes past them read column x0 and discard the result
+    const bool s1 = HW ? t < nv + 2 : t < nv;
+    int x1 = s1 ? x : x0;
     if (HW) {
         x1 = s1 ? x0 - 1 + t : x0;
         x1 = x1 < 0 ? x1 + a.nx : (x1 >= a.nx ? x1 - a.nx : x1);
@@ -145,10 +148,10 @@ __global__ __launch_bounds__(512) void k_stream_collide2(Step2Args a) {
     // sweep rows run from y0 - 1 to y1 <= ny: one wrap at either end
     auto wrap_row = [&](int r) { return r < 0 ? r + a.ny : (r >= a.ny ? r - a.ny : r); };
 
-    // halo lanes of wavefront 0: sweep offset k0 + (t >> 1), column t & 1 (x0 - 1 or x0 + tx,
-    // wrapped; tx <= nx); lanes past the chunk or the sweep load a valid row and discard it
+    // halo lanes of wavefront 0: sweep offset k0 + (t >> 1), column t & 1 (x0 - 1 or x0 + nv,
+    // wrapped); lanes past the chunk or the sweep load a valid row and discard it
     const bool w0 = !HW && t < 64;
-    const int hx = (t & 1) ? (x0 + a.tx == a.nx ? 0 : x0 + a.tx) : (x0 == 0 ? a.nx - 1 : x0 - 1);
+    const int hx = (t & 1) ? (x0 + nv == a.nx ? 0 : x0 + nv) : (x0 == 0 ? a.nx - 1 : x0 - 1);
     T h[9];
     auto halo_load = [&](int k0) {
         const int k = min(k0 + ((t & 63) >> 1), nsweep - 1);
@@ -188,7 +191,7 @@ __global__ __launch_bounds__(512) void k_stream_collide2(Step2Args a) {
         }
         if (!HW && t < 2) {
             const T *hv = hal + ((k % CH) * 2 + t) * 9;
-            const int c = t == 0 ? 0 : w1 - 1;
+            const int c = t == 0 ? 0 : nv + 1;
 #pragma unroll
             for (int i = 0; i < 9; ++i)
                 slot[i * w1 + c] = hv[i];

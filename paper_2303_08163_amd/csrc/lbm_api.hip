@@ -201,7 +201,7 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
         }
     }
     const bool t2_fits = L.dim == 2 && layout == LBM_LAYOUT_ROWS &&
-                         (cfg->dtype == LBM_FP64 || cfg->dtype == LBM_FP32_DEV) && cfg->nx % 64 == 0;
+                         (cfg->dtype == LBM_FP64 || cfg->dtype == LBM_FP32_DEV) && cfg->nx >= 64;
     // D1Q3, K steps per launch: owned nodes per workgroup (the LDS segment is 2 x 3 x
     // (tx + 2K) elements, 25 KB at K = 8), and nx >= tx + K for a single periodic wrap:
     // short rows take tx = nx - 8 (nx >= 16)
@@ -254,21 +254,26 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
     if (tblock == 2) {
         if (!t2_fits) {
             set_error("time_block = 2 needs D2Q9, the row-interleaved layout, LBM_FP64 or "
-                      "LBM_FP32_DEV, and nx a multiple of 64");
+                      "LBM_FP32_DEV, and nx >= 64");
             return LBM_EINVAL;
         }
         if (trows < 0 || trows > cfg->ny) {
             set_error("time_rows must lie in 0 .. ny");
             return LBM_EINVAL;
         }
-        // owned columns: the widest of 512 (FP32) or 128 (FP64), then 256, 128, 64 that
-        // divides nx.  Measured at 4096^2 FP32, us per step: 512 columns 139.8 (76 KB of LDS,
+        // columns per tile: the widest of 512 (FP32) or 128 (FP64), then 256, 128, 64 that
+        // divides nx, or for other widths the widest not above nx (the last tile partial).  Measured at 4096^2 FP32, us per step: 512 columns 139.8 (76 KB of LDS,
         // two workgroups per compute unit), 256 146.1 (39 KB, four), 128 156.2; FP64 takes
         // 128 (37 KB, four workgroups of three wavefronts)
         int tx = fp32 ? 512 : 128;
-        while (cfg->nx % tx != 0)
-            tx /= 2;
-        const int64_t tiles_x = cfg->nx / tx;
+        if (cfg->nx % 64 == 0) {
+            while (cfg->nx % tx != 0)
+                tx /= 2;
+        } else {
+            while (tx > cfg->nx)
+                tx /= 2;
+        }
+        const int64_t tiles_x = (cfg->nx + tx - 1) / tx;
         // workgroups resident at once: 256 compute units x those that fit 160 KB of LDS
         const int64_t per_cu = std::max<int64_t>(1, (int64_t)163840 / (int64_t)t2_lds_bytes(tx, L.elem));
         const int64_t round = 256 * std::min<int64_t>(per_cu, 8);
@@ -504,7 +509,7 @@ int launch_step2(const Layout &L, const StepArgs &args, int dtype, bool corr, hi
             return hip_fail(e, "multi-step launch");
         return LBM_OK;
     }
-    Step2Args a{args.src, args.dst, args.nx, args.ny, L.t2_tx, L.t2_rows, args.nx / L.t2_tx,
+    Step2Args a{args.src, args.dst, args.nx, args.ny, L.t2_tx, L.t2_rows, (args.nx + L.t2_tx - 1) / L.t2_tx,
                 (args.ny + L.t2_rows - 1) / L.t2_rows, L.ps, L.rs, args.relax, args.flag};
     const bool nt = t2_nt_stores(L.buf_bytes);
     void (*fn)(Step2Args) = L.eq == LBM_EQ_POLY2     ? t2_kernel<kEqPoly2>(dtype, corr, nt)

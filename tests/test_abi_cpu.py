@@ -109,8 +109,8 @@ def test_valid_tunings_accepted(lbm):
 
 
 def test_time_block_configs(lbm):
-    """Two steps per launch: D2Q9, FP64 or FP32_DEV, rows layout, nx a
-    multiple of 64; the workspace is that of the one-step domain."""
+    """Two steps per launch: D2Q9, FP64 or FP32_DEV, rows layout, nx >= 64;
+    the workspace is that of the one-step domain."""
     two = lbm.make_tuning(time_block=2)
     for dt in ("fp64", "fp32_dev"):
         for nx in (64, 192, 4096):
@@ -119,7 +119,10 @@ def test_time_block_configs(lbm):
             assert lbm.lbm_workspace_bytes(cfg, lbm.make_tuning(time_block=2, time_rows=5)) > 0
             assert lbm.lbm_workspace_bytes(cfg, lbm.make_tuning(time_block=2, time_rows=6)) == 0
             assert lbm.lbm_workspace_bytes(cfg, lbm.make_tuning(time_block=2, time_rows=-1)) == 0
-    refused = [_cfg(lbm, shape=(96, 8)), _cfg(lbm, shape=(100, 8), dtype="fp32_dev"),
+    for nx in (65, 96, 100, 1000):  # ragged widths: the last tile of a row is partial
+        for dt in ("fp64", "fp32_dev"):
+            assert lbm.lbm_workspace_bytes(_cfg(lbm, shape=(nx, 8), dtype=dt), two) > 0
+    refused = [_cfg(lbm, shape=(63, 8)), _cfg(lbm, shape=(40, 8), dtype="fp32_dev"),
                _cfg(lbm, lattice=27, shape=(64, 8, 8)), _cfg(lbm, lattice=3, shape=(15,)),
                _cfg(lbm, shape=(64, 8), dtype="fp32_dev_mixed")]
     for cfg in refused:

@@ -29,6 +29,12 @@ CASES = [  # (ny, nx), dtype, correction, time_rows, step chunks
     ((3, 512), "fp32_dev", False, 2, (4, 64)),
     ((37, 256), "fp32_dev", True, 37, (9,)),
     ((48, 320), "fp64", False, 5, (2, 2, 131)),
+    # ragged widths: the last tile of each row is partial
+    ((30, 100), "fp32_dev", True, 0, (3, 64)),
+    ((17, 1000), "fp64", True, 4, (7,)),
+    ((5, 65), "fp32_dev", False, 2, (2, 65)),
+    ((64, 777), "fp64", False, 9, (4, 33)),
+    ((40, 1500), "fp32_dev", True, 0, (11,)),
 ]
 
 
@@ -80,6 +86,19 @@ def test_two_step_domain_flag_as_one_step():
                 fa = a.moments(fields=False, raise_on_domain=False)[2]["domain_error"]
                 fb = b.moments(fields=False, raise_on_domain=False)[2]["domain_error"]
                 assert fa == fb, (seed, n)
+
+
+def test_two_step_ragged_large_bitwise():
+    """A large ragged width (4000^2, 512-column tiles with a partial last
+    one), where two steps per launch are the default."""
+    lbm = _lbm()
+    rho0, u0 = workloads.random_field((4000, 4000), seed=51, umax=0.1)
+    with lbm.Domain(rho0, u0, 0.51, dtype="fp32_dev") as a:
+        a.step(3)
+        fa = a.populations()
+    with lbm.Domain(rho0, u0, 0.51, dtype="fp32_dev", tuning=lbm.make_tuning(time_block=1)) as b:
+        b.step(3)
+        assert np.array_equal(fa, b.populations())
 
 
 @pytest.mark.parametrize("dtype", ["fp32_dev", "fp64"])
