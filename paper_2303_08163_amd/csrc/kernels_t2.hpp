@@ -1,11 +1,13 @@
-// kernels_t2.hpp -- two LBGK steps per launch on D2Q9 (temporal blocking).
+// kernels_t2.hpp -- several LBGK steps per launch (temporal blocking): two on
+// D2Q9, K = 2, 4 or 8 on D1Q3 (k_stream_collide_t1, further below).
 //
 // A step reads and writes every population once, so a one-step kernel moves
 // 2 Q s bytes per node update whatever its tiling.  Two steps in one sweep
 // halve that: the intermediate state f*(t + 1) never leaves the chip.
 //
-// Each workgroup owns tx consecutive columns [x0, x0 + tx) of `rows`
-// consecutive rows [y0, y1) and sweeps its rows in y order.  At sweep row r
+// Each workgroup owns tx consecutive columns [x0, x0 + tx) (fewer in the last
+// tile of a ragged row) of `rows` consecutive rows [y0, y1) and sweeps its
+// rows in y order.  At sweep row r
 // (r = y0 - 1 .. y1) it
 //   1. pulls f(t + 1) at row r for the tx + 2 columns [x0 - 1, x0 + tx + 1)
 //      from the source buffer, collides, and puts the post-collision values
