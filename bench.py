@@ -542,7 +542,8 @@ def main() -> int:
     ap.add_argument("--no-batch-baseline", action="store_true",
                     help="skip the one-domain-per-launch baseline of the batched section")
     ap.add_argument("--batch-tuning", default="",
-                    help="TXxTY[,persistent][,flat][,fit]: fixed pool tile instead of the autotuner's choice")
+                    help="TXxTY[,persistent][,flat][,fit][,t2]: fixed pool tile instead of the autotuner's "
+                         "choice (t2: two steps per launch)")
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-light-requests", type=int, default=40)
@@ -656,6 +657,8 @@ def main() -> int:
                 fixed["flat"] = 1
             if "fit" in parts[1:]:
                 fixed["row_fit"] = 1
+            if "t2" in parts[1:]:
+                fixed["time_block"] = 2
         out["batched"] = bench_batched(args.batch_count, args.batch_steps, baseline=not args.no_batch_baseline,
                                        fixed_tuning=fixed)
         progress("batched done")

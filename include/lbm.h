@@ -349,7 +349,13 @@ typedef struct lbm_pool_tuning {
                            when none does, with tile_x * tile_y / w rows per workgroup; a
                            wavefront always stays within one row.  0: every slot uses
                            tile_x x tile_y.  Not with flat; other values are LBM_EINVAL */
-    int32_t reserved;   /* must be 0 */
+    int32_t time_block; /* 2: D2Q9 classes (LBM_FP64 or LBM_FP32_DEV, row-interleaved slots)
+                           advance two steps per launch, the intermediate state in LDS, in
+                           runs where every slot of the class takes the same even number of
+                           steps and the class holds >= 2^22 nodes (FP32) or 2^20 (FP64);
+                           other runs take one step per launch.  Results are bitwise those
+                           of one step per launch.  0 or 1: one step per launch.
+                           Not with persistent */
 } lbm_pool_tuning;
 
 typedef struct lbm_pool_stats {

@@ -115,8 +115,8 @@ __device__ __forceinline__ void pull_row_d2q9(const T *__restrict__ src, int ny,
 // computes step 1 and step 2 at column x0 + t; with the halo wavefront, lane
 // t < nv + 2 computes step 1 at x0 - 1 + t and lane t < nv step 2 at x0 + t.
 // Other lanes load a valid node, discard the result, and keep to the barriers.
-template <int DT, bool CORR, int EQ = kEqEntropic, bool NT = false>
-__global__ __launch_bounds__(512) void k_stream_collide2(Step2Args a) {
+template <int DT, bool CORR, int EQ, bool NT>
+__device__ __forceinline__ void two_step_tile(const Step2Args &a, int tile) {
     using T = store_t<DT>;
     constexpr bool HW = t2_halo_wave(sizeof(T));
     constexpr int CH = kT2Chunk;
@@ -128,7 +128,6 @@ __global__ __launch_bounds__(512) void k_stream_collide2(Step2Args a) {
     const int w1 = a.tx + 2;  // ring columns: x0 - 1 .. x0 + tx
     T *ring = reinterpret_cast<T *>(t2_lds);
     T *hal = ring + (size_t)kT2Ring * 9 * w1;  // [CH][2][9]
-    const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int x0 = (tile % a.tiles_x) * a.tx;
     const int y0 = (tile / a.tiles_x) * a.rows;
     const int y1 = min(y0 + a.rows, a.ny);
@@ -251,6 +250,11 @@ __global__ __launch_bounds__(512) void k_stream_collide2(Step2Args a) {
         if (++r > y1)
             break;
     }
+}
+
+template <int DT, bool CORR, int EQ = kEqEntropic, bool NT = false>
+__global__ __launch_bounds__(512) void k_stream_collide2(Step2Args a) {
+    two_step_tile<DT, CORR, EQ, NT>(a, xcd_tile((int)blockIdx.x, (int)gridDim.x));
 }
 
 // ---------------------------------------------------------------------------

@@ -30,8 +30,12 @@ static int resolve_tuning(const lbm_pool_tuning *t, lbm_pool_tuning *out) {
     lbm_pool_tuning r{};
     if (t)
         r = *t;
-    if (r.reserved) {
-        set_error("lbm_pool_tuning.reserved must be 0");
+    if (r.time_block < 0 || r.time_block > 2) {
+        set_error("pool tuning: time_block must be 0, 1 or 2");
+        return LBM_EINVAL;
+    }
+    if (r.time_block == 2 && r.persistent) {
+        set_error("pool tuning: time_block = 2 is not with persistent");
         return LBM_EINVAL;
     }
     if (r.tile_x == 0)
@@ -122,6 +126,10 @@ static PoolStepFn pool_kernel(int dtype, bool corr, bool persistent) {
         return pool_kernel_dt<DIM, kF64>(corr, persistent);
     }
 }
+
+// Two-step pool tiles: 64 columns (the batched workload's rows are 32..512
+// wide, so wider tiles would idle more lanes) by 16 rows.
+constexpr int kPoolT2Tx = 64, kPoolT2Rows = 16;
 
 struct Slot {
     bool used = false;
@@ -377,13 +385,33 @@ int lbm_pool_run(lbm_pool *p, int64_t k) {
                          [&](int a, int b) { return p->slots[a].remaining > p->slots[b].remaining; });
         const int n = (int)order.size();
         const int64_t steps = std::min<int64_t>(k, p->slots[order[0]].remaining);
+        const int cdim = c >= 8 ? 3 : 2, cdtype = (c % 8) / 2;
+        // two steps per launch: D2Q9 FP64 / FP32_DEV row-interleaved slots that all take
+        // the same even number of steps in this run, with as many nodes in the class as a
+        // single domain needs for two steps per launch to pay (2048^2 FP32, 1024^2 FP64;
+        // a workgroup sweeps its rows one after another): with a few small slots the
+        // one-step form answers sooner (served p50 latency 44 against 18 ms)
+        bool two = p->tun.time_block == 2 && cdim == 2 && (cdtype == kF64 || cdtype == kDevF64) &&
+                   p->tun.layout == LBM_LAYOUT_ROWS && steps % 2 == 0;
+        size_t class_buf_bytes = 0;
+        int64_t class_nodes = 0;
+        for (int j = 0; j < n && two; ++j) {
+            two = std::min<int64_t>(k, p->slots[order[j]].remaining) == steps;
+            class_buf_bytes += p->slots[order[j]].d.L.buf_bytes;
+            class_nodes += p->slots[order[j]].d.L.n;
+        }
+        two = two && class_nodes >= (cdtype == kF64 ? (int64_t)1 << 20 : (int64_t)1 << 22);
         std::vector<int> tile_start(n + 1, 0);
         for (int j = 0; j < n; ++j) {
-            if ((int64_t)tile_start[j] + p->slots[order[j]].tiles > INT32_MAX) {
+            const Slot &sj = p->slots[order[j]];
+            const int64_t tiles = two ? ((sj.d.cfg.nx + kPoolT2Tx - 1) / kPoolT2Tx) *
+                                            ((sj.d.cfg.ny + kPoolT2Rows - 1) / kPoolT2Rows)
+                                      : (int64_t)sj.tiles;
+            if ((int64_t)tile_start[j] + tiles > INT32_MAX) {
                 set_error("pool run: more than 2^31 - 1 tiles in one class");
                 return LBM_EINVAL;
             }
-            tile_start[j + 1] = tile_start[j] + p->slots[order[j]].tiles;
+            tile_start[j + 1] = tile_start[j] + (int)tiles;
         }
         // Host copy of the class table in pinned memory; wait for the previous
         // upload from it to finish before overwriting.
@@ -440,7 +468,28 @@ int lbm_pool_run(lbm_pool *p, int64_t k) {
         PoolStepFn fn = dim == 3 ? pool_kernel<3>(dtype, corr, p->tun.persistent)
                                  : pool_kernel<2>(dtype, corr, p->tun.persistent);
         dim3 block(p->tun.tile_x, p->tun.tile_y);
-        if (p->tun.persistent) {
+        if (two) {
+            // every slot takes `steps` (even) steps: steps / 2 two-step launches over all tiles
+            const size_t elem = dtype == kF64 ? 8 : 4;
+            const bool nt = t2_nt_stores(class_buf_bytes);
+            void (*fn2)(PoolRunArgs) =
+                dtype == kF64 ? (corr ? (nt ? k_pool_step2<kF64, true, true> : k_pool_step2<kF64, true, false>)
+                                      : (nt ? k_pool_step2<kF64, false, true> : k_pool_step2<kF64, false, false>))
+                              : (corr ? (nt ? k_pool_step2<kDevF64, true, true> : k_pool_step2<kDevF64, true, false>)
+                                      : (nt ? k_pool_step2<kDevF64, false, true> : k_pool_step2<kDevF64, false, false>));
+            a.t2_tx = kPoolT2Tx;
+            a.t2_rows = kPoolT2Rows;
+            for (int64_t L = 0; L < steps / 2; ++L) {
+                a.step0 = (int)L;
+                a.nsteps = 2;
+                hipLaunchKernelGGL(fn2, dim3((unsigned)tile_start[n]), dim3((unsigned)t2_threads(kPoolT2Tx, elem)),
+                                   (unsigned)t2_lds_bytes(kPoolT2Tx, elem), p->stream, a);
+                p->launches++;
+            }
+            e = hipGetLastError();
+            if (e != hipSuccess)
+                return hip_fail(e, "pool two-step launch");
+        } else if (p->tun.persistent) {
             int per_cu = 0;
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, p->tun.tile_x * p->tun.tile_y, 0);
             if (e != hipSuccess)
@@ -482,7 +531,7 @@ int lbm_pool_run(lbm_pool *p, int64_t k) {
         for (int j = 0; j < n; ++j) {
             Slot &s = p->slots[order[j]];
             const int64_t done = std::min<int64_t>(k, s.remaining);
-            s.d.cur ^= (int)(done & 1);
+            s.d.cur ^= (int)((two ? done / 2 : done) & 1);  // one swap per launch
             s.d.steps += done;
             s.remaining -= done;
         }

@@ -26,6 +26,7 @@
 #include <stdint.h>
 
 #include "kernels.hpp"
+#include "kernels_t2.hpp"
 
 namespace lbm {
 
@@ -52,6 +53,7 @@ struct PoolRunArgs {
     int *error;               // persistent form: set on a barrier timeout
     long long spin_limit;
     int flat;                 // 1: a tile is blockDim.x * blockDim.y consecutive nodes of its slot
+    int t2_tx, t2_rows;       // two-step form: columns and rows of a tile
 };
 
 // Active tiles at step s: the tile count of the slots with remaining > s.
@@ -122,6 +124,32 @@ __device__ __forceinline__ void pool_tile(const PoolRunArgs &a, int t, int s) {
             return;
     }
     step_node<DIM, DT, CORR>(src, dst, nx, ny, nz, ps, rs, relax, flag, x, y, z, pad);
+}
+
+// Two steps per launch (D2Q9) over every tile of a class whose slots all take
+// the same even number of steps in the run: tile_start then counts each slot's
+// ceil(nx / t2_tx) x ceil(ny / t2_rows) two-step tiles, and a.step0 is the
+// launch's index in the run (one buffer swap per launch).  The per-tile code
+// is the single-domain two-step kernel's, so a slot's populations are bitwise
+// those of one-step launches.  Block t2_threads(t2_tx, elem), dynamic LDS
+// t2_lds_bytes(t2_tx, elem).
+template <int DT, bool CORR, bool NT>
+__global__ __launch_bounds__(512) void k_pool_step2(PoolRunArgs a) {
+    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    int lo = 0, hi = a.n - 1;  // last slot k with tile_start[k] <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.tile_start[mid] <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const SlotDesc &dd = a.slots[lo];
+    const int nx = dd.nx, ny = dd.ny;
+    const int p = (dd.parity + a.step0) & 1;
+    Step2Args s{dd.buf[p], dd.buf[p ^ 1], nx, ny, a.t2_tx, a.t2_rows, (nx + a.t2_tx - 1) / a.t2_tx,
+                (ny + a.t2_rows - 1) / a.t2_rows, dd.ps, dd.rs, dd.relax, dd.flag};
+    two_step_tile<DT, CORR, kEqEntropic, NT>(s, t - a.tile_start[lo]);
 }
 
 // One step (a.step0) over the active prefix; grid = its tile count.

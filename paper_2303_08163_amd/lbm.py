@@ -63,7 +63,7 @@ class lbm_diag(ctypes.Structure):
 class lbm_pool_tuning(ctypes.Structure):
     _fields_ = [("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("workgroups", ctypes.c_int32), ("layout", ctypes.c_int32), ("flat", ctypes.c_int32),
-                ("row_fit", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("row_fit", ctypes.c_int32), ("time_block", ctypes.c_int32)]
 
 
 class lbm_pool_stats(ctypes.Structure):
@@ -294,10 +294,11 @@ def lbm_destroy(h) -> None:
 
 
 def make_pool_tuning(tile_x=0, tile_y=0, persistent=0, workgroups=0, layout=0, flat=0,
-                     row_fit=0) -> lbm_pool_tuning:
+                     row_fit=0, time_block=0) -> lbm_pool_tuning:
     t = lbm_pool_tuning()
-    t.tile_x, t.tile_y, t.persistent, t.workgroups, t.layout, t.flat, t.row_fit = (
-        int(tile_x), int(tile_y), int(persistent), int(workgroups), int(layout), int(flat), int(row_fit))
+    t.tile_x, t.tile_y, t.persistent, t.workgroups, t.layout, t.flat, t.row_fit, t.time_block = (
+        int(tile_x), int(tile_y), int(persistent), int(workgroups), int(layout), int(flat), int(row_fit),
+        int(time_block))
     return t
 
 

@@ -62,14 +62,15 @@ class PoolBackend:
     tuning None selects row fit (each slot's rows mapped to 64-, 128- or
     256-wide tiles): on the serving request mix (D2Q9 64^2..1024^2, D3Q27
     32^3..192^3) it served 2.5-4 % more requests per second than the pool's
-    default 64 x 4 tiles."""
+    default 64 x 4 tiles; and two steps per launch for D2Q9 classes in runs
+    where their slots all take the same even number of steps."""
 
     def __init__(self, budget_bytes: int, max_slots: int = 256, tuning=None, dtype: str = "fp32_dev",
                  device="cuda:0", bytes_per_s: float = 5.0e12):
         from . import lbm
         self.lbm = lbm
         if tuning is None:
-            tuning = lbm.make_pool_tuning(64, 4, 0, row_fit=1)
+            tuning = lbm.make_pool_tuning(64, 4, 0, row_fit=1, time_block=2)
         self.dtype = dtype
         self.pool = lbm.Pool(budget_bytes, max_slots=max_slots, tuning=tuning, device=device)
         self.device = self.pool.device

@@ -254,11 +254,11 @@ def test_pool_host_logic(lbm):
     assert lbm.lbm_pool_slot_bytes(_cfg(lbm, tau=0.5)) == 0
     for bad in [dict(tile_x=48, tile_y=4), dict(tile_x=64, tile_y=8), dict(persistent=2), dict(workgroups=-1),
                 dict(layout=5), dict(flat=2), dict(flat=-1), dict(row_fit=2), dict(row_fit=-1),
-                dict(row_fit=1, flat=1)]:
+                dict(row_fit=1, flat=1), dict(time_block=3), dict(time_block=-1),
+                dict(time_block=2, persistent=1)]:
         assert lbm.lbm_pool_slot_bytes(cfg, lbm.make_pool_tuning(**bad)) == 0, bad
-    reserved = lbm.make_pool_tuning()
-    reserved.reserved = 1
-    assert lbm.lbm_pool_slot_bytes(cfg, reserved) == 0
+    # two steps per launch changes the launches only, not a slot's memory
+    assert lbm.lbm_pool_slot_bytes(cfg, lbm.make_pool_tuning(time_block=2)) == lbm.lbm_pool_slot_bytes(cfg)
     # row fit changes the thread mapping only, not a slot's memory
     assert lbm.lbm_pool_slot_bytes(cfg, lbm.make_pool_tuning(row_fit=1)) == lbm.lbm_pool_slot_bytes(cfg)
     h = ctypes.c_void_p()

@@ -49,11 +49,16 @@ def alone_results():
 
 @pytest.mark.parametrize("persistent", [0, 1])
 @pytest.mark.parametrize("tile", [(64, 4), (32, 2), (256, 1), ("flat", 64, 4), ("flat", 64, 1), ("fit", 64, 4),
-                                  ("fit", 64, 2), ("fit-planes", 64, 4)])
+                                  ("fit", 64, 2), ("fit-planes", 64, 4), ("two", 64, 4)])
 @pytest.mark.parametrize("chunk", [1000, 7])
 def test_pool_mix_equals_alone_bitwise(alone_results, persistent, tile, chunk):
     lbm = _lbm()
-    if tile[0] == "flat":
+    if tile[0] == "two":
+        if persistent:
+            pytest.skip("two steps per launch are not with the persistent form")
+        # uneven step counts: runs take the one-step path where slots differ
+        tun = lbm.make_pool_tuning(tile[1], tile[2], 0, time_block=2)
+    elif tile[0] == "flat":
         tun = lbm.make_pool_tuning(tile[1], tile[2], persistent, flat=1)
     elif tile[0] in ("fit", "fit-planes"):
         layout = lbm.LBM_LAYOUT_PLANES if tile[0] == "fit-planes" else 0
@@ -221,3 +226,38 @@ def test_pool_retires_failed_slots():
         assert d["steps"] == 100 and not d["domain_error"]
         with pytest.raises(lbm.LBMDomainError):
             pool.moments(b)
+
+
+def test_pool_two_steps_per_launch_equals_alone():
+    """time_block = 2: D2Q9 classes whose slots all take the same even number
+    of steps in a run, and that hold enough nodes (2^22 FP32, 2^20 FP64),
+    advance two steps per launch (ragged widths, both storage types, with and
+    without the correction); odd runs and small classes take one step per
+    launch, and the buffer parity stays right across both forms.  Every slot
+    is bitwise its single-domain run; the launch count shows which form ran."""
+    lbm = _lbm()
+    specs = [((33, 70), "fp32_dev", True, 0.6), ((64, 64), "fp64", False, 0.55), ((17, 130), "fp32_dev", False, 0.52),
+             ((100, 45), "fp64", True, 0.7), ((5, 300), "fp32_dev", False, 0.58), ((48, 513), "fp64", False, 0.51),
+             ((40, 32), "fp32_dev", True, 0.56),
+             ((2048, 2048), "fp32_dev", True, 0.51), ((1024, 1024), "fp64", False, 0.51)]  # large slots
+    steps = 30
+    fields = [workloads.random_field(shape, seed=100 + k, umax=0.1) for k, (shape, _, _, _) in enumerate(specs)]
+    r3, u3 = workloads.taylor_green_3d(16, u0=0.05)
+    with lbm.Pool(2 * GiB, max_slots=16, tuning=lbm.make_pool_tuning(64, 4, 0, time_block=2)) as pool:
+        slots = [pool.admit(r, u, tau, steps, dtype=dt, bulk_correction=corr)
+                 for (r, u), (_, dt, corr, tau) in zip(fields, specs)]
+        s3 = pool.admit(r3, u3, 0.55, steps, dtype="fp32_dev")  # D3Q27: one step per launch
+        for k in (10, 6, 7, 7):
+            pool.run(k)
+        assert sorted(pool.poll()) == sorted(slots + [s3])
+        # the FP32-corrected and FP64 classes (with the large slots): 5 + 3 two-step
+        # launches, then 7 + 7 one-step; the two small D2Q9 classes and D3Q27: 30 each
+        assert pool.stats()["launches"] == 2 * (5 + 3 + 7 + 7) + 3 * 30
+        for s, (r, u), (_, dt, corr, tau) in zip(slots, fields, specs):
+            ra, ua, da, fa = alone(r, u, tau, steps, dt, corr)
+            rb, ub, db = pool.moments(s, raise_on_domain=False)
+            assert db["steps"] == steps
+            assert np.array_equal(ra, rb) and np.array_equal(ua, ub)
+            assert np.array_equal(fa, pool.populations(s))
+        ra, ua, _, fa = alone(r3, u3, 0.55, steps, "fp32_dev", False)
+        assert np.array_equal(fa, pool.populations(s3))
