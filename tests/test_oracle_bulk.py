@@ -102,3 +102,31 @@ def test_beta_corrected():
     # polynomial correction leaves [0, 1] once A < 0
     b = oracle.beta(0.6, np.array([0.6]), corr="min", kind="poly2")
     assert not (0 <= b <= 1)
+
+
+def test_beta_corrected_product_rule():
+    """The oracle's second reading of a multi-D node's A (corr "product"):
+    A = prod_alpha A(u_alpha), each factor the 1-D A of eq. (entorpic_bulk)."""
+    tau = 0.51
+    nu = CS2 * (tau - 0.5)
+    # one non-zero component: both readings reduce to the 1-D A (A(0) = 1 exactly)
+    for u in ([0.3, 0.0], [0.0, -0.7], [0.0, 0.0, 0.45], [0.9]):
+        u = np.array(u)
+        assert oracle.beta(tau, u, corr="product") == oracle.beta(tau, u, corr="min")
+    # two components: the product of the general expression's A at each (finite
+    # differences of P*), not the smaller one
+    A1, _ = _general_A_B(1.0, 0.1)
+    A2, _ = _general_A_B(1.0, -0.2)
+    expected = 1.0 / (2.0 * nu / (A1 * A2 * CS2) + 1.0)
+    assert oracle.beta(tau, np.array([0.1, -0.2]), corr="product") == pytest.approx(expected, rel=1e-7)
+    A3, _ = _general_A_B(1.0, 0.35)
+    expected3 = 1.0 / (2.0 * nu / (A1 * A2 * A3 * CS2) + 1.0)
+    assert oracle.beta(tau, np.array([0.1, -0.2, 0.35]), corr="product") == pytest.approx(expected3, rel=1e-7)
+    # A(u) <= 1, so the product never exceeds the min: the product rule relaxes
+    # more slowly; symmetric under axis permutations and sign changes
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        u = rng.uniform(-0.95, 0.95, 3)
+        b_prod = oracle.beta(tau, u, corr="product")
+        assert 0 < b_prod <= oracle.beta(tau, u, corr="min")
+        assert oracle.beta(tau, u[::-1] * np.array([1, -1, 1]), corr="product") == pytest.approx(b_prod, rel=1e-15)

@@ -65,7 +65,7 @@ def test_tau_one_second_step_streams_local_equilibrium():
         assert np.max(np.abs(f2[i] - _shift(feq1[i], ci))) < 1e-14
 
 
-@pytest.mark.parametrize("corr", ["off", "min"])
+@pytest.mark.parametrize("corr", ["off", "min", "product"])
 def test_uniform_flow_is_fixed_point(corr):
     for U, shape in (((0.9, -0.5), (5, 6)), ((0.9, -0.5, 0.3), (3, 4, 5)), ((-0.97,), (7,))):
         rho0 = np.full(shape, 1.3)
@@ -76,7 +76,7 @@ def test_uniform_flow_is_fixed_point(corr):
         assert np.max(np.abs(u - u0)) < 1e-13
 
 
-@pytest.mark.parametrize("corr", ["off", "min"])
+@pytest.mark.parametrize("corr", ["off", "min", "product"])
 def test_global_conservation(corr):
     rho0, u0 = workloads.taylor_green_2d(24, u0=0.2)
     rng = np.random.default_rng(3)
@@ -102,7 +102,7 @@ def _reflect_x(a):
     return np.roll(a[..., ::-1], 1, axis=-1)
 
 
-@pytest.mark.parametrize("corr", ["off", "min"])
+@pytest.mark.parametrize("corr", ["off", "min", "product"])
 def test_reflection_and_permutation(corr):
     rho0, u0 = workloads.random_field((10, 10), seed=5, umax=0.4)
     r, v, _ = oracle.run(rho0, u0, tau=0.55, steps=12, corr=corr)
@@ -118,7 +118,7 @@ def test_reflection_and_permutation(corr):
     assert np.max(np.abs(vp[0] - v[1].T)) < 1e-14 and np.max(np.abs(vp[1] - v[0].T)) < 1e-14
 
 
-@pytest.mark.parametrize("corr", ["off", "min"])
+@pytest.mark.parametrize("corr", ["off", "min", "product"])
 def test_embeddings(corr):
     # D2Q9 with a z-independent, u_z = 0 field inside D3Q27
     rho2, u2 = workloads.random_field((6, 7), seed=6, umax=0.4)
