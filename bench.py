@@ -136,22 +136,30 @@ def bench_batched(count: int, steps: int, dtypes=("fp32_dev", "fp64"), baseline:
     return out
 
 
-def bench_serving(n_requests: int, rate: float, light_requests: int) -> dict:
+def bench_serving(n_requests: int, rate: float, light_requests: int, policies=("swf",)) -> dict:
     """Serving: Poisson request stream (seed 8163) mixing D2Q9 64^2..1024^2 and
     D3Q27 32^3..192^3 (log-uniform sides), Taylor-Green or shear-wave starts,
     u0 ~ U[0.01, 0.15], tau ~ U[0.5001, 0.6], 200..5000 steps, FP32 storage;
-    continuous batching on one pool against a serial one-request-at-a-time
-    server on the same GPU.  The stated rate is far above one GPU's capacity,
-    so latency there is queueing; a second, lighter stream at about half the
-    measured capacity is reported as well."""
+    continuous batching on one pool (pipelined: the next chunk is enqueued
+    before the server waits for the current one) against a serial
+    one-request-at-a-time server on the same GPU.  The stated rate is far above
+    one GPU's capacity, so latency there is queueing; a second, lighter stream
+    at about half the measured capacity is reported as well.  gpu_busy_frac is
+    the GPU time of the pool's runs over the makespan."""
     from paper_2303_08163_amd import serve, workloads
     res = {}
     trace = workloads.serving_trace(n_requests=n_requests, rate=rate, seed=8163)
+
     def pooled(tr, policy):
         be = serve.PoolBackend(96 << 30, max_slots=512)
         try:
             kw = {"policy": "swf", "lookahead": 1 << 30} if policy == "swf" else {"policy": "fifo", "lookahead": 8}
-            out = serve.summarize(serve.Server(be, **kw).serve(tr))
+            recs = serve.Server(be, **kw).serve(tr)
+            out = serve.summarize(recs)
+            busy = be.gpu_busy_seconds()
+            out["gpu_busy_s"] = round(busy, 3)
+            out["gpu_busy_frac"] = round(busy / out["makespan_s"], 4) if out["makespan_s"] else None
+            out["launches"] = int(be.pool.stats()["launches"])
         finally:
             be.close()
         progress(f"serving {len(tr)} requests, continuous batching {policy}: {out}")
@@ -162,20 +170,22 @@ def bench_serving(n_requests: int, rate: float, light_requests: int) -> dict:
         progress(f"serving {len(tr)} requests, serial: {out}")
         return out
 
-    ps = pooled(trace, "fifo")
-    pw = pooled(trace, "swf")
-    bs = serial(trace)
-    res["stated_rate"] = {"rate_req_s": rate, "requests": n_requests, "continuous_batching": ps,
-                          "continuous_batching_shortest_work_first": pw, "serial": bs}
-    cap = ps["solves_per_s"] or 1.0
+    names = {"swf": "continuous_batching_shortest_work_first", "fifo": "continuous_batching_fifo"}
+    stated = {"rate_req_s": rate, "requests": n_requests}
+    for pol in policies:
+        stated[names[pol]] = pooled(trace, pol)
+    stated["serial"] = serial(trace)
+    first = stated[names[policies[0]]]
+    stated["solves_per_s_vs_serial"] = round(first["solves_per_s"] / stated["serial"]["solves_per_s"], 3)
+    res["stated_rate"] = stated
+    cap = first["solves_per_s"] or 1.0
     light_rate = max(0.5, 0.5 * cap)
     trace_l = workloads.serving_trace(n_requests=light_requests, rate=light_rate, seed=8164)
-    pl = pooled(trace_l, "fifo")
-    plw = pooled(trace_l, "swf")
-    bl = serial(trace_l)
-    res["half_capacity_rate"] = {"rate_req_s": round(light_rate, 2), "requests": light_requests,
-                                 "continuous_batching": pl, "continuous_batching_shortest_work_first": plw,
-                                 "serial": bl}
+    light = {"rate_req_s": round(light_rate, 2), "requests": light_requests}
+    for pol in policies:
+        light[names[pol]] = pooled(trace_l, pol)
+    light["serial"] = serial(trace_l)
+    res["half_capacity_rate"] = light
     return res
 
 
@@ -357,8 +367,66 @@ def bench_variants(steps: int = 100, warmup: int = 10) -> dict:
             dom = lbm.Domain(rd, ud, 0.5005, dtype="fp32_dev", bulk_correction=corr, equilibrium=eq, stream=stream)
             out[f"d3q27_256_fp32_{eq}{'_corrected' if corr else ''}"] = timed(dom, 256 ** 3, 216)
             dom.close()
+    # full FP64 storage of the headline workload (432 B per node update)
+    for corr in (False, True):
+        dom = lbm.Domain(rd, ud, 0.5005, dtype="fp64", bulk_correction=corr, stream=stream)
+        rec = timed(dom, 256 ** 3, 432)
+        rec["kernel"] = dom.launch_info()
+        out[f"d3q27_256_fp64_entropic{'_corrected' if corr else ''}"] = rec
+        dom.close()
     del rd, ud
     return {"steps": steps, "results": out}
+
+
+def bench_ceiling(n: int = 256, steps: int = 100, warmup: int = 10) -> dict:
+    """The access pattern's own speed, measured in the library: a non-temporal
+    float4 copy of 2 GiB (read + write bytes), and free streaming (the
+    stream-collide kernel's launch, loads and stores without the collision) of
+    the D3Q27 n^3 domain with FP32 deviation storage (216 B per node) and
+    FP64 storage (432 B per node)."""
+    import torch
+
+    from paper_2303_08163_amd import lbm, workloads
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    nb = 2 << 30
+    x = torch.empty(nb // 4, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    lbm.lbm_ceiling_copy(x.data_ptr(), y.data_ptr(), nb, stream.cuda_stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = []
+    for _ in range(3):
+        e0.record(stream)
+        for _ in range(10):
+            lbm.lbm_ceiling_copy(x.data_ptr(), y.data_ptr(), nb, stream.cuda_stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        reps.append(2 * nb * 10 / (e0.elapsed_time(e1) / 1e3) / 1e9)
+    del x, y
+    out = {"copy_nt_gbs": round(max(reps), 1), "copy_nt_gbs_reps": [round(v, 1) for v in reps],
+           "copy_bytes": nb}
+    rho0, u0 = workloads.taylor_green_3d(n, u0=0.05)
+    rd = torch.from_numpy(rho0).to(dev)
+    ud = torch.from_numpy(u0).to(dev)
+    del rho0, u0
+    for dt, b in (("fp32_dev", 216), ("fp64", 432)):
+        dom = lbm.Domain(rd, ud, 0.5005, dtype=dt, stream=stream)
+        lbm.lbm_ceiling_stream(dom.handle, warmup)
+        torch.cuda.synchronize()
+        reps = []
+        for _ in range(3):
+            e0.record(stream)
+            lbm.lbm_ceiling_stream(dom.handle, steps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            reps.append(b * n ** 3 * steps / (e0.elapsed_time(e1) / 1e3) / 1e9)
+        kind = dom.launch_info()
+        dom.close()
+        out[f"free_streaming_d3q27_{dt}_gbs"] = round(max(reps), 1)
+        out[f"free_streaming_d3q27_{dt}_gbs_reps"] = [round(v, 1) for v in reps]
+        out[f"free_streaming_d3q27_{dt}_kernel"] = {k: kind[k] for k in ("kernel", "nodes_per_thread", "row_wave")}
+    return out
 
 
 def bench_d1q3(steps: int = 200, warmup: int = 20) -> dict:
@@ -376,6 +444,7 @@ def bench_d1q3(steps: int = 200, warmup: int = 20) -> dict:
     out = {}
 
     def timed(dom, nodes, bytes_per_lup):
+        k = dom.launch_info()["time_block"]
         dom.step(warmup)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -386,9 +455,10 @@ def bench_d1q3(steps: int = 200, warmup: int = 20) -> dict:
         sec = e0.elapsed_time(e1) / 1e3
         _, _, d = dom.moments(fields=False)
         mlups = nodes * steps / sec / 1e6
-        return {"mlups": round(mlups, 1), "us_per_step": round(sec / steps * 1e6, 2),
-                "gbs_2Qs_per_update": round(mlups * 1e6 * bytes_per_lup / 1e9, 1),
-                "frac": round(mlups * 1e6 * bytes_per_lup / 1e9 / HBM_PEAK_GBS, 4), "domain_error": d["domain_error"]}
+        own = bytes_per_lup * nodes / (k * sec / steps) / 1e9  # one read + one write per launch
+        return {"mlups": round(mlups, 1), "us_per_step": round(sec / steps * 1e6, 2), "steps_per_launch": k,
+                "gbs": round(own, 1), "frac": round(own / HBM_PEAK_GBS, 4),
+                "gbs_2Qs_per_update": round(mlups * 1e6 * bytes_per_lup / 1e9, 1), "domain_error": d["domain_error"]}
 
     n1 = 1 << 27
     x = np.arange(n1, dtype=np.float64)
@@ -396,7 +466,8 @@ def bench_d1q3(steps: int = 200, warmup: int = 20) -> dict:
     u1 = torch.full((1, n1), 0.1, dtype=torch.float64, device=dev)
     del x
     # the default (eight steps per launch) and one step per launch; gbs / frac count
-    # 2 Q s bytes per node update, so for the former they are equivalent rates
+    # the bytes a launch moves (2 Q s per node), gbs_2Qs_per_update the equivalent
+    # rate at 2 Q s per node update
     for dt, s in (("fp32_dev", 4), ("fp64", 8)):
         for name, tun in (("eight_steps_per_launch", None), ("one_step_per_launch", lbm.make_tuning(time_block=1))):
             dom = lbm.Domain(r1, u1, 0.6, dtype=dt, bulk_correction=True, stream=stream, tuning=tun)
@@ -408,9 +479,12 @@ def bench_d1q3(steps: int = 200, warmup: int = 20) -> dict:
 
 def bench_d2q9(steps: int = 100, warmup: int = 10) -> dict:
     """The D2Q9 4096^2 double shear layer (tau 0.5001), FP32 deviations and FP64,
-    with the default two steps per launch and with one.  gbs / frac count
-    2 Q s bytes per node update (what one step per launch moves); two steps per
-    launch move about half of that, so for them these are equivalent rates."""
+    correction off and on, with the default two steps per launch and with one.
+    gbs / frac count the bytes each launch moves by algorithm: one read and
+    one write of every population per launch (2 Q s per node per launch, so
+    Q s per node update with two steps per launch); gbs_2Qs_per_update is the
+    rate at 2 Q s per node update, an equivalent figure for the two-step
+    kernel, not bytes it moves."""
     import torch
 
     from paper_2303_08163_amd import lbm, workloads
@@ -419,28 +493,32 @@ def bench_d2q9(steps: int = 100, warmup: int = 10) -> dict:
     stream = torch.cuda.current_stream(dev)
     r2, u2 = workloads.double_shear_layer(4096)
     out = {}
-    for dt, s in (("fp32_dev", 4), ("fp64", 8)):
-        for name, tun in (("two_steps_per_launch", None), ("one_step_per_launch", lbm.make_tuning(time_block=1))):
-            dom = lbm.Domain(r2, u2, 0.5001, dtype=dt, stream=stream, tuning=tun)
-            dom.step(warmup)
-            torch.cuda.synchronize()
-            reps = []
-            for _ in range(3):
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                dom.step(steps)
-                e1.record(stream)
+    for corr in (False, True):
+        for dt, s in (("fp32_dev", 4), ("fp64", 8)):
+            for name, tun in (("two_steps_per_launch", None), ("one_step_per_launch", lbm.make_tuning(time_block=1))):
+                dom = lbm.Domain(r2, u2, 0.5001, dtype=dt, bulk_correction=corr, stream=stream, tuning=tun)
+                info = dom.launch_info()
+                dom.step(warmup)
                 torch.cuda.synchronize()
-                reps.append(e0.elapsed_time(e1) / 1e3 / steps)
-            _, _, d = dom.moments(fields=False)
-            dom.close()
-            sec = min(reps)
-            mlups = 4096 ** 2 / sec / 1e6
-            gbs = mlups * 1e6 * 2 * 9 * s / 1e9
-            out[f"{dt}_{name}"] = {"mlups": round(mlups, 1), "us_per_step": round(sec * 1e6, 1),
-                                   "us_per_step_reps": [round(v * 1e6, 1) for v in reps],
-                                   "gbs_2Qs_per_update": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
-                                   "domain_error": d["domain_error"]}
+                reps = []
+                for _ in range(3):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    dom.step(steps)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    reps.append(e0.elapsed_time(e1) / 1e3 / steps)
+                _, _, d = dom.moments(fields=False)
+                dom.close()
+                sec = min(reps)
+                mlups = 4096 ** 2 / sec / 1e6
+                k = info["time_block"]
+                own = 2 * 9 * s * 4096 ** 2 / (k * sec) / 1e9  # bytes of one launch / its time
+                out[f"{dt}_{name}{'_corrected' if corr else ''}"] = {
+                    "mlups": round(mlups, 1), "us_per_step": round(sec * 1e6, 1),
+                    "us_per_step_reps": [round(v * 1e6, 1) for v in reps], "steps_per_launch": k,
+                    "kernel": info["kernel"], "gbs": round(own, 1), "frac": round(own / HBM_PEAK_GBS, 4),
+                    "gbs_2Qs_per_update": round(mlups * 1e6 * 2 * 9 * s / 1e9, 1), "domain_error": d["domain_error"]}
     return {"workload": "D2Q9 4096^2 double shear layer, tau 0.5001", "steps": steps, "repetitions": 3,
             "statistic": "best of the repetitions", "results": out}
 
@@ -534,9 +612,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256, help="grid side (headline: 256)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sections", default="headline,batched,serving,wave,stability,variants,slab,d2q9,d1q3",
-                    help="comma list of headline, batched, serving, wave, stability, variants, slab, d2q9, d1q3, "
-                         "oracle_timing (not in the default run: several minutes of host time)")
+    ap.add_argument("--sections", default="headline,ceiling,batched,serving,wave,stability,variants,slab,d2q9,d1q3",
+                    help="comma list of headline, ceiling, batched, serving, wave, stability, variants, slab, d2q9, "
+                         "d1q3, oracle_timing (not in the default run: several minutes of host time)")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--no-batch-baseline", action="store_true",
@@ -544,9 +622,10 @@ def main() -> int:
     ap.add_argument("--batch-tuning", default="",
                     help="TXxTY[,persistent][,flat][,fit][,t2]: fixed pool tile instead of the autotuner's "
                          "choice (t2: two steps per launch)")
-    ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-light-requests", type=int, default=40)
+    ap.add_argument("--serve-policies", default="swf", help="comma list of swf, fifo (continuous batching policies)")
     args = ap.parse_args()
     sections = set(args.sections.split(","))
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -565,6 +644,7 @@ def main() -> int:
     rho0, u0 = workloads.taylor_green_3d(n, u0=0.05)
     stream = torch.cuda.current_stream(dev)
     dom = lbm.Domain(rho0, u0, tau, dtype="fp32_dev", bulk_correction=False, stream=stream)
+    launch = dom.launch_info()
     del rho0, u0
     nodes = n ** 3
     dom.step(args.warmup)
@@ -597,19 +677,9 @@ def main() -> int:
     achieved = bytes_per_lup * nodes / per_launch_s / 1e9
     traffic = measured_traffic()
 
-    # context: a plain device-to-device copy through torch (read + write bytes)
-    x = torch.empty(2 ** 30, dtype=torch.float32, device=dev)
-    y = torch.empty_like(x)
-    y.copy_(x)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(10):
-        y.copy_(x)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 2 * x.numel() * 4 * 10 / (e0.elapsed_time(e1) / 1e3) / 1e9
-    del x, y
+    ceiling = bench_ceiling(n) if "ceiling" in sections else None
+    if ceiling:
+        progress("ceiling done")
 
     out = {
         "metric": METRIC,
@@ -634,19 +704,23 @@ def main() -> int:
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "k_stream_collide_vec<D3Q27, FP32 deviations/FP64 arithmetic, no correction, "
-                      "4 nodes per thread, row-interleaved layout>",
+            "kernel": f"k_stream_collide_vec<D3Q27, FP32 deviations/FP64 arithmetic, no correction, "
+                      f"{launch['nodes_per_thread']} nodes per thread, row wave {launch['row_wave']}, "
+                      f"row-interleaved layout>",
             "bytes_per_node_update": bytes_per_lup,
             "launch_avg_ms": round(per_launch_s * 1e3, 5),
         },
-        "copy_bandwidth_gbs": round(copy_gbs, 1),
-        "frac_of_copy": round(achieved / copy_gbs, 4),
+        "launch": launch,
         "wall_s_timed_region": round(t_wall, 4),
         "repetitions_ms_per_step": [round(v, 5) for v in reps],
         "median_of_5_mlups": round(nodes / (sorted(reps)[2] / 1e3) / 1e6, 1),
         "mass_drift": abs(diag["mass"] / (nodes * 1.0) - 1.0),
         "kernel_source_digest": kernel_source_digest(),
     }
+    if ceiling:
+        out["ceiling"] = ceiling
+        out["frac_of_free_streaming"] = round(achieved / ceiling["free_streaming_d3q27_fp32_dev_gbs"], 4)
+        out["frac_of_copy_nt"] = round(achieved / ceiling["copy_nt_gbs"], 4)
     if "batched" in sections:
         fixed = None
         if args.batch_tuning:
@@ -663,7 +737,8 @@ def main() -> int:
                                        fixed_tuning=fixed)
         progress("batched done")
     if "serving" in sections:
-        out["serving"] = bench_serving(args.serve_requests, args.serve_rate, args.serve_light_requests)
+        out["serving"] = bench_serving(args.serve_requests, args.serve_rate, args.serve_light_requests,
+                                       tuple(args.serve_policies.split(",")))
     if "wave" in sections:
         out["wave"] = bench_wave()
         progress("wave done")

@@ -272,6 +272,36 @@ int lbm_moments(lbm_handle *h, double *rho, double *u, lbm_diag *diag);
  * pointer to Q * N doubles.  Synchronises the stream. */
 int lbm_get_populations(lbm_handle *h, double *out);
 
+/* The launch the library chose for a domain's steps (from its configuration
+ * and tuning), so that callers and tests can state which kernel ran. */
+enum {
+    LBM_KERNEL_NODE = 1,      /* one node per thread (any nx) */
+    LBM_KERNEL_VECTOR = 2,    /* nodes_per_thread consecutive x nodes per thread, one 16-byte
+                                 load and store per population run, x shifts by lane rotation */
+    LBM_KERNEL_TWO_STEP = 3,  /* D2Q9, two steps per launch, the intermediate state in LDS */
+    LBM_KERNEL_MULTI_STEP = 4 /* D1Q3, time_block steps per launch in LDS segments */
+};
+typedef struct lbm_launch_info {
+    int32_t kernel;           /* LBM_KERNEL_* of full launches (step counts that are not a multiple
+                                 of time_block end with launches of the one-step kernel that
+                                 block_x .. layout describe) */
+    int32_t nodes_per_thread; /* of the one-step kernel */
+    int32_t row_wave;         /* 1: one wavefront spans a whole row, so the lane rotation is
+                                 itself the periodic wrap (nx = 64 nodes_per_thread) */
+    int32_t flags;            /* LBM_TUNE_* cache hints of the one-step kernel */
+    int32_t block_x, block_y; /* one-step workgroup shape (threads) */
+    int32_t layout;           /* LBM_LAYOUT_ROWS or LBM_LAYOUT_PLANES */
+    int32_t time_block;       /* steps per launch of `kernel` (1, 2, 4 or 8) */
+    int32_t time_cols;        /* multi-step kernels: owned columns (nodes) per workgroup, else 0 */
+    int32_t time_rows;        /* two-step kernel: rows swept per workgroup, else 0 */
+    int32_t graph_steps;      /* steps per replay of the captured step graph (0: no graph) */
+    int32_t reserved;
+} lbm_launch_info;
+
+/* Fill *out for handle h (host-only; no GPU call).  Errors: LBM_EINVAL (h or
+ * out NULL). */
+int lbm_get_launch_info(const lbm_handle *h, lbm_launch_info *out);
+
 /* Checkpoint and restart: the current state as the library stores it (its
  * private format: the storage type, layout and padding of the handle's
  * configuration and tuning), so that a restart is bit-exact for every storage
@@ -306,6 +336,26 @@ int lbm_load_state(lbm_handle *h, const void *src, size_t bytes, int64_t steps);
  * LBM_EINVAL (h or out NULL, rho_ref <= 0 or not finite, U not finite);
  * LBM_EDEVICE. */
 int lbm_energy(lbm_handle *h, const double *U, double rho_ref, double *out);
+
+/* Measurement aids (not part of the method): the speed of the access pattern
+ * alone, as the ceiling against which the stream-collide kernel is read.
+ *
+ * lbm_ceiling_stream: nsteps steps of free streaming, f_i(r, t + 1) =
+ * f_i(r - c_i, t), with no collision: the launch, loads and stores of the
+ * handle's one-step kernel (the streaming half of the LBGK evolution equation
+ * of Sec. "Basic concepts") with the arithmetic left out.  It replaces the
+ * handle's state by the freely streamed one and leaves its step count alone:
+ * use a domain made for the measurement.  D2Q9 / D3Q27 periodic domains with
+ * LBM_FP64 or LBM_FP32_DEV storage, one step per launch, one node per thread
+ * or the default vector width and flags.  Enqueued without synchronising.
+ * Errors: LBM_EINVAL (h NULL, nsteps < 0, another configuration); LBM_EDEVICE.
+ *
+ * lbm_ceiling_copy: copies `bytes` (a multiple of 16) from src to dst (device
+ * pointers, 16-byte aligned, not overlapping), one 16-byte non-temporal load
+ * and store per thread; enqueued on `stream` without synchronising.  Errors:
+ * LBM_EINVAL; LBM_EDEVICE. */
+int lbm_ceiling_stream(lbm_handle *h, int64_t nsteps);
+int lbm_ceiling_copy(const void *src, void *dst, size_t bytes, void *stream);
 
 /* Release the handle (host state only; the caller's workspace is untouched).
  * Synchronises the stream first.  lbm_destroy(NULL) returns LBM_OK. */
@@ -351,11 +401,20 @@ typedef struct lbm_pool_tuning {
                            tile_x x tile_y.  Not with flat; other values are LBM_EINVAL */
     int32_t time_block; /* 2: D2Q9 classes (LBM_FP64 or LBM_FP32_DEV, row-interleaved slots)
                            advance two steps per launch, the intermediate state in LDS, in
-                           runs where every slot of the class takes the same even number of
-                           steps and the class holds >= 2^22 nodes (FP32) or 2^20 (FP64);
-                           other runs take one step per launch.  Results are bitwise those
-                           of one step per launch.  0 or 1: one step per launch.
-                           Not with persistent */
+                           runs where the class's slots that take at least two steps hold
+                           >= 2^22 nodes (FP32) or 2^20 (FP64); a slot whose step count in
+                           the run is odd takes its last step in a one-step launch.  Slots
+                           whose row, rounded up to 64, is at most 512 (FP32) or 128 (FP64)
+                           nodes run as whole-row tiles (no halo columns), wider ones as
+                           column tiles of 512 (FP32) or 64 (FP64).  Other runs take one
+                           step per launch.  Results are bitwise those of one step per
+                           launch.  0 or 1: one step per launch.  Not with persistent */
+    int32_t time_rows;  /* time_block = 2: rows swept by each whole-row sub-tile and each column
+                           tile (0 = default, 32; at most 4096) */
+    int32_t spin_log2;  /* persistent form: a workgroup waits at most 2^spin_log2 polls of the
+                           grid barrier's counter before it reports a timeout (1..40; 0 = the
+                           default, 26, seconds of waiting).  Small values exist to exercise
+                           the timeout path: every workgroup still leaves normally */
 } lbm_pool_tuning;
 
 typedef struct lbm_pool_stats {
@@ -369,8 +428,10 @@ typedef struct lbm_slot_info {
     int32_t finished;     /* 1 if its step budget is spent (or it was retired) */
     int64_t steps_done, steps_remaining;
     int64_t bytes;        /* arena bytes held */
-    int32_t domain_error; /* 1 if lbm_pool_poll retired it: its state left the domain */
-    int32_t reserved;
+    int32_t domain_error; /* 1 if it was retired because its state left the domain */
+    int32_t device_error; /* 1 if a persistent launch that advanced it stopped at a timed-out
+                             grid barrier: its state is that of an unknown step, and
+                             lbm_pool_moments / lbm_pool_get_populations return LBM_EDEVICE */
 } lbm_slot_info;
 
 /* Arena bytes the pool keeps for its tables (the rest holds slots). */
@@ -381,8 +442,11 @@ size_t lbm_pool_slot_bytes(const lbm_config *cfg, const lbm_pool_tuning *tuning)
 
 /* Create a pool of at most max_slots (1..65536) slots on `arena` (device
  * pointer, 256-byte aligned, arena_bytes > lbm_pool_table_bytes(max_slots)),
- * enqueuing on `stream`.  tuning may be NULL.  Errors: LBM_EINVAL,
- * LBM_EDEVICE (pinned staging allocation, device query). */
+ * enqueuing on `stream`.  tuning may be NULL.  The pool keeps a second,
+ * non-blocking stream of its own for reads of finished slots, pinned host
+ * staging for its run tables (8 x the table of one class) and a ring of HIP
+ * events.  Errors: LBM_EINVAL, LBM_EDEVICE (pinned staging allocation, stream
+ * or event creation, device query). */
 int lbm_pool_create(int32_t max_slots, const lbm_pool_tuning *tuning, void *arena, size_t arena_bytes,
                     void *stream, lbm_pool **out);
 
@@ -394,24 +458,63 @@ int lbm_pool_create(int32_t max_slots, const lbm_pool_tuning *tuning, void *aren
 int lbm_pool_admit(lbm_pool *pool, const lbm_config *cfg, const double *rho, const double *u, int64_t nsteps,
                    int32_t *slot);
 
+/* lbm_pool_admit without the synchronisation, for callers that keep work in
+ * flight (a serving loop): the initialisation is enqueued on the pool's stream
+ * behind the work already there, and the call returns at once.  rho and u
+ * must stay valid until the stream has run the initialisation (memory that
+ * the caller allocated in stream order on the same stream, e.g. torch's
+ * caching allocator on that stream, may be freed right after the call).  The
+ * initial state is checked on the device: a slot whose initial state has a
+ * node with rho <= 0 or |u_alpha| >= 1 is retired by the next lbm_pool_poll or
+ * lbm_pool_collect that finds its initialisation done (listed as done,
+ * domain_error = 1, lbm_pool_moments returns LBM_EDOMAIN).  Errors:
+ * LBM_EBUSY, LBM_ENOMEM, LBM_EINVAL, LBM_EDEVICE; nothing is enqueued then. */
+int lbm_pool_admit_async(lbm_pool *pool, const lbm_config *cfg, const double *rho, const double *u,
+                         int64_t nsteps, int32_t *slot);
+
 /* Advance every slot with steps remaining by min(k, remaining) steps.
- * Enqueues and returns without synchronising.  k = 0 is a no-op. */
+ * Enqueues and returns without synchronising.  k = 0 is a no-op.  Runs are
+ * numbered from 1 in lbm_pool_stats.runs (a run that enqueues nothing gets
+ * no number).  Errors: LBM_EINVAL; LBM_EDEVICE (a launch failed: the slots of
+ * the failing class keep their step counts and state of before the run). */
 int lbm_pool_run(lbm_pool *pool, int64_t k);
 
 /* Synchronise, then list (up to capacity) slots whose budget is spent and that
  * were not listed before; *count receives how many were written.  A slot whose
  * domain flag is set (some node left rho > 0, |u_alpha| < 1) is retired here:
  * its remaining steps are dropped, it is listed as done, its slot info shows
- * domain_error = 1 and lbm_pool_moments returns LBM_EDOMAIN for it.  Returns
- * LBM_EDEVICE if a persistent launch's grid barrier timed out. */
+ * domain_error = 1 and lbm_pool_moments returns LBM_EDOMAIN for it.
+ * If a persistent launch's grid barrier timed out since the last poll, every
+ * slot that such a launch advanced is retired with device_error = 1 (listed
+ * as done by this or a later poll; lbm_pool_moments returns LBM_EDEVICE for
+ * it), the barrier state is reset so that the pool stays usable, and the call
+ * returns LBM_EDEVICE after writing the list. */
 int lbm_pool_poll(lbm_pool *pool, int32_t *done, int32_t capacity, int32_t *count);
 
+/* Non-blocking completion, for callers that enqueue run n + 1 before they
+ * collect the results of run n.  First waits until the device has finished
+ * run number after_run (lbm_pool_stats.runs numbering; <= 0 or a run not yet
+ * enqueued: no wait), while later work keeps running.  Then lists, without
+ * synchronising the stream, up to capacity slots whose budget is spent, whose
+ * enqueued work has all completed on the device, and that were not listed
+ * before.  The initial states of slots admitted by lbm_pool_admit_async whose
+ * initialisation has completed are checked here too (retired as in
+ * lbm_pool_poll).  Domain flags raised later are reported by lbm_pool_moments
+ * (LBM_EDOMAIN) and by lbm_pool_poll, which also retires running slots early.
+ * Errors: LBM_EINVAL, LBM_EDEVICE. */
+int lbm_pool_collect(lbm_pool *pool, int64_t after_run, int32_t *done, int32_t capacity, int32_t *count);
+
 /* Moments / populations of one slot, as lbm_moments / lbm_get_populations.
- * LBM_EDOMAIN concerns this slot only. */
+ * LBM_EDOMAIN concerns this slot only; LBM_EDEVICE for a slot retired after a
+ * timed-out persistent launch (outputs not written).  When the slot's enqueued
+ * work has completed on the device (a slot listed by lbm_pool_collect) the
+ * read runs on the pool's second stream and does not wait for later runs;
+ * otherwise it synchronises the pool's stream. */
 int lbm_pool_moments(lbm_pool *pool, int32_t slot, double *rho, double *u, lbm_diag *diag);
 int lbm_pool_get_populations(lbm_pool *pool, int32_t slot, double *out);
 
-/* Free a slot and its arena block (synchronises first). */
+/* Free a slot and its arena block.  Waits until the device has finished the
+ * work enqueued for this slot (not the later work of other slots). */
 int lbm_pool_release(lbm_pool *pool, int32_t slot);
 
 int lbm_pool_stats_get(lbm_pool *pool, lbm_pool_stats *stats);

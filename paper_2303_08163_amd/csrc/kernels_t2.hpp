@@ -252,6 +252,114 @@ __device__ __forceinline__ void two_step_tile(const Step2Args &a, int tile) {
     }
 }
 
+// Whole-row two-step tiles, for rows no wider than a workgroup.  The
+// workgroup's B threads form S sub-tiles of w = 64 m lanes (w >= nx, S w <= B,
+// so no wavefront straddles two sub-tiles); sub-tile s of workgroup tile
+// `tile` owns the rows [(tile S + s) R, + R) of the whole width and sweeps
+// them as two_step_tile does, with a ring of four LDS rows of w + 2 columns
+// of its own.  The row is whole, so the x neighbours of step 2 at the ends of
+// the row are the row's own columns across the periodic wrap, already in the
+// ring: no halo column is loaded or computed, and no node of step 1 is
+// computed twice along x.  Lane t < nx computes column t; lanes past the row
+// load column 0 and discard the result.  Wavefronts of sub-tiles without rows
+// (past S, or past the last row) only keep to the barriers.  Every node runs
+// the same collision code as the one-step kernels, so the results are
+// bitwise those of two one-step launches.  Dynamic LDS:
+// t2_rows_lds_bytes(S, w, elem).
+__host__ __device__ constexpr size_t t2_rows_lds_bytes(int S, int w, size_t elem) {
+    return (size_t)S * kT2Ring * 9 * (size_t)(w + 2) * elem;
+}
+
+template <int DT, bool CORR, int EQ, bool NT>
+__device__ __forceinline__ void two_step_rows_tile(const Step2Args &a, int tile, int w, int S, int R) {
+    using T = store_t<DT>;
+    extern __shared__ __align__(16) unsigned char t2_lds[];
+    const T *__restrict__ src = static_cast<const T *>(a.src);
+    T *__restrict__ dst = static_cast<T *>(a.dst);
+
+    const int tid = (int)threadIdx.x;
+    const int sub = tid / w;      // uniform per wavefront (w is a multiple of 64)
+    const int t = tid - sub * w;  // column
+    const int w1 = w + 2;         // ring columns: column c holds x = c - 1 (1 .. nx)
+    const int y0 = (tile * S + sub) * R;
+    const int y1 = min(y0 + R, a.ny);
+    const bool active = sub < S && y0 < a.ny;  // uniform per wavefront
+    const int my_sweep = active ? y1 - y0 + 2 : 0;  // sweep rows y0 - 1 .. y1
+    T *ring = reinterpret_cast<T *>(t2_lds) + (size_t)(active ? sub : 0) * kT2Ring * 9 * w1;
+    const bool valid = t < a.nx;
+    const int x = valid ? t : 0;
+    // byte offsets of the source columns x - c_x (c_x = -1, 0, +1), wrapped
+    const uint32_t xb[3] = {(uint32_t)((x + 1 == a.nx ? 0 : x + 1) * (int)sizeof(T)), (uint32_t)(x * (int)sizeof(T)),
+                            (uint32_t)((x == 0 ? a.nx - 1 : x - 1) * (int)sizeof(T))};
+    // ring columns of the same sources for step 2, wrapped inside the row
+    const int cc[3] = {x + 1 == a.nx ? 1 : x + 2, x + 1, x == 0 ? a.nx : x};
+    auto wrap_row = [&](int r) { return r < 0 ? r + a.ny : (r >= a.ny ? r - a.ny : r); };
+
+    // sweep offset k: step 1 at row y0 - 1 + k from f, then (after the barrier)
+    // the loads of row y0 + 1 + k into f and step 2 at row y0 - 2 + k
+    auto sweep_row = [&](T (&f)[9], int k) {
+        const int r = y0 - 1 + k;
+        const bool work = k < my_sweep;  // uniform per wavefront
+        if (work) {
+            const bool bad1 = collide_dt<2, DT, CORR, EQ>(f, a.relax);
+            raise_flag(a.flag, bad1 && valid);
+            T *slot = ring + (size_t)(k & (kT2Ring - 1)) * 9 * w1;
+            if (valid) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i)
+                    slot[i * w1 + t + 1] = f[i];
+            }
+        }
+        // slot k + 1 (written at the next offset) is slot k - 3, last read by
+        // step 2 at offset k - 1, before this barrier
+        __syncthreads();
+        if (work) {
+            if (r + 2 <= y1)
+                pull_row_d2q9<T>(src, a.ny, a.ps, a.rs, wrap_row(r + 2), xb, f);
+            if (k >= 2) {
+                const int y = r - 1;
+                T g[9];
+#pragma unroll
+                for (int cy = 0; cy < 3; ++cy) {
+                    const T *srow = ring + (size_t)((k - cy) & (kT2Ring - 1)) * 9 * w1;
+#pragma unroll
+                    for (int cx = 0; cx < 3; ++cx)
+                        g[cx + 3 * cy] = srow[(cx + 3 * cy) * w1 + cc[cx]];
+                }
+                const bool bad2 = collide_dt<2, DT, CORR, EQ>(g, a.relax);
+                raise_flag(a.flag, bad2 && valid);
+                if (valid) {
+                    const uint32_t ob = (uint32_t)(x * (int)sizeof(T));
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) {
+                        char *base = reinterpret_cast<char *>(dst + (int64_t)y * a.rs + (int64_t)i * a.ps);
+                        if constexpr (NT)
+                            __builtin_nontemporal_store(g[i], reinterpret_cast<T *>(base + ob));
+                        else
+                            *reinterpret_cast<T *>(base + ob) = g[i];
+                    }
+                }
+            }
+        }
+    };
+
+    // every wavefront takes R + 2 offsets (the barriers of the workgroup)
+    T fa[9], fb[9];
+    if (active) {
+        pull_row_d2q9<T>(src, a.ny, a.ps, a.rs, wrap_row(y0 - 1), xb, fa);
+        pull_row_d2q9<T>(src, a.ny, a.ps, a.rs, y0, xb, fb);
+    }
+    const int nsweep = R + 2;
+    for (int k = 0;;) {
+        sweep_row(fa, k);
+        if (++k >= nsweep)
+            break;
+        sweep_row(fb, k);
+        if (++k >= nsweep)
+            break;
+    }
+}
+
 template <int DT, bool CORR, int EQ = kEqEntropic, bool NT = false>
 __global__ __launch_bounds__(512) void k_stream_collide2(Step2Args a) {
     two_step_tile<DT, CORR, EQ, NT>(a, xcd_tile((int)blockIdx.x, (int)gridDim.x));

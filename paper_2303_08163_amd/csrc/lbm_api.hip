@@ -716,6 +716,27 @@ static void launch_halo_copy(const DomainState &d, const void *lower, const void
     hipLaunchKernelGGL(k_halo_copy<E>, dim3((unsigned)(9 * ny), 2), dim3(threads), 0, stream, a);
 }
 
+// Free streaming with the one-step kernel's launch: the kernel the handle's
+// tuning selects, instantiated without the collision.
+template <int DIM, int DT>
+static StepFn stream_only_kernel(const Layout &L) {
+    if (L.npt == 1)
+        return k_stream_collide<DIM, DT, false, kEqStreamOnly>;
+    constexpr int NPT = DT == kF64 ? 2 : 4;
+    constexpr int FL = DT == kF64 ? kNtStore : kNtStore | kNtLoad;
+    return L.rowwave ? k_stream_collide_vec<DIM, DT, false, NPT, true, FL, kEqStreamOnly>
+                     : k_stream_collide_vec<DIM, DT, false, NPT, false, FL, kEqStreamOnly>;
+}
+
+// One float4 per thread, non-temporal loads and stores.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+static __global__ __launch_bounds__(256) void k_copy_nt(const f32x4 *__restrict__ src, f32x4 *__restrict__ dst,
+                                                        int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
 extern "C" {
 
 size_t lbm_workspace_bytes_tuned(const lbm_config *cfg, const lbm_tuning *tuning) {
@@ -850,7 +871,9 @@ static void prepare_step_graphs(lbm_handle *h) {
         if (!step_graph(h, cur))
             break;
     if (h->capture) {
-        hipStreamDestroy(h->capture);
+        // a failure here loses only the private capture stream; the graphs stay usable
+        if (hipStreamDestroy(h->capture) != hipSuccess)
+            (void)hipGetLastError();
         h->capture = nullptr;
     }
 }
@@ -1031,6 +1054,79 @@ int lbm_load_state(lbm_handle *h, const void *src, size_t bytes, int64_t steps) 
     return LBM_OK;
 }
 
+int lbm_ceiling_stream(lbm_handle *h, int64_t nsteps) {
+    if (!h || nsteps < 0) {
+        set_error("NULL handle or negative step count");
+        return LBM_EINVAL;
+    }
+    DomainState &d = h->d;
+    const Layout &L = d.L;
+    const int dt = d.cfg.dtype;
+    const bool default_vec = L.npt == (dt == LBM_FP64 ? 2 : 4) &&
+                             L.flags == (dt == LBM_FP64 ? LBM_TUNE_NT_STORE : LBM_TUNE_NT_STORE | LBM_TUNE_NT_LOAD);
+    if (L.dim < 2 || L.zhalo || L.tblock != 1 || (dt != LBM_FP64 && dt != LBM_FP32_DEV) ||
+        !(L.npt == 1 || default_vec)) {
+        set_error("free streaming runs on D2Q9 / D3Q27 periodic domains with FP64 or FP32_DEV storage, one step "
+                  "per launch, one node per thread or the default vector width and flags");
+        return LBM_EINVAL;
+    }
+    StepFn fn = L.dim == 2 ? (dt == LBM_FP64 ? stream_only_kernel<2, kF64>(L) : stream_only_kernel<2, kDevF64>(L))
+                           : (dt == LBM_FP64 ? stream_only_kernel<3, kF64>(L) : stream_only_kernel<3, kDevF64>(L));
+    const int tiles_x = (int)((d.cfg.nx + (int64_t)L.block_x * L.npt - 1) / ((int64_t)L.block_x * L.npt));
+    const int tiles_y = (int)((d.cfg.ny + L.block_y - 1) / L.block_y);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        StepArgs a{d.buf[d.cur], d.buf[d.cur ^ 1], (int)d.cfg.nx, (int)d.cfg.ny, (int)d.cfg.nz, tiles_x, tiles_y,
+                   L.ps, L.rs, d.relax, d.flag, 0};
+        hipLaunchKernelGGL(fn, dim3((unsigned)(tiles_x * tiles_y * d.cfg.nz)), dim3(L.block_x, L.block_y, 1), 0,
+                           h->stream, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return hip_fail(e, "free-streaming launch");
+        d.cur ^= 1;
+    }
+    return LBM_OK;
+}
+
+int lbm_ceiling_copy(const void *src, void *dst, size_t bytes, void *stream) {
+    if (!src || !dst || bytes % 16 != 0 || reinterpret_cast<uintptr_t>(src) % 16 != 0 ||
+        reinterpret_cast<uintptr_t>(dst) % 16 != 0 || bytes > ((size_t)1 << 40)) {
+        set_error("copy: NULL or misaligned buffer, or bytes not a multiple of 16");
+        return LBM_EINVAL;
+    }
+    const int64_t n = (int64_t)(bytes / 16);
+    if (n == 0)
+        return LBM_OK;
+    hipLaunchKernelGGL(k_copy_nt, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       static_cast<const f32x4 *>(src), static_cast<f32x4 *>(dst), n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return hip_fail(e, "copy launch");
+    return LBM_OK;
+}
+
+int lbm_get_launch_info(const lbm_handle *h, lbm_launch_info *out) {
+    if (!h || !out) {
+        set_error("NULL handle or output");
+        return LBM_EINVAL;
+    }
+    const Layout &L = h->d.L;
+    lbm_launch_info r{};
+    r.kernel = L.tblock > 1 ? (L.dim == 1 ? LBM_KERNEL_MULTI_STEP : LBM_KERNEL_TWO_STEP)
+                            : (L.npt > 1 ? LBM_KERNEL_VECTOR : LBM_KERNEL_NODE);
+    r.nodes_per_thread = L.npt;
+    r.row_wave = L.rowwave ? 1 : 0;
+    r.flags = L.flags;
+    r.block_x = L.block_x;
+    r.block_y = L.block_y;
+    r.layout = L.layout;
+    r.time_block = L.tblock;
+    r.time_cols = L.tblock > 1 ? L.t2_tx : 0;
+    r.time_rows = L.tblock == 2 && L.dim == 2 ? L.t2_rows : 0;
+    r.graph_steps = (h->exec[0] || h->exec[1]) && !h->graphs_off ? kGraphSteps : 0;
+    *out = r;
+    return LBM_OK;
+}
+
 int lbm_get_populations(lbm_handle *h, double *out) {
     if (!h || !out) {
         set_error("NULL handle or output");
@@ -1043,14 +1139,19 @@ int lbm_destroy(lbm_handle *h) {
     if (!h)
         return LBM_OK;
     hipError_t e = hipStreamSynchronize(h->stream);
+    // release everything even after a failure; report the first one
+    auto keep = [&e](hipError_t r) {
+        if (e == hipSuccess)
+            e = r;
+    };
     for (int k = 0; k < 2; ++k) {
         if (h->exec[k])
-            hipGraphExecDestroy(h->exec[k]);
+            keep(hipGraphExecDestroy(h->exec[k]));
         if (h->graph[k])
-            hipGraphDestroy(h->graph[k]);
+            keep(hipGraphDestroy(h->graph[k]));
     }
     if (h->capture)
-        hipStreamDestroy(h->capture);
+        keep(hipStreamDestroy(h->capture));
     delete h;
     if (e != hipSuccess)
         return hip_fail(e, "destroy synchronise");

@@ -131,6 +131,10 @@ __host__ __device__ __forceinline__ double corrected_omega(double umax, double S
 //   kEqProduct:  eq. (Product_isothermal_EDF), rho prod_a phi_{c_ia}(u_a) with
 //                phi_0 = 1 - s2 - u^2 and phi_{+-1} = (+-u + s2 + u^2) / 2.
 constexpr int kEqEntropic = 0, kEqPoly2 = 1, kEqProduct = 2;
+// Not an equilibrium: the collision is left out and the populations stream
+// unchanged.  Only the measurement of the access pattern's own ceiling uses
+// it (lbm_ceiling_stream): the same kernels, loads and stores, no arithmetic.
+constexpr int kEqStreamOnly = -1;
 
 // (phi_0 is formed as 1 - (s2 + u^2) so that the factors sum to 1 up to rounding.)
 __host__ __device__ __forceinline__ void product_factors(double u, double (&g)[3]) {
@@ -347,7 +351,9 @@ __device__ __forceinline__ bool collide_dev_f32(float (&v)[Lattice<DIM>::Q], con
 // (The single-precision ablation modes exist for the entropic equilibrium only.)
 template <int DIM, int DT, bool CORR, int EQ = kEqEntropic>
 __device__ __forceinline__ bool collide_dt(store_t<DT> (&v)[Lattice<DIM>::Q], const Relax &r) {
-    if constexpr (DT == kDevMixed)
+    if constexpr (EQ == kEqStreamOnly)
+        return false;
+    else if constexpr (DT == kDevMixed)
         return collide_dev_f32<DIM, CORR, true>(v, r);
     else if constexpr (DT == kDevF32)
         return collide_dev_f32<DIM, CORR, false>(v, r);

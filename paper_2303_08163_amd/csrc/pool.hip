@@ -16,14 +16,18 @@
 namespace lbm {
 
 constexpr int kClasses = 16;  // (D2Q9, D3Q27) x 4 dtypes x (correction off, on)
-constexpr long long kSpinLimit = 1ll << 26;
+constexpr int kSpinLog2 = 26;  // default bound of a grid-barrier wait: 2^26 polls
+constexpr int kStagingRing = 8;  // pinned run-table buffers in use in turn
+constexpr int kEpochRing = 64;   // completion events of recent runs and admissions
+constexpr int64_t kEpochStream = INT64_MAX;  // "all work on the pool's stream" (no event)
 
 static size_t round256(size_t v) { return (v + 255) / 256 * 256; }
 
 // Device table of one class: descriptors, running tile counts, remaining steps.
+// (descriptors | one-step tile starts | remaining steps | two-step tile starts)
 static size_t class_table_bytes(int max_slots) {
     return round256(sizeof(SlotDesc) * (size_t)max_slots) + round256(sizeof(int) * ((size_t)max_slots + 1)) +
-           round256(sizeof(int64_t) * (size_t)max_slots);
+           round256(sizeof(int64_t) * (size_t)max_slots) + round256(sizeof(int) * ((size_t)max_slots + 1));
 }
 
 static int resolve_tuning(const lbm_pool_tuning *t, lbm_pool_tuning *out) {
@@ -34,6 +38,16 @@ static int resolve_tuning(const lbm_pool_tuning *t, lbm_pool_tuning *out) {
         set_error("pool tuning: time_block must be 0, 1 or 2");
         return LBM_EINVAL;
     }
+    if (r.time_rows < 0 || r.time_rows > 4096) {
+        set_error("pool tuning: time_rows must lie in 0 .. 4096");
+        return LBM_EINVAL;
+    }
+    if (r.spin_log2 < 0 || r.spin_log2 > 40) {
+        set_error("pool tuning: spin_log2 must lie in 0 .. 40");
+        return LBM_EINVAL;
+    }
+    if (r.spin_log2 == 0)
+        r.spin_log2 = kSpinLog2;
     if (r.time_block == 2 && r.persistent) {
         set_error("pool tuning: time_block = 2 is not with persistent");
         return LBM_EINVAL;
@@ -127,11 +141,18 @@ static PoolStepFn pool_kernel(int dtype, bool corr, bool persistent) {
     }
 }
 
-// Two-step pool tiles: 128 columns by 16 rows.  On the batched workload (rows
-// 32..512 wide) 128 columns gave 730 solves/s FP32 and 461 FP64 against 708
-// and 457 with 64: fewer re-read halo lines outweigh the idle lanes of the
-// narrow slots.
-constexpr int kPoolT2Tx = 128, kPoolT2Rows = 16;
+// Two steps per launch in pools.  One launch has one workgroup shape: 512
+// threads for FP32 storage (column tiles of 512, the single-domain choice) and
+// 128 for FP64 (column tiles of 64 plus the halo wavefront).  A slot whose row,
+// rounded up to 64, fits the workgroup runs as whole-row tiles instead
+// (two_step_rows_tile): floor(threads / w) sub-tiles of w lanes, each sweeping
+// kPoolT2Rows rows (the default; lbm_pool_tuning.time_rows).  Whole rows need
+// no halo columns: with the earlier 128 x 16 column tiles, the batched
+// workload's narrow rows read 1.46x the algorithmic bytes, from the column
+// halos' cache lines and the 2 + 2 extra rows of every 16.
+constexpr int kPoolT2Rows = 32;
+static int t2_block(int dtype) { return dtype == kF64 ? 128 : 512; }
+static int t2_cols(int dtype) { return dtype == kF64 ? 64 : 512; }
 
 struct Slot {
     bool used = false;
@@ -139,7 +160,11 @@ struct Slot {
     DomainState d{};
     size_t off = 0, bytes = 0;
     int64_t remaining = 0;
-    bool failed = false;  // retired at poll: its state left the equilibrium's domain
+    bool failed = false;      // retired: its state left the equilibrium's domain
+    bool broken = false;      // retired: a persistent launch that advanced it timed out at a barrier
+    bool unverified = false;  // admitted without a synchronisation: initial state not checked yet
+    bool persistent = false;  // advanced by a persistent launch since the last poll
+    int64_t last_epoch = 0;   // epoch whose completion covers all work enqueued for the slot (0: none)
     int tiles_x = 0, tiles_y = 0, tiles = 0;
     int tw_shift = 0;  // row_fit: tile rows of 1 << tw_shift threads; 0: the workgroup's own shape
     int cls = 0;
@@ -151,6 +176,7 @@ using namespace lbm;
 
 struct lbm_pool {
     hipStream_t stream = nullptr;
+    hipStream_t aux = nullptr;  // reads of slots whose work has completed
     char *arena = nullptr;
     size_t arena_bytes = 0;
     lbm_pool_tuning tun{};
@@ -160,11 +186,20 @@ struct lbm_pool {
     size_t table_bytes = 0, class_bytes = 0;
     unsigned *barrier = nullptr;
     int *error = nullptr;
-    char *staging = nullptr;  // pinned host copy of one class table
+    // pinned host copies of class tables, used in turn; each buffer's event marks the
+    // end of its last upload
+    char *staging[kStagingRing] = {};
+    hipEvent_t staging_ev[kStagingRing] = {};
+    bool staging_used[kStagingRing] = {};
+    int staging_next = 0;
+    // epochs: an event recorded on the stream after each run and each unsynchronised
+    // admission; epoch e lives in ring entry e % kEpochRing while ep_seq says so
+    hipEvent_t ep_ev[kEpochRing] = {};
+    int64_t ep_seq[kEpochRing] = {};
+    int64_t epoch = 0;
+    std::vector<int64_t> run_epoch;  // epoch of run r at index r - 1
     char *gather_host = nullptr;  // pinned: flag pointers, then flag values
     char *gather_dev = nullptr;
-    hipEvent_t staging_done = nullptr;
-    bool staging_pending = false;
     int cu_count = 0;
     int64_t runs = 0, launches = 0;
 };
@@ -208,6 +243,99 @@ int check_slot(lbm_pool *p, int32_t slot) {
         return LBM_EINVAL;
     }
     return LBM_OK;
+}
+
+// Record the next epoch on the pool's stream (after everything enqueued so far).
+hipError_t record_epoch(lbm_pool *p, int64_t *out) {
+    const int64_t e = p->epoch + 1;
+    const int k = (int)(e % kEpochRing);
+    hipError_t r = hipEventRecord(p->ep_ev[k], p->stream);
+    if (r != hipSuccess)
+        return r;
+    p->epoch = e;
+    p->ep_seq[k] = e;
+    *out = e;
+    return hipSuccess;
+}
+
+// The event whose completion implies that of epoch e: its own, or, once the
+// ring has moved on, the newer epoch recorded in its entry (later in the stream).
+hipEvent_t epoch_event(const lbm_pool *p, int64_t e) { return p->ep_ev[e % kEpochRing]; }
+
+// hipSuccess when epoch e (<= 0: nothing; kEpochStream: everything enqueued on
+// the stream) has completed, hipErrorNotReady when not.
+hipError_t epoch_query(lbm_pool *p, int64_t e) {
+    if (e <= 0)
+        return hipSuccess;
+    if (e == kEpochStream)
+        return hipStreamQuery(p->stream);
+    return hipEventQuery(epoch_event(p, e));
+}
+
+hipError_t epoch_wait(lbm_pool *p, int64_t e) {
+    if (e <= 0)
+        return hipSuccess;
+    if (e == kEpochStream)
+        return hipStreamSynchronize(p->stream);
+    return hipEventSynchronize(epoch_event(p, e));
+}
+
+// Next pinned staging buffer: wait until its previous upload has left it.
+hipError_t acquire_staging(lbm_pool *p, int *idx) {
+    const int k = p->staging_next;
+    p->staging_next = (k + 1) % kStagingRing;
+    if (p->staging_used[k]) {
+        hipError_t e = hipEventSynchronize(p->staging_ev[k]);
+        if (e != hipSuccess)
+            return e;
+        p->staging_used[k] = false;
+    }
+    *idx = k;
+    return hipSuccess;
+}
+
+// Domain flags of the listed slots into vals (pinned), on stream s, synchronised.
+// The gather area is used by one call at a time: every caller synchronises
+// before it returns.
+hipError_t gather_flags(lbm_pool *p, const std::vector<int> &which, hipStream_t s, int **vals_out) {
+    const int n = (int)which.size();
+    int **ptrs = reinterpret_cast<int **>(p->gather_host);
+    int *vals = reinterpret_cast<int *>(p->gather_host + round256(sizeof(int *) * (size_t)p->max_slots));
+    int *dvals = reinterpret_cast<int *>(p->gather_dev + round256(sizeof(int *) * (size_t)p->max_slots));
+    *vals_out = vals;
+    if (n == 0)
+        return hipSuccess;
+    for (int j = 0; j < n; ++j)
+        ptrs[j] = p->slots[which[j]].d.flag;
+    hipError_t e = hipMemcpyAsync(p->gather_dev, ptrs, sizeof(int *) * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_gather_flags, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                           (const int *const *)p->gather_dev, n, dvals);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(vals, dvals, sizeof(int) * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    return e;
+}
+
+// Release everything the pool holds on the host and in the runtime.
+void pool_free_host(lbm_pool *p) {
+    for (int k = 0; k < kStagingRing; ++k) {
+        if (p->staging[k])
+            (void)hipHostFree(p->staging[k]);
+        if (p->staging_ev[k])
+            (void)hipEventDestroy(p->staging_ev[k]);
+    }
+    for (int k = 0; k < kEpochRing; ++k)
+        if (p->ep_ev[k])
+            (void)hipEventDestroy(p->ep_ev[k]);
+    if (p->gather_host)
+        (void)hipHostFree(p->gather_host);
+    if (p->aux)
+        (void)hipStreamDestroy(p->aux);
+    delete p;
 }
 
 }  // namespace
@@ -267,35 +395,35 @@ int lbm_pool_create(int32_t max_slots, const lbm_pool_tuning *tuning, void *aren
     if (e == hipSuccess)
         e = hipDeviceGetAttribute(&p->cu_count, hipDeviceAttributeMultiprocessorCount, dev);
     p->gather_dev = p->arena + (size_t)kClasses * p->class_bytes + 512;
-    if (e == hipSuccess)
-        e = hipHostMalloc(reinterpret_cast<void **>(&p->staging), p->class_bytes, hipHostMallocDefault);
+    for (int k = 0; k < kStagingRing && e == hipSuccess; ++k) {
+        e = hipHostMalloc(reinterpret_cast<void **>(&p->staging[k]), p->class_bytes, hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&p->staging_ev[k], hipEventDisableTiming);
+    }
+    for (int k = 0; k < kEpochRing && e == hipSuccess; ++k)
+        e = hipEventCreateWithFlags(&p->ep_ev[k], hipEventDisableTiming);
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void **>(&p->gather_host), gather_bytes(max_slots), hipHostMallocDefault);
     if (e == hipSuccess)
-        e = hipEventCreateWithFlags(&p->staging_done, hipEventDisableTiming);
-    if (e != hipSuccess) {
-        if (p->staging)
-            (void)hipHostFree(p->staging);
-        if (p->gather_host)
-            (void)hipHostFree(p->gather_host);
-        delete p;
-        return hip_fail(e, "pool create");
+        e = hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking);
+    if (e == hipSuccess) {
+        // barrier counter and error word (and the words between them) start at zero
+        hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(64), 0, p->stream, reinterpret_cast<int *>(p->barrier), 128);
+        e = hipGetLastError();
     }
-    hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(64), 0, p->stream, reinterpret_cast<int *>(p->barrier), 128);
-    e = hipGetLastError();
     if (e != hipSuccess) {
-        (void)hipHostFree(p->staging);
-        (void)hipHostFree(p->gather_host);
-        (void)hipEventDestroy(p->staging_done);
-        delete p;
+        pool_free_host(p);
         return hip_fail(e, "pool create");
     }
     *out = p;
     return LBM_OK;
 }
 
-int lbm_pool_admit(lbm_pool *p, const lbm_config *cfg, const double *rho, const double *u, int64_t nsteps,
-                   int32_t *slot) {
+// Admission: slot, arena block, tile counts, then f = f^eq(rho, u) enqueued.
+// sync: wait for the initialisation and check the initial state now; else
+// leave the check to the next poll or collect.
+static int pool_admit_impl(lbm_pool *p, const lbm_config *cfg, const double *rho, const double *u,
+                           int64_t nsteps, int32_t *slot, bool sync) {
     if (!p || !cfg || !rho || !u || !slot || nsteps < 0) {
         set_error("pool admit: NULL argument or negative step budget");
         return LBM_EINVAL;
@@ -315,6 +443,26 @@ int lbm_pool_admit(lbm_pool *p, const lbm_config *cfg, const double *rho, const 
         return LBM_EBUSY;
     }
     const size_t bytes = round256(L.ws_bytes);
+    // tile counts first, so that nothing is enqueued for a domain the pool refuses
+    const int64_t block = (int64_t)L.block_x * L.block_y;
+    int64_t tw = L.block_x, th = L.block_y;
+    int tw_shift = 0;
+    if (p->tun.row_fit) {
+        // narrowest power-of-two row width from 64 that covers the padded row
+        const int64_t pitch = L.layout == LBM_LAYOUT_ROWS ? L.ps : cfg->nx;
+        int shift = 6;
+        while ((int64_t)1 << shift < pitch && shift < 8 && block % ((int64_t)2 << shift) == 0)
+            ++shift;
+        tw_shift = shift;
+        tw = (int64_t)1 << shift;
+        th = block / tw;
+    }
+    const int64_t tiles_x = (cfg->nx + tw - 1) / tw, tiles_y = (cfg->ny + th - 1) / th;
+    const int64_t tiles = p->tun.flat ? (L.n + block - 1) / block : tiles_x * tiles_y * cfg->nz;
+    if (tiles > (int64_t)1 << 30) {
+        set_error("pool admit: domain has too many tiles");
+        return LBM_EINVAL;
+    }
     size_t off = 0;
     if (!pool_alloc(p, bytes, &off)) {
         set_error("pool admit: no free arena block large enough");
@@ -324,14 +472,23 @@ int lbm_pool_admit(lbm_pool *p, const lbm_config *cfg, const double *rho, const 
     s = Slot{};
     rc = domain_bind_and_init(s.d, cfg, L, p->arena + off, rho, u, p->stream);
     int flag = 0;
-    if (rc == LBM_OK)
+    if (rc == LBM_OK && sync)
         rc = domain_read_flag(s.d, p->stream, &flag);
     if (rc == LBM_OK && flag) {
         set_error("initial state has a node with rho <= 0 or |u_alpha| >= 1");
         rc = LBM_EDOMAIN;
     }
+    int64_t ep = 0;
+    if (rc == LBM_OK && !sync) {
+        hipError_t e = record_epoch(p, &ep);
+        if (e != hipSuccess)
+            rc = hip_fail(e, "pool admit event");
+    }
     if (rc != LBM_OK) {
+        // (an enqueued initialisation writes only this block, which stays free for
+        // later admissions enqueued behind it)
         pool_free(p, off, bytes);
+        s = Slot{};
         return rc;
     }
     s.used = true;
@@ -339,42 +496,39 @@ int lbm_pool_admit(lbm_pool *p, const lbm_config *cfg, const double *rho, const 
     s.bytes = bytes;
     s.remaining = nsteps;
     s.reported = false;
-    const int64_t block = (int64_t)L.block_x * L.block_y;
-    int64_t tw = L.block_x, th = L.block_y;
-    s.tw_shift = 0;
-    if (p->tun.row_fit) {
-        // narrowest power-of-two row width from 64 that covers the padded row
-        const int64_t pitch = L.layout == LBM_LAYOUT_ROWS ? L.ps : cfg->nx;
-        int shift = 6;
-        while ((int64_t)1 << shift < pitch && shift < 8 && block % ((int64_t)2 << shift) == 0)
-            ++shift;
-        s.tw_shift = shift;
-        tw = (int64_t)1 << shift;
-        th = block / tw;
-    }
-    s.tiles_x = (int)((cfg->nx + tw - 1) / tw);
-    s.tiles_y = (int)((cfg->ny + th - 1) / th);
-    const int64_t tiles = p->tun.flat ? (L.n + block - 1) / block : (int64_t)s.tiles_x * s.tiles_y * cfg->nz;
-    if (tiles > (int64_t)1 << 30) {
-        pool_free(p, off, bytes);
-        s = Slot{};
-        set_error("pool admit: domain has too many tiles");
-        return LBM_EINVAL;
-    }
+    s.unverified = !sync;
+    s.last_epoch = ep;
+    s.tw_shift = tw_shift;
+    s.tiles_x = (int)tiles_x;
+    s.tiles_y = (int)tiles_y;
     s.tiles = (int)tiles;
     s.cls = class_of(cfg);
     *slot = k;
     return LBM_OK;
 }
 
-int lbm_pool_run(lbm_pool *p, int64_t k) {
-    if (!p || k < 0) {
-        set_error("pool run: NULL pool or negative step count");
-        return LBM_EINVAL;
-    }
-    if (k == 0)
-        return LBM_OK;
-    bool any = false;
+int lbm_pool_admit(lbm_pool *p, const lbm_config *cfg, const double *rho, const double *u, int64_t nsteps,
+                   int32_t *slot) {
+    return pool_admit_impl(p, cfg, rho, u, nsteps, slot, true);
+}
+
+int lbm_pool_admit_async(lbm_pool *p, const lbm_config *cfg, const double *rho, const double *u, int64_t nsteps,
+                         int32_t *slot) {
+    return pool_admit_impl(p, cfg, rho, u, nsteps, slot, false);
+}
+
+// Enqueue the launches of every class with active slots; a slot that took part
+// gets last_epoch = -1 (resolved by the caller).
+//
+// In a run of k steps slot j of a class takes s_j = min(k, remaining_j)
+// steps.  One step per launch: launch s covers the slots with s_j > s, a
+// prefix of the slots in order of decreasing remaining steps.  Two steps per
+// launch (D2Q9): launch L covers the slots with s_j >= 2 L + 2 in two-step
+// tiles, followed, when some slot has s_j = 2 L + 1, by a one-step launch over
+// those; the slots are listed in two parts (whole-row, then column tiles),
+// each in order of decreasing s_j, so that both sets are ranges of the list.
+// A slot's buffer parity advances once per launch that covers it.
+static int pool_run_classes(lbm_pool *p, int64_t k, bool &any) {
     for (int c = 0; c < kClasses; ++c) {
         std::vector<int> order;
         for (int i = 0; i < p->max_slots; ++i)
@@ -383,51 +537,83 @@ int lbm_pool_run(lbm_pool *p, int64_t k) {
         if (order.empty())
             continue;
         any = true;
-        std::stable_sort(order.begin(), order.end(),
-                         [&](int a, int b) { return p->slots[a].remaining > p->slots[b].remaining; });
-        const int n = (int)order.size();
-        const int64_t steps = std::min<int64_t>(k, p->slots[order[0]].remaining);
+        auto steps_of = [&](int i) { return std::min<int64_t>(k, p->slots[i].remaining); };
         const int cdim = c >= 8 ? 3 : 2, cdtype = (c % 8) / 2;
-        // two steps per launch: D2Q9 FP64 / FP32_DEV row-interleaved slots that all take
-        // the same even number of steps in this run, with as many nodes in the class as a
-        // single domain needs for two steps per launch to pay (2048^2 FP32, 1024^2 FP64;
-        // a workgroup sweeps its rows one after another): with a few small slots the
-        // one-step form answers sooner (served p50 latency 44 against 18 ms)
+        const bool corr = (c & 1) != 0;
+        // two steps per launch: D2Q9 FP64 / FP32_DEV row-interleaved slots, when those
+        // taking at least two steps hold as many nodes as a single domain needs for
+        // two steps per launch to pay (2048^2 FP32, 1024^2 FP64; a workgroup sweeps its
+        // rows one after another): with a few small slots the one-step form answers
+        // sooner (served p50 latency 44 against 18 ms)
         bool two = p->tun.time_block == 2 && cdim == 2 && (cdtype == kF64 || cdtype == kDevF64) &&
-                   p->tun.layout == LBM_LAYOUT_ROWS && steps % 2 == 0;
+                   p->tun.layout == LBM_LAYOUT_ROWS;
         size_t class_buf_bytes = 0;
-        int64_t class_nodes = 0;
-        for (int j = 0; j < n && two; ++j) {
-            two = std::min<int64_t>(k, p->slots[order[j]].remaining) == steps;
-            class_buf_bytes += p->slots[order[j]].d.L.buf_bytes;
-            class_nodes += p->slots[order[j]].d.L.n;
+        int64_t two_nodes = 0;
+        for (int i : order) {
+            class_buf_bytes += p->slots[i].d.L.buf_bytes;
+            if (steps_of(i) >= 2)
+                two_nodes += p->slots[i].d.L.n;
         }
-        two = two && class_nodes >= (cdtype == kF64 ? (int64_t)1 << 20 : (int64_t)1 << 22);
-        std::vector<int> tile_start(n + 1, 0);
+        two = two && two_nodes >= (cdtype == kF64 ? (int64_t)1 << 20 : (int64_t)1 << 22);
+        const int B = t2_block(cdtype), TX = t2_cols(cdtype);
+        const int R = p->tun.time_rows > 0 ? p->tun.time_rows : kPoolT2Rows;
+        auto whole_w = [&](int i) {  // whole-row sub-tile width, 0 for column tiles
+            const int64_t w = (p->slots[i].d.cfg.nx + 63) / 64 * 64;
+            return w <= B ? (int)w : 0;
+        };
+        int nw = 0;  // slots in the whole-row part
+        if (two) {
+            std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+                const bool wa = whole_w(a) > 0, wb = whole_w(b) > 0;
+                if (wa != wb)
+                    return wa;
+                return p->slots[a].remaining > p->slots[b].remaining;
+            });
+            for (int i : order)
+                nw += whole_w(i) > 0 ? 1 : 0;
+        } else {
+            std::stable_sort(order.begin(), order.end(),
+                             [&](int a, int b) { return p->slots[a].remaining > p->slots[b].remaining; });
+        }
+        const int n = (int)order.size();
+        std::vector<int> tile_start(n + 1, 0), two_start(n + 1, 0);
+        std::vector<int> sub(n, 0);
         for (int j = 0; j < n; ++j) {
             const Slot &sj = p->slots[order[j]];
-            const int64_t tiles = two ? ((sj.d.cfg.nx + kPoolT2Tx - 1) / kPoolT2Tx) *
-                                            ((sj.d.cfg.ny + kPoolT2Rows - 1) / kPoolT2Rows)
-                                      : (int64_t)sj.tiles;
-            if ((int64_t)tile_start[j] + tiles > INT32_MAX) {
+            int64_t t2 = 0;
+            if (two) {
+                const int w = whole_w(order[j]);
+                if (w > 0) {
+                    sub[j] = B / w;
+                    t2 = (sj.d.cfg.ny + (int64_t)sub[j] * R - 1) / ((int64_t)sub[j] * R);
+                } else {
+                    t2 = ((sj.d.cfg.nx + TX - 1) / TX) * ((sj.d.cfg.ny + R - 1) / R);
+                }
+            }
+            if ((int64_t)tile_start[j] + sj.tiles > INT32_MAX || (int64_t)two_start[j] + t2 > INT32_MAX) {
                 set_error("pool run: more than 2^31 - 1 tiles in one class");
                 return LBM_EINVAL;
             }
-            tile_start[j + 1] = tile_start[j] + (int)tiles;
+            tile_start[j + 1] = tile_start[j] + sj.tiles;
+            two_start[j + 1] = two_start[j] + (int)t2;
         }
-        // Host copy of the class table in pinned memory; wait for the previous
-        // upload from it to finish before overwriting.
-        if (p->staging_pending) {
-            hipError_t e = hipEventSynchronize(p->staging_done);
+        // Host copy of the class table in the next pinned staging buffer (waiting
+        // only if that buffer's previous upload has not left it yet).  The device
+        // table is overwritten in stream order, after the previous run's kernels.
+        int sb = 0;
+        {
+            hipError_t e = acquire_staging(p, &sb);
             if (e != hipSuccess)
                 return hip_fail(e, "pool staging wait");
-            p->staging_pending = false;
         }
+        char *staging = p->staging[sb];
         const size_t off_desc = 0, off_start = round256(sizeof(SlotDesc) * p->max_slots),
-                     off_rem = off_start + round256(sizeof(int) * (p->max_slots + 1));
-        SlotDesc *desc = reinterpret_cast<SlotDesc *>(p->staging + off_desc);
-        int *starts = reinterpret_cast<int *>(p->staging + off_start);
-        int64_t *rem = reinterpret_cast<int64_t *>(p->staging + off_rem);
+                     off_rem = off_start + round256(sizeof(int) * (p->max_slots + 1)),
+                     off_two = off_rem + round256(sizeof(int64_t) * p->max_slots);
+        SlotDesc *desc = reinterpret_cast<SlotDesc *>(staging + off_desc);
+        int *starts = reinterpret_cast<int *>(staging + off_start);
+        int64_t *rem = reinterpret_cast<int64_t *>(staging + off_rem);
+        int *starts2 = reinterpret_cast<int *>(staging + off_two);
         for (int j = 0; j < n; ++j) {
             const Slot &s = p->slots[order[j]];
             SlotDesc d{};
@@ -439,6 +625,8 @@ int lbm_pool_run(lbm_pool *p, int64_t k) {
             d.tiles_x = s.tiles_x;
             d.tiles_y = s.tiles_y;
             d.tw_shift = s.tw_shift;
+            d.t2_w = two ? whole_w(order[j]) : 0;
+            d.t2_sub = sub[j];
             d.parity = s.d.cur;
             d.ps = s.d.L.ps;
             d.rs = s.d.L.rs;
@@ -448,13 +636,14 @@ int lbm_pool_run(lbm_pool *p, int64_t k) {
             rem[j] = s.remaining;
         }
         std::memcpy(starts, tile_start.data(), sizeof(int) * (n + 1));
+        std::memcpy(starts2, two_start.data(), sizeof(int) * (n + 1));
         char *table = p->arena + (size_t)c * p->class_bytes;
-        hipError_t e = hipMemcpyAsync(table, p->staging, p->class_bytes, hipMemcpyHostToDevice, p->stream);
+        hipError_t e = hipMemcpyAsync(table, staging, p->class_bytes, hipMemcpyHostToDevice, p->stream);
         if (e == hipSuccess)
-            e = hipEventRecord(p->staging_done, p->stream);
+            e = hipEventRecord(p->staging_ev[sb], p->stream);
         if (e != hipSuccess)
             return hip_fail(e, "pool table upload");
-        p->staging_pending = true;
+        p->staging_used[sb] = true;
 
         PoolRunArgs a{};
         a.slots = reinterpret_cast<const SlotDesc *>(table + off_desc);
@@ -463,15 +652,13 @@ int lbm_pool_run(lbm_pool *p, int64_t k) {
         a.n = n;
         a.barrier = p->barrier;
         a.error = p->error;
-        a.spin_limit = kSpinLimit;
+        a.spin_limit = 1ll << p->tun.spin_log2;
         a.flat = p->tun.flat;
-        const int dim = c >= 8 ? 3 : 2, dtype = (c % 8) / 2;
-        const bool corr = (c & 1) != 0;
+        const int dim = cdim, dtype = cdtype;
         PoolStepFn fn = dim == 3 ? pool_kernel<3>(dtype, corr, p->tun.persistent)
                                  : pool_kernel<2>(dtype, corr, p->tun.persistent);
         dim3 block(p->tun.tile_x, p->tun.tile_y);
         if (two) {
-            // every slot takes `steps` (even) steps: steps / 2 two-step launches over all tiles
             const size_t elem = dtype == kF64 ? 8 : 4;
             const bool nt = t2_nt_stores(class_buf_bytes);
             void (*fn2)(PoolRunArgs) =
@@ -479,19 +666,59 @@ int lbm_pool_run(lbm_pool *p, int64_t k) {
                                       : (nt ? k_pool_step2<kF64, false, true> : k_pool_step2<kF64, false, false>))
                               : (corr ? (nt ? k_pool_step2<kDevF64, true, true> : k_pool_step2<kDevF64, true, false>)
                                       : (nt ? k_pool_step2<kDevF64, false, true> : k_pool_step2<kDevF64, false, false>));
-            a.t2_tx = kPoolT2Tx;
-            a.t2_rows = kPoolT2Rows;
-            for (int64_t L = 0; L < steps / 2; ++L) {
-                a.step0 = (int)L;
-                a.nsteps = 2;
-                hipLaunchKernelGGL(fn2, dim3((unsigned)tile_start[n]), dim3((unsigned)t2_threads(kPoolT2Tx, elem)),
-                                   (unsigned)t2_lds_bytes(kPoolT2Tx, elem), p->stream, a);
+            PoolStepFn fn1 = pool_kernel<2>(dtype, corr, false);
+            // the larger LDS need of the two tile forms (whole-row: the most sub-tiles)
+            const size_t lds = std::max(t2_lds_bytes(TX, elem), t2_rows_lds_bytes(B / 64, 64, elem));
+            PoolRunArgs a2 = a;
+            a2.tile_start = reinterpret_cast<const int *>(table + off_two);
+            a2.t2_tx = TX;
+            a2.t2_rows = R;
+            a2.t2_R = R;
+            // s_j of the list, and the number of slots of each part with s_j >= m
+            std::vector<int64_t> sj(n);
+            for (int j = 0; j < n; ++j)
+                sj[j] = steps_of(order[j]);
+            auto count_ge = [&](int lo, int hi, int64_t m) {
+                int q = lo;
+                while (q < hi && sj[q] >= m)
+                    ++q;
+                return q;
+            };
+            const int64_t smax = *std::max_element(sj.begin(), sj.end());
+            auto launch = [&](void (*f)(PoolRunArgs), PoolRunArgs args, int t0, int t1, dim3 blk, size_t shm) {
+                if (t1 <= t0)
+                    return;
+                args.tile_base = t0;
+                hipLaunchKernelGGL(f, dim3((unsigned)(t1 - t0)), blk, (unsigned)shm, p->stream, args);
                 p->launches++;
+            };
+            for (int64_t L = 0; 2 * L + 1 <= smax; ++L) {
+                a2.step0 = (int)L;
+                a2.nsteps = 2;
+                // two-step tiles of the slots with s_j >= 2 L + 2: a prefix of each part
+                const int p1 = count_ge(0, nw, 2 * L + 2), p2 = count_ge(nw, n, 2 * L + 2);
+                if (p1 == nw) {
+                    launch(fn2, a2, 0, two_start[p2], dim3((unsigned)B), lds);
+                } else {
+                    launch(fn2, a2, 0, two_start[p1], dim3((unsigned)B), lds);
+                    launch(fn2, a2, two_start[nw], two_start[p2], dim3((unsigned)B), lds);
+                }
+                // one-step tiles of the slots whose last step is 2 L + 1: a range of each part
+                const int q1 = count_ge(0, nw, 2 * L + 1), q2 = count_ge(nw, n, 2 * L + 1);
+                a.step0 = (int)L;
+                a.nsteps = 1;
+                if (q1 == nw && p2 == nw) {
+                    launch(fn1, a, tile_start[p1], tile_start[q2], block, 0);
+                } else {
+                    launch(fn1, a, tile_start[p1], tile_start[q1], block, 0);
+                    launch(fn1, a, tile_start[p2], tile_start[q2], block, 0);
+                }
             }
             e = hipGetLastError();
             if (e != hipSuccess)
                 return hip_fail(e, "pool two-step launch");
         } else if (p->tun.persistent) {
+            const int64_t steps = steps_of(order[0]);
             int per_cu = 0;
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, p->tun.tile_x * p->tun.tile_y, 0);
             if (e != hipSuccess)
@@ -514,6 +741,7 @@ int lbm_pool_run(lbm_pool *p, int64_t k) {
                 p->launches++;
             }
         } else {
+            const int64_t steps = steps_of(order[0]);
             for (int64_t s = 0; s < steps; ++s) {
                 int cnt = 0;
                 while (cnt < n && p->slots[order[cnt]].remaining > s)
@@ -523,6 +751,7 @@ int lbm_pool_run(lbm_pool *p, int64_t k) {
                     break;
                 a.step0 = (int)s;
                 a.nsteps = 1;
+                a.tile_base = 0;
                 hipLaunchKernelGGL(fn, dim3((unsigned)P), block, 0, p->stream, a);
                 p->launches++;
             }
@@ -533,13 +762,42 @@ int lbm_pool_run(lbm_pool *p, int64_t k) {
         for (int j = 0; j < n; ++j) {
             Slot &s = p->slots[order[j]];
             const int64_t done = std::min<int64_t>(k, s.remaining);
-            s.d.cur ^= (int)((two ? done / 2 : done) & 1);  // one swap per launch
+            s.d.cur ^= (int)((two ? done / 2 + done % 2 : done) & 1);  // one swap per launch
             s.d.steps += done;
             s.remaining -= done;
+            s.persistent = s.persistent || (p->tun.persistent && !two);
+            s.last_epoch = -1;  // set by the caller, once the run's epoch is recorded
         }
     }
-    if (any)
+    return LBM_OK;
+}
+
+int lbm_pool_run(lbm_pool *p, int64_t k) {
+    if (!p || k < 0) {
+        set_error("pool run: NULL pool or negative step count");
+        return LBM_EINVAL;
+    }
+    if (k == 0)
+        return LBM_OK;
+    bool any = false;
+    int rc = pool_run_classes(p, k, any);
+    if (!any)
+        return rc;
+    int64_t ep = kEpochStream;
+    hipError_t e = record_epoch(p, &ep);
+    if (e == hipSuccess) {
         p->runs++;
+        p->run_epoch.push_back(ep);
+    } else {
+        ep = kEpochStream;  // no event: waits for these slots take the whole stream
+    }
+    for (Slot &s : p->slots)
+        if (s.used && s.last_epoch == -1)
+            s.last_epoch = ep;
+    if (rc != LBM_OK)
+        return rc;
+    if (e != hipSuccess)
+        return hip_fail(e, "pool run event");
     return LBM_OK;
 }
 
@@ -550,41 +808,54 @@ int lbm_pool_poll(lbm_pool *p, int32_t *done, int32_t capacity, int32_t *count) 
     }
     int err = 0;
     hipError_t e = hipMemcpyAsync(&err, p->error, sizeof(int), hipMemcpyDeviceToHost, p->stream);
-    // domain flags of the slots still running: a slot whose state left the
-    // equilibrium's domain is retired (its remaining steps are dropped)
-    std::vector<int> running;
-    for (int i = 0; i < p->max_slots; ++i)
-        if (p->slots[i].used && p->slots[i].remaining > 0)
-            running.push_back(i);
-    const int nr = (int)running.size();
-    int **ptrs = reinterpret_cast<int **>(p->gather_host);
-    int *vals = reinterpret_cast<int *>(p->gather_host + round256(sizeof(int *) * (size_t)p->max_slots));
-    int *dvals = reinterpret_cast<int *>(p->gather_dev + round256(sizeof(int *) * (size_t)p->max_slots));
-    if (e == hipSuccess && nr > 0) {
-        e = hipStreamSynchronize(p->stream);  // the pinned pointer list may still feed an earlier copy
-        for (int j = 0; j < nr && e == hipSuccess; ++j)
-            ptrs[j] = p->slots[running[j]].d.flag;
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(p->gather_dev, ptrs, sizeof(int *) * nr, hipMemcpyHostToDevice, p->stream);
-        if (e == hipSuccess) {
-            hipLaunchKernelGGL(k_gather_flags, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, p->stream,
-                               (const int *const *)p->gather_dev, nr, dvals);
-            e = hipGetLastError();
-        }
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(vals, dvals, sizeof(int) * nr, hipMemcpyDeviceToHost, p->stream);
+    // domain flags of the slots still running, and of those admitted without a check:
+    // a slot whose state left the equilibrium's domain is retired (its remaining
+    // steps are dropped)
+    std::vector<int> check;
+    for (int i = 0; i < p->max_slots; ++i) {
+        const Slot &s = p->slots[i];
+        if (s.used && !s.failed && !s.broken && (s.remaining > 0 || s.unverified))
+            check.push_back(i);
     }
     if (e == hipSuccess)
-        e = hipStreamSynchronize(p->stream);
+        e = hipStreamSynchronize(p->stream);  // every enqueued run and initialisation has completed
+    int *vals = nullptr;
+    if (e == hipSuccess)
+        e = gather_flags(p, check, p->stream, &vals);
     if (e != hipSuccess)
         return hip_fail(e, "pool poll synchronise");
-    p->staging_pending = false;
-    for (int j = 0; j < nr; ++j)
+    for (int j = 0; j < (int)check.size(); ++j) {
+        Slot &s = p->slots[check[j]];
+        s.unverified = false;
         if (vals[j]) {
-            Slot &s = p->slots[running[j]];
             s.failed = true;
             s.remaining = 0;
         }
+    }
+    if (err) {
+        // a persistent launch stopped at a timed-out grid barrier: the slots such
+        // launches advanced hold the state of an unknown step; retire them, reset
+        // the barrier words, and list them at the next poll
+        for (Slot &s : p->slots)
+            if (s.used && s.persistent) {
+                s.broken = true;
+                s.remaining = 0;
+            }
+        hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(64), 0, p->stream, reinterpret_cast<int *>(p->barrier), 128);
+        e = hipGetLastError();
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(p->stream);
+        for (Slot &s : p->slots)
+            s.persistent = false;
+        *count = 0;
+        if (e != hipSuccess)
+            return hip_fail(e, "pool barrier reset");
+        set_error("pool: a persistent launch's grid barrier timed out; the slots it advanced are retired "
+                  "(device_error) and listed by the next poll");
+        return LBM_EDEVICE;
+    }
+    for (Slot &s : p->slots)
+        s.persistent = false;
     int32_t c = 0;
     for (int i = 0; i < p->max_slots && c < capacity; ++i) {
         Slot &s = p->slots[i];
@@ -594,10 +865,71 @@ int lbm_pool_poll(lbm_pool *p, int32_t *done, int32_t capacity, int32_t *count) 
         }
     }
     *count = c;
-    if (err) {
-        set_error("pool: a persistent launch's grid barrier timed out");
-        return LBM_EDEVICE;
+    return LBM_OK;
+}
+
+int lbm_pool_collect(lbm_pool *p, int64_t after_run, int32_t *done, int32_t capacity, int32_t *count) {
+    if (!p || !count || capacity < 0 || (capacity > 0 && !done)) {
+        set_error("pool collect: bad arguments");
+        return LBM_EINVAL;
     }
+    hipError_t e = hipSuccess;
+    if (after_run >= 1 && after_run <= p->runs)
+        e = epoch_wait(p, p->run_epoch[(size_t)(after_run - 1)]);
+    // initial states of slots admitted without a check, where the initialisation is done
+    std::vector<int> check;
+    for (int i = 0; i < p->max_slots && e == hipSuccess; ++i) {
+        const Slot &s = p->slots[i];
+        if (s.used && s.unverified) {
+            // the admission's own epoch precedes every later one, so last_epoch covers it
+            const hipError_t q = epoch_query(p, s.last_epoch);
+            if (q == hipSuccess)
+                check.push_back(i);
+            else if (q != hipErrorNotReady)
+                e = q;
+        }
+    }
+    int *vals = nullptr;
+    if (e == hipSuccess)
+        e = gather_flags(p, check, p->aux, &vals);
+    if (e != hipSuccess)
+        return hip_fail(e, "pool collect");
+    for (int j = 0; j < (int)check.size(); ++j) {
+        Slot &s = p->slots[check[j]];
+        s.unverified = false;
+        if (vals[j]) {
+            s.failed = true;
+            s.remaining = 0;  // its queued steps still run on its own block; nothing reads them
+        }
+    }
+    int32_t c = 0;
+    for (int i = 0; i < p->max_slots && c < capacity; ++i) {
+        Slot &s = p->slots[i];
+        if (!s.used || s.remaining != 0 || s.reported || s.unverified)
+            continue;
+        const hipError_t q = epoch_query(p, s.last_epoch);
+        if (q == hipErrorNotReady)
+            continue;
+        if (q != hipSuccess)
+            return hip_fail(q, "pool collect event");
+        s.reported = true;
+        done[c++] = i;
+    }
+    *count = c;
+    return LBM_OK;
+}
+
+// Stream for a read of the slot: the second stream once the slot's work has
+// completed (later runs keep going), else the pool's stream.
+static int read_stream(lbm_pool *p, const Slot &s, hipStream_t *out) {
+    const hipError_t q = epoch_query(p, s.last_epoch);
+    if (q == hipSuccess) {
+        *out = p->aux;
+        return LBM_OK;
+    }
+    if (q != hipErrorNotReady)
+        return hip_fail(q, "pool slot event");
+    *out = p->stream;
     return LBM_OK;
 }
 
@@ -605,7 +937,16 @@ int lbm_pool_moments(lbm_pool *p, int32_t slot, double *rho, double *u, lbm_diag
     int rc = check_slot(p, slot);
     if (rc != LBM_OK)
         return rc;
-    return domain_moments(p->slots[slot].d, p->stream, rho, u, diag);
+    Slot &s = p->slots[slot];
+    if (s.broken) {
+        set_error("slot retired after a timed-out persistent launch: its state is not that of a known step");
+        return LBM_EDEVICE;
+    }
+    hipStream_t st;
+    rc = read_stream(p, s, &st);
+    if (rc != LBM_OK)
+        return rc;
+    return domain_moments(s.d, st, rho, u, diag);
 }
 
 int lbm_pool_get_populations(lbm_pool *p, int32_t slot, double *out) {
@@ -616,18 +957,28 @@ int lbm_pool_get_populations(lbm_pool *p, int32_t slot, double *out) {
         set_error("NULL output");
         return LBM_EINVAL;
     }
-    return domain_export(p->slots[slot].d, p->stream, out);
+    Slot &s = p->slots[slot];
+    if (s.broken) {
+        set_error("slot retired after a timed-out persistent launch: its state is not that of a known step");
+        return LBM_EDEVICE;
+    }
+    hipStream_t st;
+    rc = read_stream(p, s, &st);
+    if (rc != LBM_OK)
+        return rc;
+    return domain_export(s.d, st, out);
 }
 
 int lbm_pool_release(lbm_pool *p, int32_t slot) {
     int rc = check_slot(p, slot);
     if (rc != LBM_OK)
         return rc;
-    hipError_t e = hipStreamSynchronize(p->stream);
-    if (e != hipSuccess)
-        return hip_fail(e, "pool release synchronise");
-    p->staging_pending = false;
     Slot &s = p->slots[slot];
+    // the block may be reused at once: the work enqueued for this slot must be done
+    // (reads on the second stream are synchronous and already are)
+    hipError_t e = epoch_wait(p, s.last_epoch);
+    if (e != hipSuccess)
+        return hip_fail(e, "pool release wait");
     pool_free(p, s.off, s.bytes);
     s = Slot{};
     return LBM_OK;
@@ -666,7 +1017,7 @@ int lbm_pool_slot_info(lbm_pool *p, int32_t slot, lbm_slot_info *info) {
     info->steps_remaining = s.used ? s.remaining : 0;
     info->bytes = s.used ? (int64_t)s.bytes : 0;
     info->domain_error = (s.used && s.failed) ? 1 : 0;
-    info->reserved = 0;
+    info->device_error = (s.used && s.broken) ? 1 : 0;
     return LBM_OK;
 }
 
@@ -674,10 +1025,10 @@ int lbm_pool_destroy(lbm_pool *p) {
     if (!p)
         return LBM_OK;
     hipError_t e = hipStreamSynchronize(p->stream);
-    (void)hipHostFree(p->staging);
-    (void)hipHostFree(p->gather_host);
-    (void)hipEventDestroy(p->staging_done);
-    delete p;
+    const hipError_t e2 = hipStreamSynchronize(p->aux);
+    if (e == hipSuccess)
+        e = e2;
+    pool_free_host(p);
     if (e != hipSuccess)
         return hip_fail(e, "pool destroy synchronise");
     return LBM_OK;

@@ -36,6 +36,8 @@ struct SlotDesc {
     int tiles_x, tiles_y;
     int parity;    // buffer holding the state at the start of the run
     int tw_shift;  // > 0: tiles are rows of 1 << tw_shift threads (row fit); 0: blockDim's shape
+    int t2_w;      // two-step launches: > 0: whole-row sub-tiles of t2_w lanes, t2_sub per
+    int t2_sub;    //   workgroup (two_step_rows_tile); 0: column tiles (two_step_tile)
     int pad_;
     int64_t ps, rs;
     Relax relax;
@@ -53,7 +55,9 @@ struct PoolRunArgs {
     int *error;               // persistent form: set on a barrier timeout
     long long spin_limit;
     int flat;                 // 1: a tile is blockDim.x * blockDim.y consecutive nodes of its slot
-    int t2_tx, t2_rows;       // two-step form: columns and rows of a tile
+    int t2_tx, t2_rows;       // two-step form: columns and rows of a column tile
+    int t2_R;                 // two-step form: rows of a whole-row sub-tile
+    int tile_base;            // the launch's first tile (its blocks cover tile_base + [0, grid))
 };
 
 // Active tiles at step s: the tile count of the slots with remaining > s.
@@ -126,16 +130,20 @@ __device__ __forceinline__ void pool_tile(const PoolRunArgs &a, int t, int s) {
     step_node<DIM, DT, CORR>(src, dst, nx, ny, nz, ps, rs, relax, flag, x, y, z, pad);
 }
 
-// Two steps per launch (D2Q9) over every tile of a class whose slots all take
-// the same even number of steps in the run: tile_start then counts each slot's
-// ceil(nx / t2_tx) x ceil(ny / t2_rows) two-step tiles, and a.step0 is the
-// launch's index in the run (one buffer swap per launch).  The per-tile code
-// is the single-domain two-step kernel's, so a slot's populations are bitwise
-// those of one-step launches.  Block t2_threads(t2_tx, elem), dynamic LDS
-// t2_lds_bytes(t2_tx, elem).
+// Two steps per launch (D2Q9): tile_start counts each slot's two-step tiles --
+// ceil(ny / (t2_sub t2_R)) whole-row tiles when the row fits the workgroup
+// (t2_w > 0), else ceil(nx / t2_tx) x ceil(ny / t2_rows) column tiles -- and
+// the launch covers the tiles [tile_base, tile_base + grid): a prefix of the
+// slots that still take two steps at this point of the run.  a.step0 is the
+// launch's index in the run, the number of launches (of either kind) each
+// covered slot has had before (one buffer swap per launch).  The per-tile
+// code is the single-domain two-step kernel's, or its whole-row form, so a
+// slot's populations are bitwise those of one-step launches.  Block
+// t2_threads(t2_tx, elem) threads, which the whole-row form splits into
+// sub-tiles; dynamic LDS the larger of the two forms' needs.
 template <int DT, bool CORR, bool NT>
 __global__ __launch_bounds__(512) void k_pool_step2(PoolRunArgs a) {
-    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x) + a.tile_base;
     int lo = 0, hi = a.n - 1;  // last slot k with tile_start[k] <= t
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -149,13 +157,18 @@ __global__ __launch_bounds__(512) void k_pool_step2(PoolRunArgs a) {
     const int p = (dd.parity + a.step0) & 1;
     Step2Args s{dd.buf[p], dd.buf[p ^ 1], nx, ny, a.t2_tx, a.t2_rows, (nx + a.t2_tx - 1) / a.t2_tx,
                 (ny + a.t2_rows - 1) / a.t2_rows, dd.ps, dd.rs, dd.relax, dd.flag};
-    two_step_tile<DT, CORR, kEqEntropic, NT>(s, t - a.tile_start[lo]);
+    const int w = dd.t2_w, sub = dd.t2_sub;  // copied before any store (see pool_tile)
+    if (w > 0)  // uniform per workgroup
+        two_step_rows_tile<DT, CORR, kEqEntropic, NT>(s, t - a.tile_start[lo], w, sub, a.t2_R);
+    else
+        two_step_tile<DT, CORR, kEqEntropic, NT>(s, t - a.tile_start[lo]);
 }
 
-// One step (a.step0) over the active prefix; grid = its tile count.
+// One step (a.step0) over the tiles [tile_base, tile_base + grid): the active
+// prefix, or the range of slots whose last step of the run is a single one.
 template <int DIM, int DT, bool CORR>
 __global__ __launch_bounds__(256) void k_pool_step(PoolRunArgs a) {
-    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x) + a.tile_base;
     pool_tile<DIM, DT, CORR>(a, t, a.step0);
 }
 

@@ -28,6 +28,9 @@ LBM_FP64, LBM_FP32_DEV, LBM_FP32_DEV_MIXED, LBM_FP32_DEV_F32 = 0, 1, 2, 3
 LBM_EQ_ENTROPIC, LBM_EQ_POLY2, LBM_EQ_PRODUCT = 0, 1, 2
 EQUILIBRIA = {"entropic": LBM_EQ_ENTROPIC, "poly2": LBM_EQ_POLY2, "product": LBM_EQ_PRODUCT}
 
+LBM_KERNEL_NODE, LBM_KERNEL_VECTOR, LBM_KERNEL_TWO_STEP, LBM_KERNEL_MULTI_STEP = 1, 2, 3, 4
+KERNEL_NAMES = {1: "node", 2: "vector", 3: "two_step", 4: "multi_step"}
+
 DTYPES = {"fp64": LBM_FP64, "fp32_dev": LBM_FP32_DEV, "fp32_dev_mixed": LBM_FP32_DEV_MIXED,
           "fp32_dev_f32": LBM_FP32_DEV_F32}
 
@@ -60,10 +63,23 @@ class lbm_diag(ctypes.Structure):
                 "domain_error": bool(self.domain_error)}
 
 
+class lbm_launch_info(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("nodes_per_thread", ctypes.c_int32), ("row_wave", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("block_x", ctypes.c_int32), ("block_y", ctypes.c_int32),
+                ("layout", ctypes.c_int32), ("time_block", ctypes.c_int32), ("time_cols", ctypes.c_int32),
+                ("time_rows", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        d["kernel"] = KERNEL_NAMES.get(d["kernel"], d["kernel"])
+        return d
+
+
 class lbm_pool_tuning(ctypes.Structure):
     _fields_ = [("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("workgroups", ctypes.c_int32), ("layout", ctypes.c_int32), ("flat", ctypes.c_int32),
-                ("row_fit", ctypes.c_int32), ("time_block", ctypes.c_int32)]
+                ("row_fit", ctypes.c_int32), ("time_block", ctypes.c_int32), ("time_rows", ctypes.c_int32),
+                ("spin_log2", ctypes.c_int32)]
 
 
 class lbm_pool_stats(ctypes.Structure):
@@ -78,7 +94,7 @@ class lbm_pool_stats(ctypes.Structure):
 class lbm_slot_info(ctypes.Structure):
     _fields_ = [("used", ctypes.c_int32), ("finished", ctypes.c_int32), ("steps_done", ctypes.c_int64),
                 ("steps_remaining", ctypes.c_int64), ("bytes", ctypes.c_int64), ("domain_error", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("device_error", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -103,7 +119,8 @@ EXPORTS = ("lbm_workspace_bytes", "lbm_workspace_bytes_tuned", "lbm_create", "lb
            "lbm_pool_admit", "lbm_pool_run", "lbm_pool_poll", "lbm_pool_moments", "lbm_pool_get_populations",
            "lbm_pool_release", "lbm_pool_stats_get", "lbm_pool_slot_info", "lbm_pool_destroy",
            "lbm_vn_spectra", "lbm_vn_max_radius", "lbm_halo_bytes", "lbm_halo_pack", "lbm_halo_unpack",
-           "lbm_step_halo", "lbm_state_bytes", "lbm_save_state", "lbm_load_state")
+           "lbm_step_halo", "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_get_launch_info",
+           "lbm_pool_admit_async", "lbm_pool_collect", "lbm_ceiling_stream", "lbm_ceiling_copy")
 
 
 def load_library(path: str = LIB_PATH):
@@ -132,6 +149,9 @@ def load_library(path: str = LIB_PATH):
         "lbm_step": (ctypes.c_int, [vp, i64]),
         "lbm_moments": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(lbm_diag)]),
         "lbm_get_populations": (ctypes.c_int, [vp, vp]),
+        "lbm_get_launch_info": (ctypes.c_int, [vp, ctypes.POINTER(lbm_launch_info)]),
+        "lbm_ceiling_stream": (ctypes.c_int, [vp, i64]),
+        "lbm_ceiling_copy": (ctypes.c_int, [vp, vp, sz, vp]),
         "lbm_energy": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_double, vp]),
         "lbm_halo_bytes": (sz, [cfgp]),
         "lbm_halo_pack": (ctypes.c_int, [vp, vp, vp]),
@@ -153,7 +173,10 @@ def load_library(path: str = LIB_PATH):
         "lbm_pool_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(lbm_pool_tuning), vp, sz, vp,
                                            ctypes.POINTER(vp)]),
         "lbm_pool_admit": (ctypes.c_int, [vp, cfgp, vp, vp, i64, ctypes.POINTER(ctypes.c_int32)]),
+        "lbm_pool_admit_async": (ctypes.c_int, [vp, cfgp, vp, vp, i64, ctypes.POINTER(ctypes.c_int32)]),
         "lbm_pool_run": (ctypes.c_int, [vp, i64]),
+        "lbm_pool_collect": (ctypes.c_int, [vp, i64, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_int32)]),
         "lbm_pool_poll": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_int32)]),
         "lbm_pool_moments": (ctypes.c_int, [vp, ctypes.c_int32, vp, vp, ctypes.POINTER(lbm_diag)]),
@@ -241,6 +264,20 @@ def lbm_get_populations(h, out: int) -> None:
     _check(load_library().lbm_get_populations(h, out), "lbm_get_populations")
 
 
+def lbm_get_launch_info(h) -> dict:
+    info = lbm_launch_info()
+    _check(load_library().lbm_get_launch_info(h, ctypes.byref(info)), "lbm_get_launch_info")
+    return info.as_dict()
+
+
+def lbm_ceiling_stream(h, nsteps: int) -> None:
+    _check(load_library().lbm_ceiling_stream(h, int(nsteps)), "lbm_ceiling_stream")
+
+
+def lbm_ceiling_copy(src: int, dst: int, nbytes: int, stream=None) -> None:
+    _check(load_library().lbm_ceiling_copy(src, dst, int(nbytes), stream), "lbm_ceiling_copy")
+
+
 def lbm_state_bytes(h) -> int:
     return int(load_library().lbm_state_bytes(h))
 
@@ -294,11 +331,13 @@ def lbm_destroy(h) -> None:
 
 
 def make_pool_tuning(tile_x=0, tile_y=0, persistent=0, workgroups=0, layout=0, flat=0,
-                     row_fit=0, time_block=0) -> lbm_pool_tuning:
+                     row_fit=0, time_block=0, spin_log2=0, time_rows=0) -> lbm_pool_tuning:
     t = lbm_pool_tuning()
     t.tile_x, t.tile_y, t.persistent, t.workgroups, t.layout, t.flat, t.row_fit, t.time_block = (
         int(tile_x), int(tile_y), int(persistent), int(workgroups), int(layout), int(flat), int(row_fit),
         int(time_block))
+    t.spin_log2 = int(spin_log2)
+    t.time_rows = int(time_rows)
     return t
 
 
@@ -327,6 +366,15 @@ def lbm_pool_admit(pool, cfg: lbm_config, rho: int, u: int, nsteps: int) -> int:
     return int(slot.value)
 
 
+def lbm_pool_admit_async(pool, cfg: lbm_config, rho: int, u: int, nsteps: int) -> int:
+    """lbm_pool_admit without the synchronisation; the initial state is checked
+    by a later poll or collect."""
+    slot = ctypes.c_int32(-1)
+    _check(load_library().lbm_pool_admit_async(pool, ctypes.byref(cfg), rho, u, int(nsteps), ctypes.byref(slot)),
+           "lbm_pool_admit_async")
+    return int(slot.value)
+
+
 def lbm_pool_run(pool, k: int) -> None:
     _check(load_library().lbm_pool_run(pool, int(k)), "lbm_pool_run")
 
@@ -335,6 +383,14 @@ def lbm_pool_poll(pool, capacity: int = 65536) -> list:
     buf = (ctypes.c_int32 * max(1, capacity))()
     n = ctypes.c_int32(0)
     _check(load_library().lbm_pool_poll(pool, buf, int(capacity), ctypes.byref(n)), "lbm_pool_poll")
+    return [int(buf[i]) for i in range(n.value)]
+
+
+def lbm_pool_collect(pool, after_run: int = 0, capacity: int = 65536) -> list:
+    buf = (ctypes.c_int32 * max(1, capacity))()
+    n = ctypes.c_int32(0)
+    _check(load_library().lbm_pool_collect(pool, int(after_run), buf, int(capacity), ctypes.byref(n)),
+           "lbm_pool_collect")
     return [int(buf[i]) for i in range(n.value)]
 
 
@@ -450,6 +506,11 @@ class Domain:
         lbm_step_halo(self.handle, recv_lower.data_ptr(), recv_upper.data_ptr(), send_lower.data_ptr(),
                       send_upper.data_ptr())
 
+    def launch_info(self) -> dict:
+        """The launch the library chose for this domain (kernel kind, nodes per
+        thread, row-wave form, cache hints, workgroup shape, steps per launch)."""
+        return lbm_get_launch_info(self.handle)
+
     def save_state(self):
         """Checkpoint: a CUDA uint8 tensor holding the stored state (bit-exact),
         and the step count.  Raises LBMDomainError if the domain flag is set."""
@@ -556,6 +617,12 @@ class Pool:
         base = (self._arena.data_ptr() + 255) // 256 * 256
         self.handle = lbm_pool_create(self.max_slots, base, self.arena_bytes, self.stream.cuda_stream, tuning)
         self.shapes = {}
+        # Outputs of reads come from torch's allocator on a stream of their own: a
+        # read of a finished slot runs on the pool's second stream while later work
+        # is still queued on the pool's stream, so its output memory must not be a
+        # block that queued work there may still use (torch reuses a block freed on
+        # a stream for that stream's next allocation at once).
+        self._read_stream = torch.cuda.Stream(self.device)
 
     def slot_bytes(self, shape, tau=0.6, dtype="fp32_dev", bulk_correction=False, rho0=1.0) -> int:
         lattice = LBM_D2Q9 if len(shape) == 2 else LBM_D3Q27
@@ -597,18 +664,20 @@ class Pool:
         if not fields:
             return None, None, lbm_pool_moments(self.handle, slot, None, None, raise_on_domain).as_dict()
         shape = self.shapes[slot]
-        rho_d = torch.empty(shape, dtype=torch.float64, device=self.device)
-        u_d = torch.empty((len(shape),) + shape, dtype=torch.float64, device=self.device)
-        d = lbm_pool_moments(self.handle, slot, rho_d.data_ptr(), u_d.data_ptr(), raise_on_domain)
-        return rho_d.cpu().numpy(), u_d.cpu().numpy(), d.as_dict()
+        with torch.cuda.stream(self._read_stream):
+            rho_d = torch.empty(shape, dtype=torch.float64, device=self.device)
+            u_d = torch.empty((len(shape),) + shape, dtype=torch.float64, device=self.device)
+            d = lbm_pool_moments(self.handle, slot, rho_d.data_ptr(), u_d.data_ptr(), raise_on_domain)
+            return rho_d.cpu().numpy(), u_d.cpu().numpy(), d.as_dict()
 
     def populations(self, slot: int):
         import torch
         shape = self.shapes[slot]
         Q = 9 if len(shape) == 2 else 27
-        out = torch.empty((Q,) + shape, dtype=torch.float64, device=self.device)
-        lbm_pool_get_populations(self.handle, slot, out.data_ptr())
-        return out.cpu().numpy()
+        with torch.cuda.stream(self._read_stream):
+            out = torch.empty((Q,) + shape, dtype=torch.float64, device=self.device)
+            lbm_pool_get_populations(self.handle, slot, out.data_ptr())
+            return out.cpu().numpy()
 
     def release(self, slot: int) -> None:
         lbm_pool_release(self.handle, slot)

@@ -4,15 +4,20 @@ Requests (lattice, grid, initial field, u0, tau, step count) arrive over time.
 The server keeps the populations of admitted requests resident in HBM as slots
 of one pool, admits queued requests whenever a slot and a large enough block
 of the arena are free (admission by memory footprint), advances every active
-slot in chunks of K steps (one pool run: one kernel launch per step covering
-all active requests of a class, with the pool's default tuning), and returns a
-result as soon as a request's steps are done.  Requests arriving while others
-run join the next chunk, so their work overlaps on the device.
+slot in chunks of K steps (one pool run: one kernel launch per step, or per
+two steps, covering all active requests of a class), and returns a result as
+soon as a request's steps are done.  Requests arriving while others run join
+the next chunk, so their work overlaps on the device.
+
+The loop is pipelined so that the GPU does not drain between chunks:
+admissions are enqueued without a synchronisation, chunk n + 1 is enqueued
+before the server waits for chunk n, and the results of the requests that
+chunk n finished are read on a second stream while chunk n + 1 runs.
 
 Latency is measured from a request's arrival to the moment its result
 (diagnostics read back from the GPU) is available.
 
-The scheduling logic takes a backend object (admit / run / poll / result /
+The scheduling logic takes a backend object (admit / run / collect / result /
 release / cost estimate), so it can be exercised with a stand-in backend and a
 virtual clock; the production backend is PoolBackend over the native pool.
 """
@@ -27,12 +32,15 @@ import numpy as np
 
 def init_fields_device(req: dict, device):
     """Initial (rho, u) of a request as float64 torch tensors on `device`,
-    assembled from 1-D profiles (the same formulas as the workloads module)."""
+    assembled on the device from 1-D profiles (the same formulas and the same
+    numpy values as the workloads module).  The profiles go up through pinned
+    host memory without blocking, so that a request can be prepared while
+    earlier work is still running on the stream."""
     import torch
     n, u0 = req["n"], req["u0"]
     k = 2.0 * math.pi / n
     x = np.arange(n, dtype=np.float64)
-    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).pin_memory().to(device, non_blocking=True)
     if req["lattice"] == 9:
         if req["init"] == "taylor_green":
             cx, sx, c2x = t(np.cos(k * x)), t(np.sin(k * x)), t(np.cos(2 * k * x))
@@ -62,13 +70,19 @@ class PoolBackend:
     tuning None selects row fit (each slot's rows mapped to 64-, 128- or
     256-wide tiles): on the serving request mix (D2Q9 64^2..1024^2, D3Q27
     32^3..192^3) it served 2.5-4 % more requests per second than the pool's
-    default 64 x 4 tiles; and two steps per launch for D2Q9 classes in runs
-    where their slots all take the same even number of steps."""
+    default 64 x 4 tiles; and two steps per launch for D2Q9 classes.
+
+    Admissions are enqueued without a synchronisation (lbm_pool_admit_async)
+    on the pool's stream, which is torch's current stream when the backend is
+    made: the initial fields are built on that stream, so the allocator frees
+    them in stream order behind the initialisation that reads them."""
 
     def __init__(self, budget_bytes: int, max_slots: int = 256, tuning=None, dtype: str = "fp32_dev",
                  device="cuda:0", bytes_per_s: float = 5.0e12):
+        import torch
         from . import lbm
         self.lbm = lbm
+        self.torch = torch
         if tuning is None:
             tuning = lbm.make_pool_tuning(64, 4, 0, row_fit=1, time_block=2)
         self.dtype = dtype
@@ -76,6 +90,7 @@ class PoolBackend:
         self.device = self.pool.device
         self.bytes_per_s = bytes_per_s
         self.slot_req = {}
+        self._events = []  # (start, end) CUDA events of every run, for the GPU-busy time
 
     def footprint(self, req) -> int:
         lbm = self.lbm
@@ -86,10 +101,13 @@ class PoolBackend:
 
     def try_admit(self, req, fields=None):
         lbm = self.lbm
-        rho, u = fields if fields is not None else init_fields_device(req, self.device)
+        if self.footprint(req) > self.pool.stats()["largest_free_block"]:
+            return None
+        with self.torch.cuda.stream(self.pool.stream):
+            rho, u = fields if fields is not None else init_fields_device(req, self.device)
         cfg = lbm.make_config(req["lattice"], tuple(rho.shape[::-1]), req["tau"], self.dtype)
         try:
-            slot = lbm.lbm_pool_admit(self.pool.handle, cfg, rho.data_ptr(), u.data_ptr(), req["steps"])
+            slot = lbm.lbm_pool_admit_async(self.pool.handle, cfg, rho.data_ptr(), u.data_ptr(), req["steps"])
         except lbm.LBMError as e:
             if e.status in (lbm.LBM_EBUSY, lbm.LBM_ENOMEM):
                 return None
@@ -111,19 +129,35 @@ class PoolBackend:
     def remaining(self, slot) -> int:
         return int(self.pool.slot_info(slot)["steps_remaining"])
 
-    def run(self, k: int) -> None:
+    def run(self, k: int) -> int:
+        """Enqueue k steps of every running slot; returns the run's number."""
+        torch = self.torch
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(self.pool.stream)
         self.pool.run(k)
+        ev1.record(self.pool.stream)
+        self._events.append((ev0, ev1))
+        return int(self.pool.stats()["runs"])
 
-    def poll(self):
-        return self.pool.poll()
+    def collect(self, after_run: int) -> list:
+        """Wait for run `after_run`, then list the finished slots whose work is done."""
+        return self.lbm.lbm_pool_collect(self.pool.handle, after_run, self.pool.max_slots)
 
-    def result(self, slot) -> dict:
+    def result(self, slot, fields: bool = False) -> dict:
+        if fields:
+            rho, u, d = self.pool.moments(slot, fields=True, raise_on_domain=False)
+            return dict(d, rho=rho, u=u)
         _, _, d = self.pool.moments(slot, fields=False, raise_on_domain=False)
         return d
 
     def release(self, slot) -> None:
         self.pool.release(slot)
         self.slot_req.pop(slot, None)
+
+    def gpu_busy_seconds(self) -> float:
+        """GPU time of all runs so far (synchronises)."""
+        self.pool.stream.synchronize()
+        return sum(a.elapsed_time(b) for a, b in self._events) / 1e3
 
     def close(self):
         self.pool.close()
@@ -134,23 +168,29 @@ class Server:
 
     chunk_s: target GPU time of one run (bounds how long a newly arrived
     request waits before it joins); lookahead: how many queued requests are
-    tried per admission pass (first fit within the window).
+    tried per admission pass (first fit within the window); depth: runs kept
+    in flight (2: the next chunk is enqueued before the server waits for the
+    current one).
     policy:
       "fifo"  the window is taken in arrival order and every request that fits
               in memory is admitted (all admitted requests share the GPU);
       "swf"   (default) shortest work first: the queue is ordered by estimated work
-              (bytes per step x steps), and admission stops once the admitted
+              (bytes per step x steps), and admission stops once the running
               requests move `saturate_bytes` per step -- enough to keep the GPU
               busy -- so that short requests finish first instead of sharing
               the device with everything queued.  Admitted requests are never
               paused, so this approximates shortest-remaining-work order.
+    keep_fields: also return each request's rho and u fields (numpy; for
+    tests -- the copies to the host add to the loop's turn-around).
     """
 
     def __init__(self, backend, chunk_s: float = 0.02, lookahead: int = 64, max_chunk: int = 2000,
                  clock=time.perf_counter, sleep=time.sleep, policy: str = "swf",
-                 saturate_bytes: float = 512e6):
+                 saturate_bytes: float = 512e6, depth: int = 2, keep_fields: bool = False):
         if policy not in ("fifo", "swf"):
             raise ValueError("policy must be 'fifo' or 'swf'")
+        if depth < 1:
+            raise ValueError("depth must be >= 1")
         self.b = backend
         self.chunk_s = chunk_s
         self.lookahead = lookahead
@@ -159,6 +199,8 @@ class Server:
         self.sleep = sleep
         self.policy = policy
         self.saturate_bytes = saturate_bytes
+        self.depth = depth
+        self.keep_fields = keep_fields
 
     def _work(self, req) -> float:
         return float(self.b.step_bytes(req)) * req["steps"]
@@ -171,28 +213,43 @@ class Server:
         t0 = self.clock()
         now = lambda: self.clock() - t0
         queue = deque()
-        active = {}  # slot -> (request, admitted time)
+        active = {}  # slot -> (request, admitted time): admitted, result not yet read
+        inflight = deque()  # runs enqueued and not yet waited for
         out = []
         i = 0
         trace = sorted(trace, key=lambda r: r["arrival"])
+
+        def finish(slots):
+            for slot in slots:
+                req, adm = active.pop(slot)
+                res = b.result(slot, fields=True) if self.keep_fields else b.result(slot)
+                fin = now()
+                rec = dict(id=req["id"], arrival=req["arrival"], admitted=adm, finished=fin,
+                           latency=fin - req["arrival"], diag=res)
+                if self.keep_fields:
+                    rec["rho"], rec["u"] = res.pop("rho"), res.pop("u")
+                out.append(rec)
+                b.release(slot)
+
         while i < len(trace) or queue or active:
             t = now()
             while i < len(trace) and trace[i]["arrival"] <= t:
                 queue.append(trace[i])
                 i += 1
+            running = [s for s in active if b.remaining(s) > 0]
             # admission: first fit within the look-ahead window, in arrival order
             # (fifo) or in order of estimated work up to the saturation traffic (swf)
             tried = 0
             if self.policy == "swf":
                 order = sorted(queue, key=lambda r: (self._work(r), r["arrival"]))
-                load = sum(b.step_bytes(r) for r, _ in active.values())
+                load = sum(b.step_bytes(active[s][0]) for s in running)
             else:
                 order = list(queue)
                 load = 0.0
             for req in order:
                 if tried >= self.lookahead:
                     break
-                if self.policy == "swf" and active and load >= self.saturate_bytes:
+                if self.policy == "swf" and running and load >= self.saturate_bytes:
                     break
                 tried += 1
                 slot = b.try_admit(req)
@@ -200,6 +257,25 @@ class Server:
                     active[slot] = (req, now())
                     queue.remove(req)
                     load += b.step_bytes(req)
+                    running.append(slot)
+            running = [s for s in running if b.remaining(s) > 0]
+            enqueued = False
+            if running and len(inflight) < self.depth:
+                # one chunk: long enough to amortise launches, short enough for admission,
+                # and ending exactly when the next running request finishes
+                step_s = max(b.step_seconds(running), 1e-7)
+                k = int(max(1, min(self.max_chunk, self.chunk_s / step_s)))
+                k = min(k, min(b.remaining(s) for s in running))
+                inflight.append(b.run(max(1, k)))
+                enqueued = True
+            if inflight and (len(inflight) >= self.depth or not enqueued):
+                # wait for the oldest run (the newer one keeps the GPU busy) and read
+                # the results of the requests it finished
+                finish(b.collect(inflight.popleft()))
+                continue
+            if not inflight and active and not running:
+                finish(b.collect(0))  # finished slots whose work needs no run
+                continue
             if not active:
                 if i < len(trace):
                     wait = trace[i]["arrival"] - now()
@@ -209,19 +285,6 @@ class Server:
                 if queue:
                     raise RuntimeError(f"request {queue[0]['id']} can never be admitted (larger than the pool)")
                 break
-            # one chunk: long enough to amortise launches, short enough for admission,
-            # and ending exactly when the next active request finishes
-            step_s = max(b.step_seconds(list(active)), 1e-7)
-            k = int(max(1, min(self.max_chunk, self.chunk_s / step_s)))
-            k = min(k, min(b.remaining(s) for s in active))
-            b.run(max(1, k))
-            for slot in b.poll():
-                req, adm = active.pop(slot)
-                diag = b.result(slot)
-                fin = now()
-                out.append(dict(id=req["id"], arrival=req["arrival"], admitted=adm, finished=fin,
-                                latency=fin - req["arrival"], diag=diag))
-                b.release(slot)
         return out
 
 

@@ -80,6 +80,21 @@ def taylor_green_3d(n: int, u0: float = 0.05, rho0: float = 1.0, planes: tuple |
     return rho, np.stack([ux, uy, uz])
 
 
+def taylor_green_3d_box(nx: int, ny: int, nz: int, u0: float = 0.05, rho0: float = 1.0):
+    """The 3-D Taylor-Green field of taylor_green_3d on an nx x ny x nz box, with
+    one wavelength per axis (k_a = 2 pi / n_a):
+
+    u_x = u0 sin kx x cos ky y cos kz z, u_y = -u0 cos kx x sin ky y cos kz z, u_z = 0,
+    rho = rho0 + (3 rho0 u0^2 / 16)(cos 2kx x + cos 2ky y)(cos 2kz z + 2).
+    """
+    x, y, z = _axes3(nx, ny, nz)
+    kx, ky, kz = 2.0 * math.pi / nx, 2.0 * math.pi / ny, 2.0 * math.pi / nz
+    ux = u0 * np.sin(kx * x) * np.cos(ky * y) * np.cos(kz * z)
+    uy = -u0 * np.cos(kx * x) * np.sin(ky * y) * np.cos(kz * z)
+    rho = rho0 + (3.0 * rho0 * u0 * u0 / 16.0) * (np.cos(2 * kx * x) + np.cos(2 * ky * y)) * (np.cos(2 * kz * z) + 2.0)
+    return rho, np.stack([ux, uy, np.zeros_like(ux)])
+
+
 def shear_wave(nx: int, ny: int, amp: float, rho0: float = 1.0, nz: int | None = None):
     """Transverse shear wave u_x = amp sin(2 pi y / ny), other components 0, rho = rho0.
 

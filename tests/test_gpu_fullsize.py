@@ -5,10 +5,11 @@
     deviation storage, bulk correction off and on, compared at 4096 seeded
     nodes (normwise over the samples: 1e-12 FP64, 1e-5 FP32);
   - the first 32 domains of the batched shear-wave workload (512 domains,
-    seed 2303), 2000 steps, run together in one pool: each equals the same
-    domain run alone bitwise and matches the oracle at 64 seeded nodes;
-  - all 512 domains of that workload in one persistent pool launch equal
-    their single-domain runs bitwise.
+    seed 2303), 2000 steps, run together in one pool (one persistent launch;
+    and for FP64 two steps per launch): each equals the same domain run alone
+    bitwise and matches the oracle at 64 seeded nodes;
+  - all 512 domains of that workload in one persistent pool launch, and in
+    1000 two-step launches, equal their single-domain runs bitwise.
 """
 import os
 
@@ -73,18 +74,25 @@ def _alone(r0, u0, tau, steps, dtype):
     return rho, u
 
 
-@pytest.mark.parametrize("dtype", ["fp64", "fp32_dev"])
-def test_c4_subset_full_steps_vs_oracle_and_alone(dtype):
+# pool tunings of the batched runs: one persistent launch per run, and two steps
+# per launch (the autotuner's choice on this workload and the serving default)
+C4_TUNINGS = {"persistent": dict(persistent=1), "two_step": dict(tile_x=64, tile_y=4, time_block=2)}
+
+
+@pytest.mark.parametrize("dtype,form", [("fp64", "persistent"), ("fp32_dev", "persistent"), ("fp64", "two_step")])
+def test_c4_subset_full_steps_vs_oracle_and_alone(dtype, form):
     g = _gold("c4_subset_2000.npz")
     count, steps = int(g["count"]), int(g["steps"])
     specs = workloads.batch_domains(count=512, seed=2303)[:count]
     lbm = _lbm()
     fields = [workloads.shear_wave(sp["nx"], sp["ny"], sp["amp"]) for sp in specs]
     worst = [0.0, 0.0]
-    with lbm.Pool(GiB, max_slots=count, tuning=lbm.make_pool_tuning(persistent=1)) as pool:
+    with lbm.Pool(GiB, max_slots=count, tuning=lbm.make_pool_tuning(**C4_TUNINGS[form])) as pool:
         slots = [pool.admit(r, u, sp["tau"], steps, dtype=dtype) for (r, u), sp in zip(fields, specs)]
         pool.run(steps)
         assert set(pool.poll()) == set(slots)
+        # the form that ran: one launch per run, or one per two steps
+        assert pool.stats()["launches"] == (1 if form == "persistent" else steps // 2)
         for k, (s, sp, (r0, u0)) in enumerate(zip(slots, specs, fields)):
             assert int(g[f"bad_{k}"]) == 0
             rho, u, _ = pool.moments(s)
@@ -95,24 +103,35 @@ def test_c4_subset_full_steps_vs_oracle_and_alone(dtype):
             eu = rel_err(u[:, ys, xs], g[f"u_{k}"])
             worst = [max(worst[0], er), max(worst[1], eu)]
             assert er < TOL[dtype] and eu < TOL[dtype], (k, sp, er, eu)
-    print(f"[parity] batched shear waves, 32 domains x 2000 steps {dtype}: worst rel err rho {worst[0]:.3e}  "
+    print(f"[parity] batched shear waves, 32 domains x 2000 steps {dtype} ({form}): worst rel err rho {worst[0]:.3e}  "
           f"u {worst[1]:.3e}", flush=True)
 
 
-def test_c4_all_512_pool_equals_alone_bitwise():
-    lbm = _lbm()
+@pytest.fixture(scope="module")
+def c4_alone_fp32():
+    """All 512 batched domains run alone (FP32 deviation storage, 2000 steps)."""
     specs = workloads.batch_domains(count=512, seed=2303)
+    out = []
+    for sp in specs:
+        r0, u0 = workloads.shear_wave(sp["nx"], sp["ny"], sp["amp"])
+        out.append(_alone(r0, u0, sp["tau"], 2000, "fp32_dev"))
+    return specs, out
+
+
+@pytest.mark.parametrize("form", ["persistent", "two_step"])
+def test_c4_all_512_pool_equals_alone_bitwise(c4_alone_fp32, form):
+    lbm = _lbm()
+    specs, alone = c4_alone_fp32
     steps = 2000
-    with lbm.Pool(4 * GiB, max_slots=512, tuning=lbm.make_pool_tuning(persistent=1)) as pool:
+    with lbm.Pool(4 * GiB, max_slots=512, tuning=lbm.make_pool_tuning(**C4_TUNINGS[form])) as pool:
         slots = []
         for sp in specs:
             r0, u0 = workloads.shear_wave(sp["nx"], sp["ny"], sp["amp"])
             slots.append(pool.admit(r0, u0, sp["tau"], steps, dtype="fp32_dev"))
         pool.run(steps)
         assert set(pool.poll()) == set(slots)
-        for s, sp in zip(slots, specs):
-            r0, u0 = workloads.shear_wave(sp["nx"], sp["ny"], sp["amp"])
+        assert pool.stats()["launches"] == (1 if form == "persistent" else steps // 2)
+        for s, sp, (ra, ua) in zip(slots, specs, alone):
             rho, u, d = pool.moments(s)
-            ra, ua = _alone(r0, u0, sp["tau"], steps, "fp32_dev")
             assert d["steps"] == steps
             assert np.array_equal(rho, ra) and np.array_equal(u, ua), sp

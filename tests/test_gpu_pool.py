@@ -229,10 +229,10 @@ def test_pool_retires_failed_slots():
 
 
 def test_pool_two_steps_per_launch_equals_alone():
-    """time_block = 2: D2Q9 classes whose slots all take the same even number
-    of steps in a run, and that hold enough nodes (2^22 FP32, 2^20 FP64),
-    advance two steps per launch (ragged widths, both storage types, with and
-    without the correction); odd runs and small classes take one step per
+    """time_block = 2: D2Q9 classes that hold enough nodes (2^22 FP32, 2^20
+    FP64) advance two steps per launch (ragged widths, whole-row and column
+    tiles in one class, both storage types, with and without the correction);
+    odd runs end with a one-step launch, small classes take one step per
     launch, and the buffer parity stays right across both forms.  Every slot
     is bitwise its single-domain run; the launch count shows which form ran."""
     lbm = _lbm()
@@ -251,8 +251,9 @@ def test_pool_two_steps_per_launch_equals_alone():
             pool.run(k)
         assert sorted(pool.poll()) == sorted(slots + [s3])
         # the FP32-corrected and FP64 classes (with the large slots): 5 + 3 two-step
-        # launches, then 7 + 7 one-step; the two small D2Q9 classes and D3Q27: 30 each
-        assert pool.stats()["launches"] == 2 * (5 + 3 + 7 + 7) + 3 * 30
+        # launches, then twice 3 two-step and one one-step launch (odd runs); the two
+        # small D2Q9 classes and D3Q27: 30 each
+        assert pool.stats()["launches"] == 2 * (5 + 3 + 4 + 4) + 3 * 30
         for s, (r, u), (_, dt, corr, tau) in zip(slots, fields, specs):
             ra, ua, da, fa = alone(r, u, tau, steps, dt, corr)
             rb, ub, db = pool.moments(s, raise_on_domain=False)
@@ -261,3 +262,205 @@ def test_pool_two_steps_per_launch_equals_alone():
             assert np.array_equal(fa, pool.populations(s))
         ra, ua, _, fa = alone(r3, u3, 0.55, steps, "fp32_dev", False)
         assert np.array_equal(fa, pool.populations(s3))
+
+
+def test_pool_async_admission_and_collect_equal_alone(alone_results):
+    """Pipelined use: admissions without a synchronisation, run n + 1 enqueued
+    before the results of run n are collected, reads of finished slots on the
+    pool's second stream while later runs go on, releases that wait only for
+    the slot's own work.  Every slot is bitwise its single-domain run; an
+    initial state outside the domain is retired by collect."""
+    import torch
+    lbm = _lbm()
+    dev = torch.device("cuda:0")
+    with lbm.Pool(GiB // 4, max_slots=4) as pool:
+        pending = list(range(len(MIX)))
+        active = {}
+        inflight = []
+        checked = 0
+        bad_slot = None
+        for _ in range(2000):
+            while pending:
+                i = pending[0]
+                make, tau, steps, dtype, corr = MIX[i]
+                rho0, u0, _ = alone_results[i]
+                cfg = lbm.make_config(lbm.LATTICE_OF_DIM[rho0.ndim], rho0.shape[::-1], tau, dtype, corr)
+                rho_d = torch.from_numpy(rho0).to(dev)
+                u_d = torch.from_numpy(u0).to(dev)
+                try:
+                    slot = lbm.lbm_pool_admit_async(pool.handle, cfg, rho_d.data_ptr(), u_d.data_ptr(), steps)
+                except lbm.LBMError as e:
+                    assert e.status in (lbm.LBM_EBUSY, lbm.LBM_ENOMEM)
+                    break
+                pool.shapes[slot] = rho0.shape
+                active[slot] = i
+                pending.pop(0)
+            if bad_slot is None and not pending and len(active) < 4:
+                # an initial state with |u_x| >= 1 at one node
+                r_bad, u_bad = workloads.taylor_green_2d(32, u0=0.05)
+                u_bad[0, 5, 7] = 1.25
+                cfg = lbm.make_config(9, (32, 32), 0.6, "fp32_dev")
+                rb, ub = torch.from_numpy(r_bad).to(dev), torch.from_numpy(u_bad).to(dev)
+                bad_slot = lbm.lbm_pool_admit_async(pool.handle, cfg, rb.data_ptr(), ub.data_ptr(), 50)
+                pool.shapes[bad_slot] = r_bad.shape
+            pool.run(3)
+            inflight.append(pool.stats()["runs"])
+            if len(inflight) < 2 and (pending or active):
+                continue
+            for slot in lbm.lbm_pool_collect(pool.handle, inflight.pop(0)):
+                if slot == bad_slot:
+                    assert pool.slot_info(slot)["domain_error"] == 1
+                    with pytest.raises(lbm.LBMDomainError):
+                        pool.moments(slot)
+                    pool.release(slot)
+                    bad_slot = -1
+                    continue
+                i = active.pop(slot)
+                rho, u, _, f = alone_results[i][2]
+                r2, u2, _ = pool.moments(slot, raise_on_domain=False)
+                assert np.array_equal(r2, rho) and np.array_equal(u2, u)
+                assert np.array_equal(pool.populations(slot), f)
+                pool.release(slot)
+                checked += 1
+            if not pending and not active and bad_slot == -1:
+                break
+        assert checked == len(MIX) and bad_slot == -1
+        st = pool.stats()
+        assert st["used_slots"] == 0 and st["free_bytes"] == st["largest_free_block"]
+
+
+def test_persistent_barrier_timeout_retires_slots_and_pool_recovers():
+    """The timeout path of the persistent form's bounded grid barrier, forced
+    from the host: with a bound of 2 polls the workgroups of a full grid do not
+    all arrive in time, and every one of them leaves through the bounded wait.
+    poll reports LBM_EDEVICE; the slots that run advanced are retired with
+    device_error and refuse reads; the next poll lists them; the barrier state
+    is reset, so a later persistent run completes normally."""
+    lbm = _lbm()
+    fields = [workloads.shear_wave(256, 256, 0.05) for _ in range(8)]
+    with lbm.Pool(GiB, max_slots=16, tuning=lbm.make_pool_tuning(persistent=1, spin_log2=1)) as pool:
+        slots = [pool.admit(r, u, 0.6, 200, dtype="fp32_dev") for r, u in fields]
+        pool.run(200)
+        with pytest.raises(lbm.LBMError) as e:
+            pool.poll()
+        assert e.value.status == lbm.LBM_EDEVICE
+        for s in slots:
+            info = pool.slot_info(s)
+            assert info["device_error"] == 1 and info["finished"] == 1 and info["domain_error"] == 0
+            with pytest.raises(lbm.LBMError) as e2:
+                pool.moments(s, fields=False)
+            assert e2.value.status == lbm.LBM_EDEVICE
+        assert sorted(pool.poll()) == sorted(slots)
+        for s in slots:
+            pool.release(s)
+        # one-step runs need no barrier; after the reset, poll reports no error
+        r, u = fields[0]
+        s = pool.admit(r, u, 0.6, 1, dtype="fp32_dev")
+        pool.run(1)
+        assert pool.poll() == [s]
+        rho, vel, _ = pool.moments(s)
+        ra, ua, _, _ = alone(r, u, 0.6, 1, "fp32_dev", False)
+        assert np.array_equal(rho, ra) and np.array_equal(vel, ua)
+
+
+@pytest.mark.parametrize("form", ["rows", "fit", "flat", "persistent", "persistent-flat", "two-step"])
+def test_pool_kernels_store_only_inside_their_slots(form):
+    """Every store of the pool kernels, padding lanes included, stays inside its
+    slot's own buffers: canary bytes written into the arena around the slots
+    (a released block between two slots, the free region after them, the
+    unused words beside the grid-barrier counter and error word, and the
+    tables of classes that do not run) are intact after runs of each launch
+    form, and the slots equal their single-domain runs."""
+    import torch
+    lbm = _lbm()
+    tun = {"rows": dict(tile_x=64, tile_y=4), "fit": dict(tile_x=64, tile_y=4, row_fit=1),
+           "flat": dict(tile_x=64, tile_y=4, flat=1), "persistent": dict(persistent=1),
+           "persistent-flat": dict(persistent=1, flat=1),
+           "two-step": dict(tile_x=64, tile_y=4, time_block=2)}[form]
+    tuning = lbm.make_pool_tuning(**tun)
+    # ragged widths (padding lanes), a D3Q27 cube, and D2Q9 slots large enough for two-step launches
+    specs = [((33, 70), "fp32_dev"), ((17, 130), "fp32_dev"), ((9, 11, 13), "fp32_dev"), ((2100, 2048), "fp32_dev"),
+             ((37, 100), "fp64"), ((1100, 1030), "fp64")]
+    fields = [workloads.random_field(shape, seed=300 + k, umax=0.1) for k, (shape, _) in enumerate(specs)]
+    max_slots = 8
+    tb = lbm.lbm_pool_table_bytes(max_slots)
+    sizes = [lbm.lbm_pool_slot_bytes(lbm.make_config(lbm.LATTICE_OF_DIM[len(sh)], sh[::-1], 0.6, dt), tuning)
+             for sh, dt in specs]
+    arena = tb + (2 << 20) + sum(sizes) + (8 << 20)
+    steps = 12
+    with lbm.Pool(arena, max_slots=max_slots, tuning=tuning) as pool:
+        base = (pool._arena.data_ptr() + 255) // 256 * 256 - pool._arena.data_ptr()
+        buf = pool._arena
+        r_sp, u_sp = workloads.taylor_green_2d(16)
+        slots, offs = [], []
+        off = tb
+        gaps = []
+        for k, ((r, u), (sh, dt)) in enumerate(zip(fields, specs)):
+            if k == 3:
+                # a small slot between two others, released below: its block becomes a gap
+                sp = pool.admit(r_sp, u_sp, 0.6, 1)
+                sp_bytes = pool.slot_info(sp)["bytes"]
+                gaps.append((off, sp_bytes))
+                off += sp_bytes
+                spacer_slot = sp
+            slots.append(pool.admit(r, u, 0.6, steps, dtype=dt))
+            assert pool.slot_info(slots[-1])["bytes"] == sizes[k]
+            offs.append(off)
+            off += sizes[k]
+        pool.release(spacer_slot)
+        gaps.append((off, min(8 << 20, arena - off)))  # free region after the last slot
+        torch.cuda.synchronize()
+        CAN = 0xA5
+        # canaries: the gaps, the words between the barrier counter and the error word and
+        # after it (the table region's 512-byte barrier block), and the unused class tables;
+        # the table region is 16 class tables, the 512-byte barrier block, the gather area
+        regions = list(gaps)
+        n_classes = 16
+        gather_bytes = ((8 * max_slots + 255) // 256 * 256) + ((4 * max_slots + 255) // 256 * 256)
+        class_bytes = (tb - 512 - gather_bytes) // n_classes
+        barrier_off = n_classes * class_bytes
+        regions += [(barrier_off + 4, 252), (barrier_off + 260, 252)]
+        used_classes = {(8 if len(sh) == 3 else 0) + 2 * (0 if dt == "fp64" else 1) for sh, dt in specs}
+        regions += [(c * class_bytes, class_bytes) for c in range(n_classes) if c not in used_classes]
+        for o, ln in regions:
+            buf[base + o: base + o + ln].fill_(CAN)
+        torch.cuda.synchronize()
+        for k in (6, 6):  # even runs: the two-step form takes both D2Q9 classes
+            pool.run(k)
+        assert sorted(pool.poll()) == sorted(slots)
+        if form == "two-step":
+            assert pool.stats()["launches"] == (3 + 3) * 2 + 12  # two D2Q9 classes two-step, D3Q27 one-step
+        for o, ln in regions:
+            seg = buf[base + o: base + o + ln]
+            assert bool(torch.all(seg == CAN)), (form, o, ln)
+        for s, (r, u), (sh, dt) in zip(slots, fields, specs):
+            ra, ua, _, _ = alone(r, u, 0.6, steps, dt, False)
+            rb, ub, _ = pool.moments(s)
+            assert np.array_equal(ra, rb) and np.array_equal(ua, ub), (form, sh, dt)
+
+
+@pytest.mark.parametrize("dtype", ["fp32_dev", "fp64"])
+def test_pool_two_step_mixed_step_counts_equal_alone(dtype):
+    """Two steps per launch when the slots of a class take different numbers of
+    steps in one run: launch L covers, in two-step tiles, the slots with at
+    least 2 L + 2 steps and then, in a one-step launch, those whose last step
+    is 2 L + 1, whole-row and column-tile slots alike.  Each slot equals its
+    single-domain run bitwise after every run."""
+    lbm = _lbm()
+    big = (2048, 2100) if dtype == "fp32_dev" else (1030, 1100)
+    specs = [(big, 13), ((40, 70), 10), ((33, 100), 7), ((64, 512), 4), ((20, 700), 11), ((17, 129), 1),
+             ((90, 64), 12)]
+    fields = [workloads.random_field(shape, seed=400 + k, umax=0.1) for k, (shape, _) in enumerate(specs)]
+    with lbm.Pool(2 * GiB, max_slots=16, tuning=lbm.make_pool_tuning(64, 4, 0, time_block=2, time_rows=8)) as pool:
+        slots = [pool.admit(r, u, 0.55, steps, dtype=dtype) for (r, u), (_, steps) in zip(fields, specs)]
+        done = set()
+        for k in (5, 100):  # the first run cuts every budget at 5 steps (odd), the second finishes them
+            pool.run(k)
+            done |= set(pool.poll())
+            for s, (r, u), (_, steps) in zip(slots, fields, specs):
+                n = min(steps, 5 if k == 5 else steps)
+                ra, ua, _, _ = alone(r, u, 0.55, n, dtype, False)
+                rb, ub, db = pool.moments(s)
+                assert db["steps"] == n
+                assert np.array_equal(ra, rb) and np.array_equal(ua, ub), (s, n)
+        assert done == set(slots)

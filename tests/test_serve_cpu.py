@@ -33,6 +33,13 @@ class FakeBackend:
         self.finished = []
         self.reported = set()
         self.log = []
+        # the device: runs execute one after another from the moment they are
+        # enqueued or the previous one ends, whichever is later
+        self.gpu_free = 0.0
+        self.runs = 0
+        self.run_end = {}
+        self.done_at = {}
+        self.spans = []  # (start, end) of every run on the device
 
     def footprint(self, req):
         q, nodes = (9, req["n"] ** 2) if req["lattice"] == 9 else (27, req["n"] ** 3)
@@ -59,19 +66,33 @@ class FakeBackend:
         return self.slots[slot][1]
 
     def run(self, k):
+        """Enqueue: returns at once with the run's number; the device time of
+        each step is the traffic of the slots still active at that step."""
         act = [s for s, (_, rem) in self.slots.items() if rem > 0]
-        # cost: each step costs the traffic of the slots still active at that step
         steps = sorted(set([min(k, self.slots[s][1]) for s in act]))
+        t = max(self.clk.t, self.gpu_free)
         prev = 0
         for st in steps:
             live = [s for s in act if self.slots[s][1] > prev]
-            self.clk.t += (st - prev) * self.step_seconds(live)
+            t += (st - prev) * self.step_seconds(live)
             prev = st
+        self.spans.append((max(self.clk.t, self.gpu_free), t))
+        self.gpu_free = t
+        self.runs += 1
+        self.run_end[self.runs] = t
         for s in act:
             self.slots[s][1] -= min(k, self.slots[s][1])
+            if self.slots[s][1] == 0:
+                self.done_at[s] = t
+        self.log.append(("run", k, self.clk.t))
+        return self.runs
 
-    def poll(self):
-        out = [s for s, (_, rem) in self.slots.items() if rem == 0 and s not in self.reported]
+    def collect(self, after_run):
+        """Wait for run after_run, then list finished slots whose work is done."""
+        if after_run >= 1:
+            self.clk.t = max(self.clk.t, self.run_end[after_run])
+        out = [s for s, (_, rem) in self.slots.items()
+               if rem == 0 and s not in self.reported and self.done_at.get(s, 0.0) <= self.clk.t]
         self.reported |= set(out)
         return out
 
@@ -81,6 +102,7 @@ class FakeBackend:
     def release(self, slot):
         req, _ = self.slots.pop(slot)
         self.reported.discard(slot)
+        self.done_at.pop(slot, None)
         self.used -= self.footprint(req)
         self.log.append(("release", req["id"], self.clk.t))
 
@@ -199,8 +221,11 @@ def test_swf_admission_stops_at_saturation():
     srv = serve.Server(be, chunk_s=1.0, lookahead=16, clock=clk.clock, sleep=clk.sleep, policy="swf",
                        saturate_bytes=3 * per)
     srv.serve(reqs)
-    admits = [t for kind, _, t in be.log if kind == "admit"]
-    assert sum(1 for t in admits if t == 0.0) == 3  # three fill the saturation traffic at t = 0
+    kinds = [kind for kind, _, _ in be.log]
+    # three fill the saturation traffic of the first run; the next three are
+    # admitted (still at t = 0) for the run enqueued behind it
+    assert kinds[:4] == ["admit"] * 3 + ["run"]
+    assert kinds[4:8] == ["admit"] * 3 + ["run"]
 
 
 def test_policy_is_checked():
@@ -222,3 +247,19 @@ def test_thousand_request_trace():
         assert sorted(r["id"] for r in out) == list(range(1000)) and be.peak <= 96 << 30
         res[policy] = serve.summarize(out)
     assert res["swf"]["p50_latency_s"] < 0.25 * res["fifo"]["p50_latency_s"]
+
+
+def test_pipeline_keeps_the_device_busy():
+    """The next run is enqueued before the server waits for the current one, so
+    under load the device never idles between runs (with depth 1 it would, by
+    the host's turn-around; here the virtual host takes no time, so a gap can
+    only come from a run enqueued after its predecessor ended)."""
+    clk = VirtualClock()
+    be = FakeBackend(clk, budget=16 << 30, max_slots=32)
+    tr = _trace(n=120, rate=2000.0)  # arrivals within 0.06 s: the queue never empties
+    out = serve.Server(be, chunk_s=0.02, clock=clk.clock, sleep=clk.sleep).serve(tr)
+    assert len(out) == len(tr)
+    gaps = [b0 - a1 for (a0, a1), (b0, b1) in zip(be.spans, be.spans[1:])]
+    assert max(gaps) < 1e-12
+    busy = sum(b - a for a, b in be.spans)
+    assert busy == pytest.approx(max(r["finished"] for r in out) - be.spans[0][0], rel=1e-9)
