@@ -576,6 +576,20 @@ int lbm_vn_max_radius(int32_t lattice, int32_t equilibrium, int32_t bulk_correct
                       int64_t n_states, int32_t nk, double *max_radius, void *scratch, int32_t *unconverged,
                       void *stream);
 
+/* lbm_vn_max_radius for callers that cannot allocate memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same computation and results, with the scratch held by the library in a
+ * static device array of 65536 entries (512 KiB on each GPU the library runs
+ * on, kept until the process ends) instead of a caller's buffer.  No memory is
+ * allocated; the clear, the spectra and the conversion are three kernel
+ * launches on `stream` (the first call on a device also looks up the array's
+ * device address).  Calls on one GPU share the array: calls that overlap on
+ * the device (on different streams, or from several threads) race; calls in
+ * one stream are ordered.  Errors: as lbm_vn_max_radius, and LBM_EINVAL for
+ * n_states > 65536. */
+int lbm_vn_max_radius_noalloc(int32_t lattice, int32_t equilibrium, int32_t bulk_correction, const double *states,
+                              int64_t n_states, int32_t nk, double *max_radius, int32_t *unconverged, void *stream);
+
 /* Message of the last error raised on the calling thread (static storage,
  * empty if none). */
 const char *lbm_last_error(void);

@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "lbm.h"
 #include "lbm_internal.hpp"
@@ -161,6 +162,65 @@ static int vn_select(int32_t lattice, int32_t equilibrium, int32_t corr, Spectra
     return LBM_OK;
 }
 
+// Scratch of the allocation-free form of lbm_vn_max_radius: the per-state
+// running maxima (bit patterns) of kVnStaticStates states.  In host code the
+// name is only a stand-in; kernels get the device address that
+// hipGetSymbolAddress returns for the current device (each GPU holds its own
+// copy).
+constexpr int64_t kVnStaticStates = 65536;
+static __device__ __align__(256) unsigned long long scratch[kVnStaticStates];
+
+constexpr int kVnMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static unsigned long long *g_scratch_ptr[kVnMaxDevices];
+
+// Device address of `scratch` on the current device, looked up once per device.
+static int static_scratch(unsigned long long **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "device query");
+    if (dev < 0 || dev >= kVnMaxDevices) {
+        set_error("device index beyond the static scratch table");
+        return LBM_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return hip_fail(e, "scratch symbol address");
+        g_scratch_ptr[dev] = static_cast<unsigned long long *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return LBM_OK;
+}
+
+// The three launches of a max-radius call on `bits` (n_states entries, 8-byte
+// aligned): clear, per-matrix radii into the maxima, maxima to doubles.
+static int launch_max_radius(MaxFn mf, int dim, const double *states, int64_t n_states, int32_t nk,
+                             double *max_radius, unsigned long long *bits, int32_t *unconverged, hipStream_t s) {
+    const int64_t per = dim == 1 ? (int64_t)nk : (int64_t)nk * nk;
+    const int64_t total = n_states * per;
+    if (total > ((int64_t)INT32_MAX - 1) * kVnThreads) {
+        set_error("von Neumann max radius: too many matrices per call");
+        return LBM_EINVAL;
+    }
+    const int64_t nclear = n_states > 0 ? n_states : 1;
+    hipLaunchKernelGGL(k_vn_clear, dim3((unsigned)((nclear + 255) / 256)), dim3(256), 0, s, bits, n_states,
+                       unconverged);
+    if (total > 0) {
+        VnMaxArgs a{states, n_states, nk, per, bits, unconverged};
+        hipLaunchKernelGGL(mf, dim3((unsigned)((total + kVnThreads - 1) / kVnThreads)), dim3(kVnThreads), 0, s, a);
+        hipLaunchKernelGGL(k_vn_bits_to_double, dim3((unsigned)((n_states + 255) / 256)), dim3(256), 0, s,
+                           (const unsigned long long *)bits, n_states, max_radius);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return hip_fail(e, "von Neumann max radius launch");
+    return LBM_OK;
+}
+
 }  // namespace lbm
 
 using namespace lbm;
@@ -213,27 +273,32 @@ int lbm_vn_max_radius(int32_t lattice, int32_t equilibrium, int32_t bulk_correct
         set_error("von Neumann max radius: scratch must be 8-byte aligned");
         return LBM_EINVAL;
     }
-    const int64_t per = dim == 1 ? (int64_t)nk : (int64_t)nk * nk;
-    const int64_t total = n_states * per;
-    if (total > ((int64_t)INT32_MAX - 1) * kVnThreads) {
-        set_error("von Neumann max radius: too many matrices per call");
+    return launch_max_radius(mf, dim, states, n_states, nk, max_radius, static_cast<unsigned long long *>(scratch),
+                             unconverged, static_cast<hipStream_t>(stream));
+}
+
+int lbm_vn_max_radius_noalloc(int32_t lattice, int32_t equilibrium, int32_t bulk_correction, const double *states,
+                              int64_t n_states, int32_t nk, double *max_radius, int32_t *unconverged, void *stream) {
+    SpectraFn sf;
+    MaxFn mf;
+    int dim;
+    int rc = vn_select(lattice, equilibrium, bulk_correction, sf, mf, dim);
+    if (rc != LBM_OK)
+        return rc;
+    if (n_states < 0 || nk < 1 || nk > 65536 || (n_states > 0 && (!states || !max_radius)) || !unconverged) {
+        set_error("von Neumann max radius: NULL pointer or bad sizes");
         return LBM_EINVAL;
     }
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    auto *bits = static_cast<unsigned long long *>(scratch);
-    const int64_t nclear = n_states > 0 ? n_states : 1;
-    hipLaunchKernelGGL(k_vn_clear, dim3((unsigned)((nclear + 255) / 256)), dim3(256), 0, s, bits, n_states,
-                       unconverged);
-    if (total > 0) {
-        VnMaxArgs a{states, n_states, nk, per, bits, unconverged};
-        hipLaunchKernelGGL(mf, dim3((unsigned)((total + kVnThreads - 1) / kVnThreads)), dim3(kVnThreads), 0, s, a);
-        hipLaunchKernelGGL(k_vn_bits_to_double, dim3((unsigned)((n_states + 255) / 256)), dim3(256), 0, s,
-                           (const unsigned long long *)bits, n_states, max_radius);
+    if (n_states > kVnStaticStates) {
+        set_error("von Neumann max radius (no allocation): more than 65536 states per call");
+        return LBM_EINVAL;
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return hip_fail(e, "von Neumann max radius launch");
-    return LBM_OK;
+    unsigned long long *bits = nullptr;
+    rc = static_scratch(&bits);
+    if (rc != LBM_OK)
+        return rc;
+    return launch_max_radius(mf, dim, states, n_states, nk, max_radius, bits, unconverged,
+                             static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -120,7 +120,8 @@ EXPORTS = ("lbm_workspace_bytes", "lbm_workspace_bytes_tuned", "lbm_create", "lb
            "lbm_pool_release", "lbm_pool_stats_get", "lbm_pool_slot_info", "lbm_pool_destroy",
            "lbm_vn_spectra", "lbm_vn_max_radius", "lbm_halo_bytes", "lbm_halo_pack", "lbm_halo_unpack",
            "lbm_step_halo", "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_get_launch_info",
-           "lbm_pool_admit_async", "lbm_pool_collect", "lbm_ceiling_stream", "lbm_ceiling_copy")
+           "lbm_pool_admit_async", "lbm_pool_collect", "lbm_ceiling_stream", "lbm_ceiling_copy",
+           "lbm_vn_max_radius_noalloc")
 
 
 def load_library(path: str = LIB_PATH):
@@ -164,6 +165,8 @@ def load_library(path: str = LIB_PATH):
                                           vp]),
         "lbm_vn_max_radius": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, i64,
                                              ctypes.c_int32, vp, vp, vp, vp]),
+        "lbm_vn_max_radius_noalloc": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, i64,
+                                                     ctypes.c_int32, vp, vp, vp]),
         "lbm_destroy": (ctypes.c_int, [vp]),
         "lbm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "lbm_last_error": (ctypes.c_char_p, []),
@@ -324,6 +327,13 @@ def lbm_vn_max_radius(lattice: int, equilibrium, bulk_correction, states: int, n
     _check(load_library().lbm_vn_max_radius(int(lattice), EQUILIBRIA.get(equilibrium, equilibrium),
                                              int(bool(bulk_correction)), states, int(n_states), int(nk),
                                              max_radius, scratch, unconverged, stream), "lbm_vn_max_radius")
+
+
+def lbm_vn_max_radius_noalloc(lattice: int, equilibrium, bulk_correction, states: int, n_states: int, nk: int,
+                              max_radius: int, unconverged: int, stream=None) -> None:
+    _check(load_library().lbm_vn_max_radius_noalloc(int(lattice), EQUILIBRIA.get(equilibrium, equilibrium),
+                                                    int(bool(bulk_correction)), states, int(n_states), int(nk),
+                                                    max_radius, unconverged, stream), "lbm_vn_max_radius_noalloc")
 
 
 def lbm_destroy(h) -> None:
