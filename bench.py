@@ -53,6 +53,46 @@ def measured_traffic():
     return float(m.group(1))
 
 
+VALU_PEAK_GINST = 256 * 4 * 2.4 / 4  # G wavefront-instructions/s: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles
+VALU_PROFILE = os.path.join(ROOT, "profiles", "multistep_valu_d2q9_4096_d1q3_2e27_c4_512.md")
+
+
+def multistep_source_digest() -> str:
+    """Digest of the sources of the multi-step kernels (node arithmetic, one-step,
+    two-step and pool kernels); their counted VALU instructions are used only
+    while it matches the profile's."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2303_08163_amd", "csrc")
+    for fn in ("node.hpp", "kernels.hpp", "kernels_t2.hpp", "pool_kernels.hpp"):
+        with open(os.path.join(csrc, fn), "rb") as f:
+            h.update(fn.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def valu_counts() -> dict:
+    """VALU wavefront-instructions per launch of the multi-step kernels, from the
+    committed rocprofv3 summary, or {} when the kernels have changed since."""
+    if not os.path.exists(VALU_PROFILE):
+        return {}
+    text = open(VALU_PROFILE).read()
+    d = re.search(r"valu_kernel_source_digest:\s*([0-9a-f]+)", text)
+    if not d or d.group(1) != multistep_source_digest():
+        return {}
+    return {m.group(1): float(m.group(2)) for m in re.finditer(r"valu_insts_per_launch\.(\S+):\s*([0-9.eE+]+)", text)}
+
+
+def valu_roofline(key: str, launch_s: float):
+    """Issue-rate roofline of a multi-step kernel: counted VALU instructions per
+    launch over the launch time measured here, against 614.4 G/s."""
+    n = valu_counts().get(key)
+    if n is None:
+        return None
+    achieved = n / launch_s / 1e9
+    return {"bound": "valu", "achieved": round(achieved, 1), "peak": VALU_PEAK_GINST,
+            "unit": "G wavefront-instructions/s", "frac": round(achieved / VALU_PEAK_GINST, 4),
+            "insts_per_launch": n}
+
+
 def cpu_threads() -> int:
     n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     env = os.environ.get("OMP_NUM_THREADS")
@@ -103,22 +143,34 @@ def bench_batched(count: int, steps: int, dtypes=("fp32_dev", "fp64"), baseline:
             tuning, rep = dict(fixed_tuning), {"cached": False, "fixed": True}
         else:
             tuning, rep = autotune.tune_pool(doms, steps=10)
-        tun = lbm.make_pool_tuning(**tuning)
-        arena = lbm.lbm_pool_table_bytes(count) + sum(
-            lbm.lbm_pool_slot_bytes(lbm.make_config(9, (sp["nx"], sp["ny"]), sp["tau"], dtype), tun) for sp in specs)
-        with lbm.Pool(arena + (1 << 20), max_slots=count, tuning=tun) as pool:
-            for sp, (r0, u0) in zip(specs, fields):
-                pool.admit(r0, u0, sp["tau"], steps, dtype=dtype)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            pool.run(steps)
-            done = pool.poll()
-            dt = time.perf_counter() - t0
-            st = pool.stats()
-        assert len(done) == count
+        def timed_pool(tuning):
+            tun = lbm.make_pool_tuning(**tuning)
+            arena = lbm.lbm_pool_table_bytes(count) + sum(
+                lbm.lbm_pool_slot_bytes(lbm.make_config(9, (sp["nx"], sp["ny"]), sp["tau"], dtype), tun)
+                for sp in specs)
+            with lbm.Pool(arena + (1 << 20), max_slots=count, tuning=tun) as pool:
+                for sp, (r0, u0) in zip(specs, fields):
+                    pool.admit(r0, u0, sp["tau"], steps, dtype=dtype)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                pool.run(steps)
+                done = pool.poll()
+                dt = time.perf_counter() - t0
+                st = pool.stats()
+            assert len(done) == count
+            return dt, st
+
+        dt, st = timed_pool(tuning)
         rec = {"solves_per_s": round(count / dt, 2), "seconds": round(dt, 4), "mlups": round(nodes * steps / dt / 1e6, 1),
                "tuning": tuning, "launches": st["launches"], "autotune_cached": rep.get("cached", False),
                "autotune_fastest": (rep.get("times") or [])[:4], "autotune_failed": rep.get("failed", [])}
+        if tuning.get("time_block", 0) == 2:
+            # the same pool with one step per launch: what batching alone gives
+            one = dict(tuning, time_block=0)
+            one.pop("time_rows", None)
+            d1, st1 = timed_pool(one)
+            rec["pool_one_step_per_launch"] = {"solves_per_s": round(count / d1, 2), "seconds": round(d1, 4),
+                                               "launches": st1["launches"], "tuning": one}
         if baseline and dtype == dtypes[0]:
             doms_alone = [lbm.Domain(r0, u0, sp["tau"], dtype=dtype) for sp, (r0, u0) in zip(specs, fields)]
             torch.cuda.synchronize()
@@ -132,11 +184,15 @@ def bench_batched(count: int, steps: int, dtypes=("fp32_dev", "fp64"), baseline:
             rec["one_domain_per_launch"] = {"solves_per_s": round(count / tb, 2), "seconds": round(tb, 3),
                                             "launches": count * steps, "mlups": round(nodes * steps / tb / 1e6, 1)}
             rec["speedup_vs_one_domain_per_launch"] = round(tb / dt, 2)
+            if "pool_one_step_per_launch" in rec:
+                rec["pool_one_step_per_launch"]["speedup_vs_one_domain_per_launch"] = round(
+                    tb / rec["pool_one_step_per_launch"]["seconds"], 2)
         out[dtype] = rec
     return out
 
 
-def bench_serving(n_requests: int, rate: float, light_requests: int, policies=("swf",)) -> dict:
+def bench_serving(n_requests: int, rate: float, light_requests: int, policies=("swf",),
+                  saturate_bytes: float = 512e6) -> dict:
     """Serving: Poisson request stream (seed 8163) mixing D2Q9 64^2..1024^2 and
     D3Q27 32^3..192^3 (log-uniform sides), Taylor-Green or shear-wave starts,
     u0 ~ U[0.01, 0.15], tau ~ U[0.5001, 0.6], 200..5000 steps, FP32 storage;
@@ -153,7 +209,8 @@ def bench_serving(n_requests: int, rate: float, light_requests: int, policies=("
     def pooled(tr, policy):
         be = serve.PoolBackend(96 << 30, max_slots=512)
         try:
-            kw = {"policy": "swf", "lookahead": 1 << 30} if policy == "swf" else {"policy": "fifo", "lookahead": 8}
+            kw = {"policy": "swf", "lookahead": 1 << 30, "saturate_bytes": saturate_bytes} if policy == "swf" \
+                else {"policy": "fifo", "lookahead": 8}
             recs = serve.Server(be, **kw).serve(tr)
             out = serve.summarize(recs)
             busy = be.gpu_busy_seconds()
@@ -458,7 +515,8 @@ def bench_d1q3(steps: int = 200, warmup: int = 20) -> dict:
         own = bytes_per_lup * nodes / (k * sec / steps) / 1e9  # one read + one write per launch
         return {"mlups": round(mlups, 1), "us_per_step": round(sec / steps * 1e6, 2), "steps_per_launch": k,
                 "gbs": round(own, 1), "frac": round(own / HBM_PEAK_GBS, 4),
-                "gbs_2Qs_per_update": round(mlups * 1e6 * bytes_per_lup / 1e9, 1), "domain_error": d["domain_error"]}
+                "gbs_2Qs_per_update": round(mlups * 1e6 * bytes_per_lup / 1e9, 1), "domain_error": d["domain_error"],
+                "launch_s": k * sec / steps}
 
     n1 = 1 << 27
     x = np.arange(n1, dtype=np.float64)
@@ -471,7 +529,11 @@ def bench_d1q3(steps: int = 200, warmup: int = 20) -> dict:
     for dt, s in (("fp32_dev", 4), ("fp64", 8)):
         for name, tun in (("eight_steps_per_launch", None), ("one_step_per_launch", lbm.make_tuning(time_block=1))):
             dom = lbm.Domain(r1, u1, 0.6, dtype=dt, bulk_correction=True, stream=stream, tuning=tun)
-            out[f"{dt}_{name}"] = timed(dom, n1, 2 * 3 * s)
+            rec = timed(dom, n1, 2 * 3 * s)
+            launch_s = rec.pop("launch_s")
+            if rec["steps_per_launch"] > 1:
+                rec["roofline_valu"] = valu_roofline(f"d1q3_2e27.{dt}_{name}", launch_s)
+            out[f"{dt}_{name}"] = rec
             dom.close()
     return {"workload": "D1Q3 2^27 nodes, pressure wave rho = 1 + 1e-3 sin(2 pi x / N), U = 0.1, tau 0.6, "
                         "bulk correction on", "steps": steps, "results": out}
@@ -514,11 +576,14 @@ def bench_d2q9(steps: int = 100, warmup: int = 10) -> dict:
                 mlups = 4096 ** 2 / sec / 1e6
                 k = info["time_block"]
                 own = 2 * 9 * s * 4096 ** 2 / (k * sec) / 1e9  # bytes of one launch / its time
-                out[f"{dt}_{name}{'_corrected' if corr else ''}"] = {
+                key = f"{dt}_{name}{'_corrected' if corr else ''}"
+                out[key] = {
                     "mlups": round(mlups, 1), "us_per_step": round(sec * 1e6, 1),
                     "us_per_step_reps": [round(v * 1e6, 1) for v in reps], "steps_per_launch": k,
                     "kernel": info["kernel"], "gbs": round(own, 1), "frac": round(own / HBM_PEAK_GBS, 4),
                     "gbs_2Qs_per_update": round(mlups * 1e6 * 2 * 9 * s / 1e9, 1), "domain_error": d["domain_error"]}
+                if k > 1:
+                    out[key]["roofline_valu"] = valu_roofline(f"d2q9_4096.{key}", k * sec)
     return {"workload": "D2Q9 4096^2 double shear layer, tau 0.5001", "steps": steps, "repetitions": 3,
             "statistic": "best of the repetitions", "results": out}
 
@@ -615,6 +680,8 @@ def main() -> int:
     ap.add_argument("--sections", default="headline,ceiling,batched,serving,wave,stability,variants,slab,d2q9,d1q3",
                     help="comma list of headline, ceiling, batched, serving, wave, stability, variants, slab, d2q9, "
                          "d1q3, oracle_timing (not in the default run: several minutes of host time)")
+    ap.add_argument("--d2q9-steps", type=int, default=100, help="timed steps per repetition of the d2q9 section")
+    ap.add_argument("--d1q3-steps", type=int, default=200, help="timed steps of the d1q3 section")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--no-batch-baseline", action="store_true",
@@ -626,6 +693,8 @@ def main() -> int:
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-light-requests", type=int, default=40)
     ap.add_argument("--serve-policies", default="swf", help="comma list of swf, fifo (continuous batching policies)")
+    ap.add_argument("--serve-saturate", type=float, default=512e6,
+                    help="swf: per-step HBM bytes of the running requests at which admission pauses")
     args = ap.parse_args()
     sections = set(args.sections.split(","))
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -738,7 +807,7 @@ def main() -> int:
         progress("batched done")
     if "serving" in sections:
         out["serving"] = bench_serving(args.serve_requests, args.serve_rate, args.serve_light_requests,
-                                       tuple(args.serve_policies.split(",")))
+                                       tuple(args.serve_policies.split(",")), args.serve_saturate)
     if "wave" in sections:
         out["wave"] = bench_wave()
         progress("wave done")
@@ -752,10 +821,10 @@ def main() -> int:
         out["slab"] = bench_slab()
         progress("slab done")
     if "d2q9" in sections:
-        out["d2q9"] = bench_d2q9()
+        out["d2q9"] = bench_d2q9(steps=args.d2q9_steps)
         progress("d2q9 done")
     if "d1q3" in sections:
-        out["d1q3"] = bench_d1q3()
+        out["d1q3"] = bench_d1q3(steps=args.d1q3_steps)
         progress("d1q3 done")
     if "stability" in sections:
         out["stability"] = bench_stability(with_cpu=not args.no_cpu_baseline)

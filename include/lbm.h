@@ -403,14 +403,14 @@ typedef struct lbm_pool_tuning {
                            advance two steps per launch, the intermediate state in LDS, in
                            runs where the class's slots that take at least two steps hold
                            >= 2^22 nodes (FP32) or 2^20 (FP64); a slot whose step count in
-                           the run is odd takes its last step in a one-step launch.  Slots
-                           whose row, rounded up to 64, is at most 512 (FP32) or 128 (FP64)
-                           nodes run as whole-row tiles (no halo columns), wider ones as
-                           column tiles of 512 (FP32) or 64 (FP64).  Other runs take one
-                           step per launch.  Results are bitwise those of one step per
-                           launch.  0 or 1: one step per launch.  Not with persistent */
+                           the run is odd takes its last step in a one-step launch.  FP32:
+                           slots whose row, rounded up to 64, is at most 512 nodes run as
+                           whole-row tiles (no halo columns), wider ones as column tiles of
+                           512; FP64: column tiles of 128.  Other runs take one step per
+                           launch.  Results are bitwise those of one step per launch.
+                           0 or 1: one step per launch.  Not with persistent */
     int32_t time_rows;  /* time_block = 2: rows swept by each whole-row sub-tile and each column
-                           tile (0 = default, 32; at most 4096) */
+                           tile (0 = default: 32 for FP32, 16 for FP64; at most 4096) */
     int32_t spin_log2;  /* persistent form: a workgroup waits at most 2^spin_log2 polls of the
                            grid barrier's counter before it reports a timeout (1..40; 0 = the
                            default, 26, seconds of waiting).  Small values exist to exercise

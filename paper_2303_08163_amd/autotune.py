@@ -41,9 +41,9 @@ def candidates(persistent: bool = False):
     rows = [dict(tile_x=tx, tile_y=ty, persistent=p) for (tx, ty) in TILES for p in forms]
     flat = [dict(tile_x=tx, tile_y=ty, persistent=p, flat=1) for (tx, ty) in FLAT_TILES for p in forms]
     fit = [dict(tile_x=64, tile_y=4, persistent=p, row_fit=1) for p in forms]
-    # two steps per launch for D2Q9 classes in even runs (the tile and row fit
-    # serve the one-step launches of the other runs and classes)
-    two = [dict(tile_x=64, tile_y=4, persistent=0, row_fit=1, time_block=2)]
+    # two steps per launch for large D2Q9 classes (the tile and row fit serve the
+    # one-step launches of the other classes), with three sweep lengths
+    two = [dict(tile_x=64, tile_y=4, persistent=0, row_fit=1, time_block=2, time_rows=r) for r in (0, 16, 64)]
     return rows + flat + fit + two
 
 
@@ -118,7 +118,7 @@ def tune_pool(domains, steps: int = 20, cands=None, cache_path: str | None = DEF
     "failed", each candidate that the library refused or that raised an error
     while it ran (for instance a persistent run whose grid barrier timed out),
     with the error text."""
-    key = f"candidates-v5|{_device_key()}|{signature(domains)}" if cands is None else \
+    key = f"candidates-v6|{_device_key()}|{signature(domains)}" if cands is None else \
         f"custom-{hashlib.sha256(json.dumps(cands, sort_keys=True).encode()).hexdigest()[:12]}|{_device_key()}|" \
         f"{signature(domains)}"
     cache = _load_cache(cache_path) if cache_path else {}

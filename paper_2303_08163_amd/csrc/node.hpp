@@ -105,9 +105,47 @@ __device__ __forceinline__ void node_moments(const double (&f)[Lattice<DIM>::Q],
     }
 }
 
+// Square root of x on [1, 4), the range of S^2 = 1 + 3 u^2 for |u| < 1.  On the
+// device: the hardware estimate of 1/sqrt(x), one coupled Goldschmidt step
+// (g -> sqrt(x), h -> 1/(2 sqrt(x))) and two Newton corrections of g with the
+// residual x - g^2 taken exactly by a fused multiply-add (P. Markstein,
+// "IA-64 and Elementary Functions", 2000, ch. 8; the same scheme as a general
+// double square root, without the scaling that inputs near the ends of the
+// exponent range need and this range does not).  The result is within one
+// unit in the last place.  Outside [1, 4) -- a node that has left the
+// equilibrium's domain, flagged anyway -- its value is unspecified.
+__host__ __device__ __forceinline__ double sqrt_1to4(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    d = fma(-g, g, x);
+    return fma(d, h, g);
+#else
+    return sqrt(x);
+#endif
+}
+
+// 1 / x for the density of a node (x > 0 and of order 1 inside the
+// equilibrium's domain): the hardware reciprocal estimate and two
+// Newton-Raphson steps r <- r + r (1 - x r), within one unit in the last
+// place; for x <= 0 or non-finite (a node outside the domain, flagged) the
+// value is unspecified.
+__device__ __forceinline__ double recip_density(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 // Per-axis equilibrium factors g_{-1}, g_0, g_{+1} and S = sqrt(1 + 3 u^2).
 __host__ __device__ __forceinline__ void axis_factors(double u, double (&g)[3], double &S) {
-    S = sqrt(fma(3.0 * u, u, 1.0));
+    S = sqrt_1to4(fma(3.0 * u, u, 1.0));
     const double h = fma(2.0, S, -1.0) * (1.0 / 6.0);
     const double half_u = 0.5 * u;
     g[0] = h - half_u;
@@ -178,7 +216,7 @@ __device__ __forceinline__ bool collide(T (&v)[Lattice<DIM>::Q], const Relax &r)
         f[i] = (double)v[i];
     double rho, j[3];
     node_moments<DIM>(f, DEV ? r.rho0 : 0.0, rho, j);
-    const double inv = 1.0 / rho;
+    const double inv = recip_density(rho);
     double u[3] = {j[0] * inv, j[1] * inv, DIM == 3 ? j[2] * inv : 0.0};
     bool bad = !(rho > 0.0);
 #pragma unroll

@@ -141,18 +141,22 @@ static PoolStepFn pool_kernel(int dtype, bool corr, bool persistent) {
     }
 }
 
-// Two steps per launch in pools.  One launch has one workgroup shape: 512
-// threads for FP32 storage (column tiles of 512, the single-domain choice) and
-// 128 for FP64 (column tiles of 64 plus the halo wavefront).  A slot whose row,
-// rounded up to 64, fits the workgroup runs as whole-row tiles instead
-// (two_step_rows_tile): floor(threads / w) sub-tiles of w lanes, each sweeping
-// kPoolT2Rows rows (the default; lbm_pool_tuning.time_rows).  Whole rows need
-// no halo columns: with the earlier 128 x 16 column tiles, the batched
-// workload's narrow rows read 1.46x the algorithmic bytes, from the column
-// halos' cache lines and the 2 + 2 extra rows of every 16.
-constexpr int kPoolT2Rows = 32;
-static int t2_block(int dtype) { return dtype == kF64 ? 128 : 512; }
-static int t2_cols(int dtype) { return dtype == kF64 ? 64 : 512; }
+// Two steps per launch in pools.  One launch has one workgroup shape.  FP32
+// storage: 512 threads; a slot whose row, rounded up to 64, fits them runs as
+// whole-row tiles (two_step_rows_tile: floor(512 / w) sub-tiles of w lanes,
+// each sweeping 32 rows by default), wider slots as column tiles of 512.  Whole
+// rows need no halo columns: with the earlier 128 x 16 column tiles the
+// batched workload's narrow rows read 1.46x the algorithmic bytes (the column
+// halos' cache lines and the 2 + 2 extra rows of every 16), with whole rows
+// 1.10x.  FP64 storage: column tiles of 128 plus the halo wavefront (192
+// threads) and 16 rows.  Whole-row tiles of up to 128 nodes in 128-thread
+// workgroups (two wavefronts, four workgroups per compute unit) ran slower on
+// the batched workload, 399 against 461 solves/s: FP64 rows need the loads
+// in flight that only wider workgroups keep.
+static int t2_block(int dtype) { return dtype == kF64 ? 192 : 512; }
+static int t2_cols(int dtype) { return dtype == kF64 ? 128 : 512; }
+static int t2_rows_default(int dtype) { return dtype == kF64 ? 16 : 32; }
+static bool t2_whole_rows(int dtype) { return dtype != kF64; }
 
 struct Slot {
     bool used = false;
@@ -556,10 +560,10 @@ static int pool_run_classes(lbm_pool *p, int64_t k, bool &any) {
         }
         two = two && two_nodes >= (cdtype == kF64 ? (int64_t)1 << 20 : (int64_t)1 << 22);
         const int B = t2_block(cdtype), TX = t2_cols(cdtype);
-        const int R = p->tun.time_rows > 0 ? p->tun.time_rows : kPoolT2Rows;
+        const int R = p->tun.time_rows > 0 ? p->tun.time_rows : t2_rows_default(cdtype);
         auto whole_w = [&](int i) {  // whole-row sub-tile width, 0 for column tiles
             const int64_t w = (p->slots[i].d.cfg.nx + 63) / 64 * 64;
-            return w <= B ? (int)w : 0;
+            return t2_whole_rows(cdtype) && w <= B ? (int)w : 0;
         };
         int nw = 0;  // slots in the whole-row part
         if (two) {
@@ -668,7 +672,8 @@ static int pool_run_classes(lbm_pool *p, int64_t k, bool &any) {
                                       : (nt ? k_pool_step2<kDevF64, false, true> : k_pool_step2<kDevF64, false, false>));
             PoolStepFn fn1 = pool_kernel<2>(dtype, corr, false);
             // the larger LDS need of the two tile forms (whole-row: the most sub-tiles)
-            const size_t lds = std::max(t2_lds_bytes(TX, elem), t2_rows_lds_bytes(B / 64, 64, elem));
+            const size_t lds = nw > 0 ? std::max(t2_lds_bytes(TX, elem), t2_rows_lds_bytes(B / 64, 64, elem))
+                                      : t2_lds_bytes(TX, elem);
             PoolRunArgs a2 = a;
             a2.tile_start = reinterpret_cast<const int *>(table + off_two);
             a2.t2_tx = TX;
