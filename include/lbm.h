@@ -372,10 +372,13 @@ const char *lbm_status_string(int status);
  * list).  A slot is one periodic domain (any lattice and dtype; its own tau,
  * correction and step budget).  lbm_pool_run advances every active slot; one
  * step of all slots of a (lattice, dtype) class is one kernel launch (the
- * default), or all steps of a run are one persistent cooperative launch with
- * a device-side grid barrier between steps (on MI355X the barrier costs more
- * than a kernel boundary, 0.2-0.3 ms per step at full occupancy, so the
- * persistent form is an option, not the default).  A slot's populations are bitwise the same as
+ * default), or all steps of a run are one persistent cooperative launch.  In
+ * that launch one-step classes wait at a device-side grid barrier between
+ * steps (on MI355X the barrier costs more than a kernel boundary, 0.2-0.3 ms
+ * per step at full occupancy).  D2Q9 two-step classes (persistent with
+ * time_block = 2) have no grid barrier: each two-step tile keeps a completion
+ * counter, and a tile's next two steps wait only for the tiles within two
+ * nodes of it.  A slot's populations are bitwise the same as
  * those of a single domain (lbm_create) with the same configuration and
  * layout: every kernel uses the same per-node arithmetic.  Pools are not
  * thread-safe; slots of one pool share its stream.
@@ -408,11 +411,18 @@ typedef struct lbm_pool_tuning {
                            whole-row tiles (no halo columns), wider ones as column tiles of
                            512; FP64: column tiles of 128.  Other runs take one step per
                            launch.  Results are bitwise those of one step per launch.
-                           0 or 1: one step per launch.  Not with persistent */
+                           With persistent = 1 such a class takes every iteration of a
+                           run (two steps each, and a last single step for slots with
+                           an odd count) in one cooperative launch ordered by per-tile
+                           counters, for runs of at most 2^30 steps; its slots then hold
+                           8 bytes per two-step tile more (lbm_pool_slot_bytes).  Other
+                           classes of such a pool run persistent as with time_block 0.
+                           0 or 1: one step per launch */
     int32_t time_rows;  /* time_block = 2: rows swept by each whole-row sub-tile and each column
                            tile (0 = default: 32 for FP32, 16 for FP64; at most 4096) */
     int32_t spin_log2;  /* persistent form: a workgroup waits at most 2^spin_log2 polls of the
-                           grid barrier's counter before it reports a timeout (1..40; 0 = the
+                           grid barrier's counter, or of its tile's neighbours' counters,
+                           before it reports a timeout (1..40; 0 = the
                            default, 26, seconds of waiting).  Small values exist to exercise
                            the timeout path: every workgroup still leaves normally */
 } lbm_pool_tuning;
@@ -430,7 +440,7 @@ typedef struct lbm_slot_info {
     int64_t bytes;        /* arena bytes held */
     int32_t domain_error; /* 1 if it was retired because its state left the domain */
     int32_t device_error; /* 1 if a persistent launch that advanced it stopped at a timed-out
-                             grid barrier: its state is that of an unknown step, and
+                             wait: its state is that of an unknown step, and
                              lbm_pool_moments / lbm_pool_get_populations return LBM_EDEVICE */
 } lbm_slot_info;
 
@@ -484,7 +494,7 @@ int lbm_pool_run(lbm_pool *pool, int64_t k);
  * domain flag is set (some node left rho > 0, |u_alpha| < 1) is retired here:
  * its remaining steps are dropped, it is listed as done, its slot info shows
  * domain_error = 1 and lbm_pool_moments returns LBM_EDOMAIN for it.
- * If a persistent launch's grid barrier timed out since the last poll, every
+ * If a persistent launch's wait timed out since the last poll, every
  * slot that such a launch advanced is retired with device_error = 1 (listed
  * as done by this or a later poll; lbm_pool_moments returns LBM_EDEVICE for
  * it), the barrier state is reset so that the pool stays usable, and the call

@@ -48,10 +48,6 @@ static int resolve_tuning(const lbm_pool_tuning *t, lbm_pool_tuning *out) {
     }
     if (r.spin_log2 == 0)
         r.spin_log2 = kSpinLog2;
-    if (r.time_block == 2 && r.persistent) {
-        set_error("pool tuning: time_block = 2 is not with persistent");
-        return LBM_EINVAL;
-    }
     if (r.tile_x == 0)
         r.tile_x = 64;
     if (r.tile_y == 0)
@@ -157,6 +153,41 @@ static int t2_block(int dtype) { return dtype == kF64 ? 192 : 512; }
 static int t2_cols(int dtype) { return dtype == kF64 ? 128 : 512; }
 static int t2_rows_default(int dtype) { return dtype == kF64 ? 16 : 32; }
 static bool t2_whole_rows(int dtype) { return dtype != kF64; }
+static int t2_rows(const lbm_pool_tuning &t, int dtype) { return t.time_rows > 0 ? t.time_rows : t2_rows_default(dtype); }
+
+// Two-step tiling of a D2Q9 slot: whole-row tiles of sub sub-tiles of R rows
+// each when the padded row fits the workgroup (w > 0, FP32 storage), else
+// column tiles of t2_cols x R.
+struct T2Geom {
+    int w = 0, sub = 0;
+    int64_t tiles = 0;
+};
+static T2Geom t2_geom(int64_t nx, int64_t ny, int dtype, int R) {
+    T2Geom g;
+    const int B = t2_block(dtype), TX = t2_cols(dtype);
+    const int64_t w = (nx + 63) / 64 * 64;
+    if (t2_whole_rows(dtype) && w <= B) {
+        g.w = (int)w;
+        g.sub = B / g.w;
+        g.tiles = (ny + (int64_t)g.sub * R - 1) / ((int64_t)g.sub * R);
+    } else {
+        g.tiles = ((nx + TX - 1) / TX) * ((ny + R - 1) / R);
+    }
+    return g;
+}
+
+// Slots that the tile-ordered persistent form may advance (D2Q9, FP64 or FP32
+// deviation storage, row-interleaved layout, persistent two-step tuning) carry
+// one 8-byte completion counter per two-step tile after their buffers.
+static bool t2_counters(const lbm_config *cfg, const lbm_pool_tuning &t) {
+    return t.persistent && t.time_block == 2 && t.layout == LBM_LAYOUT_ROWS && cfg->lattice == LBM_D2Q9 &&
+           (cfg->dtype == kF64 || cfg->dtype == kDevF64);
+}
+static size_t t2_counter_bytes(const lbm_config *cfg, const lbm_pool_tuning &t) {
+    if (!t2_counters(cfg, t))
+        return 0;
+    return round256(sizeof(int64_t) * (size_t)t2_geom(cfg->nx, cfg->ny, cfg->dtype, t2_rows(t, cfg->dtype)).tiles);
+}
 
 struct Slot {
     bool used = false;
@@ -172,6 +203,7 @@ struct Slot {
     int tiles_x = 0, tiles_y = 0, tiles = 0;
     int tw_shift = 0;  // row_fit: tile rows of 1 << tw_shift threads; 0: the workgroup's own shape
     int cls = 0;
+    int64_t *tdone = nullptr;  // two-step tile counters of the tile-ordered persistent form
 };
 
 }  // namespace lbm
@@ -206,6 +238,7 @@ struct lbm_pool {
     char *gather_dev = nullptr;
     int cu_count = 0;
     int64_t runs = 0, launches = 0;
+    int64_t df_base = 0;  // tile-ordered form: above every counter value stored so far
 };
 
 namespace {
@@ -362,7 +395,7 @@ size_t lbm_pool_slot_bytes(const lbm_config *cfg, const lbm_pool_tuning *tuning)
     Layout L;
     if (resolve_tuning(tuning, &t) != LBM_OK || slot_layout(cfg, t, &L) != LBM_OK)
         return 0;
-    return round256(L.ws_bytes);
+    return round256(L.ws_bytes) + t2_counter_bytes(cfg, t);
 }
 
 int lbm_pool_create(int32_t max_slots, const lbm_pool_tuning *tuning, void *arena, size_t arena_bytes,
@@ -446,7 +479,8 @@ static int pool_admit_impl(lbm_pool *p, const lbm_config *cfg, const double *rho
         set_error("pool admit: no free slot");
         return LBM_EBUSY;
     }
-    const size_t bytes = round256(L.ws_bytes);
+    const size_t counter_bytes = t2_counter_bytes(cfg, p->tun);
+    const size_t bytes = round256(L.ws_bytes) + counter_bytes;
     // tile counts first, so that nothing is enqueued for a domain the pool refuses
     const int64_t block = (int64_t)L.block_x * L.block_y;
     int64_t tw = L.block_x, th = L.block_y;
@@ -463,7 +497,7 @@ static int pool_admit_impl(lbm_pool *p, const lbm_config *cfg, const double *rho
     }
     const int64_t tiles_x = (cfg->nx + tw - 1) / tw, tiles_y = (cfg->ny + th - 1) / th;
     const int64_t tiles = p->tun.flat ? (L.n + block - 1) / block : tiles_x * tiles_y * cfg->nz;
-    if (tiles > (int64_t)1 << 30) {
+    if (tiles > (int64_t)1 << 30 || counter_bytes > ((size_t)1 << 30)) {
         set_error("pool admit: domain has too many tiles");
         return LBM_EINVAL;
     }
@@ -475,6 +509,15 @@ static int pool_admit_impl(lbm_pool *p, const lbm_config *cfg, const double *rho
     Slot &s = p->slots[k];
     s = Slot{};
     rc = domain_bind_and_init(s.d, cfg, L, p->arena + off, rho, u, p->stream);
+    if (rc == LBM_OK && counter_bytes > 0) {
+        // tile counters start at zero, below every value a launch waits for
+        s.tdone = reinterpret_cast<int64_t *>(p->arena + off + round256(L.ws_bytes));
+        hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(256), 0, p->stream, reinterpret_cast<int *>(s.tdone),
+                           (int)(counter_bytes / sizeof(int)));
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            rc = hip_fail(e, "pool counter clear");
+    }
     int flag = 0;
     if (rc == LBM_OK && sync)
         rc = domain_read_flag(s.d, p->stream, &flag);
@@ -560,11 +603,9 @@ static int pool_run_classes(lbm_pool *p, int64_t k, bool &any) {
         }
         two = two && two_nodes >= (cdtype == kF64 ? (int64_t)1 << 20 : (int64_t)1 << 22);
         const int B = t2_block(cdtype), TX = t2_cols(cdtype);
-        const int R = p->tun.time_rows > 0 ? p->tun.time_rows : t2_rows_default(cdtype);
-        auto whole_w = [&](int i) {  // whole-row sub-tile width, 0 for column tiles
-            const int64_t w = (p->slots[i].d.cfg.nx + 63) / 64 * 64;
-            return t2_whole_rows(cdtype) && w <= B ? (int)w : 0;
-        };
+        const int R = t2_rows(p->tun, cdtype);
+        auto geom = [&](int i) { return t2_geom(p->slots[i].d.cfg.nx, p->slots[i].d.cfg.ny, cdtype, R); };
+        auto whole_w = [&](int i) { return geom(i).w; };  // whole-row sub-tile width, 0 for column tiles
         int nw = 0;  // slots in the whole-row part
         if (two) {
             std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
@@ -580,19 +621,21 @@ static int pool_run_classes(lbm_pool *p, int64_t k, bool &any) {
                              [&](int a, int b) { return p->slots[a].remaining > p->slots[b].remaining; });
         }
         const int n = (int)order.size();
+        int64_t smax = 0;
+        for (int i : order)
+            smax = std::max(smax, steps_of(i));
+        // tile-ordered persistent form: all two-step iterations in one launch (runs
+        // of up to 2^30 steps; longer ones take the launch-per-iteration form)
+        const bool df = two && p->tun.persistent && smax <= ((int64_t)1 << 30);
         std::vector<int> tile_start(n + 1, 0), two_start(n + 1, 0);
         std::vector<int> sub(n, 0);
         for (int j = 0; j < n; ++j) {
             const Slot &sj = p->slots[order[j]];
             int64_t t2 = 0;
             if (two) {
-                const int w = whole_w(order[j]);
-                if (w > 0) {
-                    sub[j] = B / w;
-                    t2 = (sj.d.cfg.ny + (int64_t)sub[j] * R - 1) / ((int64_t)sub[j] * R);
-                } else {
-                    t2 = ((sj.d.cfg.nx + TX - 1) / TX) * ((sj.d.cfg.ny + R - 1) / R);
-                }
+                const T2Geom g = geom(order[j]);
+                sub[j] = g.sub;
+                t2 = g.tiles;
             }
             if ((int64_t)tile_start[j] + sj.tiles > INT32_MAX || (int64_t)two_start[j] + t2 > INT32_MAX) {
                 set_error("pool run: more than 2^31 - 1 tiles in one class");
@@ -631,6 +674,8 @@ static int pool_run_classes(lbm_pool *p, int64_t k, bool &any) {
             d.tw_shift = s.tw_shift;
             d.t2_w = two ? whole_w(order[j]) : 0;
             d.t2_sub = sub[j];
+            d.run_steps = df ? (int)steps_of(order[j]) : 0;
+            d.tdone = s.tdone;
             d.parity = s.d.cur;
             d.ps = s.d.L.ps;
             d.rs = s.d.L.rs;
@@ -641,6 +686,32 @@ static int pool_run_classes(lbm_pool *p, int64_t k, bool &any) {
         }
         std::memcpy(starts, tile_start.data(), sizeof(int) * (n + 1));
         std::memcpy(starts2, two_start.data(), sizeof(int) * (n + 1));
+        // two-step launch parameters: block, dynamic LDS (the larger need of the two tile
+        // forms: whole-row with the most sub-tiles, columns) and store kind
+        const size_t elem = cdtype == kF64 ? 8 : 4;
+        const bool nt = t2_nt_stores(class_buf_bytes);
+        const size_t lds = nw > 0 ? std::max(t2_lds_bytes(TX, elem), t2_rows_lds_bytes(B / 64, 64, elem))
+                                  : t2_lds_bytes(TX, elem);
+        void (*fd)(PoolRunArgs) = nullptr;
+        int64_t G = 0;
+        if (df) {
+            fd = cdtype == kF64 ? (corr ? (nt ? k_pool_df2<kF64, true, true> : k_pool_df2<kF64, true, false>)
+                                        : (nt ? k_pool_df2<kF64, false, true> : k_pool_df2<kF64, false, false>))
+                                : (corr ? (nt ? k_pool_df2<kDevF64, true, true> : k_pool_df2<kDevF64, true, false>)
+                                        : (nt ? k_pool_df2<kDevF64, false, true> : k_pool_df2<kDevF64, false, false>));
+            int per_cu = 0;
+            hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(fd), B, lds);
+            if (e != hipSuccess)
+                return hip_fail(e, "pool occupancy query");
+            G = (int64_t)per_cu * p->cu_count;
+            if (p->tun.workgroups > 0)
+                G = std::min<int64_t>(G, p->tun.workgroups);
+            // as few workgroups as give every one the same number of tiles, m or m - 1
+            const int64_t T = two_start[n];
+            G = std::max<int64_t>(1, std::min<int64_t>(G, T));
+            const int64_t m = (T + G - 1) / G;
+            G = (T + m - 1) / m;
+        }
         char *table = p->arena + (size_t)c * p->class_bytes;
         hipError_t e = hipMemcpyAsync(table, staging, p->class_bytes, hipMemcpyHostToDevice, p->stream);
         if (e == hipSuccess)
@@ -663,8 +734,6 @@ static int pool_run_classes(lbm_pool *p, int64_t k, bool &any) {
                                  : pool_kernel<2>(dtype, corr, p->tun.persistent);
         dim3 block(p->tun.tile_x, p->tun.tile_y);
         if (two) {
-            const size_t elem = dtype == kF64 ? 8 : 4;
-            const bool nt = t2_nt_stores(class_buf_bytes);
             void (*fn2)(PoolRunArgs) =
                 dtype == kF64 ? (corr ? (nt ? k_pool_step2<kF64, true, true> : k_pool_step2<kF64, true, false>)
                                       : (nt ? k_pool_step2<kF64, false, true> : k_pool_step2<kF64, false, false>))
@@ -672,13 +741,23 @@ static int pool_run_classes(lbm_pool *p, int64_t k, bool &any) {
                                       : (nt ? k_pool_step2<kDevF64, false, true> : k_pool_step2<kDevF64, false, false>));
             PoolStepFn fn1 = pool_kernel<2>(dtype, corr, false);
             // the larger LDS need of the two tile forms (whole-row: the most sub-tiles)
-            const size_t lds = nw > 0 ? std::max(t2_lds_bytes(TX, elem), t2_rows_lds_bytes(B / 64, 64, elem))
-                                      : t2_lds_bytes(TX, elem);
             PoolRunArgs a2 = a;
             a2.tile_start = reinterpret_cast<const int *>(table + off_two);
             a2.t2_tx = TX;
             a2.t2_rows = R;
             a2.t2_R = R;
+            if (df) {
+                a2.base = p->df_base;
+                a2.step0 = 0;
+                a2.nsteps = 0;
+                void *args[] = {&a2};
+                e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(fd), dim3((unsigned)G), dim3((unsigned)B),
+                                               args, (unsigned)lds, p->stream);
+                if (e != hipSuccess)
+                    return hip_fail(e, "pool tile-ordered launch");
+                p->launches++;
+                p->df_base += (smax + 1) / 2 + 1;
+            }
             // s_j of the list, and the number of slots of each part with s_j >= m
             std::vector<int64_t> sj(n);
             for (int j = 0; j < n; ++j)
@@ -689,7 +768,6 @@ static int pool_run_classes(lbm_pool *p, int64_t k, bool &any) {
                     ++q;
                 return q;
             };
-            const int64_t smax = *std::max_element(sj.begin(), sj.end());
             auto launch = [&](void (*f)(PoolRunArgs), PoolRunArgs args, int t0, int t1, dim3 blk, size_t shm) {
                 if (t1 <= t0)
                     return;
@@ -697,7 +775,7 @@ static int pool_run_classes(lbm_pool *p, int64_t k, bool &any) {
                 hipLaunchKernelGGL(f, dim3((unsigned)(t1 - t0)), blk, (unsigned)shm, p->stream, args);
                 p->launches++;
             };
-            for (int64_t L = 0; 2 * L + 1 <= smax; ++L) {
+            for (int64_t L = 0; !df && 2 * L + 1 <= smax; ++L) {
                 a2.step0 = (int)L;
                 a2.nsteps = 2;
                 // two-step tiles of the slots with s_j >= 2 L + 2: a prefix of each part
@@ -770,7 +848,7 @@ static int pool_run_classes(lbm_pool *p, int64_t k, bool &any) {
             s.d.cur ^= (int)((two ? done / 2 + done % 2 : done) & 1);  // one swap per launch
             s.d.steps += done;
             s.remaining -= done;
-            s.persistent = s.persistent || (p->tun.persistent && !two);
+            s.persistent = s.persistent || (p->tun.persistent && (!two || df));
             s.last_epoch = -1;  // set by the caller, once the run's epoch is recorded
         }
     }
@@ -838,7 +916,7 @@ int lbm_pool_poll(lbm_pool *p, int32_t *done, int32_t capacity, int32_t *count) 
         }
     }
     if (err) {
-        // a persistent launch stopped at a timed-out grid barrier: the slots such
+        // a persistent launch stopped at a timed-out wait: the slots such
         // launches advanced hold the state of an unknown step; retire them, reset
         // the barrier words, and list them at the next poll
         for (Slot &s : p->slots)
@@ -855,8 +933,8 @@ int lbm_pool_poll(lbm_pool *p, int32_t *done, int32_t capacity, int32_t *count) 
         *count = 0;
         if (e != hipSuccess)
             return hip_fail(e, "pool barrier reset");
-        set_error("pool: a persistent launch's grid barrier timed out; the slots it advanced are retired "
-                  "(device_error) and listed by the next poll");
+        set_error("pool: a persistent launch timed out at a grid barrier or a tile wait; the slots it "
+                  "advanced are retired (device_error) and listed by the next poll");
         return LBM_EDEVICE;
     }
     for (Slot &s : p->slots)

@@ -38,10 +38,11 @@ struct SlotDesc {
     int tw_shift;  // > 0: tiles are rows of 1 << tw_shift threads (row fit); 0: blockDim's shape
     int t2_w;      // two-step launches: > 0: whole-row sub-tiles of t2_w lanes, t2_sub per
     int t2_sub;    //   workgroup (two_step_rows_tile); 0: column tiles (two_step_tile)
-    int pad_;
+    int run_steps; // tile-ordered persistent form: steps of this slot in the launch
     int64_t ps, rs;
     Relax relax;
     int *flag;
+    int64_t *tdone;  // tile-ordered persistent form: one completion counter per two-step tile
 };
 
 struct PoolRunArgs {
@@ -58,6 +59,7 @@ struct PoolRunArgs {
     int t2_tx, t2_rows;       // two-step form: columns and rows of a column tile
     int t2_R;                 // two-step form: rows of a whole-row sub-tile
     int tile_base;            // the launch's first tile (its blocks cover tile_base + [0, grid))
+    int64_t base;             // tile-ordered form: counter value of a tile with no iteration of this launch done
 };
 
 // Active tiles at step s: the tile count of the slots with remaining > s.
@@ -217,6 +219,188 @@ __global__ __launch_bounds__(256) void k_pool_persistent(PoolRunArgs a) {
             pool_tile<DIM, DT, CORR>(a, t, step);
         if (s + 1 < a.nsteps && !grid_barrier(a.barrier, (unsigned)G * (unsigned)(s + 1), a.error, a.spin_limit))
             return;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tile-ordered persistent form (D2Q9 two-step classes): every iteration of a
+// run in one cooperative launch, with no grid-wide barrier.  Slot j takes its
+// s_j = run_steps steps as n_j = ceil(s_j / 2) iterations over its two-step
+// tiles: two steps each and, for odd s_j, a last iteration of one step over
+// the tile's own nodes.  Iteration k of a tile reads buffer (parity + k) & 1
+// at the tile's nodes and the two columns and rows around them, and writes
+// the other buffer at its own nodes only.  It may therefore start once every
+// tile whose nodes lie within two nodes of it (itself included, periodic wrap)
+// has finished iteration k - 1: the state it reads is then complete, and the
+// state it overwrites (that of iteration k - 1's input) has no reader left.
+// The relation is symmetric and stays inside a slot.
+//
+// Each tile has a completion counter; iteration k done is base + k + 1, and
+// base exceeds every value an earlier launch stored, so the counters need no
+// clearing between runs (they are zeroed once, at admission).
+//
+// Workgroup L (XCD-ordered) owns the tiles L, L + G, L + 2 G, ... of the
+// class and takes them in that order for iteration 0, then for iteration 1,
+// and so on.  At any moment the workgroups therefore work on about G
+// consecutive tiles, each XCD on a contiguous part of them, as the hardware
+// dispatcher would order one launch per iteration: neighbouring tiles share
+// halo lines in L2 and the pages in use stay few.  (Contiguous ranges per
+// workgroup spread the grid over the whole footprint at once; on the batched
+// shear-wave workload that ran 17% slower, fences aside.)  A workgroup
+// publishes an iteration once, after all its tiles of it: one agent-scope
+// release (a write-back of the XCD's L2), then the counters of those tiles.
+// One release per tile cost FP64 half its rate: on MI355X each release waits
+// for the L2 write-back.  Every workgroup is resident (cooperative launch), and
+// a tile's wait at iteration k needs only iteration k - 1 of other workgroups,
+// which they publish without waiting on anything later, so every wait ends.
+// Each is nevertheless bounded like the grid barrier's: past the bound, or
+// once another workgroup has reported a timeout, the workgroup leaves.
+
+__device__ __forceinline__ int df_wrap(int c, int n) {
+    c %= n;
+    return c < 0 ? c + n : c;
+}
+
+// Wait until the tiles within two nodes of tile tt of a slot (whole-row tiles
+// of rr rows when w > 0, else column tiles of tx x rows) have counters >=
+// need.  Wavefront 0 polls: lane ix + 5 iy the tile holding column
+// x0 - 2, x0 - 1, x0, x0 + nv, x0 + nv + 1 (by ix) and row y0 - 2, y0 - 1,
+// y0, y1, y1 + 1 (by iy) -- every tile that the dilated box [x0 - 2, x0 + nv
+// + 2) x [y0 - 2, y1 + 2) meets, some of them repeatedly.  Wavefront 0
+// then acquires at agent scope (dropping stale L1 and L2 lines), and the
+// workgroup barrier orders the other wavefronts' loads after it.  Returns
+// false (the same in every thread) when the wait timed out or another
+// workgroup reported a timeout.
+__device__ __forceinline__ bool df_wait(const PoolRunArgs &a, const int64_t *tdone, int nx, int ny, int w, int rr,
+                                        int tx, int rows, int tt, int64_t need) {
+    __shared__ int df_ok;
+    if (threadIdx.x < 64) {  // wavefront 0, all lanes active
+        const int l = (int)threadIdx.x, ix = l % 5, iy = l / 5;
+        int idx = -1;
+        if (w > 0) {
+            if (l < 5) {
+                const int y0 = tt * rr, y1 = min(y0 + rr, ny);
+                const int ry[5] = {y0 - 2, y0 - 1, y0, y1, y1 + 1};
+                idx = df_wrap(ry[ix], ny) / rr;
+            }
+        } else if (l < 25) {
+            const int tiles_x = (nx + tx - 1) / tx;
+            const int x0 = (tt % tiles_x) * tx, nv = min(tx, nx - x0);
+            const int y0 = (tt / tiles_x) * rows, y1 = min(y0 + rows, ny);
+            const int cx[5] = {x0 - 2, x0 - 1, x0, x0 + nv, x0 + nv + 1};
+            const int ry[5] = {y0 - 2, y0 - 1, y0, y1, y1 + 1};
+            idx = (df_wrap(ry[iy], ny) / rows) * tiles_x + df_wrap(cx[ix], nx) / tx;
+        }
+        bool ready = idx < 0 || __hip_atomic_load(tdone + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
+        long long spins = 0;
+        int good = 1;
+        while (!__all(ready)) {
+            const int err =
+                __builtin_amdgcn_readfirstlane(__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            if (err != 0 || ++spins > a.spin_limit) {
+                if (l == 0)
+                    __hip_atomic_fetch_or(a.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                good = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+            if (!ready)
+                ready = __hip_atomic_load(tdone + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
+        }
+        if (l == 0)
+            df_ok = good;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    return df_ok != 0;
+}
+
+// Slot of class tile t: the last j with tile_start[j] <= t.
+__device__ __forceinline__ int df_slot(const PoolRunArgs &a, int t) {
+    int lo = 0, hi = a.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.tile_start[mid] <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Grid: G <= resident workgroups of t2_threads(t2_tx, elem) threads, the
+// larger LDS need of the two tile forms; a.tile_start holds the two-step tile
+// counts.
+template <int DT, bool CORR, bool NT>
+__global__ __launch_bounds__(512) void k_pool_df2(PoolRunArgs a) {
+    using T = store_t<DT>;
+    const int G = (int)gridDim.x;
+    const int L = xcd_tile((int)blockIdx.x, G);
+    const int ntiles = a.tile_start[a.n];
+    int kmax = 0;  // most iterations among the owned tiles' slots
+    for (int t = L; t < ntiles; t += G)
+        kmax = max(kmax, (a.slots[df_slot(a, t)].run_steps + 1) / 2);
+    for (int k = 0; k < kmax; ++k) {
+        for (int t = L; t < ntiles; t += G) {
+            const int j = df_slot(a, t);
+            // descriptor fields into locals before any store (see pool_tile)
+            const SlotDesc &dd = a.slots[j];
+            const int steps = dd.run_steps;
+            if (2 * k >= steps)  // this slot's run is over (uniform per workgroup)
+                continue;
+            const int nx = dd.nx, ny = dd.ny, w = dd.t2_w, sub = dd.t2_sub;
+            const int64_t ps = dd.ps, rs = dd.rs;
+            const Relax relax = dd.relax;
+            int *flag = dd.flag;
+            int64_t *tdone = dd.tdone;
+            const int p = (dd.parity + k) & 1;
+            void *src = dd.buf[p], *dst = dd.buf[p ^ 1];
+            const int tt = t - a.tile_start[j];
+            const int rr = sub * a.t2_R;  // rows of a whole-row tile
+            if (k > 0 && !df_wait(a, tdone, nx, ny, w, rr, a.t2_tx, a.t2_rows, tt, a.base + k))
+                return;
+            if (2 * k + 2 <= steps) {
+                Step2Args s{src, dst, nx, ny, a.t2_tx, a.t2_rows, (nx + a.t2_tx - 1) / a.t2_tx,
+                            (ny + a.t2_rows - 1) / a.t2_rows, ps, rs, relax, flag};
+                if (w > 0)
+                    two_step_rows_tile<DT, CORR, kEqEntropic, NT>(s, tt, w, sub, a.t2_R);
+                else
+                    two_step_tile<DT, CORR, kEqEntropic, NT>(s, tt);
+            } else {  // the odd last step: one step over the tile's own nodes
+                int bx0 = 0, bnx = nx, by0, by1;
+                if (w > 0) {
+                    by0 = tt * rr;
+                    by1 = min(by0 + rr, ny);
+                } else {
+                    const int tiles_x = (nx + a.t2_tx - 1) / a.t2_tx;
+                    bx0 = (tt % tiles_x) * a.t2_tx;
+                    bnx = min(a.t2_tx, nx - bx0);
+                    by0 = (tt / tiles_x) * a.t2_rows;
+                    by1 = min(by0 + a.t2_rows, ny);
+                }
+                const int cnt = bnx * (by1 - by0);
+                for (int q = (int)threadIdx.x; q < cnt; q += (int)blockDim.x) {
+                    const int yy = by0 + q / bnx, xx = bx0 + q % bnx;
+                    step_node<2, DT, CORR>(static_cast<const T *>(src), static_cast<T *>(dst), nx, ny, 1, ps, rs,
+                                           relax, flag, xx, yy, 0);
+                }
+            }
+            // every wave's stores done before the next tile reuses the LDS ring (and
+            // before the release below)
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+        }
+        // publish iteration k: one release at agent scope, then, by the same thread,
+        // the counters of the tiles that took part
+        if (threadIdx.x == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            for (int t = L; t < ntiles; t += G) {
+                const int j = df_slot(a, t);
+                if (2 * k < a.slots[j].run_steps)
+                    __hip_atomic_store(a.slots[j].tdone + (t - a.tile_start[j]), a.base + k + 1, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
     }
 }
 

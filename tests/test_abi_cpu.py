@@ -254,11 +254,22 @@ def test_pool_host_logic(lbm):
     assert lbm.lbm_pool_slot_bytes(_cfg(lbm, tau=0.5)) == 0
     for bad in [dict(tile_x=48, tile_y=4), dict(tile_x=64, tile_y=8), dict(persistent=2), dict(workgroups=-1),
                 dict(layout=5), dict(flat=2), dict(flat=-1), dict(row_fit=2), dict(row_fit=-1),
-                dict(row_fit=1, flat=1), dict(time_block=3), dict(time_block=-1),
-                dict(time_block=2, persistent=1)]:
+                dict(row_fit=1, flat=1), dict(time_block=3), dict(time_block=-1)]:
         assert lbm.lbm_pool_slot_bytes(cfg, lbm.make_pool_tuning(**bad)) == 0, bad
     # two steps per launch changes the launches only, not a slot's memory
     assert lbm.lbm_pool_slot_bytes(cfg, lbm.make_pool_tuning(time_block=2)) == lbm.lbm_pool_slot_bytes(cfg)
+    # the tile-ordered persistent form keeps one 8-byte counter per two-step tile after the
+    # buffers of D2Q9 FP64 and FP32-deviation slots (rounded up to 256 bytes): FP64 column
+    # tiles of 128 x 16, FP32 whole-row tiles (row 300 -> 320 lanes, one sub-tile of 32 rows)
+    to = lbm.make_pool_tuning(time_block=2, persistent=1)
+    for kw, extra in [(dict(shape=(300, 1000)), 256 * 6),  # 3 x 63 tiles: 1512 bytes
+                      (dict(shape=(300, 1000), dtype="fp32_dev"), 256),  # 32 tiles
+                      (dict(shape=(600, 1000), dtype="fp32_dev"), 256 * 2),  # 2 x 32 column tiles of 512
+                      (dict(), 256),  # 1 x 2 tiles
+                      (dict(shape=(300, 1000), dtype="fp32_dev_mixed"), 0),
+                      (dict(lattice=27, shape=(16, 16, 16), dtype="fp32_dev"), 0)]:
+        c = _cfg(lbm, **kw)
+        assert lbm.lbm_pool_slot_bytes(c, to) == lbm.lbm_pool_slot_bytes(c) + extra, kw
     # row fit changes the thread mapping only, not a slot's memory
     assert lbm.lbm_pool_slot_bytes(cfg, lbm.make_pool_tuning(row_fit=1)) == lbm.lbm_pool_slot_bytes(cfg)
     h = ctypes.c_void_p()

@@ -6,10 +6,12 @@
     nodes (normwise over the samples: 1e-12 FP64, 1e-5 FP32);
   - the first 32 domains of the batched shear-wave workload (512 domains,
     seed 2303), 2000 steps, run together in one pool (one persistent launch;
-    and for FP64 two steps per launch): each equals the same domain run alone
+    and for FP64 two steps per launch, in 1000 launches and in one
+    tile-ordered persistent launch): each equals the same domain run alone
     bitwise and matches the oracle at 64 seeded nodes;
-  - all 512 domains of that workload in one persistent pool launch, and in
-    1000 two-step launches, equal their single-domain runs bitwise.
+  - all 512 domains of that workload in one persistent pool launch, in 1000
+    two-step launches, and in one tile-ordered two-step launch, equal their
+    single-domain runs bitwise.
 """
 import os
 
@@ -74,12 +76,16 @@ def _alone(r0, u0, tau, steps, dtype):
     return rho, u
 
 
-# pool tunings of the batched runs: one persistent launch per run, and two steps
-# per launch (the autotuner's choice on this workload and the serving default)
-C4_TUNINGS = {"persistent": dict(persistent=1), "two_step": dict(tile_x=64, tile_y=4, time_block=2)}
+# pool tunings of the batched runs: one persistent launch per run (one step per
+# grid-barrier phase), two steps per launch (the serving default), and every
+# two-step iteration in one tile-ordered persistent launch
+C4_TUNINGS = {"persistent": dict(persistent=1), "two_step": dict(tile_x=64, tile_y=4, time_block=2),
+              "tile_ordered": dict(tile_x=64, tile_y=4, time_block=2, persistent=1)}
+C4_LAUNCHES = {"persistent": lambda steps: 1, "two_step": lambda steps: steps // 2, "tile_ordered": lambda steps: 1}
 
 
-@pytest.mark.parametrize("dtype,form", [("fp64", "persistent"), ("fp32_dev", "persistent"), ("fp64", "two_step")])
+@pytest.mark.parametrize("dtype,form", [("fp64", "persistent"), ("fp32_dev", "persistent"), ("fp64", "two_step"),
+                                        ("fp64", "tile_ordered")])
 def test_c4_subset_full_steps_vs_oracle_and_alone(dtype, form):
     g = _gold("c4_subset_2000.npz")
     count, steps = int(g["count"]), int(g["steps"])
@@ -92,7 +98,7 @@ def test_c4_subset_full_steps_vs_oracle_and_alone(dtype, form):
         pool.run(steps)
         assert set(pool.poll()) == set(slots)
         # the form that ran: one launch per run, or one per two steps
-        assert pool.stats()["launches"] == (1 if form == "persistent" else steps // 2)
+        assert pool.stats()["launches"] == C4_LAUNCHES[form](steps)
         for k, (s, sp, (r0, u0)) in enumerate(zip(slots, specs, fields)):
             assert int(g[f"bad_{k}"]) == 0
             rho, u, _ = pool.moments(s)
@@ -118,7 +124,7 @@ def c4_alone_fp32():
     return specs, out
 
 
-@pytest.mark.parametrize("form", ["persistent", "two_step"])
+@pytest.mark.parametrize("form", ["persistent", "two_step", "tile_ordered"])
 def test_c4_all_512_pool_equals_alone_bitwise(c4_alone_fp32, form):
     lbm = _lbm()
     specs, alone = c4_alone_fp32
@@ -130,7 +136,7 @@ def test_c4_all_512_pool_equals_alone_bitwise(c4_alone_fp32, form):
             slots.append(pool.admit(r0, u0, sp["tau"], steps, dtype="fp32_dev"))
         pool.run(steps)
         assert set(pool.poll()) == set(slots)
-        assert pool.stats()["launches"] == (1 if form == "persistent" else steps // 2)
+        assert pool.stats()["launches"] == C4_LAUNCHES[form](steps)
         for s, sp, (ra, ua) in zip(slots, specs, alone):
             rho, u, d = pool.moments(s)
             assert d["steps"] == steps

@@ -228,13 +228,17 @@ def test_pool_retires_failed_slots():
             pool.moments(b)
 
 
-def test_pool_two_steps_per_launch_equals_alone():
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_pool_two_steps_per_launch_equals_alone(persistent):
     """time_block = 2: D2Q9 classes that hold enough nodes (2^22 FP32, 2^20
     FP64) advance two steps per launch (ragged widths, whole-row and column
     tiles in one class, both storage types, with and without the correction);
     odd runs end with a one-step launch, small classes take one step per
-    launch, and the buffer parity stays right across both forms.  Every slot
-    is bitwise its single-domain run; the launch count shows which form ran."""
+    launch, and the buffer parity stays right across both forms.  With
+    persistent = 1 the two-step classes take each run in one tile-ordered
+    launch (odd runs end inside it) and the other classes in one grid-barrier
+    launch.  Every slot is bitwise its single-domain run; the launch count
+    shows which form ran."""
     lbm = _lbm()
     specs = [((33, 70), "fp32_dev", True, 0.6), ((64, 64), "fp64", False, 0.55), ((17, 130), "fp32_dev", False, 0.52),
              ((100, 45), "fp64", True, 0.7), ((5, 300), "fp32_dev", False, 0.58), ((48, 513), "fp64", False, 0.51),
@@ -243,7 +247,7 @@ def test_pool_two_steps_per_launch_equals_alone():
     steps = 30
     fields = [workloads.random_field(shape, seed=100 + k, umax=0.1) for k, (shape, _, _, _) in enumerate(specs)]
     r3, u3 = workloads.taylor_green_3d(16, u0=0.05)
-    with lbm.Pool(2 * GiB, max_slots=16, tuning=lbm.make_pool_tuning(64, 4, 0, time_block=2)) as pool:
+    with lbm.Pool(2 * GiB, max_slots=16, tuning=lbm.make_pool_tuning(64, 4, persistent, time_block=2)) as pool:
         slots = [pool.admit(r, u, tau, steps, dtype=dt, bulk_correction=corr)
                  for (r, u), (_, dt, corr, tau) in zip(fields, specs)]
         s3 = pool.admit(r3, u3, 0.55, steps, dtype="fp32_dev")  # D3Q27: one step per launch
@@ -252,8 +256,8 @@ def test_pool_two_steps_per_launch_equals_alone():
         assert sorted(pool.poll()) == sorted(slots + [s3])
         # the FP32-corrected and FP64 classes (with the large slots): 5 + 3 two-step
         # launches, then twice 3 two-step and one one-step launch (odd runs); the two
-        # small D2Q9 classes and D3Q27: 30 each
-        assert pool.stats()["launches"] == 2 * (5 + 3 + 4 + 4) + 3 * 30
+        # small D2Q9 classes and D3Q27: 30 each; persistent: one launch per class and run
+        assert pool.stats()["launches"] == (5 * 4 if persistent else 2 * (5 + 3 + 4 + 4) + 3 * 30)
         for s, (r, u), (_, dt, corr, tau) in zip(slots, fields, specs):
             ra, ua, da, fa = alone(r, u, tau, steps, dt, corr)
             rb, ub, db = pool.moments(s, raise_on_domain=False)
@@ -363,7 +367,44 @@ def test_persistent_barrier_timeout_retires_slots_and_pool_recovers():
         assert np.array_equal(rho, ra) and np.array_equal(vel, ua)
 
 
-@pytest.mark.parametrize("form", ["rows", "fit", "flat", "persistent", "persistent-flat", "two-step"])
+def test_tile_ordered_timeout_retires_slots_and_pool_recovers():
+    """The timeout path of the tile-ordered persistent form, forced from the
+    host: four 1024^2 FP32 slots take 256 column tiles, one per workgroup, and
+    with a bound of 2 polls a tile's second iteration does not find all eight
+    neighbours done in time; the workgroup reports the timeout and every other
+    one leaves at its next wait.  poll reports LBM_EDEVICE, the slots are
+    retired with device_error, and a later run (one step, which waits for no
+    neighbour) completes and equals the single-domain run."""
+    lbm = _lbm()
+    fields = [workloads.shear_wave(1024, 1024, 0.05) for _ in range(4)]
+    tuning = lbm.make_pool_tuning(64, 4, persistent=1, time_block=2, spin_log2=1)
+    with lbm.Pool(GiB, max_slots=8, tuning=tuning) as pool:
+        slots = [pool.admit(r, u, 0.6, 40, dtype="fp32_dev") for r, u in fields]
+        pool.run(40)
+        assert pool.stats()["launches"] == 1
+        with pytest.raises(lbm.LBMError) as e:
+            pool.poll()
+        assert e.value.status == lbm.LBM_EDEVICE
+        for s in slots:
+            info = pool.slot_info(s)
+            assert info["device_error"] == 1 and info["finished"] == 1 and info["domain_error"] == 0
+            with pytest.raises(lbm.LBMError) as e2:
+                pool.moments(s, fields=False)
+            assert e2.value.status == lbm.LBM_EDEVICE
+        assert sorted(pool.poll()) == sorted(slots)
+        for s in slots:
+            pool.release(s)
+        r, u = fields[0]
+        s = pool.admit(r, u, 0.6, 1, dtype="fp32_dev")
+        pool.run(1)
+        assert pool.poll() == [s]
+        rho, vel, _ = pool.moments(s)
+        ra, ua, _, _ = alone(r, u, 0.6, 1, "fp32_dev", False)
+        assert np.array_equal(rho, ra) and np.array_equal(vel, ua)
+
+
+@pytest.mark.parametrize("form", ["rows", "fit", "flat", "persistent", "persistent-flat", "two-step",
+                                  "two-step-persistent"])
 def test_pool_kernels_store_only_inside_their_slots(form):
     """Every store of the pool kernels, padding lanes included, stays inside its
     slot's own buffers: canary bytes written into the arena around the slots
@@ -376,7 +417,8 @@ def test_pool_kernels_store_only_inside_their_slots(form):
     tun = {"rows": dict(tile_x=64, tile_y=4), "fit": dict(tile_x=64, tile_y=4, row_fit=1),
            "flat": dict(tile_x=64, tile_y=4, flat=1), "persistent": dict(persistent=1),
            "persistent-flat": dict(persistent=1, flat=1),
-           "two-step": dict(tile_x=64, tile_y=4, time_block=2)}[form]
+           "two-step": dict(tile_x=64, tile_y=4, time_block=2),
+           "two-step-persistent": dict(tile_x=64, tile_y=4, time_block=2, persistent=1)}[form]
     tuning = lbm.make_pool_tuning(**tun)
     # ragged widths (padding lanes), a D3Q27 cube, and D2Q9 slots large enough for two-step launches
     specs = [((33, 70), "fp32_dev"), ((17, 130), "fp32_dev"), ((9, 11, 13), "fp32_dev"), ((2100, 2048), "fp32_dev"),
@@ -430,6 +472,8 @@ def test_pool_kernels_store_only_inside_their_slots(form):
         assert sorted(pool.poll()) == sorted(slots)
         if form == "two-step":
             assert pool.stats()["launches"] == (3 + 3) * 2 + 12  # two D2Q9 classes two-step, D3Q27 one-step
+        if form == "two-step-persistent":
+            assert pool.stats()["launches"] == 3 * 2  # one launch per class and run
         for o, ln in regions:
             seg = buf[base + o: base + o + ln]
             assert bool(torch.all(seg == CAN)), (form, o, ln)
@@ -439,23 +483,32 @@ def test_pool_kernels_store_only_inside_their_slots(form):
             assert np.array_equal(ra, rb) and np.array_equal(ua, ub), (form, sh, dt)
 
 
+@pytest.mark.parametrize("form", ["launches", "tile_ordered", "tile_ordered_5wg"])
 @pytest.mark.parametrize("dtype", ["fp32_dev", "fp64"])
-def test_pool_two_step_mixed_step_counts_equal_alone(dtype):
+def test_pool_two_step_mixed_step_counts_equal_alone(dtype, form):
     """Two steps per launch when the slots of a class take different numbers of
     steps in one run: launch L covers, in two-step tiles, the slots with at
     least 2 L + 2 steps and then, in a one-step launch, those whose last step
-    is 2 L + 1, whole-row and column-tile slots alike.  Each slot equals its
-    single-domain run bitwise after every run."""
+    is 2 L + 1, whole-row and column-tile slots alike.  The tile-ordered
+    persistent form takes each run in one launch: a slot with s steps takes
+    ceil(s / 2) iterations, the last of one step when s is odd; with 5
+    workgroups each owns many tiles of several slots with different iteration
+    counts.  Each slot equals its single-domain run bitwise after every run."""
     lbm = _lbm()
+    extra = {"launches": {}, "tile_ordered": dict(persistent=1), "tile_ordered_5wg": dict(persistent=1, workgroups=5)}
+    tuning = lbm.make_pool_tuning(64, 4, time_block=2, time_rows=8, **extra[form])
     big = (2048, 2100) if dtype == "fp32_dev" else (1030, 1100)
     specs = [(big, 13), ((40, 70), 10), ((33, 100), 7), ((64, 512), 4), ((20, 700), 11), ((17, 129), 1),
              ((90, 64), 12)]
     fields = [workloads.random_field(shape, seed=400 + k, umax=0.1) for k, (shape, _) in enumerate(specs)]
-    with lbm.Pool(2 * GiB, max_slots=16, tuning=lbm.make_pool_tuning(64, 4, 0, time_block=2, time_rows=8)) as pool:
+    with lbm.Pool(2 * GiB, max_slots=16, tuning=tuning) as pool:
         slots = [pool.admit(r, u, 0.55, steps, dtype=dtype) for (r, u), (_, steps) in zip(fields, specs)]
         done = set()
         for k in (5, 100):  # the first run cuts every budget at 5 steps (odd), the second finishes them
+            launches = pool.stats()["launches"]
             pool.run(k)
+            if form != "launches":
+                assert pool.stats()["launches"] == launches + 1
             done |= set(pool.poll())
             for s, (r, u), (_, steps) in zip(slots, fields, specs):
                 n = min(steps, 5 if k == 5 else steps)
