@@ -165,12 +165,18 @@ def bench_batched(count: int, steps: int, dtypes=("fp32_dev", "fp64"), baseline:
                "tuning": tuning, "launches": st["launches"], "autotune_cached": rep.get("cached", False),
                "autotune_fastest": (rep.get("times") or [])[:4], "autotune_failed": rep.get("failed", [])}
         if tuning.get("time_block", 0) == 2:
-            # the same pool with one step per launch: what batching alone gives
-            one = dict(tuning, time_block=0)
+            # the other launch forms of the same pool: one step per launch (what batching
+            # alone gives), the same as one persistent launch per run with a grid barrier
+            # between steps, and two steps per launch with the other persistent setting
+            # (one launch per two steps, or one tile-ordered launch per run)
+            one = dict(tuning, time_block=0, persistent=0)
             one.pop("time_rows", None)
-            d1, st1 = timed_pool(one)
-            rec["pool_one_step_per_launch"] = {"solves_per_s": round(count / d1, 2), "seconds": round(d1, 4),
-                                               "launches": st1["launches"], "tuning": one}
+            other = dict(tuning, persistent=0 if tuning.get("persistent") else 1)
+            for key, tun in (("pool_one_step_per_launch", one), ("pool_one_step_grid_barrier", dict(one, persistent=1)),
+                             ("pool_two_step_launches" if other["persistent"] == 0 else "pool_tile_ordered", other)):
+                d1, st1 = timed_pool(tun)
+                rec[key] = {"solves_per_s": round(count / d1, 2), "seconds": round(d1, 4),
+                            "launches": st1["launches"], "tuning": tun}
         if baseline and dtype == dtypes[0]:
             doms_alone = [lbm.Domain(r0, u0, sp["tau"], dtype=dtype) for sp, (r0, u0) in zip(specs, fields)]
             torch.cuda.synchronize()

@@ -3,8 +3,10 @@
 For a set of domains (lattice, grid, storage), it times a short run of each
 candidate pool tuning -- workgroup tile shape (one node per thread; rows of
 tile_x nodes, rows fitted to each slot's width, or runs of consecutive nodes
-across rows) and launch form (one launch per step; on request also one
-persistent cooperative launch per run) -- on a scratch pool holding domains
+across rows) and launch form (one launch per step or per two steps; two-step
+classes also as one tile-ordered persistent launch per run; on request every
+shape also as one grid-barrier persistent launch per run) -- on a scratch
+pool holding domains
 of exactly those sizes, and returns the fastest.  Results do not depend on
 the tuning (the per-node arithmetic is the same in every kernel), so only
 time is compared.  Choices are cached in a JSON file keyed by the candidate
@@ -32,11 +34,14 @@ FLAT_TILES = [(64, 4), (64, 2), (64, 1)]  # flat mode: 256, 128 or 64 consecutiv
 
 def candidates(persistent: bool = False):
     """Tile shapes with one launch per step; with persistent, each also as one
-    cooperative launch per run.  The persistent form is left out by default:
-    its grid barrier cost 200-260 us per step on MI355X (every workgroup polls
-    one device-coherent counter and does an agent-scope release and acquire),
-    against a few microseconds between back-to-back launches, and it was the
-    slower form on every workload measured."""
+    cooperative launch per run with a grid barrier between steps.  That form
+    is left out by default: its grid barrier cost 200-260 us per step on
+    MI355X (every workgroup polls one device-coherent counter and does an
+    agent-scope release and acquire), against a few microseconds between
+    back-to-back launches, and it was the slower form on every workload
+    measured.  Two steps per launch come with three sweep lengths, and as one
+    tile-ordered persistent launch per run (no grid barrier; the two-step
+    classes only) with two."""
     forms = (0, 1) if persistent else (0,)
     rows = [dict(tile_x=tx, tile_y=ty, persistent=p) for (tx, ty) in TILES for p in forms]
     flat = [dict(tile_x=tx, tile_y=ty, persistent=p, flat=1) for (tx, ty) in FLAT_TILES for p in forms]
@@ -44,7 +49,8 @@ def candidates(persistent: bool = False):
     # two steps per launch for large D2Q9 classes (the tile and row fit serve the
     # one-step launches of the other classes), with three sweep lengths
     two = [dict(tile_x=64, tile_y=4, persistent=0, row_fit=1, time_block=2, time_rows=r) for r in (0, 16, 64)]
-    return rows + flat + fit + two
+    ordered = [dict(tile_x=64, tile_y=4, persistent=1, row_fit=1, time_block=2, time_rows=r) for r in (0, 64)]
+    return rows + flat + fit + two + ordered
 
 
 def signature(domains) -> str:
@@ -118,7 +124,7 @@ def tune_pool(domains, steps: int = 20, cands=None, cache_path: str | None = DEF
     "failed", each candidate that the library refused or that raised an error
     while it ran (for instance a persistent run whose grid barrier timed out),
     with the error text."""
-    key = f"candidates-v6|{_device_key()}|{signature(domains)}" if cands is None else \
+    key = f"candidates-v7|{_device_key()}|{signature(domains)}" if cands is None else \
         f"custom-{hashlib.sha256(json.dumps(cands, sort_keys=True).encode()).hexdigest()[:12]}|{_device_key()}|" \
         f"{signature(domains)}"
     cache = _load_cache(cache_path) if cache_path else {}

@@ -42,11 +42,15 @@ def test_all_candidates_failing_raises(monkeypatch):
 
 def test_candidate_sets():
     default = autotune.candidates()
-    assert default and all(c["persistent"] == 0 for c in default)
+    # persistent by default: only the tile-ordered two-step form (no grid barrier)
+    assert default and all(c["persistent"] == 0 or c.get("time_block") == 2 for c in default)
+    ordered = [c for c in default if c["persistent"] == 1]
+    assert ordered and sorted(c["time_rows"] for c in ordered) == [0, 64]
     both = autotune.candidates(persistent=True)
-    two = [c for c in default if c.get("time_block") == 2]  # no persistent form
+    two = [c for c in default if c.get("time_block") == 2]  # no grid-barrier variant of these
     assert two and len(both) == 2 * len(default) - len(two)
-    assert sorted(map(str, (c for c in both if c["persistent"] == 0))) == sorted(map(str, default))
+    assert sorted(map(str, (c for c in both if c["persistent"] == 0 or c.get("time_block") == 2))) == \
+        sorted(map(str, default))
 
 
 def test_custom_candidates_do_not_share_the_default_cache(monkeypatch, tmp_path):
