@@ -103,15 +103,42 @@ def test_two_step_ragged_large_bitwise():
 
 @pytest.mark.parametrize("dtype", ["fp32_dev", "fp64"])
 def test_two_step_full_size_bitwise(dtype):
-    """D2Q9 4096^2 (the large 2-D workload), 4 steps in default tiles."""
+    """D2Q9 4096^2 (the large 2-D workload), 4 steps with the default
+    two-step kernel (columns of 512 for FP32 storage, 128 for FP64) against
+    one step per launch."""
     lbm = _lbm()
     rho0, u0 = workloads.random_field((4096, 4096), seed=50, umax=0.1)
-    with lbm.Domain(rho0, u0, 0.51, dtype=dtype, tuning=lbm.make_tuning(time_block=2)) as a:
+    with lbm.Domain(rho0, u0, 0.51, dtype=dtype) as a:
+        info = a.launch_info()
+        assert info["kernel"] == "two_step", info
+        assert info["time_cols"] == (512 if dtype == "fp32_dev" else 128), info
         a.step(4)
         fa = a.populations()
-    with lbm.Domain(rho0, u0, 0.51, dtype=dtype) as b:
+    with lbm.Domain(rho0, u0, 0.51, dtype=dtype, tuning=lbm.make_tuning(time_block=1)) as b:
         b.step(4)
         assert np.array_equal(fa, b.populations())
+
+
+def test_two_step_fp32_ragged_matches_oracle():
+    """The two-step kernel with FP32 deviation storage against the FP64
+    oracle on a ragged width (165: column tiles of 128, the last of 37) and
+    ragged rows (45 in tiles of 8), with and without the correction, 60
+    steps."""
+    lbm = _lbm()
+    rho0, u0 = workloads.random_field((45, 165), seed=77, umax=0.1)
+    for corr in (False, True):
+        r_ref, u_ref, bad = oracle.run(rho0, u0, 0.53, 60, corr="min" if corr else "off")
+        assert bad == 0
+        with lbm.Domain(rho0, u0, 0.53, dtype="fp32_dev", bulk_correction=corr,
+                        tuning=lbm.make_tuning(time_block=2, time_rows=8)) as d:
+            info = d.launch_info()
+            assert info["kernel"] == "two_step" and info["time_cols"] == 128, info
+            d.step(60)
+            rho, u, diag = d.moments()
+        er = np.max(np.abs(rho - r_ref)) / np.max(np.abs(r_ref))
+        eu = np.max(np.abs(u - u_ref)) / np.max(np.abs(u_ref))
+        print(f"[parity] D2Q9 165x45 two-step FP32 corr={corr} 60 steps: rel err rho {er:.3e} u {eu:.3e}", flush=True)
+        assert er < 1e-5 and eu < 1e-5
 
 
 D1Q3_CASES = [  # nx, dtype, correction, K, step chunks
