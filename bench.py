@@ -197,8 +197,12 @@ def bench_batched(count: int, steps: int, dtypes=("fp32_dev", "fp64"), baseline:
     return out
 
 
+SERVE_TUNINGS = {"default": None, "64x4": dict(tile_x=64, tile_y=4, time_block=2),
+                 "fit": dict(tile_x=64, tile_y=4, row_fit=1, time_block=2)}
+
+
 def bench_serving(n_requests: int, rate: float, light_requests: int, policies=("swf",),
-                  saturate_bytes: float = 512e6) -> dict:
+                  saturate_bytes: float = 512e6, tuning: str = "default") -> dict:
     """Serving: Poisson request stream (seed 8163) mixing D2Q9 64^2..1024^2 and
     D3Q27 32^3..192^3 (log-uniform sides), Taylor-Green or shear-wave starts,
     u0 ~ U[0.01, 0.15], tau ~ U[0.5001, 0.6], 200..5000 steps, FP32 storage;
@@ -213,7 +217,9 @@ def bench_serving(n_requests: int, rate: float, light_requests: int, policies=("
     trace = workloads.serving_trace(n_requests=n_requests, rate=rate, seed=8163)
 
     def pooled(tr, policy):
-        be = serve.PoolBackend(96 << 30, max_slots=512)
+        from paper_2303_08163_amd import lbm
+        tk = SERVE_TUNINGS[tuning]
+        be = serve.PoolBackend(96 << 30, max_slots=512, tuning=None if tk is None else lbm.make_pool_tuning(**tk))
         try:
             kw = {"policy": "swf", "lookahead": 1 << 30, "saturate_bytes": saturate_bytes} if policy == "swf" \
                 else {"policy": "fifo", "lookahead": 8}
@@ -701,6 +707,8 @@ def main() -> int:
     ap.add_argument("--serve-policies", default="swf", help="comma list of swf, fifo (continuous batching policies)")
     ap.add_argument("--serve-saturate", type=float, default=512e6,
                     help="swf: per-step HBM bytes of the running requests at which admission pauses")
+    ap.add_argument("--serve-tuning", default="default", choices=sorted(SERVE_TUNINGS),
+                    help="pool tuning of the continuous-batching server (default: the backend's own)")
     args = ap.parse_args()
     sections = set(args.sections.split(","))
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -813,7 +821,8 @@ def main() -> int:
         progress("batched done")
     if "serving" in sections:
         out["serving"] = bench_serving(args.serve_requests, args.serve_rate, args.serve_light_requests,
-                                       tuple(args.serve_policies.split(",")), args.serve_saturate)
+                                       tuple(args.serve_policies.split(",")), args.serve_saturate,
+                                       args.serve_tuning)
     if "wave" in sections:
         out["wave"] = bench_wave()
         progress("wave done")
