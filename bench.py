@@ -123,7 +123,7 @@ def cpu_baseline(budget_s: float = 12.0) -> dict:
 
 
 def bench_batched(count: int, steps: int, dtypes=("fp32_dev", "fp64"), baseline: bool = True,
-                  fixed_tuning: dict | None = None) -> dict:
+                  fixed_tuning: dict | None = None, other_forms: bool = True) -> dict:
     """Batched workload: `count` independent D2Q9 shear-wave domains (Nx, Ny
     uniform in 32..512, amplitude U[0.01, 0.2], nu log-uniform 1e-5..1e-1),
     `steps` steps each, all advanced together by one pool kernel launch per
@@ -164,7 +164,7 @@ def bench_batched(count: int, steps: int, dtypes=("fp32_dev", "fp64"), baseline:
         rec = {"solves_per_s": round(count / dt, 2), "seconds": round(dt, 4), "mlups": round(nodes * steps / dt / 1e6, 1),
                "tuning": tuning, "launches": st["launches"], "autotune_cached": rep.get("cached", False),
                "autotune_fastest": (rep.get("times") or [])[:4], "autotune_failed": rep.get("failed", [])}
-        if tuning.get("time_block", 0) == 2:
+        if tuning.get("time_block", 0) == 2 and other_forms:
             # the other launch forms of the same pool: one step per launch (what batching
             # alone gives), the same as one persistent launch per run with a grid barrier
             # between steps, and two steps per launch with the other persistent setting
@@ -698,6 +698,8 @@ def main() -> int:
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--no-batch-baseline", action="store_true",
                     help="skip the one-domain-per-launch baseline of the batched section")
+    ap.add_argument("--no-batch-forms", action="store_true",
+                    help="batched: time the chosen tuning only, not the pool's other launch forms")
     ap.add_argument("--batch-tuning", default="",
                     help="TXxTY[,persistent][,flat][,fit][,t2]: fixed pool tile instead of the autotuner's "
                          "choice (t2: two steps per launch)")
@@ -817,7 +819,7 @@ def main() -> int:
             if "t2" in parts[1:]:
                 fixed["time_block"] = 2
         out["batched"] = bench_batched(args.batch_count, args.batch_steps, baseline=not args.no_batch_baseline,
-                                       fixed_tuning=fixed)
+                                       fixed_tuning=fixed, other_forms=not args.no_batch_forms)
         progress("batched done")
     if "serving" in sections:
         out["serving"] = bench_serving(args.serve_requests, args.serve_rate, args.serve_light_requests,
