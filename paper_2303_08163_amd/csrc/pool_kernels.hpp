@@ -27,6 +27,7 @@
 
 #include "kernels.hpp"
 #include "kernels_t2.hpp"
+#include "tile_deps.hpp"
 
 namespace lbm {
 
@@ -256,17 +257,11 @@ __global__ __launch_bounds__(256) void k_pool_persistent(PoolRunArgs a) {
 // Each is nevertheless bounded like the grid barrier's: past the bound, or
 // once another workgroup has reported a timeout, the workgroup leaves.
 
-__device__ __forceinline__ int df_wrap(int c, int n) {
-    c %= n;
-    return c < 0 ? c + n : c;
-}
-
 // Wait until the tiles within two nodes of tile tt of a slot (whole-row tiles
 // of rr rows when w > 0, else column tiles of tx x rows) have counters >=
-// need.  Wavefront 0 polls: lane ix + 5 iy the tile holding column
-// x0 - 2, x0 - 1, x0, x0 + nv, x0 + nv + 1 (by ix) and row y0 - 2, y0 - 1,
-// y0, y1, y1 + 1 (by iy) -- every tile that the dilated box [x0 - 2, x0 + nv
-// + 2) x [y0 - 2, y1 + 2) meets, some of them repeatedly.  Wavefront 0
+// need.  Wavefront 0 polls, lane l the candidate df_neighbour(l, ...) (every
+// tile that the dilated box [x0 - 2, x0 + nv + 2) x [y0 - 2, y1 + 2) meets,
+// some of them repeatedly; tile_deps.hpp).  Wavefront 0
 // then acquires at agent scope (dropping stale L1 and L2 lines), and the
 // workgroup barrier orders the other wavefronts' loads after it.  Returns
 // false (the same in every thread) when the wait timed out or another
@@ -275,22 +270,8 @@ __device__ __forceinline__ bool df_wait(const PoolRunArgs &a, const int64_t *tdo
                                         int tx, int rows, int tt, int64_t need) {
     __shared__ int df_ok;
     if (threadIdx.x < 64) {  // wavefront 0, all lanes active
-        const int l = (int)threadIdx.x, ix = l % 5, iy = l / 5;
-        int idx = -1;
-        if (w > 0) {
-            if (l < 5) {
-                const int y0 = tt * rr, y1 = min(y0 + rr, ny);
-                const int ry[5] = {y0 - 2, y0 - 1, y0, y1, y1 + 1};
-                idx = df_wrap(ry[ix], ny) / rr;
-            }
-        } else if (l < 25) {
-            const int tiles_x = (nx + tx - 1) / tx;
-            const int x0 = (tt % tiles_x) * tx, nv = min(tx, nx - x0);
-            const int y0 = (tt / tiles_x) * rows, y1 = min(y0 + rows, ny);
-            const int cx[5] = {x0 - 2, x0 - 1, x0, x0 + nv, x0 + nv + 1};
-            const int ry[5] = {y0 - 2, y0 - 1, y0, y1, y1 + 1};
-            idx = (df_wrap(ry[iy], ny) / rows) * tiles_x + df_wrap(cx[ix], nx) / tx;
-        }
+        const int l = (int)threadIdx.x;
+        const int idx = df_neighbour(l, nx, ny, w, rr, tx, rows, tt);
         bool ready = idx < 0 || __hip_atomic_load(tdone + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
         long long spins = 0;
         int good = 1;
