@@ -63,7 +63,7 @@ def multistep_source_digest() -> str:
     while it matches the profile's."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2303_08163_amd", "csrc")
-    for fn in ("node.hpp", "kernels.hpp", "kernels_t2.hpp", "pool_kernels.hpp"):
+    for fn in ("node.hpp", "kernels.hpp", "kernels_t2.hpp", "pool_kernels.hpp", "tile_deps.hpp"):
         with open(os.path.join(csrc, fn), "rb") as f:
             h.update(fn.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
