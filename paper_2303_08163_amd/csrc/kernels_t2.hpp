@@ -427,69 +427,95 @@ __device__ __forceinline__ void two_step_rows_tile(const Step2Args &a, int tile,
     const int cc[3] = {x + 1 == a.nx ? 1 : x + 2, x + 1, x == 0 ? a.nx : x};
     auto wrap_row = [&](int r) { return r < 0 ? r + a.ny : (r >= a.ny ? r - a.ny : r); };
 
-    // sweep offset k: step 1 at row y0 - 1 + k from f, then (after the barrier)
-    // the loads of row y0 + 1 + k into f and step 2 at row y0 - 2 + k
-    auto sweep_row = [&](T (&f)[9], int k) {
-        const int r = y0 - 1 + k;
-        const bool work = k < my_sweep;  // uniform per wavefront
-        if (work) {
-            const bool bad1 = collide_dt<2, DT, CORR, EQ>(f, a.relax);
-            raise_flag(a.flag, bad1 && valid);
+    // The sweep in intervals between barriers, as in two_step_tile's float
+    // form: interval k holds step 1 at offset k (row y0 - 1 + k) into ring slot
+    // k mod 4 and step 2 at row y0 - 3 + k from the slots k - 3 .. k - 1, the two
+    // collisions in one block; the domain checks are raised once at the end.
+    // A wavefront's sub-tile takes my_sweep offsets (fewer, or none, at the end
+    // of the slot); every wavefront passes R + 2 barriers, one after each of
+    // the intervals 0 .. R + 1.
+    bool bad_any = false;
+    auto interval = [&](T (&f)[9], int k, auto do1_, auto do2_) {
+        constexpr bool DO1 = decltype(do1_)::value, DO2 = decltype(do2_)::value;
+        T g[9];
+        if constexpr (DO2) {
+#pragma unroll
+            for (int cy = 0; cy < 3; ++cy) {
+                const T *srow = ring + (size_t)((k - 1 - cy) & (kT2Ring - 1)) * 9 * w1;
+#pragma unroll
+                for (int cx = 0; cx < 3; ++cx)
+                    g[cx + 3 * cy] = srow[(cx + 3 * cy) * w1 + cc[cx]];
+            }
+        }
+        bool bad1 = false, bad2 = false;
+        if constexpr (DO1)
+            bad1 = collide_dt<2, DT, CORR, EQ>(f, a.relax);
+        if constexpr (DO2)
+            bad2 = collide_dt<2, DT, CORR, EQ>(g, a.relax);
+        // (an empty asm uses both results, so that neither collision is sunk into its
+        // lanes' conditional store; no instruction, values unchanged)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            if constexpr (DO1)
+                asm("" : "+v"(f[i]));
+            if constexpr (DO2)
+                asm("" : "+v"(g[i]));
+        }
+        bad_any |= (bad1 | bad2) && valid;
+        if constexpr (DO2) {
+            if (valid) {
+                const int y = y0 - 3 + k;
+                const uint32_t ob = (uint32_t)(x * (int)sizeof(T));
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    char *base = reinterpret_cast<char *>(dst + (int64_t)y * a.rs + (int64_t)i * a.ps);
+                    if constexpr (NT)
+                        __builtin_nontemporal_store(g[i], reinterpret_cast<T *>(base + ob));
+                    else
+                        *reinterpret_cast<T *>(base + ob) = g[i];
+                }
+            }
+        }
+        if constexpr (DO1) {
             T *slot = ring + (size_t)(k & (kT2Ring - 1)) * 9 * w1;
             if (valid) {
 #pragma unroll
                 for (int i = 0; i < 9; ++i)
                     slot[i * w1 + t + 1] = f[i];
             }
+            if (k + 2 < my_sweep)  // two offsets of loads in flight
+                pull_row_d2q9<T>(src, a.ny, a.ps, a.rs, wrap_row(y0 + 1 + k), xb, f);
         }
-        // slot k + 1 (written at the next offset) is slot k - 3, last read by
-        // step 2 at offset k - 1, before this barrier
-        __syncthreads();
-        if (work) {
-            if (r + 2 <= y1)
-                pull_row_d2q9<T>(src, a.ny, a.ps, a.rs, wrap_row(r + 2), xb, f);
-            if (k >= 2) {
-                const int y = r - 1;
-                T g[9];
-#pragma unroll
-                for (int cy = 0; cy < 3; ++cy) {
-                    const T *srow = ring + (size_t)((k - cy) & (kT2Ring - 1)) * 9 * w1;
-#pragma unroll
-                    for (int cx = 0; cx < 3; ++cx)
-                        g[cx + 3 * cy] = srow[(cx + 3 * cy) * w1 + cc[cx]];
-                }
-                const bool bad2 = collide_dt<2, DT, CORR, EQ>(g, a.relax);
-                raise_flag(a.flag, bad2 && valid);
-                if (valid) {
-                    const uint32_t ob = (uint32_t)(x * (int)sizeof(T));
-#pragma unroll
-                    for (int i = 0; i < 9; ++i) {
-                        char *base = reinterpret_cast<char *>(dst + (int64_t)y * a.rs + (int64_t)i * a.ps);
-                        if constexpr (NT)
-                            __builtin_nontemporal_store(g[i], reinterpret_cast<T *>(base + ob));
-                        else
-                            *reinterpret_cast<T *>(base + ob) = g[i];
-                    }
-                }
-            }
-        }
+        // slot k + 1 (written in the next interval) is slot k - 3, last read here
+        if (k <= R + 1)
+            __syncthreads();
     };
+    using Y = std::true_type;
+    using N = std::false_type;
 
-    // every wavefront takes R + 2 offsets (the barriers of the workgroup)
-    T fa[9], fb[9];
-    if (active) {
+    int k = 0;
+    if (active) {  // uniform per wavefront; my_sweep >= 3
+        T fa[9], fb[9];
         pull_row_d2q9<T>(src, a.ny, a.ps, a.rs, wrap_row(y0 - 1), xb, fa);
         pull_row_d2q9<T>(src, a.ny, a.ps, a.rs, y0, xb, fb);
+        interval(fa, 0, Y{}, N{});
+        interval(fb, 1, Y{}, N{});
+        interval(fa, 2, Y{}, N{});
+        for (k = 3;;) {
+            if (k >= my_sweep)
+                break;
+            interval(fb, k, Y{}, Y{});
+            if (++k >= my_sweep)
+                break;
+            interval(fa, k, Y{}, Y{});
+            ++k;
+        }
+        interval(fa, k, N{}, Y{});  // k = my_sweep: the last step 2
+        ++k;
     }
-    const int nsweep = R + 2;
-    for (int k = 0;;) {
-        sweep_row(fa, k);
-        if (++k >= nsweep)
-            break;
-        sweep_row(fb, k);
-        if (++k >= nsweep)
-            break;
-    }
+    for (; k <= R + 1; ++k)  // the workgroup's remaining barriers
+        __syncthreads();
+    raise_flag(a.flag, bad_any);
 }
 
 template <int DT, bool CORR, int EQ = kEqEntropic, bool NT = false>
