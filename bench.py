@@ -142,7 +142,7 @@ def bench_batched(count: int, steps: int, dtypes=("fp32_dev", "fp64"), baseline:
         if fixed_tuning is not None:
             tuning, rep = dict(fixed_tuning), {"cached": False, "fixed": True}
         else:
-            tuning, rep = autotune.tune_pool(doms, steps=10)
+            tuning, rep = autotune.tune_pool(doms, steps=100)
         def timed_pool(tuning):
             tun = lbm.make_pool_tuning(**tuning)
             arena = lbm.lbm_pool_table_bytes(count) + sum(

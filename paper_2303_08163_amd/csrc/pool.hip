@@ -140,7 +140,7 @@ static PoolStepFn pool_kernel(int dtype, bool corr, bool persistent) {
 // Two steps per launch in pools.  One launch has one workgroup shape.  FP32
 // storage: 512 threads; a slot whose row, rounded up to 64, fits them runs as
 // whole-row tiles (two_step_rows_tile: floor(512 / w) sub-tiles of w lanes,
-// each sweeping 32 rows by default), wider slots as column tiles of 512.  Whole
+// each sweeping its rows), wider slots as column tiles of 512.  Whole
 // rows need no halo columns: with the earlier 128 x 16 column tiles the
 // batched workload's narrow rows read 1.46x the algorithmic bytes (the column
 // halos' cache lines and the 2 + 2 extra rows of every 16), with whole rows
@@ -151,9 +151,14 @@ static PoolStepFn pool_kernel(int dtype, bool corr, bool persistent) {
 // in flight that only wider workgroups keep.
 static int t2_block(int dtype) { return dtype == kF64 ? 192 : 512; }
 static int t2_cols(int dtype) { return dtype == kF64 ? 128 : 512; }
-static int t2_rows_default(int dtype) { return dtype == kF64 ? 16 : 32; }
+// Rows per sweep: 16 (measured on the batched workload, FP32 with two-step launches: 16
+// rows 830 solves/s, 12: 821, 24: 821, 32: 809, 48: 778; FP64: 8 to 16 within 1 %, 32:
+// 452), except 32 for FP32 in the tile-ordered persistent form (622 against 593 with 16).
+static int t2_rows_default(int dtype, bool persistent) { return dtype == kF64 || !persistent ? 16 : 32; }
 static bool t2_whole_rows(int dtype) { return dtype != kF64; }
-static int t2_rows(const lbm_pool_tuning &t, int dtype) { return t.time_rows > 0 ? t.time_rows : t2_rows_default(dtype); }
+static int t2_rows(const lbm_pool_tuning &t, int dtype) {
+    return t.time_rows > 0 ? t.time_rows : t2_rows_default(dtype, t.persistent != 0);
+}
 
 // Two-step tiling of a D2Q9 slot: whole-row tiles of sub sub-tiles of R rows
 // each when the padded row fits the workgroup (w > 0, FP32 storage), else
