@@ -419,8 +419,8 @@ typedef struct lbm_pool_tuning {
                            classes of such a pool run persistent as with time_block 0.
                            0 or 1: one step per launch */
     int32_t time_rows;  /* time_block = 2: rows swept by each whole-row sub-tile and each column
-                           tile (0 = default: 16; 32 for FP32 in the tile-ordered persistent
-                           form; at most 4096) */
+                           tile (0 = default: 16; in the tile-ordered persistent form 32
+                           for FP32, 64 for FP64; at most 4096) */
     int32_t spin_log2;  /* persistent form: a workgroup waits at most 2^spin_log2 polls of the
                            grid barrier's counter, or of its tile's neighbours' counters,
                            before it reports a timeout (1..40; 0 = the

@@ -151,10 +151,16 @@ static PoolStepFn pool_kernel(int dtype, bool corr, bool persistent) {
 // in flight that only wider workgroups keep.
 static int t2_block(int dtype) { return dtype == kF64 ? 192 : 512; }
 static int t2_cols(int dtype) { return dtype == kF64 ? 128 : 512; }
-// Rows per sweep: 16 (measured on the batched workload, FP32 with two-step launches: 16
+// Rows per sweep, measured on the batched workload: 16 with two-step launches (FP32: 16
 // rows 830 solves/s, 12: 821, 24: 821, 32: 809, 48: 778; FP64: 8 to 16 within 1 %, 32:
-// 452), except 32 for FP32 in the tile-ordered persistent form (622 against 593 with 16).
-static int t2_rows_default(int dtype, bool persistent) { return dtype == kF64 || !persistent ? 16 : 32; }
+// 452); in the tile-ordered persistent form, where longer sweeps mean fewer tiles to
+// wait for, 32 for FP32 (664-670 against 629-639 with 16, 613-618 with 64) and 64 for
+// FP64 (413 against 385 with 16).
+static int t2_rows_default(int dtype, bool persistent) {
+    if (!persistent)
+        return 16;
+    return dtype == kF64 ? 64 : 32;
+}
 static bool t2_whole_rows(int dtype) { return dtype != kF64; }
 static int t2_rows(const lbm_pool_tuning &t, int dtype) {
     return t.time_rows > 0 ? t.time_rows : t2_rows_default(dtype, t.persistent != 0);

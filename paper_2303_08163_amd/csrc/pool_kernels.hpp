@@ -311,9 +311,13 @@ __device__ __forceinline__ int df_slot(const PoolRunArgs &a, int t) {
 
 // Grid: G <= resident workgroups of t2_threads(t2_tx, elem) threads, the
 // larger LDS need of the two tile forms; a.tile_start holds the two-step tile
-// counts.
+// counts.  At least four wavefronts per SIMD: the LDS of FP32 tiles admits two
+// 512-thread workgroups per compute unit, and the registers the compiler chose
+// otherwise (140) left one (batched workload, FP32: 666 against 622 solves/s,
+// with 32 bytes of spills per lane; FP64, held to four workgroups of three
+// wavefronts by its LDS, unchanged).
 template <int DT, bool CORR, bool NT>
-__global__ __launch_bounds__(512) void k_pool_df2(PoolRunArgs a) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_pool_df2(PoolRunArgs a) {
     using T = store_t<DT>;
     const int G = (int)gridDim.x;
     const int L = xcd_tile((int)blockIdx.x, G);

@@ -260,9 +260,9 @@ def test_pool_host_logic(lbm):
     assert lbm.lbm_pool_slot_bytes(cfg, lbm.make_pool_tuning(time_block=2)) == lbm.lbm_pool_slot_bytes(cfg)
     # the tile-ordered persistent form keeps one 8-byte counter per two-step tile after the
     # buffers of D2Q9 FP64 and FP32-deviation slots (rounded up to 256 bytes): FP64 column
-    # tiles of 128 x 16, FP32 whole-row tiles (row 300 -> 320 lanes, one sub-tile of 32 rows)
+    # tiles of 128 x 64, FP32 whole-row tiles (row 300 -> 320 lanes, one sub-tile of 32 rows)
     to = lbm.make_pool_tuning(time_block=2, persistent=1)
-    for kw, extra in [(dict(shape=(300, 1000)), 256 * 6),  # 3 x 63 tiles: 1512 bytes
+    for kw, extra in [(dict(shape=(300, 1000)), 256 * 2),  # 3 x 16 tiles: 384 bytes
                       (dict(shape=(300, 1000), dtype="fp32_dev"), 256),  # 32 tiles
                       (dict(shape=(600, 1000), dtype="fp32_dev"), 256 * 2),  # 2 x 32 column tiles of 512
                       (dict(), 256),  # 1 x 2 tiles
