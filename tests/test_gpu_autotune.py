@@ -31,3 +31,19 @@ def test_autotune_small_batch(tmp_path):
             results.append([pool.moments(k)[:2] for k in slots])
     for (ra, ua), (rb, ub) in zip(*results):
         assert np.array_equal(ra, rb) and np.array_equal(ua, ub)
+
+
+def test_default_candidates_all_run(tmp_path):
+    """Every candidate of the default set runs on a mix that reaches each launch
+    form: a D2Q9 FP32 class large enough for two steps per launch (so that the
+    two-step and tile-ordered candidates take those forms), ragged small D2Q9
+    slots in the same class, and a D3Q27 class (one step per launch, or the
+    grid-barrier form for the persistent candidates).  None is refused or fails."""
+    from paper_2303_08163_amd import autotune
+    doms = [(9, (2048, 2100), "fp32_dev"), (9, (100, 37), "fp32_dev"), (9, (513, 65), "fp32_dev"),
+            (27, (40, 33, 21), "fp32_dev")]
+    cands = autotune.candidates()
+    assert any(c.get("persistent") and c.get("time_block") == 2 for c in cands)
+    best, rep = autotune.tune_pool(doms, steps=6, cands=cands, cache_path=str(tmp_path / "tune.json"))
+    assert rep["failed"] == [], rep["failed"]
+    assert len(rep["times"]) == len(cands) and best in cands

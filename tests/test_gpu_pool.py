@@ -54,10 +54,9 @@ def alone_results():
 def test_pool_mix_equals_alone_bitwise(alone_results, persistent, tile, chunk):
     lbm = _lbm()
     if tile[0] == "two":
-        if persistent:
-            pytest.skip("two steps per launch are not with the persistent form")
-        # uneven step counts: runs take the one-step path where slots differ
-        tun = lbm.make_pool_tuning(tile[1], tile[2], 0, time_block=2)
+        # every class here is below the two-step size threshold, so the tuning
+        # falls back to one step per launch (persistent: the grid-barrier form)
+        tun = lbm.make_pool_tuning(tile[1], tile[2], persistent, time_block=2)
     elif tile[0] == "flat":
         tun = lbm.make_pool_tuning(tile[1], tile[2], persistent, flat=1)
     elif tile[0] in ("fit", "fit-planes"):
