@@ -61,19 +61,28 @@ __host__ __device__ __forceinline__ cplx csub(cplx a, cplx b) { return {a.re - b
 __host__ __device__ __forceinline__ cplx cscale(double s, cplx a) { return {s * a.re, s * a.im}; }
 __host__ __device__ __forceinline__ double cabs1(cplx a) { return fabs(a.re) + fabs(a.im); }
 __host__ __device__ __forceinline__ double cabs(cplx a) { return hypot(a.re, a.im); }
-__host__ __device__ __forceinline__ cplx csqrt_(cplx a) {
-    // principal square root, written to avoid cancellation
-    const double r = cabs(a);
-    if (r == 0.0)
-        return {0.0, 0.0};
-    const double t = sqrt(0.5 * (r + fabs(a.re)));
-    if (a.re >= 0.0)
-        return {t, a.im / (2.0 * t)};
-    return {fabs(a.im) / (2.0 * t), a.im >= 0.0 ? t : -t};
+// c x + s y for real c and complex s, as three-term fused sums per component
+// (one multiplication and two fused multiply-adds each): the form in which
+// rotations are applied.
+__host__ __device__ __forceinline__ cplx crot(double c, cplx x, cplx s, cplx y) {
+    return {fma(c, x.re, fma(s.re, y.re, -(s.im * y.im))), fma(c, x.im, fma(s.re, y.im, s.im * y.re))};
 }
-__host__ __device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
-    const double d = fma(b.re, b.re, b.im * b.im);
-    return {fma(a.re, b.re, a.im * b.im) / d, fma(a.im, b.re, -a.re * b.im) / d};
+// w + conj(a) b and w - a b as two fused multiply-adds per component.
+__host__ __device__ __forceinline__ cplx cmulc_add(cplx a, cplx b, cplx w) {
+    return {fma(a.re, b.re, fma(a.im, b.im, w.re)), fma(a.re, b.im, fma(-a.im, b.re, w.im))};
+}
+__host__ __device__ __forceinline__ cplx cmul_sub(cplx a, cplx b, cplx w) {
+    return {fma(-a.re, b.re, fma(a.im, b.im, w.re)), fma(-a.re, b.im, fma(-a.im, b.re, w.im))};
+}
+// Principal square root of z for O(1) entries: the modulus from the squared
+// norm (no rescaling), one division, the sign cases selected (z = 0 gives 0).
+__host__ __device__ __forceinline__ cplx csqrt_sq(cplx z) {
+    const double r = sqrt(fma(z.re, z.re, z.im * z.im));
+    const double t = sqrt(0.5 * (r + fabs(z.re)));
+    const double h = 0.5 * z.im / (t > 0.0 ? t : 1.0);  // im / (2 t)
+    const cplx pos = {t, h}, neg = {fabs(h), z.im >= 0.0 ? t : -t};
+    const cplx w = z.re >= 0.0 ? pos : neg;
+    return t > 0.0 ? w : cplx{0.0, 0.0};
 }
 
 // Relaxation omega = 2 beta at velocity u (lattice units, 2 beta = 1 / tau
@@ -115,6 +124,10 @@ __host__ __device__ __forceinline__ void vn_matrix(double tau, const double (&u)
         }
     }
     const double omega = vn_omega<DIM, EQ, CORR>(tau, u);
+    // E_ii = exp(-i c_i . k) = ex^(-c_x) ey^(-c_y) with ex = exp(i k_x),
+    // ey = exp(i k_y): two sine-cosine pairs, products for the diagonal moves
+    const cplx ex = {cos(k[0]), sin(k[0])};
+    const cplx ey = DIM == 2 ? cplx{cos(k[1]), sin(k[1])} : cplx{1.0, 0.0};
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         const int cx = i % 3 - 1, cy = DIM == 2 ? i / 3 - 1 : 0;
@@ -133,9 +146,9 @@ __host__ __device__ __forceinline__ void vn_matrix(double tau, const double (&u)
             if (DIM == 2)
                 Uy = gx * dg[1][cy + 1];
         }
-        // E_ii = exp(-i c_i . k)
-        const double phase = -(cx * k[0] + (DIM == 2 ? cy * k[1] : 0.0));
-        const cplx e = {cos(phase), sin(phase)};
+        const cplx fx = cx < 0 ? ex : cplx{ex.re, -ex.im};  // ex^(-c_x) for c_x != 0
+        const cplx fy = cy < 0 ? ey : cplx{ey.re, -ey.im};
+        const cplx e = cx == 0 ? (cy == 0 ? cplx{1.0, 0.0} : fy) : (cy == 0 ? fx : cmul(fx, fy));
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             const int jx = j % 3 - 1, jy = DIM == 2 ? j / 3 - 1 : 0;
@@ -148,47 +161,43 @@ __host__ __device__ __forceinline__ void vn_matrix(double tau, const double (&u)
     }
 }
 
+// 1 / sqrt(p) for p > 0 in the normal range: the hardware reciprocal square
+// root estimate refined by two Newton-Raphson steps y <- y (3 - p y^2) / 2,
+// each of which squares the relative error (the result is within a few ulp).
+// p = 0 gives NaN; callers select another value then.
+__host__ __device__ __forceinline__ double rsqrt_nr(double p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    double y = __builtin_amdgcn_rsq(p);
+#else
+    double y = (1.0 / sqrt(p)) * (1.0 + 3e-8);  // host stand-in for the estimate
+#endif
+    const double h = 0.5 * p;
+    y = fma(y, fma(-h * y, y, 0.5), y);
+    y = fma(y, fma(-h * y, y, 0.5), y);
+    return y;
+}
+
 // Unitary Givens rotation G = [[c, s], [-conj(s), c]] (c real) with
 // G (a, b)^T = (r, 0)^T; exactly the identity when b = 0.
 //
-// The rotations form the serial chain of a QR step, so they are computed from
-// the squared norms with one square root and one division in sequence:
-// q = 1 / sqrt(|a|^2 r^2) gives c = |a| / r = |a|^2 q and |s| scale 1 / (|a| r)
-// = q.  Entries here are O(1) and deflation zeroes any below ulp times its
-// scale, so the products neither overflow nor underflow; should they reach
-// the underflow range anyway, the rescaling form below runs.
+// c = |a| / r and s = (a / |a|) conj(b) / r come from the squared norms with
+// one reciprocal square root, q = 1 / sqrt(|a|^2 r^2): c = |a|^2 q and
+// s = q a conj(b).  The cases are selected, not branched on (branches here
+// made the compiler hold much of the matrix twice): when |b|^2 is zero (b = 0,
+// or below 1e-162) the rotation is the identity, and the b it leaves is at most
+// that small; when |a|^2 < 1e-150, a is dropped (c = 0, s = conj(b) / |b|),
+// which perturbs the matrix by |a| < 1e-75.  Entries here are O(1), so neither
+// is above rounding, and otherwise |a|^2 r^2 >= 1e-300 stays normal.
 __host__ __device__ __forceinline__ void givens(cplx a, cplx b, double &c, cplx &s) {
-    if (b.re == 0.0 && b.im == 0.0) {
-        c = 1.0;
-        s = {0.0, 0.0};
-        return;
-    }
     const double na2 = fma(a.re, a.re, a.im * a.im), nb2 = fma(b.re, b.re, b.im * b.im);
-    const double r2 = na2 + nb2;
-    if (na2 == 0.0 && r2 > 1e-300) {
-        c = 0.0;
-        s = cscale(1.0 / sqrt(r2), {b.re, -b.im});  // conj(b) / |b|
-        return;
-    }
-    const double p = na2 * r2;
-    if (p > 1e-300) {
-        const double q = 1.0 / sqrt(p);
-        c = na2 * q;
-        // s = (a / |a|) conj(b) / r = a conj(b) q
-        s = cscale(q, cmul(a, {b.re, -b.im}));
-        return;
-    }
-    const double na = cabs(a), nb = cabs(b);
-    if (na == 0.0) {
-        c = 0.0;
-        s = cscale(1.0 / nb, {b.re, -b.im});  // conj(b) / |b|
-        return;
-    }
-    const double r = hypot(na, nb);
-    c = na / r;
-    // s = (a / |a|) conj(b) / r
-    const cplx ph = cscale(1.0 / na, a);
-    s = cscale(1.0 / r, cmul(ph, {b.re, -b.im}));
+    const bool drop_a = na2 < 1e-150;
+    const double q = rsqrt_nr(drop_a ? nb2 : na2 * (na2 + nb2));
+    const cplx ap = drop_a ? cplx{1.0, 0.0} : a;
+    const cplx sq = cscale(q, cmul(ap, {b.re, -b.im}));
+    const double cq = drop_a ? 0.0 : na2 * q;
+    const bool ident = nb2 == 0.0;
+    c = ident ? 1.0 : cq;
+    s = ident ? cplx{0.0, 0.0} : sq;
 }
 
 // Reduce A to upper Hessenberg form by Householder reflections (similarity).
@@ -222,12 +231,12 @@ __host__ __device__ __forceinline__ void hessenberg(cplx (&A)[N][N]) {
             cplx w = {0.0, 0.0};
             static_for<k + 1, N>([&](auto ii) {
                 constexpr int i = decltype(ii)::value;
-                w = cadd(w, cmulc(v[i], A[i][j]));
+                w = cmulc_add(v[i], A[i][j], w);
             });
             w = cscale(tau2, w);
             static_for<k + 1, N>([&](auto ii) {
                 constexpr int i = decltype(ii)::value;
-                A[i][j] = csub(A[i][j], cmul(v[i], w));
+                A[i][j] = cmul_sub(v[i], w, A[i][j]);
             });
         });
         // right: A <- A H (all rows, columns k+1..N-1)
@@ -236,12 +245,12 @@ __host__ __device__ __forceinline__ void hessenberg(cplx (&A)[N][N]) {
             cplx w = {0.0, 0.0};
             static_for<k + 1, N>([&](auto jj) {
                 constexpr int j = decltype(jj)::value;
-                w = cadd(w, cmul(A[i][j], v[j]));
+                w = cmulc_add({A[i][j].re, -A[i][j].im}, v[j], w);  // w + A v
             });
             w = cscale(tau2, w);
             static_for<k + 1, N>([&](auto jj) {
                 constexpr int j = decltype(jj)::value;
-                A[i][j] = csub(A[i][j], cmul(w, {v[j].re, -v[j].im}));
+                A[i][j] = cmul_sub(w, {v[j].re, -v[j].im}, A[i][j]);
             });
         });
         // column k below the subdiagonal is annihilated: H x = -e^{i arg x0} alpha e_1
@@ -255,9 +264,17 @@ __host__ __device__ __forceinline__ void hessenberg(cplx (&A)[N][N]) {
 
 // One explicit shifted QR step on the leading M x M block of H:
 // H - mu I = Q R, H <- R Q + mu I, with the shift applied to rows 0..hi only
-// (hi >= M - 1 never happens: M - 1 is the wavefront's largest hi).  Rows
+// (hi > M - 1 never happens: M - 1 is the wavefront's largest hi).  Rows
 // below hi are deflated (zero subdiagonal), the rotations there are exact
-// identities, so without the shift they are left bit-for-bit unchanged.
+// identities, so without the shift their values are left unchanged (a zero
+// may change sign).
+//
+// R Q applies the column rotation k to rows 0..k+1 of columns k, k+1; those
+// rows are final in R once the row rotation k+1 is done, and no later row
+// rotation reads or writes them.  So column rotation k runs right after row
+// rotation k+1: every entry sees the same operations in the same order as
+// with all row rotations first, and only two rotations are live at a time
+// (which keeps the matrix in registers).
 template <int N, int M>
 __host__ __device__ __forceinline__ void qr_step(cplx (&H)[N][N], cplx mu, int hi) {
     static_for<0, M>([&](auto kk) {
@@ -265,30 +282,37 @@ __host__ __device__ __forceinline__ void qr_step(cplx (&H)[N][N], cplx mu, int h
         if (k <= hi)
             H[k][k] = csub(H[k][k], mu);
     });
-    double cs[M - 1];
-    cplx sn[M - 1];
-    static_for<0, M - 1>([&](auto kk) {
-        constexpr int k = decltype(kk)::value;
-        givens(H[k][k], H[k + 1][k], cs[k], sn[k]);
-        static_for<k, M>([&](auto jj) {
-            constexpr int j = decltype(jj)::value;
-            const cplx x = H[k][j], y = H[k + 1][j];
-            // row k <- c x + s y ; row k+1 <- -conj(s) x + c y
-            H[k][j] = cadd(cscale(cs[k], x), cmul(sn[k], y));
-            H[k + 1][j] = csub(cscale(cs[k], y), cmulc(sn[k], x));
-        });
-        H[k + 1][k] = {0.0, 0.0};
-    });
-    static_for<0, M - 1>([&](auto kk) {
+    // columns k, k+1 times G_k^H: col k <- c x + conj(s) y ; col k+1 <- -s x + c y
+    auto column_rotation = [&](auto kk, double c, cplx s) {
         constexpr int k = decltype(kk)::value;
         static_for<0, k + 2>([&](auto ii) {
             constexpr int i = decltype(ii)::value;
             const cplx x = H[i][k], y = H[i][k + 1];
-            // columns k, k+1 times G^H: col k <- c x + conj(s) y ; col k+1 <- -s x + c y
-            H[i][k] = cadd(cscale(cs[k], x), cmulc(sn[k], y));
-            H[i][k + 1] = csub(cscale(cs[k], y), cmul(sn[k], x));
+            H[i][k] = crot(c, x, {s.re, -s.im}, y);
+            H[i][k + 1] = crot(c, y, {-s.re, -s.im}, x);
         });
+    };
+    double c_prev = 1.0;
+    cplx s_prev = {0.0, 0.0};
+    static_for<0, M - 1>([&](auto kk) {
+        constexpr int k = decltype(kk)::value;
+        double c;
+        cplx s;
+        givens(H[k][k], H[k + 1][k], c, s);
+        static_for<k, M>([&](auto jj) {
+            constexpr int j = decltype(jj)::value;
+            const cplx x = H[k][j], y = H[k + 1][j];
+            // row k <- c x + s y ; row k+1 <- -conj(s) x + c y
+            H[k][j] = crot(c, x, s, y);
+            H[k + 1][j] = crot(c, y, {-s.re, s.im}, x);
+        });
+        H[k + 1][k] = {0.0, 0.0};
+        if constexpr (k > 0)
+            column_rotation(std::integral_constant<int, k - 1>{}, c_prev, s_prev);
+        c_prev = c;
+        s_prev = s;
     });
+    column_rotation(std::integral_constant<int, M - 2>{}, c_prev, s_prev);
     static_for<0, M>([&](auto kk) {
         constexpr int k = decltype(kk)::value;
         if (k <= hi)
@@ -297,7 +321,9 @@ __host__ __device__ __forceinline__ void qr_step(cplx (&H)[N][N], cplx mu, int h
 }
 
 // FP64 operations (a fused multiply-add counts 2; divisions, square roots and
-// transcendentals 1) of the solver as written: building M, the Householder
+// transcendentals 1; the refined reciprocal square root that forms a rotation
+// counts 2, as the square root and the division it stands for) of the solver
+// as written: building M, the Householder
 // reduction and the norm (fixed), and one QR step on an active block of M
 // rows (its rotations, the shift on M rows, the deflation scan and the shift
 // choice).  Used to report the arithmetic rate; they count each matrix's own
@@ -307,13 +333,15 @@ __host__ __device__ constexpr double vn_fixed_flops() {
     double h = 0.0;
     for (int m = 2; m <= N - 1; ++m)
         h += 16.0 * m * m + (6.0 + 16.0 * N) * m + 2.0 * N + 14.0;
-    const double build = 9.0 * N * N + 20.0 * N + 40.0;
+    const double build = 9.0 * N * N + 15.0 * N + 40.0 + (N == 9 ? 4.0 + 24.0 : 2.0);
     const double norm = 3.0 * (N * (N + 1) / 2 + N - 1) + 4.0 * N;
     return h + build + norm;
 }
 __host__ __device__ constexpr double vn_step_flops(int M) {
     // per rotation: applying it to two rows and two columns (20 M) and
-    // forming it from squared norms (19) with the rest of its bookkeeping (46)
+    // forming it from squared norms (19) with the rest of its bookkeeping (46);
+    // per step: the shift on M rows and back (4 M), the deflation scan and the
+    // shift choice (150)
     return (M - 1) * (20.0 * M + 65.0) + 4.0 * M + 150.0;
 }
 
@@ -328,7 +356,15 @@ __host__ __device__ constexpr double vn_step_flops(int M) {
 // thread itself on the host); M is taken from it so that every thread of a
 // wavefront runs the same compile-time block size.  Every thread must call
 // this function (none may have left early), and the loop runs until every
-// thread of the group is done; a finished thread's steps are exact no-ops.
+// thread of the group is done; a finished thread's steps leave its values
+// unchanged.
+//
+// The group's M never grows: a zero subdiagonal entry stays exactly zero
+// (its rotation is the identity) and a thread that gives up reports hi = 0
+// from then on.  So the iteration is a sequence of loops, one per block size
+// from N down to 2, each running while M has its size; the deflation scan and
+// the shift then look at the rows of that block only (the rows below are
+// deflated in every thread that is still iterating).
 template <int N, typename GroupMax>
 __host__ __device__ __forceinline__ int hessenberg_eigenvalues(cplx (&H)[N][N], GroupMax group_max,
                                                                double *work = nullptr) {
@@ -346,35 +382,37 @@ __host__ __device__ __forceinline__ int hessenberg_eigenvalues(cplx (&H)[N][N], 
     norm *= 1e-2;
     int steps = 0, since_deflation = 0, last_hi = N;
     bool failed = false;
-    for (;;) {
-        // deflate negligible subdiagonal entries (relative to their diagonal
-        // neighbours, or to the matrix norm when those are tiny); hi = lowest
-        // unreduced row
-        int hi = 0;
-        static_for<1, N>([&](auto kk) {
+    // deflate negligible subdiagonal entries of rows 1..M-1 (relative to their
+    // diagonal neighbours, or to the matrix norm when those are tiny); returns
+    // hi = the lowest unreduced row, 0 once the iteration limit is reached
+    auto deflate = [&](auto mm) {
+        constexpr int M = decltype(mm)::value;
+        int h = 0;
+        static_for<1, M>([&](auto kk) {
             constexpr int k = decltype(kk)::value;
             const double scale = fmax(cabs1(H[k][k]) + cabs1(H[k - 1][k - 1]), norm);
             if (cabs1(H[k][k - 1]) <= kUlp * scale)
                 H[k][k - 1] = {0.0, 0.0};
             if (H[k][k - 1].re != 0.0 || H[k][k - 1].im != 0.0)
-                hi = k;
+                h = k;
         });
-        if (hi > 0 && steps >= 30 * N) {
+        if (h > 0 && steps >= 30 * N) {
             failed = true;
-            hi = 0;  // give up: stop stepping this matrix
+            h = 0;  // give up: stop stepping this matrix
         }
-        const int wave_hi = group_max(hi);
-        if (wave_hi == 0)
-            return failed ? -1 : steps;
-        cplx mu = {0.0, 0.0};
-        if (hi > 0) {
-            if (hi != last_hi) {
-                last_hi = hi;
-                since_deflation = 0;
-            }
-            // trailing 2 x 2 of the active block: [[a, b], [c, d]] at rows hi-1, hi
-            cplx a = {0.0, 0.0}, b = a, c = a, d = a, e = a;  // e = H[hi-1][hi-2] (0 if hi = 1)
-            static_for<1, N>([&](auto kk) {
+        return h;
+    };
+    int hi = deflate(std::integral_constant<int, N>{});
+    int wave_hi = group_max(hi);
+    static_for<0, N - 1>([&](auto dd) {
+        constexpr int M = N - decltype(dd)::value;  // N, N - 1, ..., 2
+        while (wave_hi + 1 == M) {
+            // shift from the trailing 2 x 2 of this thread's active block,
+            // [[a, b], [c, d]] at rows hi-1, hi (zero when hi = 0, where the
+            // shift is not used); computed without branches, cases selected
+            cplx a = {0.0, 0.0}, b = a, c = a, d = a;
+            double e1 = 0.0;  // |H[hi-1][hi-2]| (1-norm; 0 if hi = 1)
+            static_for<1, M>([&](auto kk) {
                 constexpr int k = decltype(kk)::value;
                 if (k == hi) {
                     a = H[k - 1][k - 1];
@@ -382,33 +420,40 @@ __host__ __device__ __forceinline__ int hessenberg_eigenvalues(cplx (&H)[N][N], 
                     c = H[k][k - 1];
                     d = H[k][k];
                     if constexpr (k >= 2)
-                        e = H[k - 1][k - 2];
+                        e1 = cabs1(H[k - 1][k - 2]);
                 }
             });
-            if (since_deflation == 10 || since_deflation == 20) {
-                // exceptional shift
-                const double t = cabs1(c) + cabs1(e);
-                mu = {d.re + 0.75 * t, d.im};
-            } else {
-                // Wilkinson: eigenvalue of the 2 x 2 closer to d
-                const cplx half = cscale(0.5, csub(a, d));
-                const cplx disc = csqrt_(cadd(cmul(half, half), cmul(b, c)));
-                const cplx m1 = cadd(half, disc), m2 = csub(half, disc);
-                const cplx den = cabs1(m1) >= cabs1(m2) ? m1 : m2;  // larger root for stability
-                mu = (den.re == 0.0 && den.im == 0.0) ? d : csub(d, cdiv(cmul(b, c), den));
-            }
-            ++steps;
-            ++since_deflation;
+            const bool active = hi > 0;
+            const bool fresh = hi != last_hi;
+            last_hi = active && fresh ? hi : last_hi;
+            since_deflation = active && fresh ? 0 : since_deflation;
+            // Wilkinson: the eigenvalue of the 2 x 2 closer to d, d - b c / den
+            // with den the larger root of z^2 = half^2 + b c (for stability)
+            const cplx half = cscale(0.5, csub(a, d));
+            const cplx bc = cmul(b, c);
+            const cplx disc = csqrt_sq(cadd(cmul(half, half), bc));
+            const cplx m1 = cadd(half, disc), m2 = csub(half, disc);
+            const cplx den = cabs1(m1) >= cabs1(m2) ? m1 : m2;
+            const double den2 = fma(den.re, den.re, den.im * den.im);
+            const double inv = 1.0 / (den2 > 0.0 ? den2 : 1.0);
+            const cplx wil = csub(d, cscale(inv, cmulc({den.re, den.im}, bc)));
+            const cplx wilk = den2 > 0.0 ? wil : d;
+            // exceptional shift after 10 and 20 steps without deflation
+            const bool exceptional = since_deflation == 10 || since_deflation == 20;
+            const cplx exc = {d.re + 0.75 * (cabs1(c) + e1), d.im};
+            const cplx mu_a = exceptional ? exc : wilk;
+            const cplx mu = active ? mu_a : cplx{0.0, 0.0};
+            steps += active ? 1 : 0;
+            since_deflation += active ? 1 : 0;
             if (work)
-                *work += vn_step_flops(hi + 1);
+                *work += active ? vn_step_flops(hi + 1) : 0.0;
+            // one QR step on the leading M x M block, the same size for the group
+            qr_step<N, M>(H, mu, hi);
+            hi = deflate(std::integral_constant<int, M>{});
+            wave_hi = group_max(hi);
         }
-        // one QR step on the leading (wave_hi + 1) block, the same size for the group
-        static_for<2, N + 1>([&](auto mm) {
-            constexpr int M = decltype(mm)::value;
-            if (wave_hi + 1 == M)
-                qr_step<N, M>(H, mu, hi);
-        });
-    }
+    });
+    return failed ? -1 : steps;
 }
 
 }  // namespace lbm
