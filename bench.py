@@ -498,7 +498,7 @@ def bench_ceiling(n: int = 256, steps: int = 100, warmup: int = 10) -> dict:
     return out
 
 
-def bench_d1q3(steps: int = 200, warmup: int = 20) -> dict:
+def bench_d1q3(steps: int = 200, warmup: int = 64) -> dict:
     """A D1Q3 row of 2^27 nodes (a pressure wave, U = 0.1, tau 0.6, with the
     correction), FP32 deviations and FP64, with the default eight steps per
     launch and with one; more steps than elsewhere (one step takes ~0.6 ms,
@@ -551,7 +551,7 @@ def bench_d1q3(steps: int = 200, warmup: int = 20) -> dict:
                         "bulk correction on", "steps": steps, "results": out}
 
 
-def bench_d2q9(steps: int = 100, warmup: int = 10) -> dict:
+def bench_d2q9(steps: int = 100, warmup: int = 200) -> dict:
     """The D2Q9 4096^2 double shear layer (tau 0.5001), FP32 deviations and FP64,
     correction off and on, with the default two steps per launch and with one.
     gbs / frac count the bytes each launch moves by algorithm: one read and
@@ -596,8 +596,8 @@ def bench_d2q9(steps: int = 100, warmup: int = 10) -> dict:
                     "gbs_2Qs_per_update": round(mlups * 1e6 * 2 * 9 * s / 1e9, 1), "domain_error": d["domain_error"]}
                 if k > 1:
                     out[key]["roofline_valu"] = valu_roofline(f"d2q9_4096.{key}", k * sec)
-    return {"workload": "D2Q9 4096^2 double shear layer, tau 0.5001", "steps": steps, "repetitions": 3,
-            "statistic": "best of the repetitions", "results": out}
+    return {"workload": "D2Q9 4096^2 double shear layer, tau 0.5001", "steps": steps, "warmup_steps": warmup,
+            "repetitions": 3, "statistic": "best of the repetitions", "results": out}
 
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6
