@@ -182,22 +182,22 @@ __host__ __device__ __forceinline__ double rsqrt_nr(double p) {
 //
 // c = |a| / r and s = (a / |a|) conj(b) / r come from the squared norms with
 // one reciprocal square root, q = 1 / sqrt(|a|^2 r^2): c = |a|^2 q and
-// s = q a conj(b).  The cases are selected, not branched on (branches here
-// made the compiler hold much of the matrix twice): when |b|^2 is zero (b = 0,
-// or below 1e-162) the rotation is the identity, and the b it leaves is at most
-// that small; when |a|^2 < 1e-150, a is dropped (c = 0, s = conj(b) / |b|),
-// which perturbs the matrix by |a| < 1e-75.  Entries here are O(1), so neither
-// is above rounding, and otherwise |a|^2 r^2 >= 1e-300 stays normal.
+// s = q a conj(b).  The cases are not branched on (branches here made the
+// compiler hold much of the matrix twice):
+// - b = 0 (or |b|^2 below 1e-162): c is set to 1 and s comes out 0 (q is
+//   finite), so the rotation is exactly the identity;
+// - |a|^2 < 1e-150: a is dropped, q = 1 / |b| and a + 1 stands for the unit
+//   phase of a, so s = conj(b) / |b| and c = |a|^2 q ~ 0, each to a relative
+//   1e-75.  Entries here are O(1) and a live b is above ulp times the
+//   matrix scale (smaller ones are deflated to exact zeros), so neither is
+//   above rounding, and otherwise |a|^2 r^2 >= 1e-300 stays normal.
 __host__ __device__ __forceinline__ void givens(cplx a, cplx b, double &c, cplx &s) {
     const double na2 = fma(a.re, a.re, a.im * a.im), nb2 = fma(b.re, b.re, b.im * b.im);
     const bool drop_a = na2 < 1e-150;
-    const double q = rsqrt_nr(drop_a ? nb2 : na2 * (na2 + nb2));
-    const cplx ap = drop_a ? cplx{1.0, 0.0} : a;
-    const cplx sq = cscale(q, cmul(ap, {b.re, -b.im}));
-    const double cq = drop_a ? 0.0 : na2 * q;
-    const bool ident = nb2 == 0.0;
-    c = ident ? 1.0 : cq;
-    s = ident ? cplx{0.0, 0.0} : sq;
+    const double q = rsqrt_nr(drop_a ? fmax(nb2, 1e-300) : na2 * (na2 + nb2));
+    const cplx ap = {a.re + (drop_a ? 1.0 : 0.0), a.im};
+    c = nb2 == 0.0 ? 1.0 : na2 * q;
+    s = cscale(q, cmul(ap, {b.re, -b.im}));
 }
 
 // Reduce A to upper Hessenberg form by Householder reflections (similarity).
@@ -277,10 +277,12 @@ __host__ __device__ __forceinline__ void hessenberg(cplx (&A)[N][N]) {
 // (which keeps the matrix in registers).
 template <int N, int M>
 __host__ __device__ __forceinline__ void qr_step(cplx (&H)[N][N], cplx mu, int hi) {
+    // the shift on rows 0..hi: f = 1 there subtracts mu exactly as a
+    // subtraction rounds, f = 0 leaves the row's value as it is
     static_for<0, M>([&](auto kk) {
         constexpr int k = decltype(kk)::value;
-        if (k <= hi)
-            H[k][k] = csub(H[k][k], mu);
+        const double f = k <= hi ? 1.0 : 0.0;
+        H[k][k] = {fma(-f, mu.re, H[k][k].re), fma(-f, mu.im, H[k][k].im)};
     });
     // columns k, k+1 times G_k^H: col k <- c x + conj(s) y ; col k+1 <- -s x + c y
     auto column_rotation = [&](auto kk, double c, cplx s) {
@@ -315,8 +317,8 @@ __host__ __device__ __forceinline__ void qr_step(cplx (&H)[N][N], cplx mu, int h
     column_rotation(std::integral_constant<int, M - 2>{}, c_prev, s_prev);
     static_for<0, M>([&](auto kk) {
         constexpr int k = decltype(kk)::value;
-        if (k <= hi)
-            H[k][k] = cadd(H[k][k], mu);
+        const double f = k <= hi ? 1.0 : 0.0;
+        H[k][k] = {fma(f, mu.re, H[k][k].re), fma(f, mu.im, H[k][k].im)};
     });
 }
 
@@ -391,10 +393,11 @@ __host__ __device__ __forceinline__ int hessenberg_eigenvalues(cplx (&H)[N][N], 
         static_for<1, M>([&](auto kk) {
             constexpr int k = decltype(kk)::value;
             const double scale = fmax(cabs1(H[k][k]) + cabs1(H[k - 1][k - 1]), norm);
-            if (cabs1(H[k][k - 1]) <= kUlp * scale)
-                H[k][k - 1] = {0.0, 0.0};
-            if (H[k][k - 1].re != 0.0 || H[k][k - 1].im != 0.0)
-                h = k;
+            // kept entries are nonzero (and a NaN is kept), so one comparison
+            // decides both
+            const bool keep = !(cabs1(H[k][k - 1]) <= kUlp * scale);
+            H[k][k - 1] = keep ? H[k][k - 1] : cplx{0.0, 0.0};
+            h = keep ? k : h;
         });
         if (h > 0 && steps >= 30 * N) {
             failed = true;
