@@ -52,17 +52,17 @@ __global__ __launch_bounds__(kVnThreads) void k_vn_spectra(VnSpectraArgs a) {
     const int steps = hessenberg_eigenvalues<N>(H, wave_max_int, &work);
     if (!live)
         return;
-    double r = 0.0;
+    double r2 = 0.0;  // largest |eigenvalue|^2 (O(1) values: no rescaling)
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-        r = fmax(r, cabs(H[i][i]));
+        r2 = fmax(r2, fma(H[i][i].re, H[i][i].re, H[i][i].im * H[i][i].im));
         if (a.eig) {
             a.eig[(t * N + i) * 2 + 0] = H[i][i].re;
             a.eig[(t * N + i) * 2 + 1] = H[i][i].im;
         }
     }
     if (a.radius)
-        a.radius[t] = r;
+        a.radius[t] = sqrt(r2);
     if (a.info)
         a.info[t] = steps;
     if (a.flops)
@@ -99,10 +99,11 @@ __global__ __launch_bounds__(kVnThreads) void k_vn_max_radius(VnMaxArgs a) {
     const int steps = hessenberg_eigenvalues<N>(H, wave_max_int);
     if (!live)
         return;
-    double r = 0.0;
+    double r2 = 0.0;  // largest |eigenvalue|^2 (O(1) values: no rescaling)
 #pragma unroll
     for (int i = 0; i < N; ++i)
-        r = fmax(r, cabs(H[i][i]));
+        r2 = fmax(r2, fma(H[i][i].re, H[i][i].re, H[i][i].im * H[i][i].im));
+    const double r = sqrt(r2);
     if (steps < 0)
         atomicAdd(a.unconverged, 1);
     atomicMax(a.rmax + s, (unsigned long long)__double_as_longlong(r));

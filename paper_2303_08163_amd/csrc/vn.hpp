@@ -60,7 +60,6 @@ __host__ __device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.re + b
 __host__ __device__ __forceinline__ cplx csub(cplx a, cplx b) { return {a.re - b.re, a.im - b.im}; }
 __host__ __device__ __forceinline__ cplx cscale(double s, cplx a) { return {s * a.re, s * a.im}; }
 __host__ __device__ __forceinline__ double cabs1(cplx a) { return fabs(a.re) + fabs(a.im); }
-__host__ __device__ __forceinline__ double cabs(cplx a) { return hypot(a.re, a.im); }
 // c x + s y for real c and complex s, as three-term fused sums per component
 // (one multiplication and two fused multiply-adds each): the form in which
 // rotations are applied.
@@ -211,12 +210,21 @@ __host__ __device__ __forceinline__ void hessenberg(cplx (&A)[N][N]) {
             constexpr int i = decltype(ii)::value;
             nrm2 = fma(A[i][k].re, A[i][k].re, fma(A[i][k].im, A[i][k].im, nrm2));
         });
-        const double alpha = sqrt(nrm2);
-        if (alpha == 0.0)
+        // a column below 1e-130 needs no reflection: the QR iteration reads only
+        // the Hessenberg part, so its entries below the subdiagonal count as
+        // zeros (a perturbation of that size; exact when the column is zero)
+        if (nrm2 <= 1e-260)
             return;
+        const double alpha = sqrt(nrm2);
+        // |x0| and the phase of x0 from one refined reciprocal square root (the
+        // phase taken as 1 when |x0|^2 <= 1e-300, where v^H v below is then off
+        // by a relative |x0| / alpha < 1e-20)
         const cplx x0 = A[k + 1][k];
-        const double ax0 = cabs(x0);
-        const cplx ph = ax0 > 0.0 ? cscale(1.0 / ax0, x0) : cplx{1.0, 0.0};
+        const double n0 = fma(x0.re, x0.re, x0.im * x0.im);
+        const bool has_phase = n0 > 1e-300;
+        const double r0 = rsqrt_nr(has_phase ? n0 : 1.0);
+        const double ax0 = has_phase ? n0 * r0 : 0.0;
+        const cplx ph = has_phase ? cscale(r0, x0) : cplx{1.0, 0.0};
         cplx v[N];
         v[k + 1] = cadd(x0, cscale(alpha, ph));
         static_for<k + 2, N>([&](auto ii) {
