@@ -682,6 +682,30 @@ def bench_stability(cpu_budget_s: float = 5.0, with_cpu: bool = True) -> dict:
     return out
 
 
+def env_info() -> dict:
+    """ROCm version and the GPU's clocks as rocm-smi reports them, read in a
+    child process before this process touches the GPU (rocm-smi reads the
+    driver's sysfs files; a failure is recorded, not raised)."""
+    import subprocess
+    env = {}
+    try:
+        with open("/opt/rocm/.info/version") as f:
+            env["rocm"] = f.read().strip()
+    except OSError:
+        env["rocm"] = None
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=30)
+        data = json.loads(r.stdout) if r.returncode == 0 else None
+        if isinstance(data, dict):
+            env["rocm_smi_clocks_at_start"] = {card: {k: v for k, v in vals.items() if "clock" in k.lower()}
+                                               for card, vals in data.items() if isinstance(vals, dict)}
+        else:
+            env["rocm_smi_clocks_at_start"] = f"unavailable (exit {r.returncode}): {(r.stderr or r.stdout)[-200:]}"
+    except (OSError, ValueError, subprocess.SubprocessError) as err:
+        env["rocm_smi_clocks_at_start"] = f"unavailable: {err}"
+    return env
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -719,12 +743,17 @@ def main() -> int:
               file=sys.stderr)
         return 2
 
+    env = env_info()  # before anything initialises the GPU
+
     import numpy as np
     import torch
 
     from paper_2303_08163_amd import lbm, workloads
 
     dev = torch.device("cuda:0")
+    props = torch.cuda.get_device_properties(0)
+    env.update(device=torch.cuda.get_device_name(0), arch=getattr(props, "gcnArchName", None),
+               compute_units=props.multi_processor_count, hip=torch.version.hip, torch=torch.__version__)
     n, tau = args.n, 0.5005
     rho0, u0 = workloads.taylor_green_3d(n, u0=0.05)
     stream = torch.cuda.current_stream(dev)
@@ -801,6 +830,7 @@ def main() -> int:
         "median_of_5_mlups": round(nodes / (sorted(reps)[2] / 1e3) / 1e6, 1),
         "mass_drift": abs(diag["mass"] / (nodes * 1.0) - 1.0),
         "kernel_source_digest": kernel_source_digest(),
+        "env": env,
     }
     if ceiling:
         out["ceiling"] = ceiling
