@@ -262,9 +262,10 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
             return LBM_EINVAL;
         }
         // columns per tile: the widest of 512 (FP32) or 128 (FP64), then 256, 128, 64 that
-        // divides nx, or for other widths the widest not above nx (the last tile partial).  Measured at 4096^2 FP32, us per step: 512 columns 139.8 (76 KB of LDS,
-        // two workgroups per compute unit), 256 146.1 (39 KB, four), 128 156.2; FP64 takes
-        // 128 (37 KB, four workgroups of three wavefronts)
+        // divides nx, or for other widths the widest not above nx (the last tile partial).
+        // Measured at 4096^2 FP32, us per step, one box: 512 columns 117.7 (76 KB of LDS,
+        // two workgroups per compute unit), 256 126.9 (39 KB, four); with the correction
+        // 131.3 and 140.1.  FP64 takes 128 (37 KB, four workgroups of three wavefronts)
         int tx = fp32 ? 512 : 128;
         if (cfg->nx % 64 == 0) {
             while (cfg->nx % tx != 0)
