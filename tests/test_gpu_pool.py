@@ -231,7 +231,8 @@ def test_pool_retires_failed_slots():
 def test_pool_two_steps_per_launch_equals_alone(persistent):
     """time_block = 2: D2Q9 classes that hold enough nodes (2^22 FP32, 2^20
     FP64) advance two steps per launch (ragged widths, whole-row and column
-    tiles in one class, both storage types, with and without the correction);
+    tiles in one class, both storage types, FP32 with the correction and FP64
+    with and without it);
     odd runs end with a one-step launch, small classes take one step per
     launch, and the buffer parity stays right across both forms.  With
     persistent = 1 the two-step classes take each run in one tile-ordered
@@ -242,7 +243,8 @@ def test_pool_two_steps_per_launch_equals_alone(persistent):
     specs = [((33, 70), "fp32_dev", True, 0.6), ((64, 64), "fp64", False, 0.55), ((17, 130), "fp32_dev", False, 0.52),
              ((100, 45), "fp64", True, 0.7), ((5, 300), "fp32_dev", False, 0.58), ((48, 513), "fp64", False, 0.51),
              ((40, 32), "fp32_dev", True, 0.56),
-             ((2048, 2048), "fp32_dev", True, 0.51), ((1024, 1024), "fp64", False, 0.51)]  # large slots
+             ((2048, 2048), "fp32_dev", True, 0.51), ((1024, 1024), "fp64", False, 0.51),
+             ((1024, 1024), "fp64", True, 0.52)]  # large slots: every D2Q9 class but one takes two steps
     steps = 30
     fields = [workloads.random_field(shape, seed=100 + k, umax=0.1) for k, (shape, _, _, _) in enumerate(specs)]
     r3, u3 = workloads.taylor_green_3d(16, u0=0.05)
@@ -253,10 +255,11 @@ def test_pool_two_steps_per_launch_equals_alone(persistent):
         for k in (10, 6, 7, 7):
             pool.run(k)
         assert sorted(pool.poll()) == sorted(slots + [s3])
-        # the FP32-corrected and FP64 classes (with the large slots): 5 + 3 two-step
-        # launches, then twice 3 two-step and one one-step launch (odd runs); the two
-        # small D2Q9 classes and D3Q27: 30 each; persistent: one launch per class and run
-        assert pool.stats()["launches"] == (5 * 4 if persistent else 2 * (5 + 3 + 4 + 4) + 3 * 30)
+        # the three D2Q9 classes with a large slot (FP32 corrected, FP64 with and
+        # without the correction): 5 + 3 two-step launches, then twice 3 two-step and
+        # one one-step launch (odd runs); the small FP32 class and D3Q27: 30 each;
+        # persistent: one launch per class and run
+        assert pool.stats()["launches"] == (5 * 4 if persistent else 3 * (5 + 3 + 4 + 4) + 2 * 30)
         for s, (r, u), (_, dt, corr, tau) in zip(slots, fields, specs):
             ra, ua, da, fa = alone(r, u, tau, steps, dt, corr)
             rb, ub, db = pool.moments(s, raise_on_domain=False)
