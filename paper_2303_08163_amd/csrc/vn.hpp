@@ -438,8 +438,9 @@ __host__ __device__ __forceinline__ int hessenberg_eigenvalues(cplx (&H)[N][N], 
             const bool fresh = hi != last_hi;
             last_hi = active && fresh ? hi : last_hi;
             since_deflation = active && fresh ? 0 : since_deflation;
-            // Wilkinson: the eigenvalue of the 2 x 2 closer to d, d - b c / den
-            // with den the larger root of z^2 = half^2 + b c (for stability)
+            // Wilkinson: the eigenvalue of the 2 x 2 closer to d, d - b c / den,
+            // with den = half +- disc (disc^2 = half^2 + b c) the one of larger
+            // size (for stability)
             const cplx half = cscale(0.5, csub(a, d));
             const cplx bc = cmul(b, c);
             const cplx disc = csqrt_sq(cadd(cmul(half, half), bc));
