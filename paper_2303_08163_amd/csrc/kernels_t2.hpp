@@ -37,7 +37,7 @@ struct Step2Args {
     const void *src;  // f*(t), row-interleaved layout
     void *dst;        // f*(t + 2)
     int nx, ny;
-    int tx;           // columns per workgroup tile (64 .. 512; the last tile of a row may be partial)
+    int tx;           // columns per workgroup tile (64 .. 1024; the last tile of a row may be partial)
     int rows;         // owned rows per workgroup
     int tiles_x, tiles_y;
     int64_t ps, rs;
@@ -536,7 +536,7 @@ __device__ __forceinline__ void two_step_rows_tile(const Step2Args &a, int tile,
 }
 
 template <int DT, bool CORR, int EQ = kEqEntropic, bool NT = false>
-__global__ __launch_bounds__(512) void k_stream_collide2(Step2Args a) {
+__global__ __launch_bounds__(1024) void k_stream_collide2(Step2Args a) {
     two_step_tile<DT, CORR, EQ, NT>(a, xcd_tile((int)blockIdx.x, (int)gridDim.x));
 }
 

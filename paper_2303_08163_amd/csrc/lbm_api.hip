@@ -261,12 +261,14 @@ int validate_config(const lbm_config *cfg, const lbm_tuning *tun, Layout *out) {
             set_error("time_rows must lie in 0 .. ny");
             return LBM_EINVAL;
         }
-        // columns per tile: the widest of 512 (FP32) or 128 (FP64), then 256, 128, 64 that
-        // divides nx, or for other widths the widest not above nx (the last tile partial).
-        // Measured at 4096^2 FP32, us per step, one box: 512 columns 117.7 (76 KB of LDS,
-        // two workgroups per compute unit), 256 126.9 (39 KB, four); with the correction
-        // 131.3 and 140.1.  FP64 takes 128 (37 KB, four workgroups of three wavefronts)
-        int tx = fp32 ? 512 : 128;
+        // columns per tile: the widest of 1024 (FP32) or 128 (FP64), then 512, 256, 128, 64
+        // that divides nx, or for other widths the widest not above nx (the last tile
+        // partial).  FP32, us per step on one box, 512 against 1024 columns (76 KB of LDS and
+        // two workgroups per compute unit, against 147 KB and one of 16 wavefronts): 2048^2
+        // 35.0 / 34.4, 2500^2 57.6 / 57.6, 3072^2 81.8 / 76.7, 4000^2 122.7 / 116.0, 4096^2
+        // 120.1 / 115.6, 6144^2 270.0 / 264.8 (256 columns: 126.9 at 4096^2 on another box,
+        // 117.7 for 512 there).  FP64 takes 128 (37 KB, four workgroups of three wavefronts)
+        int tx = fp32 ? 1024 : 128;
         if (cfg->nx % 64 == 0) {
             while (cfg->nx % tx != 0)
                 tx /= 2;

@@ -89,8 +89,8 @@ def test_two_step_domain_flag_as_one_step():
 
 
 def test_two_step_ragged_large_bitwise():
-    """A large ragged width (4000^2, 512-column tiles with a partial last
-    one), where two steps per launch are the default."""
+    """A large ragged width (4000^2, 1024-column tiles with a partial last
+    one of 928), where two steps per launch are the default."""
     lbm = _lbm()
     rho0, u0 = workloads.random_field((4000, 4000), seed=51, umax=0.1)
     with lbm.Domain(rho0, u0, 0.51, dtype="fp32_dev") as a:
@@ -104,14 +104,14 @@ def test_two_step_ragged_large_bitwise():
 @pytest.mark.parametrize("dtype", ["fp32_dev", "fp64"])
 def test_two_step_full_size_bitwise(dtype):
     """D2Q9 4096^2 (the large 2-D workload), 4 steps with the default
-    two-step kernel (columns of 512 for FP32 storage, 128 for FP64) against
+    two-step kernel (columns of 1024 for FP32 storage, 128 for FP64) against
     one step per launch."""
     lbm = _lbm()
     rho0, u0 = workloads.random_field((4096, 4096), seed=50, umax=0.1)
     with lbm.Domain(rho0, u0, 0.51, dtype=dtype) as a:
         info = a.launch_info()
         assert info["kernel"] == "two_step", info
-        assert info["time_cols"] == (512 if dtype == "fp32_dev" else 128), info
+        assert info["time_cols"] == (1024 if dtype == "fp32_dev" else 128), info
         a.step(4)
         fa = a.populations()
     with lbm.Domain(rho0, u0, 0.51, dtype=dtype, tuning=lbm.make_tuning(time_block=1)) as b:
