@@ -407,9 +407,10 @@ typedef struct lbm_pool_tuning {
                            runs where the class's slots that take at least two steps hold
                            >= 2^22 nodes (FP32) or 2^20 (FP64); a slot whose step count in
                            the run is odd takes its last step in a one-step launch.  FP32:
-                           slots whose row, rounded up to 64, is at most 512 nodes run as
-                           whole-row tiles (no halo columns), wider ones as column tiles of
-                           512; FP64: column tiles of 128.  Other runs take one step per
+                           slots whose row, rounded up to 64, is at most 512 nodes (1024
+                           with persistent = 1) run as whole-row tiles (no halo columns),
+                           wider ones as column tiles of 512 (1024); FP64: column tiles of
+                           128.  Other runs take one step per
                            launch.  Results are bitwise those of one step per launch.
                            With persistent = 1 such a class takes every iteration of a
                            run (two steps each, and a last single step for slots with
@@ -419,7 +420,7 @@ typedef struct lbm_pool_tuning {
                            classes of such a pool run persistent as with time_block 0.
                            0 or 1: one step per launch */
     int32_t time_rows;  /* time_block = 2: rows swept by each whole-row sub-tile and each column
-                           tile (0 = default: 16; in the tile-ordered persistent form 32
+                           tile (0 = default: 16; in the tile-ordered persistent form 16
                            for FP32, 64 for FP64; at most 4096) */
     int32_t spin_log2;  /* persistent form: a workgroup waits at most 2^spin_log2 polls of the
                            grid barrier's counter, or of its tile's neighbours' counters,

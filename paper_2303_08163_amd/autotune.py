@@ -49,7 +49,7 @@ def candidates(persistent: bool = False):
     # two steps per launch for large D2Q9 classes (the tile and row fit serve the
     # one-step launches of the other classes), with three sweep lengths
     two = [dict(tile_x=64, tile_y=4, persistent=0, row_fit=1, time_block=2, time_rows=r) for r in (0, 32, 64)]
-    ordered = [dict(tile_x=64, tile_y=4, persistent=1, row_fit=1, time_block=2, time_rows=r) for r in (0, 64)]
+    ordered = [dict(tile_x=64, tile_y=4, persistent=1, row_fit=1, time_block=2, time_rows=r) for r in (0, 32)]
     return rows + flat + fit + two + ordered
 
 
@@ -127,7 +127,7 @@ def tune_pool(domains, steps: int = 60, cands=None, cache_path: str | None = DEF
     "failed", each candidate that the library refused or that raised an error
     while it ran (for instance a persistent run whose grid barrier timed out),
     with the error text."""
-    key = f"candidates-v8|{_device_key()}|{signature(domains)}" if cands is None else \
+    key = f"candidates-v9|{_device_key()}|{signature(domains)}" if cands is None else \
         f"custom-{hashlib.sha256(json.dumps(cands, sort_keys=True).encode()).hexdigest()[:12]}|{_device_key()}|" \
         f"{signature(domains)}"
     cache = _load_cache(cache_path) if cache_path else {}

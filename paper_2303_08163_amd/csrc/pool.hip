@@ -149,17 +149,22 @@ static PoolStepFn pool_kernel(int dtype, bool corr, bool persistent) {
 // workgroups (two wavefronts, four workgroups per compute unit) ran slower on
 // the batched workload, 399 against 461 solves/s: FP64 rows need the loads
 // in flight that only wider workgroups keep.
-static int t2_block(int dtype) { return dtype == kF64 ? 192 : 512; }
-static int t2_cols(int dtype) { return dtype == kF64 ? 128 : 512; }
+//
+// The tile-ordered persistent form (persistent tunings) gives FP32 workgroups
+// 1024 threads, one per compute unit: twice the sub-tiles per tile, half the
+// tiles to wait for and publish (batched workload, FP32: 363 against 382 us per
+// step; launches per two steps ran slower with them, 322 against 312).
+static int t2_block(int dtype, bool persistent) { return dtype == kF64 ? 192 : (persistent ? 1024 : 512); }
+static int t2_cols(int dtype, bool persistent) { return dtype == kF64 ? 128 : (persistent ? 1024 : 512); }
 // Rows per sweep, measured on the batched workload: 16 with two-step launches (FP32: 16
 // rows 830 solves/s, 12: 821, 24: 821, 32: 809, 48: 778; FP64: 8 to 16 within 1 %, 32:
-// 452); in the tile-ordered persistent form, where longer sweeps mean fewer tiles to
-// wait for, 32 for FP32 (664-670 against 629-639 with 16, 613-618 with 64) and 64 for
-// FP64 (413 against 385 with 16).
+// 452); in the tile-ordered persistent form 16 for FP32 in its 1024-thread workgroups
+// (us per step: 8 rows 368, 12 352, 16 344, 20 345, 32 363, 48 379) and 64 for FP64,
+// where longer sweeps mean fewer tiles to wait for (413 against 385 solves/s with 16).
 static int t2_rows_default(int dtype, bool persistent) {
     if (!persistent)
         return 16;
-    return dtype == kF64 ? 64 : 32;
+    return dtype == kF64 ? 64 : 16;
 }
 static bool t2_whole_rows(int dtype) { return dtype != kF64; }
 static int t2_rows(const lbm_pool_tuning &t, int dtype) {
@@ -173,9 +178,9 @@ struct T2Geom {
     int w = 0, sub = 0;
     int64_t tiles = 0;
 };
-static T2Geom t2_geom(int64_t nx, int64_t ny, int dtype, int R) {
+static T2Geom t2_geom(int64_t nx, int64_t ny, int dtype, int R, bool persistent) {
     T2Geom g;
-    const int B = t2_block(dtype), TX = t2_cols(dtype);
+    const int B = t2_block(dtype, persistent), TX = t2_cols(dtype, persistent);
     const int64_t w = (nx + 63) / 64 * 64;
     if (t2_whole_rows(dtype) && w <= B) {
         g.w = (int)w;
@@ -197,7 +202,8 @@ static bool t2_counters(const lbm_config *cfg, const lbm_pool_tuning &t) {
 static size_t t2_counter_bytes(const lbm_config *cfg, const lbm_pool_tuning &t) {
     if (!t2_counters(cfg, t))
         return 0;
-    return round256(sizeof(int64_t) * (size_t)t2_geom(cfg->nx, cfg->ny, cfg->dtype, t2_rows(t, cfg->dtype)).tiles);
+    return round256(sizeof(int64_t) *
+                    (size_t)t2_geom(cfg->nx, cfg->ny, cfg->dtype, t2_rows(t, cfg->dtype), t.persistent != 0).tiles);
 }
 
 struct Slot {
@@ -613,9 +619,10 @@ static int pool_run_classes(lbm_pool *p, int64_t k, bool &any) {
                 two_nodes += p->slots[i].d.L.n;
         }
         two = two && two_nodes >= (cdtype == kF64 ? (int64_t)1 << 20 : (int64_t)1 << 22);
-        const int B = t2_block(cdtype), TX = t2_cols(cdtype);
+        const bool pers = p->tun.persistent != 0;
+        const int B = t2_block(cdtype, pers), TX = t2_cols(cdtype, pers);
         const int R = t2_rows(p->tun, cdtype);
-        auto geom = [&](int i) { return t2_geom(p->slots[i].d.cfg.nx, p->slots[i].d.cfg.ny, cdtype, R); };
+        auto geom = [&](int i) { return t2_geom(p->slots[i].d.cfg.nx, p->slots[i].d.cfg.ny, cdtype, R, pers); };
         auto whole_w = [&](int i) { return geom(i).w; };  // whole-row sub-tile width, 0 for column tiles
         int nw = 0;  // slots in the whole-row part
         if (two) {

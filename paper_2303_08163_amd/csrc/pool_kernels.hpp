@@ -145,7 +145,7 @@ __device__ __forceinline__ void pool_tile(const PoolRunArgs &a, int t, int s) {
 // t2_threads(t2_tx, elem) threads, which the whole-row form splits into
 // sub-tiles; dynamic LDS the larger of the two forms' needs.
 template <int DT, bool CORR, bool NT>
-__global__ __launch_bounds__(512) void k_pool_step2(PoolRunArgs a) {
+__global__ __launch_bounds__(1024) void k_pool_step2(PoolRunArgs a) {
     const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x) + a.tile_base;
     int lo = 0, hi = a.n - 1;  // last slot k with tile_start[k] <= t
     while (lo < hi) {
@@ -309,15 +309,15 @@ __device__ __forceinline__ int df_slot(const PoolRunArgs &a, int t) {
     return lo;
 }
 
-// Grid: G <= resident workgroups of t2_threads(t2_tx, elem) threads, the
-// larger LDS need of the two tile forms; a.tile_start holds the two-step tile
-// counts.  At least four wavefronts per SIMD: the LDS of FP32 tiles admits two
-// 512-thread workgroups per compute unit, and the registers the compiler chose
-// otherwise (140) left one (batched workload, FP32: 666 against 622 solves/s,
-// with 32 bytes of spills per lane; FP64, held to four workgroups of three
-// wavefronts by its LDS, unchanged).
+// Grid: G <= resident workgroups of the pool's two-step block (1024 threads
+// for FP32, one per compute unit by its LDS; 192 for FP64), the larger LDS
+// need of the two tile forms; a.tile_start holds the two-step tile counts.  At
+// least four wavefronts per SIMD: the registers the compiler chose otherwise
+// (140) left fewer (batched workload, FP32 with 512-thread workgroups: 666
+// against 622 solves/s, with 32 bytes of spills per lane; FP64, held to four
+// workgroups of three wavefronts by its LDS, unchanged).
 template <int DT, bool CORR, bool NT>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_pool_df2(PoolRunArgs a) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void k_pool_df2(PoolRunArgs a) {
     using T = store_t<DT>;
     const int G = (int)gridDim.x;
     const int L = xcd_tile((int)blockIdx.x, G);

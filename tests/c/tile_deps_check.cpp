@@ -59,10 +59,11 @@ int main() {
     long cases = 0;
     // whole-row tiles: row width w (64 m) >= nx, rr = sub-tiles x rows
     for (int n = 0; n < 3000; ++n) {
-        const int w = 64 * (1 + std::rand() % 8);
+        const int block = n % 2 ? 1024 : 512;  // two-step launches, tile-ordered form
+        const int w = 64 * (1 + std::rand() % (block / 64));
         const int nx = 1 + std::rand() % w;
         const int ny = 1 + std::rand() % 300;
-        const int sub = 512 / w;
+        const int sub = block / w;
         const int R = 1 + std::rand() % 40;
         if (check(nx, ny, w, sub * R, 0, 0))
             return 1;
@@ -70,9 +71,9 @@ int main() {
     }
     // column tiles of tx x rows (the last ones partial), small grids included; tiles
     // of 1 .. 3 columns make every candidate column matter
-    const int txs[6] = {128, 512, 64, 1, 2, 3};
+    const int txs[7] = {128, 512, 1024, 64, 1, 2, 3};
     for (int n = 0; n < 3000; ++n) {
-        const int tx = txs[std::rand() % 6];
+        const int tx = txs[std::rand() % 7];
         const int nx = 1 + std::rand() % (n < 1500 ? 3 * tx + 2 : 8);
         const int ny = 1 + std::rand() % (n % 2 ? 200 : 6);
         const int rows = 1 + std::rand() % 33;
@@ -82,7 +83,7 @@ int main() {
     }
     // a last tile of one or two columns, whose left neighbour across the wrap is two
     // tiles away from tile 0 (nx = k tx + 1 or + 2)
-    for (int tx : {64, 128, 512})
+    for (int tx : {64, 128, 512, 1024})
         for (int k = 1; k <= 3; ++k)
             for (int extra = 1; extra <= 2; ++extra)
                 for (int rows : {1, 2, 16})

@@ -260,11 +260,13 @@ def test_pool_host_logic(lbm):
     assert lbm.lbm_pool_slot_bytes(cfg, lbm.make_pool_tuning(time_block=2)) == lbm.lbm_pool_slot_bytes(cfg)
     # the tile-ordered persistent form keeps one 8-byte counter per two-step tile after the
     # buffers of D2Q9 FP64 and FP32-deviation slots (rounded up to 256 bytes): FP64 column
-    # tiles of 128 x 64, FP32 whole-row tiles (row 300 -> 320 lanes, one sub-tile of 32 rows)
+    # tiles of 128 x 64; FP32 in 1024-thread workgroups, whole-row tiles of 16-row sub-tiles
+    # (row 300 -> 320 lanes, three sub-tiles) or column tiles of 1024 x 16
     to = lbm.make_pool_tuning(time_block=2, persistent=1)
     for kw, extra in [(dict(shape=(300, 1000)), 256 * 2),  # 3 x 16 tiles: 384 bytes
-                      (dict(shape=(300, 1000), dtype="fp32_dev"), 256),  # 32 tiles
-                      (dict(shape=(600, 1000), dtype="fp32_dev"), 256 * 2),  # 2 x 32 column tiles of 512
+                      (dict(shape=(300, 1000), dtype="fp32_dev"), 256),  # 21 tiles of 48 rows
+                      (dict(shape=(600, 1000), dtype="fp32_dev"), 256 * 2),  # rows of 640 lanes: 63 tiles
+                      (dict(shape=(1500, 1000), dtype="fp32_dev"), 256 * 4),  # 2 x 63 column tiles of 1024
                       (dict(), 256),  # 1 x 2 tiles
                       (dict(shape=(300, 1000), dtype="fp32_dev_mixed"), 0),
                       (dict(lattice=27, shape=(16, 16, 16), dtype="fp32_dev"), 0)]:

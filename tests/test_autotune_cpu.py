@@ -45,7 +45,7 @@ def test_candidate_sets():
     # persistent by default: only the tile-ordered two-step form (no grid barrier)
     assert default and all(c["persistent"] == 0 or c.get("time_block") == 2 for c in default)
     ordered = [c for c in default if c["persistent"] == 1]
-    assert ordered and sorted(c["time_rows"] for c in ordered) == [0, 64]
+    assert ordered and sorted(c["time_rows"] for c in ordered) == [0, 32]
     both = autotune.candidates(persistent=True)
     two = [c for c in default if c.get("time_block") == 2]  # no grid-barrier variant of these
     assert two and len(both) == 2 * len(default) - len(two)
