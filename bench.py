@@ -685,7 +685,9 @@ def bench_stability(cpu_budget_s: float = 5.0, with_cpu: bool = True) -> dict:
 def env_info() -> dict:
     """ROCm version and the GPU's clocks as rocm-smi reports them, read in a
     child process before this process touches the GPU (rocm-smi reads the
-    driver's sysfs files; a failure is recorded, not raised)."""
+    driver's sysfs files; a failure is recorded, not raised).  Under rocprofv3
+    the clocks are not read: its preloaded library initialises the GPU in every
+    process it starts, and rocm-smi re-executes itself through its interpreter."""
     import subprocess
     env = {}
     try:
@@ -693,6 +695,9 @@ def env_info() -> dict:
             env["rocm"] = f.read().strip()
     except OSError:
         env["rocm"] = None
+    if any(k.startswith("ROCPROF_") for k in os.environ) or "rocprof" in os.environ.get("LD_PRELOAD", ""):
+        env["rocm_smi_clocks_at_start"] = "not read under rocprofv3"
+        return env
     try:
         r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=30)
         data = json.loads(r.stdout) if r.returncode == 0 else None
