@@ -16,13 +16,11 @@ namespace lbm {
 
 constexpr int kVnThreads = 64;  // one wavefront per workgroup
 
-// Largest v over the wavefront (all 64 lanes take part).
-__device__ __forceinline__ int wave_max_int(int v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-        v = max(v, __shfl_xor(v, off, 64));
-    return v;
-}
+// Largest v over the wavefront (all 64 lanes take part): the device
+// library's reduction, by lane moves within and across rows of 16 lanes and
+// two lane reads, with none of the round trips through LDS that a shuffle
+// takes (the QR loop waits on this value after every step).
+__device__ __forceinline__ int wave_max_int(int v) { return __ockl_wfred_max_i32(v); }
 
 struct VnSpectraArgs {
     const double *cases;  // count x 5: tau, u_x, u_y, k_x, k_y
