@@ -69,6 +69,31 @@ def test_spectra_match_lapack(D, kind, corr):
           f"QR steps mean {info.mean():.1f} max {info.max()}", flush=True)
 
 
+@pytest.mark.parametrize("D", [1, 2])
+def test_spectra_independent_of_wavefront_grouping(D):
+    """QR steps sweep the largest active block of any lane of the wavefront, but
+    the rows past a lane's own block see only exact identities (zero
+    subdiagonals, no shift), so a matrix's eigenvalues and step count do not
+    depend on the cases that share its wavefront: a permuted order (1000 cases,
+    a ragged last wavefront) and cases run alone (a wavefront of one live lane)
+    give bitwise the same results.  Adding 0.0 maps -0 to +0, the one change an
+    identity rotation may make."""
+    vn = _vn()
+    cases = random_cases(D, 1000, seed=77 + D)
+    perm = np.random.default_rng(3).permutation(len(cases))
+    r1, e1, i1 = vn.spectra(cases, dim=D, equilibrium="product")
+    r2, e2, i2 = vn.spectra(cases[perm], dim=D, equilibrium="product")
+    assert np.all(i1 >= 0)
+    assert np.array_equal(i1[perm], i2)
+    assert np.array_equal(r1[perm], r2)
+    assert np.array_equal(e1[perm] + 0.0, e2 + 0.0)
+    for t in (0, 5, 6, 100, 999, int(np.argmax(i1)), int(np.argmin(i1))):
+        ra, ea, ia = vn.spectra(cases[t:t + 1], dim=D, equilibrium="product")
+        assert ia[0] == i1[t] and ra[0] == r1[t], t
+        assert np.array_equal(ea[0] + 0.0, e1[t] + 0.0), t
+    print(f"[vn] D{D}: QR steps per case {i1.min()}..{i1.max()}, grouping-independent", flush=True)
+
+
 @pytest.mark.parametrize("kind", KINDS)
 def test_k0_spectrum(kind):
     vn = _vn()
