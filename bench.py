@@ -614,13 +614,14 @@ def bench_stability(cpu_budget_s: float = 5.0, with_cpu: bool = True) -> dict:
 
     thetas = [math.radians(5 * a) for a in range(19)]
     out = {"workload": "D2Q9 von Neumann stability domains: 15 nu x 19 theta x 3 equilibria, "
-                       "k grid 33^2 on [0, pi]^2, 24 bisection steps, FP64"}
+                       "k grid 33^2 on [0, pi]^2, 24 bisection steps run in lockstep for the three "
+                       "equilibria (one host wait per step), FP64"}
     table = {}
     total_m = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for eq in ("entropic", "poly2", "product"):
-        umax, st = vn.stability_domain(vn.PAPER_NUS, thetas, equilibrium=eq, nk=33, iters=24)
+    for eq, (umax, st) in vn.stability_domains(vn.PAPER_NUS, thetas, ("entropic", "poly2", "product"), nk=33,
+                                               iters=24).items():
         total_m += st["matrices"]
         table[eq] = {"u_max_theta0": [round(float(v), 5) for v in umax[:, 0]],
                      "u_max_theta45": [round(float(v), 5) for v in umax[:, 9]],

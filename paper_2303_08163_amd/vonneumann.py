@@ -13,6 +13,10 @@ stability_domain():  largest stable speed |u| per (nu, theta), theta the angle
                      [0, pi]^2; here |lambda| <= 1 + tol, tol absorbing
                      rounding).  The stable set along a direction is read as
                      the interval [0, u_max).
+stability_domains(): the same for several equilibria in lockstep: each
+                     bisection step enqueues one call per equilibrium and
+                     waits once, so the host's round trip between steps is
+                     paid once per step, not once per call.
 Every matrix and eigenvalue is computed in the library's kernels; the host
 only forms the inputs and keeps the bisection brackets.
 """
@@ -70,26 +74,39 @@ class RadiusEvaluator:
         self.dim, self.eq, self.corr, self.nk = dim, equilibrium, bulk_correction, nk
         self.device = torch.device(device)
         self.capacity = n_states
+        # pinned staging, so that enqueueing a call does not wait for the stream
+        self.host_states = torch.empty((n_states, 3), dtype=torch.float64, pin_memory=True)
         self.states = torch.empty((n_states, 3), dtype=torch.float64, device=self.device)
         self.rmax = torch.empty(n_states, dtype=torch.float64, device=self.device)
         self.scratch = torch.empty(n_states, dtype=torch.int64, device=self.device)
         self.unconverged = torch.zeros(1, dtype=torch.int32, device=self.device)
         self.stream = torch.cuda.current_stream(self.device)
         self.matrices = 0
+        self.n = 0
 
-    def __call__(self, states: np.ndarray):
-        """states (n, 3): tau, u_x, u_y.  Returns (max radius (n,), unconverged count)."""
-        import torch
+    def launch(self, states: np.ndarray) -> None:
+        """Enqueue one call over states (n, 3): tau, u_x, u_y (no wait).  The
+        staging buffer is reused, so result() must come before the next launch."""
         n = states.shape[0]
         if n > self.capacity:
             raise ValueError("more states than the evaluator holds")
-        self.states[:n].copy_(torch.from_numpy(np.ascontiguousarray(states, dtype=np.float64)))
+        self.host_states[:n].numpy()[:] = states
+        self.states[:n].copy_(self.host_states[:n], non_blocking=True)
         lbm.lbm_vn_max_radius(_lattice(self.dim), self.eq, self.corr, self.states.data_ptr(), n, self.nk,
                               self.rmax.data_ptr(), self.scratch.data_ptr(), self.unconverged.data_ptr(),
                               self.stream.cuda_stream)
         self.matrices += n * self.nk ** self.dim
-        r = self.rmax[:n].cpu().numpy()  # synchronises the stream
+        self.n = n
+
+    def result(self):
+        """(max radius (n,), unconverged count) of the last launch; waits for it."""
+        r = self.rmax[:self.n].cpu().numpy()  # synchronises the stream
         return r, int(self.unconverged.item())
+
+    def __call__(self, states: np.ndarray):
+        """states (n, 3): tau, u_x, u_y.  Returns (max radius (n,), unconverged count)."""
+        self.launch(np.asarray(states, dtype=np.float64))
+        return self.result()
 
 
 def max_radius(states, dim: int = 2, equilibrium="entropic", bulk_correction=False, nk: int = 33,
@@ -99,38 +116,53 @@ def max_radius(states, dim: int = 2, equilibrium="entropic", bulk_correction=Fal
     return ev(states)
 
 
-def stability_domain(nus, thetas, equilibrium="entropic", bulk_correction=False, nk: int = 33, iters: int = 24,
-                     tol: float = 1e-9, device="cuda:0"):
-    """Largest stable speed for every (nu, theta) pair; returns (u_max array of
-    shape (len(nus), len(thetas)), stats dict)."""
+def stability_domains(nus, thetas, equilibria=("entropic", "poly2", "product"), bulk_correction=False,
+                      nk: int = 33, iters: int = 24, tol: float = 1e-9, device="cuda:0"):
+    """Largest stable speed for every (nu, theta) pair and every equilibrium;
+    returns {equilibrium: (u_max array of shape (len(nus), len(thetas)), stats
+    dict)}.  The bisections run in lockstep (one wait per step for all
+    equilibria); each equilibrium's calls and results are those of
+    stability_domain alone."""
     nus = np.asarray(nus, dtype=np.float64)
     thetas = np.asarray(thetas, dtype=np.float64)
     P = len(nus) * len(thetas)
     nu_p = np.repeat(nus, len(thetas))
     th_p = np.tile(thetas, len(nus))
     tau_p = 0.5 + nu_p / NU_PER_TAU
-    s_max = 1.0 / np.maximum(np.abs(np.cos(th_p)), np.abs(np.sin(th_p)))
-    ev = RadiusEvaluator(P, 2, equilibrium, bulk_correction, nk, device)
-    unconverged = 0
+    cos_p, sin_p = np.cos(th_p), np.sin(th_p)
+    s_max = 1.0 / np.maximum(np.abs(cos_p), np.abs(sin_p))
+    evs = {eq: RadiusEvaluator(P, 2, eq, bulk_correction, nk, device) for eq in equilibria}
+    unconverged = {eq: 0 for eq in equilibria}
 
-    def stable(speed):
-        nonlocal unconverged
-        st = np.stack([tau_p, speed * np.cos(th_p), speed * np.sin(th_p)], axis=1)
-        r, bad = ev(st)
-        unconverged += bad
-        return r <= 1.0 + tol
+    def stable(speeds):
+        for eq, ev in evs.items():
+            ev.launch(np.stack([tau_p, speeds[eq] * cos_p, speeds[eq] * sin_p], axis=1))
+        out = {}
+        for eq, ev in evs.items():
+            r, bad = ev.result()
+            unconverged[eq] += bad
+            out[eq] = r <= 1.0 + tol
+        return out
 
-    lo = np.zeros(P)
-    hi = s_max.copy()
-    ok0 = stable(np.zeros(P))
+    lo = {eq: np.zeros(P) for eq in equilibria}
+    hi = {eq: s_max.copy() for eq in equilibria}
+    ok0 = stable({eq: np.zeros(P) for eq in equilibria})
     for _ in range(iters):
-        mid = 0.5 * (lo + hi)
+        mid = {eq: 0.5 * (lo[eq] + hi[eq]) for eq in equilibria}
         s = stable(mid)
-        lo = np.where(s, mid, lo)
-        hi = np.where(s, hi, mid)
-    lo = np.where(ok0, lo, 0.0)
-    return lo.reshape(len(nus), len(thetas)), {"matrices": ev.matrices, "unconverged": unconverged,
-                                                "calls": iters + 1}
+        for eq in equilibria:
+            lo[eq] = np.where(s[eq], mid[eq], lo[eq])
+            hi[eq] = np.where(s[eq], hi[eq], mid[eq])
+    return {eq: (np.where(ok0[eq], lo[eq], 0.0).reshape(len(nus), len(thetas)),
+                 {"matrices": evs[eq].matrices, "unconverged": unconverged[eq], "calls": iters + 1})
+            for eq in equilibria}
+
+
+def stability_domain(nus, thetas, equilibrium="entropic", bulk_correction=False, nk: int = 33, iters: int = 24,
+                     tol: float = 1e-9, device="cuda:0"):
+    """Largest stable speed for every (nu, theta) pair; returns (u_max array of
+    shape (len(nus), len(thetas)), stats dict)."""
+    return stability_domains(nus, thetas, (equilibrium,), bulk_correction, nk, iters, tol, device)[equilibrium]
 
 
 PAPER_NUS = [1e-6, 5e-6, 1e-5, 5e-5, 1e-4, 5e-4, 1e-3, 5e-3, 1e-2, 5e-2, 0.1, 0.5, 1.0, 1.1, 1.2]

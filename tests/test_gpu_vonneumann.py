@@ -150,6 +150,23 @@ def test_stability_domain_matches_oracle_bisection():
                 assert abs(got[a, b] - ref) <= s_max * 2.0 ** (1 - iters), (kind, nu, th, got[a, b], ref)
 
 
+@pytest.mark.parametrize("corr", [False, True])
+def test_stability_domains_lockstep_equals_separate(corr):
+    """The lockstep sweep over three equilibria (one host wait per bisection
+    step) gives each equilibrium exactly the domain, call count and matrix count
+    of its own sweep."""
+    vn = _vn()
+    nus = [1e-6, 1e-3, 0.5]
+    thetas = [0.0, math.pi / 8, math.pi / 4, math.pi / 2]
+    together = vn.stability_domains(nus, thetas, KINDS, bulk_correction=corr, nk=17, iters=16)
+    assert list(together) == KINDS
+    for kind in KINDS:
+        alone, st = vn.stability_domain(nus, thetas, equilibrium=kind, bulk_correction=corr, nk=17, iters=16)
+        got, st_t = together[kind]
+        assert np.array_equal(got, alone), kind
+        assert st_t == st and st["unconverged"] == 0, (kind, st_t, st)
+
+
 def test_paper_stability_limits_on_gpu():
     """Sec. "Linear stability domain": polynomial equilibria stop at
     1 - varsigma at large viscosity, the product form reaches 0.598 on the
