@@ -561,8 +561,11 @@ int lbm_pool_destroy(lbm_pool *pool);
  *   info    device pointer to count int32: QR steps taken, or -1 when the
  *           iteration limit (30 Q steps) was reached first (NULL: not written).
  *   flops   device pointer to count doubles: FP64 operations the solver spent
- *           on the case, counting its own active block at every QR step (a
- *           fused multiply-add counts 2) (NULL: not written).
+ *           on the case, counting its own active block at every QR step
+ *           (additions, multiplications, divisions, square roots, sines and
+ *           cosines 1, a fused multiply-add 2, the refined reciprocal square
+ *           root 2; absolute values, maxima and comparisons 0) (NULL: not
+ *           written).
  *   stream  hipStream_t (NULL = the null stream).
  * Enqueues one kernel and returns without synchronising.  Errors: LBM_EINVAL
  * (lattice other than D1Q3/D2Q9, bad equilibrium or bulk_correction, count < 0,

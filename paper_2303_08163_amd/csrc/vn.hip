@@ -46,7 +46,7 @@ __global__ __launch_bounds__(kVnThreads) void k_vn_spectra(VnSpectraArgs a) {
     cplx H[N][N];
     vn_matrix<DIM, EQ, CORR>(tau, u, k, H);
     hessenberg<N>(H);
-    double work = vn_fixed_flops<N>();
+    double work = vn_build_flops<DIM, EQ, CORR>() + vn_reduce_flops<N>();
     const int steps = hessenberg_eigenvalues<N>(H, wave_max_int, &work);
     if (!live)
         return;

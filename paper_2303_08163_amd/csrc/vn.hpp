@@ -330,29 +330,61 @@ __host__ __device__ __forceinline__ void qr_step(cplx (&H)[N][N], cplx mu, int h
     });
 }
 
-// FP64 operations (a fused multiply-add counts 2; divisions, square roots and
-// transcendentals 1; the refined reciprocal square root that forms a rotation
-// counts 2, as the square root and the division it stands for) of the solver
-// as written: building M, the Householder
-// reduction and the norm (fixed), and one QR step on an active block of M
-// rows (its rotations, the shift on M rows, the deflation scan and the shift
-// choice).  Used to report the arithmetic rate; they count each matrix's own
-// active block, not the wavefront's common one.
+// Operation counts, used to report the solver's arithmetic rate: the FP64
+// operations the code performs for one matrix's own work.  Additions,
+// subtractions, multiplications, divisions, square roots, sines and cosines
+// count 1, a fused multiply-add 2, the refined reciprocal square root 2 (as the
+// square root and division it stands for); absolute values, maxima,
+// comparisons, selects and negations count 0.  A QR step counts the matrix's
+// own active block of m rows, not the wavefront's common one, and the shift's
+// subtraction and return 1 per component each (written as fused multiply-adds
+// with a factor 0 or 1).
+//
+// Building M (vn_matrix, without or with the correction's relaxation rate).
+template <int DIM, int EQ, bool CORR>
+__host__ __device__ constexpr double vn_build_flops() {
+    constexpr double N = DIM == 1 ? 3.0 : 9.0;
+    // per axis: the factors g_c(u_a) and their derivatives (entropic: S,
+    // the three factors, u / S and three derivatives; product form: seven
+    // for the factors, three derivatives)
+    const double axis = EQ == kEqEntropic ? 16.0 : (EQ == kEqProduct ? 10.0 : 0.0);
+    // per population: U_0 and U_a (product forms: products of factors; the
+    // polynomial: c.u, U_0 and U_a from it), once: u^2, 1 - 1.5 u^2, 3 u_a
+    const double per_i = EQ == kEqPoly2 ? (DIM - 1.0) + 5.0 + 5.0 * DIM : (DIM == 2 ? 3.0 : 0.0);
+    const double once = EQ == kEqPoly2 ? 2.0 * DIM + 2.0 + DIM : 0.0;
+    const double omega = !CORR ? 1.0 : (EQ == kEqEntropic ? 25.0 : 8.0);
+    // sin and cos of each k_a; the four diagonal moves' phase products
+    const double phases = 2.0 * DIM + (DIM == 2 ? 4.0 * 6.0 : 0.0);
+    // c_ja - u_a; per entry P_ij (one fused multiply-add per axis), omega P_ij,
+    // times E_ii (2); the diagonal's 1 - omega and its addition
+    const double entries = 3.0 * DIM + N * N * (2.0 * DIM + 3.0) + 1.0 + N;
+    return DIM * axis + N * per_i + once + omega + phases + entries;
+}
+// The Householder reduction (a reflector of length m = N - 1 .. 2: its norm
+// 4 m, alpha, |x0| and phase 9, v 4, tau 3, the left update m (16 m + 2), the
+// right update N (16 m + 2), the new subdiagonal 2), the deflation scan before
+// the first step (5 per row), the norm of the Hessenberg part (one addition per
+// entry, times 1e-2) and the radius (|lambda|^2 of each eigenvalue, one square
+// root).
 template <int N>
-__host__ __device__ constexpr double vn_fixed_flops() {
+__host__ __device__ constexpr double vn_reduce_flops() {
     double h = 0.0;
     for (int m = 2; m <= N - 1; ++m)
-        h += 16.0 * m * m + (6.0 + 16.0 * N) * m + 2.0 * N + 14.0;
-    const double build = 9.0 * N * N + 15.0 * N + 40.0 + (N == 9 ? 4.0 + 24.0 : 2.0);
-    const double norm = 3.0 * (N * (N + 1) / 2 + N - 1) + 4.0 * N;
-    return h + build + norm;
+        h += 16.0 * m * m + (6.0 + 16.0 * N) * m + 2.0 * N + 18.0;
+    const double deflation = 5.0 * (N - 1);
+    const double norm = N * (N + 1) / 2 + (N - 1) + 1.0;
+    const double radius = 3.0 * N + 1.0;
+    return h + deflation + norm + radius;
 }
-__host__ __device__ constexpr double vn_step_flops(int M) {
-    // per rotation: applying it to two rows and two columns (20 M) and
-    // forming it from squared norms (19) with the rest of its bookkeeping (46);
-    // per step: the shift on M rows and back (4 M), the deflation scan and the
-    // shift choice (150)
-    return (M - 1) * (20.0 * M + 65.0) + 4.0 * M + 150.0;
+// One QR step on an active block of m rows.  Per rotation: forming it (20)
+// and applying it to rows k, k + 1 of columns k..m-1 (10 for column k, whose
+// lower entry is set to zero, 20 for each other) and to rows 0..k+1 of columns
+// k, k + 1 (20 each): 20 m + 50.  Per step: the deflation scan (5 per row
+// below the first), the shift (52: the trailing 2 x 2's eigenvalue nearer its
+// last diagonal entry and the exceptional shift, both formed) and its
+// subtraction and return on the block's rows (4 m).
+__host__ __device__ constexpr double vn_step_flops(int m) {
+    return (m - 1) * (20.0 * m + 55.0) + 4.0 * m + 52.0;
 }
 
 // Eigenvalues of an upper Hessenberg matrix (overwritten; the diagonal holds
