@@ -80,18 +80,23 @@ class RadiusEvaluator:
         self.rmax = torch.empty(n_states, dtype=torch.float64, device=self.device)
         self.scratch = torch.empty(n_states, dtype=torch.int64, device=self.device)
         self.unconverged = torch.zeros(1, dtype=torch.int32, device=self.device)
-        self.stream = torch.cuda.current_stream(self.device)
+        # a stream of its own (default priority): the calls of evaluators run in
+        # lockstep overlap on the GPU, one kernel's last wavefronts beside the
+        # next one's first
+        self.stream = torch.cuda.Stream(device=self.device)
         self.matrices = 0
         self.n = 0
 
     def launch(self, states: np.ndarray) -> None:
         """Enqueue one call over states (n, 3): tau, u_x, u_y (no wait).  The
         staging buffer is reused, so result() must come before the next launch."""
+        import torch
         n = states.shape[0]
         if n > self.capacity:
             raise ValueError("more states than the evaluator holds")
         self.host_states[:n].numpy()[:] = states
-        self.states[:n].copy_(self.host_states[:n], non_blocking=True)
+        with torch.cuda.stream(self.stream):
+            self.states[:n].copy_(self.host_states[:n], non_blocking=True)
         lbm.lbm_vn_max_radius(_lattice(self.dim), self.eq, self.corr, self.states.data_ptr(), n, self.nk,
                               self.rmax.data_ptr(), self.scratch.data_ptr(), self.unconverged.data_ptr(),
                               self.stream.cuda_stream)
@@ -100,8 +105,11 @@ class RadiusEvaluator:
 
     def result(self):
         """(max radius (n,), unconverged count) of the last launch; waits for it."""
-        r = self.rmax[:self.n].cpu().numpy()  # synchronises the stream
-        return r, int(self.unconverged.item())
+        import torch
+        with torch.cuda.stream(self.stream):
+            r = self.rmax[:self.n].cpu().numpy()  # waits for the evaluator's stream
+            bad = int(self.unconverged.item())
+        return r, bad
 
     def __call__(self, states: np.ndarray):
         """states (n, 3): tau, u_x, u_y.  Returns (max radius (n,), unconverged count)."""
