@@ -84,6 +84,8 @@ class RadiusEvaluator:
         # lockstep overlap on the GPU, one kernel's last wavefronts beside the
         # next one's first
         self.stream = torch.cuda.Stream(device=self.device)
+        for t in (self.states, self.rmax, self.scratch, self.unconverged):
+            t.record_stream(self.stream)  # not reused before that stream's work is done
         self.matrices = 0
         self.n = 0
 
