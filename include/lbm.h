@@ -337,6 +337,22 @@ int lbm_load_state(lbm_handle *h, const void *src, size_t bytes, int64_t steps);
  * LBM_EDEVICE. */
 int lbm_energy(lbm_handle *h, const double *U, double rho_ref, double *out);
 
+/* An energy history over a run (Sec. "Validation via dissipation of isothermal
+ * pressure waves": the decay of E(t) gives the effective viscosity): the
+ * energy of lbm_energy before the first step and after every `every` steps of
+ * lbm_step, over `steps` steps, all enqueued by this one call.
+ *   steps  >= 0, a multiple of every;  every >= 1.
+ *   U, rho_ref  as for lbm_energy.
+ *   out    device pointer to steps / every + 1 doubles: out[k] is the energy
+ *          after k * every steps, written when the stream reaches it.
+ * The same kernels run in the same order as the calls made one by one, so the
+ * values and the final state are bitwise theirs.  Returns without
+ * synchronising.  Errors: LBM_EINVAL (those of lbm_energy; every < 1, steps
+ * < 0 or not a multiple of every; a z-slab domain), checked before anything is
+ * enqueued; LBM_EDEVICE (the work enqueued before the failing launch stays
+ * enqueued). */
+int lbm_energy_history(lbm_handle *h, int64_t steps, int64_t every, const double *U, double rho_ref, double *out);
+
 /* Measurement aids (not part of the method): the speed of the access pattern
  * alone, as the ceiling against which the stream-collide kernel is read.
  *

@@ -1020,6 +1020,24 @@ int lbm_energy(lbm_handle *h, const double *U, double rho_ref, double *out) {
     return domain_energy(h->d, h->stream, U, rho_ref, out);
 }
 
+int lbm_energy_history(lbm_handle *h, int64_t steps, int64_t every, const double *U, double rho_ref, double *out) {
+    if (!h || !out || every < 1 || steps < 0 || steps % every != 0) {
+        set_error("NULL handle or output, every < 1, or steps not a non-negative multiple of every");
+        return LBM_EINVAL;
+    }
+    if (h->d.L.zhalo) {
+        set_error("a z-slab's steps need halo exchanges between them");
+        return LBM_EINVAL;
+    }
+    int rc = lbm_energy(h, U, rho_ref, out);  // also checks U and rho_ref
+    for (int64_t k = 1; rc == LBM_OK && k <= steps / every; ++k) {
+        rc = lbm_step(h, every);
+        if (rc == LBM_OK)
+            rc = domain_energy(h->d, h->stream, U, rho_ref, out + k);
+    }
+    return rc;
+}
+
 // Checkpoint / restart: the stored population buffer holding the current
 // state (whole, including row padding and a z-slab's halo planes), copied
 // device to device on the handle's stream.

@@ -114,7 +114,7 @@ _lib = None
 
 # Exported symbols the header declares (checked by the CPU test suite).
 EXPORTS = ("lbm_workspace_bytes", "lbm_workspace_bytes_tuned", "lbm_create", "lbm_create_tuned",
-           "lbm_step", "lbm_moments", "lbm_get_populations", "lbm_energy", "lbm_destroy", "lbm_status_string",
+           "lbm_step", "lbm_moments", "lbm_get_populations", "lbm_energy", "lbm_energy_history", "lbm_destroy", "lbm_status_string",
            "lbm_last_error", "lbm_version", "lbm_pool_table_bytes", "lbm_pool_slot_bytes", "lbm_pool_create",
            "lbm_pool_admit", "lbm_pool_run", "lbm_pool_poll", "lbm_pool_moments", "lbm_pool_get_populations",
            "lbm_pool_release", "lbm_pool_stats_get", "lbm_pool_slot_info", "lbm_pool_destroy",
@@ -154,6 +154,7 @@ def load_library(path: str = LIB_PATH):
         "lbm_ceiling_stream": (ctypes.c_int, [vp, i64]),
         "lbm_ceiling_copy": (ctypes.c_int, [vp, vp, sz, vp]),
         "lbm_energy": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_double, vp]),
+        "lbm_energy_history": (ctypes.c_int, [vp, i64, i64, ctypes.POINTER(ctypes.c_double), ctypes.c_double, vp]),
         "lbm_halo_bytes": (sz, [cfgp]),
         "lbm_halo_pack": (ctypes.c_int, [vp, vp, vp]),
         "lbm_halo_unpack": (ctypes.c_int, [vp, vp, vp]),
@@ -313,6 +314,14 @@ def lbm_energy(h, U, rho_ref: float, out: int) -> None:
     """Enqueue E about (rho_ref, U) into the device double at address out."""
     arr = None if U is None else (ctypes.c_double * 3)(*[float(v) for v in U] + [0.0] * (3 - len(U)))
     _check(load_library().lbm_energy(h, arr, float(rho_ref), out), "lbm_energy")
+
+
+def lbm_energy_history(h, steps: int, every: int, U, rho_ref: float, out: int) -> None:
+    """Enqueue steps // every + 1 energies, every `every` steps of a run, into
+    the device doubles at address out."""
+    arr = None if U is None else (ctypes.c_double * 3)(*[float(v) for v in U] + [0.0] * (3 - len(U)))
+    _check(load_library().lbm_energy_history(h, int(steps), int(every), arr, float(rho_ref), out),
+           "lbm_energy_history")
 
 
 def lbm_vn_spectra(lattice: int, equilibrium, bulk_correction, cases: int, count: int, radius, eig, info,
@@ -585,6 +594,19 @@ class Domain:
         if out.dtype != torch.float64 or not out.is_cuda:
             raise ValueError("out must be a float64 CUDA tensor")
         lbm_energy(self.handle, U, rho_ref, out.data_ptr())
+        return out
+
+    def energy_history(self, steps: int, every: int, U=None, rho_ref: float = 1.0, out=None):
+        """Enqueue `steps` steps with the energy recorded before the first and
+        after every `every` (no synchronisation).  out: a float64 CUDA tensor
+        of steps // every + 1 elements (a new one when None).  Returns it."""
+        import torch
+        n = steps // every + 1 if every > 0 else 0
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=self.device)
+        if out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous() or out.numel() < n:
+            raise ValueError("out must be a contiguous float64 CUDA tensor of steps // every + 1 elements")
+        lbm_energy_history(self.handle, steps, every, U, rho_ref, out.data_ptr())
         return out
 
     def close(self) -> None:

@@ -11,7 +11,7 @@ least-squares slope of log E(t) gives nu_eff = -slope / (2 k^2).  Without the
 bulk correction nu_eff / nu follows A(U0); with it, it returns close to 1.
 
 Every step and every energy reduction runs in the library's kernels; the
-energy history is recorded on the device (lbm_energy into one float64 tensor)
+energy history is recorded on the device (lbm_energy_history: the whole run in one call)
 and read once, so the host does not synchronise inside the run.  Only the
 final log-linear fit runs on the host.
 """
@@ -45,7 +45,6 @@ def energy_history(nx: int, drho: float, U0: float, tau: float, steps: int, ever
                    dim: int = 1, width: int = 1, rho0: float = 1.0, device="cuda:0"):
     """Run the wave for `steps` steps and return (t, E(t)) sampled every
     `every` steps (t = 0 included), plus the run's final diagnostics."""
-    import torch
     if steps % every:
         raise ValueError("steps must be a multiple of every")
     rho, u = wave_fields(nx, drho, U0, rho0, dim, width)
@@ -53,11 +52,7 @@ def energy_history(nx: int, drho: float, U0: float, tau: float, steps: int, ever
     n = steps // every
     with lbm.Domain(rho, u, tau, dtype=dtype, bulk_correction=bulk_correction, rho0=rho0,
                     equilibrium=equilibrium, device=device) as d:
-        hist = torch.empty(n + 1, dtype=torch.float64, device=d.device)
-        d.energy(U, rho0, out=hist[0:1])
-        for k in range(1, n + 1):
-            d.step(every)
-            d.energy(U, rho0, out=hist[k:k + 1])
+        hist = d.energy_history(steps, every, U, rho0)
         _, _, diag = d.moments(fields=False)  # synchronises; raises on a domain error
         E = hist.cpu().numpy()
     return np.arange(n + 1, dtype=np.int64) * every, E, diag

@@ -205,6 +205,11 @@ def test_vn_argument_checks(lbm):
     assert lib.lbm_vn_max_radius(1, 0, 0, 256, 4, 33, 256, 256, 256, None) == E
 
 
+def test_energy_history_null_handle(lbm):
+    lib = lbm.load_library()
+    assert lib.lbm_energy_history(None, 10, 10, None, 1.0, 256) == lbm.LBM_EINVAL
+
+
 def test_create_argument_checks_precede_gpu_work(lbm):
     lib = lbm.load_library()
     cfg = _cfg(lbm)

@@ -154,6 +154,36 @@ def test_energy_argument_checks():
         assert float(out.item()) == pytest.approx(energy_np(rho0, u0, [0.0]), rel=1e-12)
 
 
+@pytest.mark.parametrize("dtype", ["fp64", "fp32_dev"])
+def test_energy_history_equals_calls_one_by_one(dtype):
+    """lbm_energy_history enqueues the same kernels as lbm_energy and
+    lbm_step called one by one: the energies and the final populations are
+    bitwise theirs (D1Q3 with eight steps per launch and a remainder of 5 per
+    interval, and D2Q9); bad arguments are refused before anything runs."""
+    import torch
+    lbm = _lbm()
+    for shape in ((300,), (40, 24)):
+        rho0, u0 = workloads.random_field(shape, seed=97, umax=0.1)
+        with lbm.Domain(rho0, u0, 0.6, dtype=dtype) as a, lbm.Domain(rho0, u0, 0.6, dtype=dtype) as b:
+            U = [0.05] + [0.0] * (len(shape) - 1)
+            ha = a.energy_history(65, 13, U, 1.02)
+            hb = torch.empty(6, dtype=torch.float64, device=b.device)
+            b.energy(U, 1.02, out=hb[0:1])
+            for k in range(1, 6):
+                b.step(13)
+                b.energy(U, 1.02, out=hb[k:k + 1])
+            torch.cuda.synchronize()
+            assert torch.equal(ha, hb), shape
+            assert np.array_equal(a.populations(), b.populations()), shape
+            for steps, every in ((10, 0), (10, 3), (-2, 1)):
+                with pytest.raises(lbm.LBMError) as e:
+                    a.energy_history(steps, every, U, 1.0, out=ha)
+                assert e.value.status == lbm.LBM_EINVAL
+            with pytest.raises(lbm.LBMError):
+                a.energy_history(13, 13, U, float("nan"), out=ha)
+            assert a.moments(fields=False)[2]["steps"] == 65
+
+
 # --- pressure-wave workload --------------------------------------------------
 
 @pytest.mark.parametrize("eq", ["entropic", "product"])
