@@ -576,7 +576,10 @@ __global__ __launch_bounds__(256) void k_stream_collide_t1(StepKArgs a) {
     const T *__restrict__ src = static_cast<const T *>(a.src);
     T *__restrict__ dst = static_cast<T *>(a.dst);
     const int w = a.tx + 2 * a.K;  // segment length
-    T *buf[2] = {reinterpret_cast<T *>(t1_lds), reinterpret_cast<T *>(t1_lds) + 3 * w};
+    // the two buffers at offsets 0 and 3 w of the LDS array: offsets, not a
+    // chosen pointer, so that every access keeps the LDS address space (a
+    // pointer picked from an array of two compiles to flat accesses)
+    T *lds = reinterpret_cast<T *>(t1_lds);
     const int x0 = (int)blockIdx.x * a.tx;
     const int nthr = (int)blockDim.x;
     auto wrap = [&](int x) { return x < 0 ? x + a.nx : (x >= a.nx ? x - a.nx : x); };
@@ -598,19 +601,18 @@ __global__ __launch_bounds__(256) void k_stream_collide_t1(StepKArgs a) {
         } else {
 #pragma unroll
             for (int i = 0; i < 3; ++i)
-                buf[0][i * w + m] = f[i];
+                lds[i * w + m] = f[i];
         }
     }
     // steps 2 .. K from LDS; the last one stores the owned positions
     for (int j = 2; j <= a.K; ++j) {
         __syncthreads();
-        const T *in = buf[j & 1 ? 1 : 0];
-        T *out = buf[j & 1 ? 0 : 1];
+        const int in = j & 1 ? 3 * w : 0, out = 3 * w - in;
         for (int m = j + (int)threadIdx.x; m < w - j; m += nthr) {
             T f[3];
 #pragma unroll
             for (int cx = 0; cx < 3; ++cx)
-                f[cx] = in[cx * w + m + 1 - cx];
+                f[cx] = lds[in + cx * w + m + 1 - cx];
             const bool bad = collide_dt<1, DT, CORR, EQ>(f, a.relax);
             raise_flag(a.flag, bad);
             if (j == a.K) {
@@ -629,7 +631,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_t1(StepKArgs a) {
             } else {
 #pragma unroll
                 for (int i = 0; i < 3; ++i)
-                    out[i * w + m] = f[i];
+                    lds[out + i * w + m] = f[i];
             }
         }
     }
