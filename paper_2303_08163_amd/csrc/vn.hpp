@@ -295,12 +295,17 @@ __host__ __device__ __forceinline__ void qr_step(cplx (&H)[N][N], cplx mu, int h
     // columns k, k+1 times G_k^H: col k <- c x + conj(s) y ; col k+1 <- -s x + c y
     auto column_rotation = [&](auto kk, double c, cplx s) {
         constexpr int k = decltype(kk)::value;
-        static_for<0, k + 2>([&](auto ii) {
+        static_for<0, k + 1>([&](auto ii) {
             constexpr int i = decltype(ii)::value;
             const cplx x = H[i][k], y = H[i][k + 1];
             H[i][k] = crot(c, x, {s.re, -s.im}, y);
             H[i][k + 1] = crot(c, y, {-s.re, -s.im}, x);
         });
+        // row k + 1: its column-k entry is the exact zero row rotation k left,
+        // so the terms with it drop out (the same values; a zero may change sign)
+        const cplx y = H[k + 1][k + 1];
+        H[k + 1][k] = cmul({s.re, -s.im}, y);
+        H[k + 1][k + 1] = cscale(c, y);
     };
     double c_prev = 1.0;
     cplx s_prev = {0.0, 0.0};
@@ -379,12 +384,13 @@ __host__ __device__ constexpr double vn_reduce_flops() {
 // One QR step on an active block of m rows.  Per rotation: forming it (20)
 // and applying it to rows k, k + 1 of columns k..m-1 (10 for column k, whose
 // lower entry is set to zero, 20 for each other) and to rows 0..k+1 of columns
-// k, k + 1 (20 each): 20 m + 50.  Per step: the deflation scan (5 per row
-// below the first), the shift (52: the trailing 2 x 2's eigenvalue nearer its
-// last diagonal entry and the exceptional shift, both formed) and its
-// subtraction and return on the block's rows (4 m).
+// k, k + 1 (20 each, 8 for row k + 1, whose column-k entry is zero): 20 m + 38.
+// Per step: the deflation scan (5 per row below the first), the shift (52: the
+// trailing 2 x 2's eigenvalue nearer its last diagonal entry and the
+// exceptional shift, both formed) and its subtraction and return on the
+// block's rows (4 m).
 __host__ __device__ constexpr double vn_step_flops(int m) {
-    return (m - 1) * (20.0 * m + 55.0) + 4.0 * m + 52.0;
+    return (m - 1) * (20.0 * m + 43.0) + 4.0 * m + 52.0;
 }
 
 // Eigenvalues of an upper Hessenberg matrix (overwritten; the diagonal holds
